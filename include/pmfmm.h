@@ -1,0 +1,206 @@
+/*
+ * pmfmm.h - C ABI of the short-range PM-FMM gravity library for MI355X.
+ *
+ * The library evaluates the short-range part of the Gaussian-split gravity
+ * of the PM-FMM method (Wang & Meng, "PhotoNs-GPU", arXiv 2107.14008):
+ * particles in a periodic cube, split radius r_s (Sec. 2: r_s = 1.2 of the
+ * PM cell), a cutoff radius (Sec. 2: the kernel is truncated there), the
+ * leaf size MAXLEAF of the ORB tree (Sec. 2) and the expansion order p of
+ * the truncated M2L (Sec. 2, M2L equation) in; the short-range
+ * accelerations out.
+ *
+ * Per particle i the result is
+ *     a_i = G sum_j m_j T(|d_ij| / 2 r_s) d_ij / |d_ij|^3,  0 < |d_ij|^2 < r_cut^2,
+ * with d_ij the periodic displacement from i to j and
+ * T(x) = erfc(x) + (2x / sqrt(pi)) exp(-x^2) (Sec. 2, Eq. (tr)).  Pairs of
+ * ORB leaves within the cutoff are summed directly (P2P, Sec. 3.2 Alg. 1 and
+ * Alg. 2); with the far field on, well separated cell pairs lying wholly
+ * inside the cutoff go through P2M, M2M, M2L, L2L and L2P instead (Sec. 2).
+ *
+ * Conventions for every call:
+ *   - return value: PMFMM_OK (0) or a negative pmfmm_status; no C++
+ *     exception crosses the ABI; pmfmm_last_error() gives the message of the
+ *     last failure on the calling thread;
+ *   - arrays of particles are in the caller's order, positions as (n, 3)
+ *     row-major float64, masses (n) float64, accelerations (n, 3) float64;
+ *   - a "device" pointer is HIP device memory of the current device; a
+ *     "host" pointer is ordinary host memory;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *     device work is enqueued on it and the call returns without waiting,
+ *     except where stated;
+ *   - a context is used by one thread at a time; contexts are independent.
+ */
+#ifndef PMFMM_H
+#define PMFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pmfmm_status {
+    PMFMM_OK = 0,
+    PMFMM_EINVAL = -1,       /* bad argument or parameter                  */
+    PMFMM_ENOMEM = -2,       /* host or device allocation failed           */
+    PMFMM_EDEVICE = -3,      /* a HIP call failed (no device, launch error) */
+    PMFMM_ESTATE = -4,       /* call out of order (e.g. forward before build) */
+    PMFMM_EUNSUPPORTED = -5  /* valid request this build does not provide   */
+} pmfmm_status;
+
+/* Arithmetic of the pair force (Sec. 4 compares single and double). */
+enum { PMFMM_FP64 = 0, PMFMM_FP32 = 1 };
+/* Truncation factor T: library erfc/exp, or the Taylor table of Eq. (int). */
+enum { PMFMM_TRUNC_EXACT = 0, PMFMM_TRUNC_TABLE = 1 };
+/* Table node choice for x: nearest node or the node below x. */
+enum { PMFMM_ROUND_NEAREST = 0, PMFMM_ROUND_FLOOR = 1 };
+
+typedef struct pmfmm_params {
+    /* geometry and force split (Sec. 2) */
+    double box;          /* side L of the periodic cube, > 0                     */
+    double r_s;          /* split radius, > 0                                     */
+    double r_cut;        /* cutoff radius, 0 < r_cut < box / 2                    */
+    double G;            /* gravitational constant multiplying every force        */
+    double theta;        /* opening angle of the M2L acceptance test
+                            (r_A + r_B) < theta |R|; 0 turns the far field off  */
+    int32_t max_leaf;    /* MAXLEAF of the ORB tree, 1..64                        */
+    int32_t order;       /* expansion order p, 0..6; < 0 turns the far field off  */
+    /* evaluation of the pair force (Sec. 3.3) */
+    int32_t precision;   /* PMFMM_FP64 or PMFMM_FP32                              */
+    int32_t trunc;       /* PMFMM_TRUNC_EXACT or PMFMM_TRUNC_TABLE                 */
+    int32_t table_size;  /* nodes on x in [0, 3]: 16..4096                        */
+    int32_t table_level; /* Taylor terms kept, 0..4 (T_[0] .. T_[4])              */
+    int32_t table_round; /* PMFMM_ROUND_NEAREST or PMFMM_ROUND_FLOOR              */
+    /* scheduling of the P2P work (no effect on results) */
+    int32_t chunk;       /* j-leaves per work item, 0 = automatic                 */
+    int32_t wg_waves;    /* wavefronts per workgroup of the P2P launch, 0 = auto  */
+    int32_t grid_wgs;    /* workgroups of the persistent launch, 0 = auto         */
+    int32_t timing;      /* 1: time each phase with HIP events (see get_timings)  */
+    int32_t threads;     /* host threads for the tree build, 0 = all              */
+} pmfmm_params;
+
+typedef struct pmfmm_ctx pmfmm_ctx;
+
+/* Fill *p with defaults: box 100, r_s 3.75, r_cut 4.5 r_s, G 1, theta 0,
+ * max_leaf 64, order 4, FP64, exact T, 2048-node table, level 4, nearest. */
+void pmfmm_params_init(pmfmm_params* p);
+
+/* Validate and copy *p into a new context.  *out receives the context, to be
+ * released by pmfmm_destroy.  No device memory is taken yet.
+ * Errors: EINVAL for any parameter outside the ranges above, ENOMEM. */
+int pmfmm_create(const pmfmm_params* p, pmfmm_ctx** out);
+
+/* Release the context and all host and device memory it owns (waits for
+ * the device work it enqueued).  NULL is accepted. */
+void pmfmm_destroy(pmfmm_ctx* ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* pmfmm_last_error(void);
+
+/* Host-only planning (Sec. 2 ORB tree; Sec. 3 dual walk and task lists;
+ * Sec. 3.2 TaskGroup / GroupIdx).  `pos` (n, 3) and `mass` (n) are host
+ * pointers, copied.  Positions are wrapped into [0, box).  Builds the tree,
+ * the P2P list (i leaf, j leaf, image shift) sorted by (i, j, shift), the
+ * M2L list sorted by (target, source, shift) and the work items; touches no
+ * GPU.  Errors: EINVAL (n < 1, NaN/Inf position, negative mass), ENOMEM. */
+int pmfmm_plan(pmfmm_ctx* ctx, int64_t n, const double* pos,
+               const double* mass);
+
+/* Several independent boxes in one plan (one persistent launch later).
+ * Box b holds counts[b] >= 1 particles, stored consecutively in `pos` and
+ * `mass` (host pointers) in box order; per_box[b] gives its geometry, split,
+ * cutoff, G, max_leaf, order and theta; the evaluation fields are the
+ * context's.  Errors as pmfmm_plan; the message names the first bad box. */
+int pmfmm_plan_batch(pmfmm_ctx* ctx, int32_t nbox,
+                     const pmfmm_params* per_box, const int64_t* counts,
+                     const double* pos, const double* mass);
+
+/* pmfmm_plan followed by the upload of everything the kernels read.
+ * on_device = 0: pos and mass are host pointers; 1: device pointers (they
+ * are copied to the host for the tree, synchronously on `stream`).  The
+ * particles are then gathered into leaf order on the device.  The caller
+ * may free or change pos and mass when the call returns.
+ * Errors: those of pmfmm_plan, EDEVICE, ENOMEM. */
+int pmfmm_build(pmfmm_ctx* ctx, int64_t n, const double* pos,
+                const double* mass, int32_t on_device, void* stream);
+
+/* pmfmm_plan_batch followed by the upload, as pmfmm_build. */
+int pmfmm_build_batch(pmfmm_ctx* ctx, int32_t nbox,
+                      const pmfmm_params* per_box, const int64_t* counts,
+                      const double* pos, const double* mass,
+                      int32_t on_device, void* stream);
+
+/* Change how the pair force is evaluated (precision, trunc, table_*) and
+ * how the P2P work is scheduled (chunk, wg_waves, grid_wgs, timing) without
+ * rebuilding the tree.  Geometry, split and tree fields of *p are ignored.
+ * A change of chunk re-cuts the work items (needs a prior plan; re-uploads
+ * them if the context was built).  Errors: EINVAL. */
+int pmfmm_set_eval(pmfmm_ctx* ctx, const pmfmm_params* p);
+
+/* Short-range accelerations of the built particles.  `acc` is a device
+ * pointer to (n_total, 3) float64, written in the caller's particle order
+ * (boxes consecutive for a batch).  Enqueues: far field (if on), the
+ * persistent P2P kernel (Alg. 1 / Alg. 2), the ordered reduction of the
+ * work-item partials, all on `stream`.  Results are bitwise reproducible
+ * run to run.  Errors: ESTATE (not built), EDEVICE. */
+int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream);
+
+/* Gradient of loss = sum_i w_i . a_i with respect to positions and masses
+ * for the P2P-only force (far field off).  w, grad_pos: device (n_total, 3);
+ * grad_mass: device (n_total); caller order.  The almost-everywhere
+ * gradient: the step of the hard cutoff is left out.
+ * Errors: ESTATE, EUNSUPPORTED (far field on), EDEVICE. */
+int pmfmm_adjoint(pmfmm_ctx* ctx, const double* w, double* grad_pos,
+                  double* grad_mass, void* stream);
+
+/* Host views of the plan, valid until the next plan/build or destroy.
+ * Particle and leaf indices are global over the batch; `perm[k]` is the
+ * caller index of the particle stored k-th (leaf order). */
+typedef struct pmfmm_lists {
+    int64_t n;                 /* particles over all boxes                */
+    int64_t n_boxes, n_leaves, n_cells, n_p2p, n_m2l, n_items;
+    int64_t candidate_pairs;   /* sum over P2P tasks of n_i * n_j         */
+    const int32_t* perm;       /* (n)                                     */
+    const int32_t* box_first_leaf; /* (n_boxes + 1)                        */
+    const int32_t* box_first_cell; /* (n_boxes + 1)                        */
+    const int32_t* leaf_first; /* (n_leaves) first particle, leaf order   */
+    const int32_t* leaf_count; /* (n_leaves)                              */
+    const int32_t* leaf_cell;  /* (n_leaves) cell of each leaf            */
+    const int32_t* cell_first; /* (n_cells)                               */
+    const int32_t* cell_count; /* (n_cells)                               */
+    const int32_t* cell_child; /* (n_cells, 2), -1 for a leaf             */
+    const double* cell_lo;     /* (n_cells, 3)                            */
+    const double* cell_hi;     /* (n_cells, 3)                            */
+    const int32_t* p2p_row;    /* (n_leaves + 1) CSR rows of i leaves     */
+    const int32_t* p2p_j;      /* (n_p2p) source leaf                     */
+    const int32_t* p2p_shift;  /* (n_p2p) (sx+1) + 3 (sy+1) + 9 (sz+1)   */
+    const int32_t* m2l_row;    /* (n_cells + 1) CSR rows of target cells  */
+    const int32_t* m2l_src;    /* (n_m2l) source cell                     */
+    const int32_t* m2l_shift;  /* (n_m2l)                                 */
+} pmfmm_lists;
+
+/* Fill *out with views of the current plan.  Errors: ESTATE (no plan). */
+int pmfmm_get_lists(const pmfmm_ctx* ctx, pmfmm_lists* out);
+
+/* Phase times of the last forward/adjoint, in milliseconds, measured with
+ * HIP events recorded on the call's stream (only when params.timing = 1;
+ * this call waits for those events). */
+typedef struct pmfmm_timings {
+    double far_ms;       /* P2M .. L2P                               */
+    double p2p_ms;       /* the persistent P2P kernel alone          */
+    double reduce_ms;    /* ordered reduction + write-back           */
+    double total_ms;     /* whole forward                            */
+    double adjoint_ms;   /* adjoint P2P kernel alone                 */
+} pmfmm_timings;
+
+/* Errors: ESTATE (timing off or nothing timed yet), EDEVICE. */
+int pmfmm_get_timings(const pmfmm_ctx* ctx, pmfmm_timings* out);
+
+/* Library version string. */
+const char* pmfmm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMFMM_H */

@@ -63,7 +63,16 @@ def _r2(d):
     return (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
 
 
-def _pair_accel(xi, xj, mj, box, r_s, rc2):
+def _T(x, table):
+    """T(x) of Eq. (tr), or its Eq. (int) table form when ``table`` is
+    (n_tab, level, rounding)."""
+    if table is None:
+        return erfc(x) + (2.0 / SQRT_PI) * x * np.exp(-x * x)
+    from .truncation import T_table
+    return T_table(x, table[0], table[1], table[2])
+
+
+def _pair_accel(xi, xj, mj, box, r_s, rc2, table=None):
     """Acceleration on each row of xi from every row of xj (no G)."""
     d = image_displacement(xi[:, None, :], xj[None, :, :], box)
     r2 = _r2(d)
@@ -71,13 +80,17 @@ def _pair_accel(xi, xj, mj, box, r_s, rc2):
     r2s = np.where(ok, r2, 1.0)
     r = np.sqrt(r2s)
     x = r / (2.0 * r_s)
-    T = erfc(x) + (2.0 / SQRT_PI) * x * np.exp(-x * x)
+    T = _T(x, table)
     g = np.where(ok, mj[None, :] * T / (r2s * r), 0.0)
     return np.einsum("ij,ijk->ik", g, d), ok.sum(axis=1)
 
 
-def all_pairs(pos, mass, box, r_s, r_cut, G=1.0, targets=None, chunk=256):
-    """O(N^2) minimum-image truncated sum; returns (acc, neighbour counts)."""
+def all_pairs(pos, mass, box, r_s, r_cut, G=1.0, targets=None, chunk=256,
+              table=None):
+    """O(N^2) minimum-image truncated sum; returns (acc, neighbour counts).
+
+    ``table`` = (n_tab, level, rounding) replaces T by its Eq. (int) table.
+    """
     pos = np.asarray(pos, np.float64)
     mass = np.asarray(mass, np.float64)
     rc2 = r_cut * r_cut
@@ -86,7 +99,7 @@ def all_pairs(pos, mass, box, r_s, r_cut, G=1.0, targets=None, chunk=256):
     cnt = np.zeros(len(idx), np.int64)
     for s in range(0, len(idx), chunk):
         sl = idx[s:s + chunk]
-        a, c = _pair_accel(pos[sl], pos, mass, box, r_s, rc2)
+        a, c = _pair_accel(pos[sl], pos, mass, box, r_s, rc2, table)
         acc[s:s + chunk] = G * a
         cnt[s:s + chunk] = c
     return acc, cnt
@@ -196,24 +209,26 @@ def _run_cells(pos, mass, box, r_cut, fn_name, targets, workers, extra=None):
 def _force_fn(ti, nb):
     w = _WORK
     return _pair_accel(w["pos"][ti], w["pos"][nb], w["mass"][nb], w["box"],
-                       w["r_s"], w["rc2"])
+                       w["r_s"], w["rc2"], w.get("table"))
 
 
-def brute_force(pos, mass, box, r_s, r_cut, G=1.0, targets=None, workers=None):
+def brute_force(pos, mass, box, r_s, r_cut, G=1.0, targets=None, workers=None,
+                table=None):
     """Truncated minimum-image sum over a cell grid.
 
     Returns (acc, neighbour counts) for every particle, or for ``targets``
     (in the order given) when that is set.  ``workers`` processes share the
     target cells (default: the CPUs this process may run on, at most 16).
+    ``table`` = (n_tab, level, rounding) replaces T by its Eq. (int) table.
     """
     pos = np.ascontiguousarray(pos, np.float64)
     mass = np.ascontiguousarray(mass, np.float64)
     if r_cut >= 0.5 * box:
         raise ValueError("r_cut must be below half the box")
     if math.floor(box / r_cut) < 3:
-        return all_pairs(pos, mass, box, r_s, r_cut, G, targets)
+        return all_pairs(pos, mass, box, r_s, r_cut, G, targets, table=table)
     res = _run_cells(pos, mass, box, r_cut, "_force_fn", targets, workers,
-                     dict(box=box, r_s=r_s, rc2=r_cut * r_cut))
+                     dict(box=box, r_s=r_s, rc2=r_cut * r_cut, table=table))
     acc = np.zeros((len(pos), 3))
     cnt = np.zeros(len(pos), np.int64)
     for ti, (a, c) in res:

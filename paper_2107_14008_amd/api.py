@@ -1,0 +1,104 @@
+"""torch-facing helpers over the C ABI (device memory and streams only).
+
+``ShortRange`` owns one library context: ``build`` plans the tree and task
+lists for a particle set and uploads them, ``forward`` returns the
+short-range accelerations, ``adjoint`` the gradient of sum_i w_i . a_i.
+``ShortRangeForce`` exposes forward and adjoint as a torch.autograd.Function
+(gradients with respect to positions and masses).
+"""
+
+from __future__ import annotations
+
+import torch
+
+from . import binding as B
+
+_PREC = {"fp64": B.PMFMM_FP64, "fp32": B.PMFMM_FP32}
+_TRUNC = {"exact": B.TRUNC_EXACT, "table": B.TRUNC_TABLE}
+_ROUND = {"nearest": B.ROUND_NEAREST, "floor": B.ROUND_FLOOR}
+
+
+def _params(kw):
+    out = dict(kw)
+    if isinstance(out.get("precision"), str):
+        out["precision"] = _PREC[out["precision"]]
+    if isinstance(out.get("trunc"), str):
+        out["trunc"] = _TRUNC[out["trunc"]]
+    if isinstance(out.get("table_round"), str):
+        out["table_round"] = _ROUND[out["table_round"]]
+    return out
+
+
+class ShortRange:
+    """Short-range force of one periodic box (or a batch of boxes)."""
+
+    def __init__(self, **params):
+        self.ctx = B.Context(**_params(params))
+        self.n = 0
+
+    def build(self, pos: torch.Tensor, mass: torch.Tensor):
+        if pos.device.type != "cuda":
+            raise ValueError("pos must be a CUDA tensor")
+        pos = pos.detach().to(torch.float64).contiguous()
+        mass = mass.detach().to(torch.float64).contiguous()
+        self.ctx.build(pos, mass, torch.cuda.current_stream(pos.device))
+        self.n = pos.shape[0]
+        self.device = pos.device
+        return self
+
+    def build_batch(self, per_box: list, counts, pos, mass):
+        boxes = [B.make_params(**_params(p)) for p in per_box]
+        pos = pos.detach().to(torch.float64).contiguous()
+        mass = mass.detach().to(torch.float64).contiguous()
+        self.ctx.build_batch(boxes, list(counts), pos, mass,
+                             torch.cuda.current_stream(pos.device))
+        self.n = pos.shape[0]
+        self.device = pos.device
+        return self
+
+    def set_eval(self, **kw):
+        self.ctx.set_eval(**_params(kw))
+
+    def forward(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty((self.n, 3), dtype=torch.float64,
+                              device=self.device)
+        self.ctx.forward(out, torch.cuda.current_stream(self.device))
+        return out
+
+    def adjoint(self, w: torch.Tensor):
+        w = w.detach().to(torch.float64).contiguous()
+        gp = torch.empty((self.n, 3), dtype=torch.float64, device=self.device)
+        gm = torch.empty((self.n,), dtype=torch.float64, device=self.device)
+        self.ctx.adjoint(w, gp, gm, torch.cuda.current_stream(self.device))
+        return gp, gm
+
+    def lists(self):
+        return self.ctx.lists()
+
+    def timings(self):
+        return self.ctx.timings()
+
+
+def short_range_accel(pos: torch.Tensor, mass: torch.Tensor, **params):
+    """Accelerations (n, 3) float64 of the truncated short-range force."""
+    return ShortRange(**params).build(pos, mass).forward()
+
+
+class ShortRangeForce(torch.autograd.Function):
+    """acc = ShortRangeForce.apply(pos, mass, params_dict).
+
+    The backward pass runs the library's adjoint kernel: for a cotangent w it
+    returns (dL/dpos, dL/dmass) of L = sum_i w_i . acc_i (P2P-only force).
+    """
+
+    @staticmethod
+    def forward(ctx, pos, mass, params):
+        sr = ShortRange(**params).build(pos, mass)
+        ctx.sr = sr
+        return sr.forward().to(pos.dtype)
+
+    @staticmethod
+    def backward(ctx, grad_acc):
+        gp, gm = ctx.sr.adjoint(grad_acc)
+        return gp, gm, None

@@ -1,0 +1,147 @@
+// Device-side data layout and kernel launchers of the short-range library.
+//
+// Layout in HBM (all arrays global over a batch of boxes):
+//   x64[k]  double4 (x, y, z, m)            particle k in leaf order
+//   x32[k]  float4  (x - c_leaf, m)         single-precision cell-relative form
+//   leaf[l] int4    (first, count, box, cell)
+//   leafc[l] double4 (centre x, y, z, 0)    expansion / offset centre
+//   p2p_row[l] .. p2p_row[l+1]              TaskGroup rows of i leaf l
+//   p2p_js[t] = (j leaf << 5) | shift code  TaskGroup entries
+//   items[q] int4 (leaf, t0, t1, slot)      work items; queue = longest first
+//   partial[(slot * 3 + axis) * 64 + lane]  per-item float64 partial sums
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pmfmm {
+
+enum Mode : int { kFP64Exact = 0, kFP64Table = 1, kFP32Exact = 2, kFP32Table = 3 };
+
+struct BoxDev {
+    double L;        // box side
+    double alpha;    // 1 / (2 r_s)
+    double rc2;      // r_cut * r_cut
+    double G;
+    float alpha_f, rc2_f, tab_scale_f, pad_f;
+    double tab_scale;  // n_tab / 3 / (2 r_s): x-table units per unit distance
+    int32_t order;     // expansion order p of this box (< 0: no far field)
+    int32_t pad;
+};
+
+struct P2PArgs {
+    const double4* x64;
+    const float4* x32;
+    const int4* leaf;
+    const double4* leafc;
+    const int32_t* p2p_js;
+    const int4* items;
+    const int32_t* queue;
+    int32_t n_items;
+    int32_t* counter;
+    double* partial;
+    const BoxDev* boxes;
+    const void* table;   // coefficient table, layout per mode (see p2p.hip)
+    int32_t n_tab;
+    int32_t level;
+    int32_t round_floor;
+};
+
+struct ReduceArgs {
+    const int4* leaf;
+    const int32_t* leaf_slot;   // n_leaves + 1
+    const double* partial;
+    const double* far;          // (n, 3) leaf order or nullptr
+    const int32_t* perm;
+    const BoxDev* boxes;
+    double* out;                // (n, 3) caller order
+    int32_t n_leaves;
+};
+
+struct GatherArgs {
+    const double* pos_in;       // (n, 3) caller order
+    const double* mass_in;      // (n)
+    const int32_t* perm;
+    const int4* leaf;
+    const double4* leafc;
+    const BoxDev* boxes;
+    double4* x64;
+    float4* x32;
+    int32_t n_leaves;
+};
+
+struct FarArgs {
+    const double4* x64;
+    const int4* leaf;
+    const double4* leafc;
+    const int4* cell;           // (first, count, parent, leaf) per cell
+    const int4* cell_aux;       // (child0, child1, box, depth) per cell
+    const double4* cellc;       // centre per cell
+    const int32_t* m2l_row;
+    const int32_t* m2l_src;
+    const int32_t* m2l_shift;
+    const int32_t* level_cells; // cells of one depth
+    int32_t n_level;
+    const BoxDev* boxes;
+    double* M;                  // (n_cells, ncoef)
+    double* Lc;                 // (n_cells, ncoef)
+    double* far;                // (n, 3) leaf order
+    int32_t n_cells, n_leaves, order, ncoef;
+};
+
+struct AdjArgs {
+    const double4* x64;
+    const float4* x32;
+    const double4* w64;         // (w, 0) per particle, leaf order
+    const int4* leaf;
+    const double4* leafc;
+    const int32_t* p2p_js;
+    const int4* items;
+    const int32_t* queue;
+    int32_t n_items;
+    int32_t* counter;
+    double* partial;            // (slot, 4, 64): grad x, y, z, m
+    const BoxDev* boxes;
+    const void* table;
+    int32_t n_tab, level, round_floor;
+};
+
+struct AdjReduceArgs {
+    const int4* leaf;
+    const int32_t* leaf_slot;
+    const double* partial;
+    const int32_t* perm;
+    const BoxDev* boxes;
+    double* grad_pos;           // (n, 3) caller order
+    double* grad_mass;          // (n)
+    int32_t n_leaves;
+};
+
+// Launchers (return the hipError_t of the launch).
+hipError_t launch_gather(const GatherArgs& a, const double* pos_dev_unwrapped,
+                         hipStream_t s);
+hipError_t launch_zero_i32(int32_t* p, int32_t n, hipStream_t s);
+hipError_t launch_p2p(int mode, const P2PArgs& a, int wg_waves, int grid_wgs,
+                      size_t lds_bytes, hipStream_t s);
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+hipError_t launch_gather_w(const double* w, const int32_t* perm, double4* w64,
+                           int32_t n, hipStream_t s);
+hipError_t launch_adjoint(int mode, const AdjArgs& a, int wg_waves, int grid_wgs,
+                          size_t lds_bytes, hipStream_t s);
+hipError_t launch_adj_reduce(const AdjReduceArgs& a, hipStream_t s);
+
+// Far field (far.hip).
+hipError_t launch_p2m(const FarArgs& a, hipStream_t s);
+hipError_t launch_m2m_level(const FarArgs& a, hipStream_t s);
+hipError_t launch_m2l(const FarArgs& a, hipStream_t s);
+hipError_t launch_l2l_level(const FarArgs& a, hipStream_t s);
+hipError_t launch_l2p(const FarArgs& a, hipStream_t s);
+hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t s);
+
+// Occupancy helpers: max resident workgroups per CU of the P2P kernel.
+int p2p_blocks_per_cu(int mode, int wg_waves, size_t lds_bytes);
+int adjoint_blocks_per_cu(int mode, int wg_waves, size_t lds_bytes);
+int n_coef(int order);
+
+}  // namespace pmfmm

@@ -1,0 +1,329 @@
+// Truncated far field of the short-range tree (Sec. 2): P2M, M2M (pass-up),
+// M2L over the M2L task list, L2L (pass-down) and L2P, in float64.
+//
+// Expansion (centres z = cell AABB centres; R = z_B - (z_A + s L)):
+//   M_m(z_A) = sum_j m_j (z_A - y_j)^m / m!
+//   M_m(z_P) = sum_{k <= m} M_k(z_C) (z_P - z_C)^(m-k) / (m-k)!
+//   L_n(z_B) = sum_{|m| <= p-|n|} M_m(z_A) D_{n+m}(R)      (Sec. 2, M2L equation)
+//   L_n(z_c) = sum_{k >= n} L_k(z_P) (z_c - z_P)^(k-n) / (k-n)!
+//   a(x)     = grad_u sum_n L_n u^n / n!,  u = x - z_B   (G applied later)
+// D_k = d^k psi for psi = erfc(r / 2 r_s) / r, as the full Cartesian tensor
+// of a radial function (the truncated kernel is not harmonic, so the
+// traceless shortcut of the plain 1/r kernel does not apply):
+//   D_k = sum_{2m <= k} prod_a k_a! / (2^m_a m_a! (k_a - 2 m_a)!) R_a^(k_a - 2 m_a) f_(|k|-|m|)(r)
+// with f_(j) = ((1/r) d/dr)^j psi obtained by the upward recursion
+//   B_0 = erfc(a r) / r,  B_j = ((2j - 1) B_(j-1) + (2 a^2)^j exp(-a^2 r^2) / (a sqrt(pi))) / r^2,
+//   f_(j) = (-1)^j B_j,  a = 1 / (2 r_s),
+// which adds only positive terms (stable at small r / r_s).
+//
+// Mapping: one wavefront per cell (or per leaf); lanes own coefficients
+// (P2M, M2M, M2L, L2L) or particles (L2P).  These operators are a small
+// share of the step (the paper measures P2P as the dominant cost, Sec. 3);
+// they run as plain vector-ALU kernels, one launch per tree level for the
+// pass-up and pass-down.
+#include "device.h"
+
+namespace pmfmm {
+namespace {
+
+constexpr int kMaxP = 6;
+constexpr int kMaxNC = 84;
+
+struct MITable {
+    signed char a[kMaxNC], b[kMaxNC], c[kMaxNC];
+    short idx[kMaxP + 1][kMaxP + 1][kMaxP + 1];
+};
+
+constexpr MITable make_mi() {
+    MITable t{};
+    int k = 0;
+    for (int deg = 0; deg <= kMaxP; ++deg)
+        for (int a = deg; a >= 0; --a)
+            for (int b = deg - a; b >= 0; --b) {
+                const int c = deg - a - b;
+                t.a[k] = (signed char)a;
+                t.b[k] = (signed char)b;
+                t.c[k] = (signed char)c;
+                t.idx[a][b][c] = (short)k;
+                ++k;
+            }
+    return t;
+}
+
+__constant__ MITable c_mi = make_mi();
+__constant__ double c_fact[kMaxP + 1] = {1.0, 1.0, 2.0, 6.0, 24.0, 120.0, 720.0};
+__constant__ double c_ifact[kMaxP + 1] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0,
+                                          1.0 / 720.0};
+
+constexpr double kInvSqrtPi = 0.56418958354775628695;
+
+__device__ __forceinline__ double ipow(double x, int n) {
+    double r = 1.0;
+    for (int i = 0; i < n; ++i) r *= x;
+    return r;
+}
+
+__device__ __forceinline__ int ncoef_of(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+
+// Radial derivatives f_(0..p) of the truncated kernel at distance r.
+__device__ void radial_f(double r, double alpha, int p, double* f) {
+    const double r2 = r * r;
+    const double g = exp(-alpha * alpha * r2) / (alpha) * kInvSqrtPi;
+    double B = erfc(alpha * r) / r;
+    double two_a2_pow = 1.0;
+    f[0] = B;
+    for (int j = 1; j <= p; ++j) {
+        two_a2_pow *= 2.0 * alpha * alpha;
+        B = ((2.0 * j - 1.0) * B + two_a2_pow * g) / r2;
+        f[j] = (j & 1) ? -B : B;
+    }
+}
+
+__device__ double d_entry(int a, int b, int c, const double R[3], const double* f) {
+    double sum = 0.0;
+    for (int ma = 0; 2 * ma <= a; ++ma) {
+        const double ca = c_fact[a] / (ipow(2.0, ma) * c_fact[ma] * c_fact[a - 2 * ma]);
+        const double pa = ipow(R[0], a - 2 * ma);
+        for (int mb = 0; 2 * mb <= b; ++mb) {
+            const double cb = c_fact[b] / (ipow(2.0, mb) * c_fact[mb] * c_fact[b - 2 * mb]);
+            const double pb = ipow(R[1], b - 2 * mb);
+            for (int mc = 0; 2 * mc <= c; ++mc) {
+                const double cc = c_fact[c] / (ipow(2.0, mc) * c_fact[mc] * c_fact[c - 2 * mc]);
+                const double pc = ipow(R[2], c - 2 * mc);
+                sum += ca * cb * cc * pa * pb * pc * f[a + b + c - ma - mb - mc];
+            }
+        }
+    }
+    return sum;
+}
+
+// ---- P2M: one wavefront per leaf, lanes own coefficients.
+__global__ void __launch_bounds__(64)
+p2m_kernel(const double4* __restrict__ x64, const int4* __restrict__ leaf,
+           const double4* __restrict__ cellc, const BoxDev* __restrict__ boxes,
+           double* __restrict__ M, int n_leaves, int ncoef) {
+    const int l = blockIdx.x;
+    if (l >= n_leaves) return;
+    const int4 li = leaf[l];
+    const int p = boxes[li.z].order;
+    if (p < 0) return;
+    const int nc = ncoef_of(p);
+    const double4 c = cellc[li.w];
+    for (int k = threadIdx.x; k < nc; k += 64) {
+        const int a = c_mi.a[k], b = c_mi.b[k], cc = c_mi.c[k];
+        const double inv = c_ifact[a] * c_ifact[b] * c_ifact[cc];
+        double acc = 0.0;
+        for (int j = 0; j < li.y; ++j) {
+            const double4 q = x64[li.x + j];
+            acc += q.w * ipow(c.x - q.x, a) * ipow(c.y - q.y, b) * ipow(c.z - q.z, cc);
+        }
+        M[(size_t)li.w * ncoef + k] = acc * inv;
+    }
+}
+
+// ---- M2M for the internal cells of one depth.
+__global__ void __launch_bounds__(64)
+m2m_kernel(const int32_t* __restrict__ level_cells, int n_level, const int4* __restrict__ cell,
+           const int4* __restrict__ aux, const double4* __restrict__ cellc,
+           const BoxDev* __restrict__ boxes, double* __restrict__ M, int ncoef) {
+    if ((int)blockIdx.x >= n_level) return;
+    const int P = level_cells[blockIdx.x];
+    if (cell[P].w >= 0) return;                       // leaf: P2M already did it
+    const int4 ax = aux[P];
+    const int p = boxes[ax.z].order;
+    if (p < 0) return;
+    const int nc = ncoef_of(p);
+    const double4 cp = cellc[P];
+    for (int m = threadIdx.x; m < nc; m += 64) {
+        const int m0 = c_mi.a[m], m1 = c_mi.b[m], m2 = c_mi.c[m];
+        double acc = 0.0;
+        for (int ch = 0; ch < 2; ++ch) {
+            const int C = ch == 0 ? ax.x : ax.y;
+            const double4 cc = cellc[C];
+            const double dz[3] = {cp.x - cc.x, cp.y - cc.y, cp.z - cc.z};
+            const double* MC = M + (size_t)C * ncoef;
+            for (int k0 = 0; k0 <= m0; ++k0)
+                for (int k1 = 0; k1 <= m1; ++k1)
+                    for (int k2 = 0; k2 <= m2; ++k2) {
+                        const double w = ipow(dz[0], m0 - k0) * c_ifact[m0 - k0] *
+                                         ipow(dz[1], m1 - k1) * c_ifact[m1 - k1] *
+                                         ipow(dz[2], m2 - k2) * c_ifact[m2 - k2];
+                        acc += MC[c_mi.idx[k0][k1][k2]] * w;
+                    }
+        }
+        M[(size_t)P * ncoef + m] = acc;
+    }
+}
+
+// ---- M2L: one wavefront per target cell over its M2L row; the D tensor of
+// each source is built in LDS by the lanes, then lane n accumulates L_n.
+__global__ void __launch_bounds__(64)
+m2l_kernel(const int32_t* __restrict__ row, const int32_t* __restrict__ src,
+           const int32_t* __restrict__ shift, const int4* __restrict__ aux,
+           const double4* __restrict__ cellc, const BoxDev* __restrict__ boxes,
+           const double* __restrict__ M, double* __restrict__ Lc, int n_cells, int ncoef) {
+    __shared__ double Dsh[kMaxNC];
+    const int t = blockIdx.x;
+    if (t >= n_cells) return;
+    const int r0 = row[t], r1 = row[t + 1];
+    const int lane = threadIdx.x;
+    if (r0 == r1) {
+        for (int n = lane; n < ncoef; n += 64) Lc[(size_t)t * ncoef + n] = 0.0;
+        return;
+    }
+    const BoxDev bx = boxes[aux[t].z];
+    const int p = bx.order;
+    const int nc = ncoef_of(p);
+    const double4 ct = cellc[t];
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int q = r0; q < r1; ++q) {
+        const int u = src[q];
+        const int s = shift[q];
+        const double4 cu = cellc[u];
+        const double R[3] = {ct.x - (cu.x + (double)(s % 3 - 1) * bx.L),
+                             ct.y - (cu.y + (double)((s / 3) % 3 - 1) * bx.L),
+                             ct.z - (cu.z + (double)(s / 9 - 1) * bx.L)};
+        const double r = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+        double f[kMaxP + 1];
+        radial_f(r, bx.alpha, p, f);
+        for (int k = lane; k < nc; k += 64) Dsh[k] = d_entry(c_mi.a[k], c_mi.b[k], c_mi.c[k], R, f);
+        __syncthreads();
+        const double* Mu = M + (size_t)u * ncoef;
+        for (int half = 0; half < 2; ++half) {
+            const int n = lane + 64 * half;
+            if (n >= nc) break;
+            const int n0 = c_mi.a[n], n1 = c_mi.b[n], n2 = c_mi.c[n];
+            const int rem = p - (n0 + n1 + n2);
+            const int mend = ncoef_of(rem);
+            double s_acc = 0.0;
+            for (int m = 0; m < mend; ++m)
+                s_acc += Mu[m] * Dsh[c_mi.idx[n0 + c_mi.a[m]][n1 + c_mi.b[m]][n2 + c_mi.c[m]]];
+            if (half == 0) acc0 += s_acc; else acc1 += s_acc;
+        }
+        __syncthreads();
+    }
+    if (lane < nc) Lc[(size_t)t * ncoef + lane] = acc0;
+    if (lane + 64 < nc) Lc[(size_t)t * ncoef + lane + 64] = acc1;
+    for (int n = nc + lane; n < ncoef; n += 64) Lc[(size_t)t * ncoef + n] = 0.0;
+}
+
+// ---- L2L for the cells of one depth (>= 1): add the parent's shifted local.
+__global__ void __launch_bounds__(64)
+l2l_kernel(const int32_t* __restrict__ level_cells, int n_level, const int4* __restrict__ cell,
+           const int4* __restrict__ aux, const double4* __restrict__ cellc,
+           const BoxDev* __restrict__ boxes, double* __restrict__ Lc, int ncoef) {
+    if ((int)blockIdx.x >= n_level) return;
+    const int C = level_cells[blockIdx.x];
+    const int P = cell[C].z;
+    if (P < 0) return;
+    const int p = boxes[aux[C].z].order;
+    if (p < 0) return;
+    const int nc = ncoef_of(p);
+    const double4 cc = cellc[C], cp = cellc[P];
+    const double dz[3] = {cc.x - cp.x, cc.y - cp.y, cc.z - cp.z};
+    const double* LP = Lc + (size_t)P * ncoef;
+    for (int n = threadIdx.x; n < nc; n += 64) {
+        const int n0 = c_mi.a[n], n1 = c_mi.b[n], n2 = c_mi.c[n];
+        const int deg = n0 + n1 + n2;
+        double acc = 0.0;
+        for (int k0 = n0; k0 <= p; ++k0)
+            for (int k1 = n1; k0 + k1 <= p; ++k1)
+                for (int k2 = n2; k0 + k1 + k2 <= p; ++k2) {
+                    const double w = ipow(dz[0], k0 - n0) * c_ifact[k0 - n0] *
+                                     ipow(dz[1], k1 - n1) * c_ifact[k1 - n1] *
+                                     ipow(dz[2], k2 - n2) * c_ifact[k2 - n2];
+                    acc += LP[c_mi.idx[k0][k1][k2]] * w;
+                }
+        (void)deg;
+        Lc[(size_t)C * ncoef + n] += acc;
+    }
+}
+
+// ---- L2P: one wavefront per leaf, lane = particle.
+__global__ void __launch_bounds__(64)
+l2p_kernel(const double4* __restrict__ x64, const int4* __restrict__ leaf,
+           const double4* __restrict__ cellc, const BoxDev* __restrict__ boxes,
+           const double* __restrict__ Lc, double* __restrict__ far, int n_leaves, int ncoef) {
+    const int l = blockIdx.x;
+    if (l >= n_leaves) return;
+    const int4 li = leaf[l];
+    const int lane = threadIdx.x;
+    if (lane >= li.y) return;
+    const int k = li.x + lane;
+    const int p = boxes[li.z].order;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    if (p >= 0) {
+        const int nc = ncoef_of(p);
+        const double4 c = cellc[li.w];
+        const double4 q = x64[k];
+        const double u[3] = {q.x - c.x, q.y - c.y, q.z - c.z};
+        double pw[3][kMaxP + 1];
+        for (int a = 0; a < 3; ++a) {
+            pw[a][0] = 1.0;
+            for (int i = 1; i <= kMaxP; ++i) pw[a][i] = pw[a][i - 1] * u[a] / (double)i;
+        }
+        const double* L = Lc + (size_t)li.w * ncoef;
+        for (int n = 1; n < nc; ++n) {
+            const int n0 = c_mi.a[n], n1 = c_mi.b[n], n2 = c_mi.c[n];
+            const double Ln = L[n];
+            if (n0 > 0) ax += Ln * pw[0][n0 - 1] * pw[1][n1] * pw[2][n2];
+            if (n1 > 0) ay += Ln * pw[0][n0] * pw[1][n1 - 1] * pw[2][n2];
+            if (n2 > 0) az += Ln * pw[0][n0] * pw[1][n1] * pw[2][n2 - 1];
+        }
+    }
+    far[3 * (size_t)k] = ax;
+    far[3 * (size_t)k + 1] = ay;
+    far[3 * (size_t)k + 2] = az;
+}
+
+__global__ void zero_f64_kernel(double* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+}  // namespace
+
+int n_coef(int order) { return order < 0 ? 1 : (order + 1) * (order + 2) * (order + 3) / 6; }
+
+hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_f64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_p2m(const FarArgs& a, hipStream_t s) {
+    if (a.n_leaves == 0) return hipSuccess;
+    hipLaunchKernelGGL(p2m_kernel, dim3(a.n_leaves), dim3(64), 0, s, a.x64, a.leaf, a.cellc,
+                       a.boxes, a.M, a.n_leaves, a.ncoef);
+    return hipGetLastError();
+}
+
+hipError_t launch_m2m_level(const FarArgs& a, hipStream_t s) {
+    if (a.n_level == 0) return hipSuccess;
+    hipLaunchKernelGGL(m2m_kernel, dim3(a.n_level), dim3(64), 0, s, a.level_cells, a.n_level,
+                       a.cell, a.cell_aux, a.cellc, a.boxes, a.M, a.ncoef);
+    return hipGetLastError();
+}
+
+hipError_t launch_m2l(const FarArgs& a, hipStream_t s) {
+    if (a.n_cells == 0) return hipSuccess;
+    hipLaunchKernelGGL(m2l_kernel, dim3(a.n_cells), dim3(64), 0, s, a.m2l_row, a.m2l_src,
+                       a.m2l_shift, a.cell_aux, a.cellc, a.boxes, a.M, a.Lc, a.n_cells, a.ncoef);
+    return hipGetLastError();
+}
+
+hipError_t launch_l2l_level(const FarArgs& a, hipStream_t s) {
+    if (a.n_level == 0) return hipSuccess;
+    hipLaunchKernelGGL(l2l_kernel, dim3(a.n_level), dim3(64), 0, s, a.level_cells, a.n_level,
+                       a.cell, a.cell_aux, a.cellc, a.boxes, a.Lc, a.ncoef);
+    return hipGetLastError();
+}
+
+hipError_t launch_l2p(const FarArgs& a, hipStream_t s) {
+    if (a.n_leaves == 0) return hipSuccess;
+    hipLaunchKernelGGL(l2p_kernel, dim3(a.n_leaves), dim3(64), 0, s, a.x64, a.leaf, a.cellc,
+                       a.boxes, a.Lc, a.far, a.n_leaves, a.ncoef);
+    return hipGetLastError();
+}
+
+}  // namespace pmfmm

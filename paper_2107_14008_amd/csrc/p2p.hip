@@ -1,0 +1,438 @@
+// P2P kernels: the truncated pair force over TaskGroup rows (Sec. 3.2,
+// Alg. 1 and Alg. 2), the ordered reduction of work-item partials, and the
+// particle gather into leaf order (Sec. 3.1).
+//
+// Mapping on CDNA4: one wavefront (64 lanes) per work item; lane l holds
+// target particle l of the i leaf (Alg. 1: one thread per i particle).
+// Sources are read with wave-uniform addresses, so the compiler turns them
+// into scalar loads broadcast from SGPRs instead of staging each j leaf
+// through LDS; LDS holds the interpolation table of Eq. (int) instead (the
+// paper keeps T_i and E_i in shared memory, Sec. 3.3).  Work items
+// (i leaf, a range of its j leaves) are pulled from an atomic queue by a
+// persistent grid, longest first, and every item writes its own partial
+// sums, which a second kernel adds in a fixed order: results do not depend
+// on scheduling.
+#include "device.h"
+
+namespace pmfmm {
+namespace {
+
+constexpr double kTwoOverSqrtPi = 1.12837916709551257390;
+constexpr float kTwoOverSqrtPiF = 1.12837916709551257390f;
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ void shift_of(int s, double L, double& sx, double& sy, double& sz) {
+    sx = (double)(s % 3 - 1) * L;
+    sy = (double)((s / 3) % 3 - 1) * L;
+    sz = (double)(s / 9 - 1) * L;
+}
+
+// Wrap into [0, L); identical steps to the host plan (no contraction).
+__device__ __forceinline__ double wrap_coord(double x, double L) {
+#pragma clang fp contract(off)
+    if (x >= 0.0 && x < L) return x;
+    double y = x - L * floor(x / L);
+    if (y >= L) y -= L;
+    if (y < 0.0) y += L;
+    if (!(y >= 0.0 && y < L)) y = 0.0;
+    return y;
+}
+
+// ------------------------------------------------------------ pair forms
+
+// float64, library erfc / exp.  The displacement and r^2 follow the exact
+// steps of the definition (d = (x_j - x_i) + s L; r2 = (dx dx + dy dy) +
+// dz dz, no fused multiply-add) so the cutoff decision is bit-identical
+// to a plain float64 evaluation.
+template <bool SHIFTED>
+__device__ __forceinline__ void pair_f64_exact(const double4 q, double xi, double yi, double zi,
+                                               double sx, double sy, double sz, double rc2,
+                                               double alpha, double& ax, double& ay, double& az) {
+    double dx, dy, dz, r2;
+    {
+#pragma clang fp contract(off)
+        dx = q.x - xi;
+        dy = q.y - yi;
+        dz = q.z - zi;
+        if (SHIFTED) {
+            dx = dx + sx;
+            dy = dy + sy;
+            dz = dz + sz;
+        }
+        r2 = (dx * dx + dy * dy) + dz * dz;
+    }
+    const bool ok = (r2 > 0.0) & (r2 < rc2);
+    const double r2s = ok ? r2 : 1.0;
+    const double idr = rsqrt(r2s);
+    const double x = r2s * idr * alpha;
+    const double T = erfc(x) + kTwoOverSqrtPi * x * exp(-x * x);
+    const double g = ok ? q.w * T * (idr * idr * idr) : 0.0;
+    ax = fma(g, dx, ax);
+    ay = fma(g, dy, ay);
+    az = fma(g, dz, az);
+}
+
+// float64, Taylor table of Eq. (int) with coefficients pre-scaled to table
+// units: T = c0 + e (c1 + e (c2 + e (c3 + e c4))), e = u - d, u = x n_tab / 3.
+template <int LEVEL, bool SHIFTED>
+__device__ __forceinline__ void pair_f64_table(const double4 q, double xi, double yi, double zi,
+                                               double sx, double sy, double sz, double rc2,
+                                               double scale, double rnd, int dmax,
+                                               const double2* __restrict__ t01,
+                                               const double2* __restrict__ t23,
+                                               const double* __restrict__ t4, double& ax,
+                                               double& ay, double& az) {
+    double dx, dy, dz, r2;
+    {
+#pragma clang fp contract(off)
+        dx = q.x - xi;
+        dy = q.y - yi;
+        dz = q.z - zi;
+        if (SHIFTED) {
+            dx = dx + sx;
+            dy = dy + sy;
+            dz = dz + sz;
+        }
+        r2 = (dx * dx + dy * dy) + dz * dz;
+    }
+    const bool ok = (r2 > 0.0) & (r2 < rc2);
+    const double r2s = ok ? r2 : 1.0;
+    const double idr = rsqrt(r2s);
+    const double u = r2s * idr * scale;
+    int d = (int)(u + rnd);
+    d = min(d, dmax);
+    const double e = u - (double)d;
+    const double2 c01 = t01[d];
+    double T;
+    if constexpr (LEVEL == 0) {
+        T = c01.x;
+    } else if constexpr (LEVEL == 1) {
+        T = fma(c01.y, e, c01.x);
+    } else {
+        const double2 c23 = t23[d];
+        if constexpr (LEVEL == 2) {
+            T = fma(fma(c23.x, e, c01.y), e, c01.x);
+        } else if constexpr (LEVEL == 3) {
+            T = fma(fma(fma(c23.y, e, c23.x), e, c01.y), e, c01.x);
+        } else {
+            T = fma(fma(fma(fma(t4[d], e, c23.y), e, c23.x), e, c01.y), e, c01.x);
+        }
+    }
+    const double g = ok ? q.w * T * (idr * idr * idr) : 0.0;
+    ax = fma(g, dx, ax);
+    ay = fma(g, dy, ay);
+    az = fma(g, dz, az);
+}
+
+// float32 on cell-relative offsets: (px, py, pz) = target offset minus the
+// source leaf's offset, so d = q.xyz - p.
+__device__ __forceinline__ void pair_f32_exact(const float4 q, float px, float py, float pz,
+                                               float rc2, float alpha, float& ax, float& ay,
+                                               float& az) {
+    const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const bool ok = (r2 > 0.f) & (r2 < rc2);
+    const float r2s = ok ? r2 : 1.f;
+    const float idr = rsqrtf(r2s);
+    const float x = r2s * idr * alpha;
+    const float T = erfcf(x) + kTwoOverSqrtPiF * x * expf(-x * x);
+    const float g = ok ? q.w * T * (idr * idr * idr) : 0.f;
+    ax = fmaf(g, dx, ax);
+    ay = fmaf(g, dy, ay);
+    az = fmaf(g, dz, az);
+}
+
+template <int LEVEL>
+__device__ __forceinline__ void pair_f32_table(const float4 q, float px, float py, float pz,
+                                               float rc2, float scale, float rnd, int dmax,
+                                               const float4* __restrict__ t03,
+                                               const float* __restrict__ t4, float& ax, float& ay,
+                                               float& az) {
+    const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const bool ok = (r2 > 0.f) & (r2 < rc2);
+    const float r2s = ok ? r2 : 1.f;
+    const float idr = rsqrtf(r2s);
+    const float u = r2s * idr * scale;
+    int d = (int)(u + rnd);
+    d = min(d, dmax);
+    const float e = u - (float)d;
+    const float4 c = t03[d];
+    float T;
+    if constexpr (LEVEL == 0) {
+        T = c.x;
+    } else if constexpr (LEVEL == 1) {
+        T = fmaf(c.y, e, c.x);
+    } else if constexpr (LEVEL == 2) {
+        T = fmaf(fmaf(c.z, e, c.y), e, c.x);
+    } else if constexpr (LEVEL == 3) {
+        T = fmaf(fmaf(fmaf(c.w, e, c.z), e, c.y), e, c.x);
+    } else {
+        T = fmaf(fmaf(fmaf(fmaf(t4[d], e, c.w), e, c.z), e, c.y), e, c.x);
+    }
+    const float g = ok ? q.w * T * (idr * idr * idr) : 0.f;
+    ax = fmaf(g, dx, ax);
+    ay = fmaf(g, dy, ay);
+    az = fmaf(g, dz, az);
+}
+
+// LDS table layouts (bytes), matching the host builder in abi.cpp:
+//   float32: float4 c0..c3 [n_tab], then float c4 [n_tab]
+//   float64: double2 (c0, c1) [n_tab], double2 (c2, c3) [n_tab], double c4 [n_tab]
+__device__ __forceinline__ void load_table(unsigned char* lds, const void* __restrict__ table,
+                                           int bytes) {
+    const uint4* src = reinterpret_cast<const uint4*>(table);
+    uint4* dst = reinterpret_cast<uint4*>(lds);
+    for (int i = threadIdx.x; i < bytes / 16; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+}
+
+template <int MODE, int LEVEL>
+__global__ void __launch_bounds__(1024)
+p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
+           const int4* __restrict__ leaf, const double4* __restrict__ leafc,
+           const int32_t* __restrict__ p2p_js, const int4* __restrict__ items,
+           const int32_t* __restrict__ queue, int32_t n_items, int32_t* __restrict__ counter,
+           double* __restrict__ partial, const BoxDev* __restrict__ boxes,
+           const void* __restrict__ table, int32_t n_tab, int32_t table_bytes,
+           int32_t round_floor) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    constexpr bool kTable = (MODE == kFP64Table) || (MODE == kFP32Table);
+    if constexpr (kTable) load_table(lds, table, table_bytes);
+    const int lane = threadIdx.x & 63;
+    const int dmax = n_tab - 1;
+
+    for (;;) {
+        int q = 0;
+        if (lane == 0) q = atomicAdd(counter, 1);
+        q = uni(q);
+        if (q >= n_items) break;
+        const int slot = uni(queue[q]);
+        const int4 it = items[slot];
+        const int il = uni(it.x), t0 = uni(it.y), t1 = uni(it.z);
+        const int4 li = leaf[il];
+        const int ni = uni(li.y);
+        const int pi = uni(li.x) + (lane < ni ? lane : 0);
+        const BoxDev bx = boxes[uni(li.z)];
+        const double4 ci = leafc[il];
+        double ax = 0.0, ay = 0.0, az = 0.0;
+
+        if constexpr (MODE == kFP32Exact || MODE == kFP32Table) {
+            const float4 pv = x32[pi];
+            const float rc2 = bx.rc2_f;
+            const float rnd = round_floor ? 0.f : 0.5f;
+            const float4* t03 = reinterpret_cast<const float4*>(lds);
+            const float* t4 = reinterpret_cast<const float*>(lds + 16 * n_tab);
+            for (int t = t0; t < t1; ++t) {
+                const int js = uni(p2p_js[t]);
+                const int jl = js >> 5;
+                const int4 lj = leaf[jl];
+                const double4 cj = leafc[jl];
+                double sx, sy, sz;
+                shift_of(js & 31, bx.L, sx, sy, sz);
+                const float px = pv.x - (float)((cj.x - ci.x) + sx);
+                const float py = pv.y - (float)((cj.y - ci.y) + sy);
+                const float pz = pv.z - (float)((cj.z - ci.z) + sz);
+                const float4* __restrict__ src = x32 + uni(lj.x);
+                const int nj = uni(lj.y);
+                float fx = 0.f, fy = 0.f, fz = 0.f;
+                if constexpr (MODE == kFP32Exact) {
+                    for (int k = 0; k < nj; ++k)
+                        pair_f32_exact(src[k], px, py, pz, rc2, bx.alpha_f, fx, fy, fz);
+                } else {
+#pragma unroll 4
+                    for (int k = 0; k < nj; ++k)
+                        pair_f32_table<LEVEL>(src[k], px, py, pz, rc2, bx.tab_scale_f, rnd, dmax,
+                                              t03, t4, fx, fy, fz);
+                }
+                ax += (double)fx;
+                ay += (double)fy;
+                az += (double)fz;
+            }
+        } else {
+            const double4 pv = x64[pi];
+            const double rc2 = bx.rc2;
+            const double rnd = round_floor ? 0.0 : 0.5;
+            const double2* t01 = reinterpret_cast<const double2*>(lds);
+            const double2* t23 = reinterpret_cast<const double2*>(lds + 16 * n_tab);
+            const double* t4 = reinterpret_cast<const double*>(lds + 32 * n_tab);
+            for (int t = t0; t < t1; ++t) {
+                const int js = uni(p2p_js[t]);
+                const int jl = js >> 5;
+                const int s = js & 31;
+                const int4 lj = leaf[jl];
+                double sx, sy, sz;
+                shift_of(s, bx.L, sx, sy, sz);
+                const double4* __restrict__ src = x64 + uni(lj.x);
+                const int nj = uni(lj.y);
+                if (s == 13) {
+                    for (int k = 0; k < nj; ++k) {
+                        if constexpr (MODE == kFP64Exact)
+                            pair_f64_exact<false>(src[k], pv.x, pv.y, pv.z, 0.0, 0.0, 0.0, rc2,
+                                                  bx.alpha, ax, ay, az);
+                        else
+                            pair_f64_table<LEVEL, false>(src[k], pv.x, pv.y, pv.z, 0.0, 0.0, 0.0,
+                                                         rc2, bx.tab_scale, rnd, dmax, t01, t23,
+                                                         t4, ax, ay, az);
+                    }
+                } else {
+                    for (int k = 0; k < nj; ++k) {
+                        if constexpr (MODE == kFP64Exact)
+                            pair_f64_exact<true>(src[k], pv.x, pv.y, pv.z, sx, sy, sz, rc2,
+                                                 bx.alpha, ax, ay, az);
+                        else
+                            pair_f64_table<LEVEL, true>(src[k], pv.x, pv.y, pv.z, sx, sy, sz, rc2,
+                                                        bx.tab_scale, rnd, dmax, t01, t23, t4, ax,
+                                                        ay, az);
+                    }
+                }
+            }
+        }
+        double* dst = partial + (size_t)slot * 192;
+        dst[lane] = ax;
+        dst[64 + lane] = ay;
+        dst[128 + lane] = az;
+    }
+}
+
+// One wavefront per leaf: sum the leaf's item partials in slot order, add
+// the far-field part, scale by G and scatter to the caller's order.
+__global__ void __launch_bounds__(256)
+reduce_kernel(const int4* __restrict__ leaf, const int32_t* __restrict__ leaf_slot,
+              const double* __restrict__ partial, const double* __restrict__ far,
+              const int32_t* __restrict__ perm, const BoxDev* __restrict__ boxes,
+              double* __restrict__ out, int32_t n_leaves) {
+    const int l = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (l >= n_leaves) return;
+    const int4 li = leaf[l];
+    if (lane >= li.y) return;
+    const int s0 = leaf_slot[l], s1 = leaf_slot[l + 1];
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (int s = s0; s < s1; ++s) {
+        const double* p = partial + (size_t)s * 192;
+        ax += p[lane];
+        ay += p[64 + lane];
+        az += p[128 + lane];
+    }
+    const int k = li.x + lane;
+    if (far != nullptr) {
+        ax += far[3 * (size_t)k];
+        ay += far[3 * (size_t)k + 1];
+        az += far[3 * (size_t)k + 2];
+    }
+    const double G = boxes[li.z].G;
+    const int o = perm[k];
+    out[3 * (size_t)o] = G * ax;
+    out[3 * (size_t)o + 1] = G * ay;
+    out[3 * (size_t)o + 2] = G * az;
+}
+
+// One wavefront per leaf: particles into leaf order, wrapped, as float64
+// records and as float32 offsets from the leaf centre.
+__global__ void __launch_bounds__(256)
+gather_kernel(const double* __restrict__ pos_in, const double* __restrict__ mass_in,
+              const int32_t* __restrict__ perm, const int4* __restrict__ leaf,
+              const double4* __restrict__ leafc, const BoxDev* __restrict__ boxes,
+              double4* __restrict__ x64, float4* __restrict__ x32, int32_t n_leaves) {
+    const int l = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (l >= n_leaves) return;
+    const int4 li = leaf[l];
+    if (lane >= li.y) return;
+    const int k = li.x + lane;
+    const int o = perm[k];
+    const double L = boxes[li.z].L;
+    const double x = wrap_coord(pos_in[3 * (size_t)o], L);
+    const double y = wrap_coord(pos_in[3 * (size_t)o + 1], L);
+    const double z = wrap_coord(pos_in[3 * (size_t)o + 2], L);
+    const double m = mass_in[o];
+    x64[k] = make_double4(x, y, z, m);
+    const double4 c = leafc[l];
+    x32[k] = make_float4((float)(x - c.x), (float)(y - c.y), (float)(z - c.z), (float)m);
+}
+
+__global__ void zero_i32_kernel(int32_t* p, int32_t n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+template <int MODE, int LEVEL>
+hipError_t launch_one(const P2PArgs& a, int wg_waves, int grid_wgs, size_t lds, hipStream_t s) {
+    const int tb = (int)lds;
+    hipLaunchKernelGGL((p2p_kernel<MODE, LEVEL>), dim3(grid_wgs), dim3(64 * wg_waves), lds, s,
+                       a.x64, a.x32, a.leaf, a.leafc, a.p2p_js, a.items, a.queue, a.n_items,
+                       a.counter, a.partial, a.boxes, a.table, a.n_tab, tb, a.round_floor);
+    return hipGetLastError();
+}
+
+template <int MODE, int LEVEL>
+int occ_one(int wg_waves, size_t lds) {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, p2p_kernel<MODE, LEVEL>,
+                                                     64 * wg_waves, lds) != hipSuccess)
+        return 1;
+    return blocks > 0 ? blocks : 1;
+}
+
+}  // namespace
+
+hipError_t launch_p2p(int mode, const P2PArgs& a, int wg_waves, int grid_wgs, size_t lds,
+                      hipStream_t s) {
+    if (a.n_items == 0) return hipSuccess;
+    switch (mode) {
+        case kFP64Exact: return launch_one<kFP64Exact, 0>(a, wg_waves, grid_wgs, 0, s);
+        case kFP32Exact: return launch_one<kFP32Exact, 0>(a, wg_waves, grid_wgs, 0, s);
+        case kFP32Table:
+            switch (a.level) {
+                case 0: return launch_one<kFP32Table, 0>(a, wg_waves, grid_wgs, lds, s);
+                case 1: return launch_one<kFP32Table, 1>(a, wg_waves, grid_wgs, lds, s);
+                case 2: return launch_one<kFP32Table, 2>(a, wg_waves, grid_wgs, lds, s);
+                case 3: return launch_one<kFP32Table, 3>(a, wg_waves, grid_wgs, lds, s);
+                default: return launch_one<kFP32Table, 4>(a, wg_waves, grid_wgs, lds, s);
+            }
+        case kFP64Table:
+            switch (a.level) {
+                case 0: return launch_one<kFP64Table, 0>(a, wg_waves, grid_wgs, lds, s);
+                case 1: return launch_one<kFP64Table, 1>(a, wg_waves, grid_wgs, lds, s);
+                case 2: return launch_one<kFP64Table, 2>(a, wg_waves, grid_wgs, lds, s);
+                case 3: return launch_one<kFP64Table, 3>(a, wg_waves, grid_wgs, lds, s);
+                default: return launch_one<kFP64Table, 4>(a, wg_waves, grid_wgs, lds, s);
+            }
+    }
+    return hipErrorInvalidValue;
+}
+
+int p2p_blocks_per_cu(int mode, int wg_waves, size_t lds) {
+    switch (mode) {
+        case kFP64Exact: return occ_one<kFP64Exact, 0>(wg_waves, 0);
+        case kFP32Exact: return occ_one<kFP32Exact, 0>(wg_waves, 0);
+        case kFP32Table: return occ_one<kFP32Table, 2>(wg_waves, lds);
+        default: return occ_one<kFP64Table, 4>(wg_waves, lds);
+    }
+}
+
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
+    if (a.n_leaves == 0) return hipSuccess;
+    const int wgs = (a.n_leaves + 3) / 4;
+    hipLaunchKernelGGL(reduce_kernel, dim3(wgs), dim3(256), 0, s, a.leaf, a.leaf_slot, a.partial,
+                       a.far, a.perm, a.boxes, a.out, a.n_leaves);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const GatherArgs& a, const double* /*unused*/, hipStream_t s) {
+    if (a.n_leaves == 0) return hipSuccess;
+    const int wgs = (a.n_leaves + 3) / 4;
+    hipLaunchKernelGGL(gather_kernel, dim3(wgs), dim3(256), 0, s, a.pos_in, a.mass_in, a.perm,
+                       a.leaf, a.leafc, a.boxes, a.x64, a.x32, a.n_leaves);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(int32_t* p, int32_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace pmfmm

@@ -1,0 +1,72 @@
+// Host-side plan: ORB tree, dual-walk task lists and P2P work items.
+//
+// Built on the CPU (the paper builds the tree and both task lists on the
+// host as well, Sec. 3) and uploaded once per build.  All geometry decisions
+// use correctly rounded float64 +, -, *, sqrt, fabs, max and comparisons in
+// a fixed order; this file must be compiled without floating-point
+// contraction.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace pmfmm {
+
+struct BoxParams {
+    double box, r_s, r_cut, G, theta;
+    int32_t max_leaf, order;
+};
+
+struct Cell {
+    double lo[3], hi[3];
+    int32_t first, count;   // leaf-order particle range (global)
+    int32_t child[2];       // global cell ids, -1 for a leaf
+    int32_t parent;         // global cell id, -1 for a root
+    int32_t depth;          // 0 at the box root
+    int32_t leaf;           // global leaf id, -1 for an internal cell
+    int32_t box;
+};
+
+// Work item of the persistent P2P launch: the tasks [t0, t1) of one i leaf.
+struct WorkItem {
+    int32_t leaf, t0, t1, slot;
+};
+
+struct Plan {
+    int64_t n = 0;
+    std::vector<BoxParams> boxes;
+    std::vector<int32_t> box_first_particle;  // nbox + 1
+    std::vector<int32_t> box_first_leaf;      // nbox + 1
+    std::vector<int32_t> box_first_cell;      // nbox + 1
+    std::vector<double> pos;                  // (n, 3) wrapped, caller order
+    std::vector<double> mass;                 // (n)
+    std::vector<int32_t> perm;                // leaf order -> caller index
+    std::vector<Cell> cells;
+    std::vector<int32_t> leaf_cell;           // leaf -> cell
+    std::vector<int32_t> leaf_first, leaf_count, leaf_box;
+    std::vector<int32_t> p2p_row, p2p_j, p2p_shift;
+    std::vector<int32_t> m2l_row, m2l_src, m2l_shift;
+    std::vector<int32_t> cell_first, cell_count, cell_child;  // views for the ABI
+    std::vector<double> cell_lo, cell_hi;
+    std::vector<WorkItem> items;              // natural (slot) order
+    std::vector<int32_t> queue;               // slots, longest first
+    std::vector<int32_t> leaf_slot_begin;     // n_leaves + 1
+    std::vector<int32_t> cells_by_depth;      // cells grouped by depth
+    std::vector<int32_t> depth_begin;         // max_depth + 2
+    int64_t candidate_pairs = 0;
+    bool far_field = false;                   // any box with M2L tasks
+    int max_order = -1;
+};
+
+// Builds tree + lists for every box.  Returns an empty string on success,
+// otherwise a message (invalid input).
+std::string make_plan(Plan& plan, const std::vector<BoxParams>& boxes,
+                      const std::vector<int64_t>& counts, const double* pos,
+                      const double* mass, int threads);
+
+// (Re)cuts the P2P rows into work items of at most `chunk` tasks
+// (0 = automatic) and orders the queue by decreasing pair count.
+void make_items(Plan& plan, int chunk);
+
+}  // namespace pmfmm

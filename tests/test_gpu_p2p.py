@@ -1,0 +1,227 @@
+"""GPU parity of the P2P path against the CPU oracle (through the C ABI).
+
+Tolerances (relative force error e_i = |a_i - a_ref| / |a_ref|):
+  * float64, exact T:          max e_i <= 1e-12
+  * float64, 2048-node T_[4]:  max e_i <= 1e-12 against the oracle's table
+                               sum, and <= 1e-11 against the exact sum
+  * float32 (any T form):      median <= 1e-5, 99.9th percentile <= 1e-4
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import direct, metrics
+from paper_2107_14008_amd import binding as B
+from paper_2107_14008_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_forward(pos, mass, box, r_s, r_cut, max_leaf, order=-1, theta=0.0,
+                **ev):
+    ctx = B.Context(box=box, r_s=r_s, r_cut=r_cut, max_leaf=max_leaf,
+                    order=order, theta=theta, **ev)
+    p = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    m = torch.tensor(mass, dtype=torch.float64, device="cuda")
+    s = torch.cuda.current_stream()
+    ctx.build(p, m, s)
+    out = torch.full((len(mass), 3), float("nan"), dtype=torch.float64,
+                     device="cuda")
+    ctx.forward(out, s)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), ctx
+
+
+def check_fp32(acc, ref):
+    s = metrics.error_summary(acc, ref)
+    assert s["median"] <= 1e-5, s
+    assert s["p999"] <= 1e-4, s
+    return s
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = inputs.uniform_32k()
+    ref, cnt = direct.brute_force(w.pos, w.mass, w.box, w.r_s, w.r_cut)
+    return w, ref
+
+
+@pytest.fixture(scope="module")
+def clustered():
+    w = inputs.clustered_small(24, 77, halo_frac=0.3, n_halos=6)
+    ref, _ = direct.brute_force(w.pos, w.mass, w.box, w.r_s, w.r_cut)
+    return w, ref
+
+
+def test_fp64_exact_uniform_32k(c1):
+    w, ref = c1
+    print("case: uniform 32^3, fp64 exact, leaf 32", flush=True)
+    acc, ctx = gpu_forward(w.pos, w.mass, w.box, w.r_s, w.r_cut, w.max_leaf)
+    s = metrics.error_summary(acc, ref)
+    assert s["max"] <= 1e-12, s
+
+
+def test_fp64_exact_clustered(clustered):
+    w, ref = clustered
+    print("case: clustered 24^3, fp64 exact, leaf 64", flush=True)
+    acc, _ = gpu_forward(w.pos, w.mass, w.box, w.r_s, w.r_cut, 64)
+    assert metrics.error_summary(acc, ref)["max"] <= 1e-12
+
+
+@pytest.mark.parametrize("chunk", [1, 3, 1000])
+def test_fp64_exact_any_chunking(clustered, chunk):
+    w, ref = clustered
+    print(f"case: clustered 24^3, fp64 exact, chunk {chunk}", flush=True)
+    acc, _ = gpu_forward(w.pos, w.mass, w.box, w.r_s, w.r_cut, 64,
+                         chunk=chunk)
+    assert metrics.error_summary(acc, ref)["max"] <= 1e-12
+
+
+def test_fp64_table_level4(clustered):
+    w, ref = clustered
+    print("case: clustered 24^3, fp64 table 2048 T_[4]", flush=True)
+    acc, _ = gpu_forward(w.pos, w.mass, w.box, w.r_s, w.r_cut, 64,
+                         precision=B.PMFMM_FP64, trunc=B.TRUNC_TABLE,
+                         table_size=2048, table_level=4)
+    ref_tab, _ = direct.brute_force(w.pos, w.mass, w.box, w.r_s, w.r_cut,
+                                    table=(2048, 4, "nearest"))
+    assert metrics.error_summary(acc, ref_tab)["max"] <= 1e-12
+    assert metrics.error_summary(acc, ref)["max"] <= 1e-11
+
+
+@pytest.mark.parametrize("level,n_tab,rnd", [(2, 512, B.ROUND_NEAREST),
+                                             (1, 2048, B.ROUND_NEAREST),
+                                             (3, 2048, B.ROUND_NEAREST),
+                                             (2, 512, B.ROUND_FLOOR)])
+def test_fp32_table(c1, level, n_tab, rnd):
+    w, ref = c1
+    print(f"case: uniform 32^3 fp32 table {n_tab} level {level}", flush=True)
+    acc, _ = gpu_forward(w.pos, w.mass, w.box, w.r_s, w.r_cut, w.max_leaf,
+                         precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
+                         table_size=n_tab, table_level=level, table_round=rnd)
+    check_fp32(acc, ref)
+
+
+def test_fp32_exact_and_table_clustered(clustered):
+    w, ref = clustered
+    for trunc in (B.TRUNC_EXACT, B.TRUNC_TABLE):
+        print(f"case: clustered 24^3 fp32 trunc {trunc}", flush=True)
+        acc, _ = gpu_forward(w.pos, w.mass, w.box, w.r_s, w.r_cut, 64,
+                             precision=B.PMFMM_FP32, trunc=trunc,
+                             table_size=2048, table_level=2)
+        check_fp32(acc, ref)
+
+
+def test_bitwise_reproducible(clustered):
+    w, _ = clustered
+    for prec in (B.PMFMM_FP64, B.PMFMM_FP32):
+        a1, ctx = gpu_forward(w.pos, w.mass, w.box, w.r_s, w.r_cut, 64,
+                              precision=prec)
+        out = torch.empty((len(w.mass), 3), dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            ctx.forward(out, torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), a1)
+
+
+def test_reused_context_switching_modes(clustered):
+    w, ref = clustered
+    acc, ctx = gpu_forward(w.pos, w.mass, w.box, w.r_s, w.r_cut, 64)
+    out = torch.empty((len(w.mass), 3), dtype=torch.float64, device="cuda")
+    for prec, trunc in [(B.PMFMM_FP32, B.TRUNC_TABLE), (B.PMFMM_FP64,
+                                                        B.TRUNC_EXACT),
+                        (B.PMFMM_FP32, B.TRUNC_EXACT)]:
+        ctx.set_eval(precision=prec, trunc=trunc, table_size=1024,
+                     table_level=2, chunk=7)
+        ctx.forward(out, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        a = out.cpu().numpy()
+        if prec == B.PMFMM_FP64:
+            assert metrics.error_summary(a, ref)["max"] <= 1e-12
+        else:
+            check_fp32(a, ref)
+
+
+# ------------------------------------------------------------- edge cases
+
+def test_single_particle_and_pair():
+    box, r_s, r_cut = 10.0, 0.5, 2.25
+    acc, _ = gpu_forward(np.array([[1.0, 2.0, 3.0]]), np.array([2.0]), box,
+                         r_s, r_cut, 8)
+    assert np.all(acc == 0.0)
+    pos = np.array([[9.8, 5.0, 5.0], [0.3, 5.0, 5.0]])   # across the boundary
+    m = np.array([1.5, 0.5])
+    acc, _ = gpu_forward(pos, m, box, r_s, r_cut, 8, G=3.0)
+    ref, _ = direct.all_pairs(pos, m, box, r_s, r_cut, G=3.0)
+    assert metrics.error_summary(acc, ref)["max"] <= 1e-14
+    assert acc[0, 0] > 0 and acc[1, 0] < 0
+
+
+def test_coincident_and_ragged():
+    rng = np.random.default_rng(9)
+    pos = rng.uniform(0, 20.0, (3001, 3))
+    pos[100:140] = pos[0]                       # 41 coincident particles
+    m = rng.uniform(0.2, 1.0, 3001)
+    for ml in (1, 7, 64):
+        print(f"case: ragged 3001 coincident, leaf {ml}", flush=True)
+        acc, _ = gpu_forward(pos, m, 20.0, 0.6, 2.7, ml)
+        ref, _ = direct.all_pairs(pos, m, 20.0, 0.6, 2.7)
+        assert np.all(np.isfinite(acc))
+        assert metrics.error_summary(acc, ref)["max"] <= 1e-12
+
+
+def test_unwrapped_device_input_is_wrapped():
+    rng = np.random.default_rng(3)
+    pos = rng.uniform(0, 20.0, (500, 3))
+    shifted = pos + rng.integers(-2, 3, (500, 3)) * 20.0
+    m = np.ones(500)
+    a0, _ = gpu_forward(pos, m, 20.0, 0.6, 2.7, 16)
+    a1, _ = gpu_forward(shifted, m, 20.0, 0.6, 2.7, 16)
+    ref, _ = direct.all_pairs(pos, m, 20.0, 0.6, 2.7)
+    assert metrics.error_summary(a1, ref)["max"] <= 1e-12
+    assert metrics.error_summary(a0, ref)["max"] <= 1e-12
+
+
+def test_host_input_build():
+    rng = np.random.default_rng(4)
+    pos = rng.uniform(0, 20.0, (700, 3))
+    m = np.ones(700)
+    ctx = B.Context(box=20.0, r_s=0.6, r_cut=2.7, max_leaf=16, order=-1)
+    ctx.build(pos, m)                        # host pointers
+    out = torch.empty((700, 3), dtype=torch.float64, device="cuda")
+    ctx.forward(out)
+    torch.cuda.synchronize()
+    ref, _ = direct.all_pairs(pos, m, 20.0, 0.6, 2.7)
+    assert metrics.error_summary(out.cpu().numpy(), ref)["max"] <= 1e-12
+
+
+# ------------------------------------------------------------- full size
+
+@pytest.fixture(scope="module")
+def c2():
+    return inputs.clustered_2m()
+
+
+def test_full_size_clustered_2m_sampled(c2):
+    """128^3 clustered at full size: sampled particles against the oracle."""
+    w = c2
+    rng = np.random.default_rng(2024)
+    sample = rng.choice(len(w.mass), 1500, replace=False)
+    ref, _ = direct.brute_force(w.pos, w.mass, w.box, w.r_s, w.r_cut,
+                                targets=sample)
+    print("case: clustered 128^3 fp64 exact (sampled)", flush=True)
+    acc, ctx = gpu_forward(w.pos, w.mass, w.box, w.r_s, w.r_cut, 64)
+    assert metrics.error_summary(acc[sample], ref)["max"] <= 1e-12
+    out = torch.empty((len(w.mass), 3), dtype=torch.float64, device="cuda")
+    for trunc, level, n_tab in [(B.TRUNC_TABLE, 2, 512),
+                                (B.TRUNC_TABLE, 1, 2048),
+                                (B.TRUNC_EXACT, 0, 2048)]:
+        print(f"case: clustered 128^3 fp32 trunc {trunc} {n_tab} {level}",
+              flush=True)
+        ctx.set_eval(precision=B.PMFMM_FP32, trunc=trunc, table_size=n_tab,
+                     table_level=level)
+        ctx.forward(out, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        check_fp32(out.cpu().numpy()[sample], ref)

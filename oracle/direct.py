@@ -265,13 +265,23 @@ def _pair_grad(k_idx, l_idx):
     dwk = np.sum(d * wk, axis=-1)[..., None]
     gg = g[..., None]
     hh = h[..., None]
-    gx = mk * (gg * wl + hh * dwl * d) - ml * (gg * wk + hh * dwk * d)
+    ta = mk * (gg * wl + hh * dwl * d)
+    tb = ml * (gg * wk + hh * dwk * d)
     gm = -(g * dwl[..., 0])
-    return gx.sum(axis=1), gm.sum(axis=1)
+    # sums of term magnitudes: the scale a rounding error is measured against
+    sx = (np.linalg.norm(ta, axis=-1) + np.linalg.norm(tb, axis=-1)).sum(axis=1)
+    sm = np.abs(gm).sum(axis=1)
+    return (ta - tb).sum(axis=1), gm.sum(axis=1), sx, sm
 
 
-def gradient(pos, mass, w, box, r_s, r_cut, G=1.0, targets=None, workers=None):
-    """dL/dpos (N, 3) and dL/dmass (N) of L = sum_i w_i . a_i."""
+def gradient(pos, mass, w, box, r_s, r_cut, G=1.0, targets=None, workers=None,
+             with_scale=False):
+    """dL/dpos (N, 3) and dL/dmass (N) of L = sum_i w_i . a_i.
+
+    With ``with_scale`` also the per-particle sums of the magnitudes of the
+    summed pair terms (for dL/dpos and dL/dmass): a sum with heavy
+    cancellation is only resolved to rounding times this scale.
+    """
     pos = np.ascontiguousarray(pos, np.float64)
     mass = np.ascontiguousarray(mass, np.float64)
     w = np.ascontiguousarray(w, np.float64)
@@ -279,18 +289,26 @@ def gradient(pos, mass, w, box, r_s, r_cut, G=1.0, targets=None, workers=None):
     if math.floor(box / r_cut) < 3:
         _init_worker(dict(pos=pos, mass=mass, **extra))
         idx = np.arange(len(pos)) if targets is None else np.asarray(targets)
-        gx, gm = _pair_grad(idx, np.arange(len(pos)))
+        gx, gm, sx, sm = _pair_grad(idx, np.arange(len(pos)))
+        if with_scale:
+            return G * gx, G * gm, abs(G) * sx, abs(G) * sm
         return G * gx, G * gm
     res = _run_cells(pos, mass, box, r_cut, "_pair_grad", targets, workers,
                      extra)
     gx = np.zeros((len(pos), 3))
     gm = np.zeros(len(pos))
-    for ti, (a, b) in res:
+    sx = np.zeros(len(pos))
+    sm = np.zeros(len(pos))
+    for ti, (a, b, c, e) in res:
         gx[ti] = G * a
         gm[ti] = G * b
+        sx[ti] = abs(G) * c
+        sm[ti] = abs(G) * e
     if targets is not None:
         t = np.asarray(targets)
-        return gx[t], gm[t]
+        gx, gm, sx, sm = gx[t], gm[t], sx[t], sm[t]
+    if with_scale:
+        return gx, gm, sx, sm
     return gx, gm
 
 

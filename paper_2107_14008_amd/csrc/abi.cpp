@@ -154,7 +154,7 @@ struct pmfmm_ctx {
     DevBuf perm, leaf, leafc, js, items, queue, leaf_slot, partial, counter, boxes, table;
     DevBuf x64, x32, stage_pos, stage_mass, far;
     DevBuf cell, cell_aux, cellc, M, Lc, m2l_row, m2l_src, m2l_shift, level_cells;
-    DevBuf w64, gpart;
+    DevBuf w64, w32;
     std::vector<unsigned char> table_host;
     bool table_dirty = true;
     int last_mode = -1;
@@ -170,7 +170,7 @@ struct pmfmm_ctx {
         }
         for (DevBuf* b : {&perm, &leaf, &leafc, &js, &items, &queue, &leaf_slot, &partial, &counter,
                           &boxes, &table, &x64, &x32, &stage_pos, &stage_mass, &far, &cell, &cell_aux,
-                          &cellc, &M, &Lc, &m2l_row, &m2l_src, &m2l_shift, &level_cells, &w64, &gpart})
+                          &cellc, &M, &Lc, &m2l_row, &m2l_src, &m2l_shift, &level_cells, &w64, &w32})
             b->release();
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
@@ -640,8 +640,48 @@ int pmfmm_adjoint(pmfmm_ctx* ctx, const double* w, double* grad_pos, double* gra
     if (!ctx || !w || !grad_pos || !grad_mass) return fail(PMFMM_EINVAL, "null argument");
     if (!ctx->built) return fail(PMFMM_ESTATE, "adjoint before build");
     if (ctx->plan.far_field) return fail(PMFMM_EUNSUPPORTED, "adjoint covers the P2P-only force (far field off)");
-    return fail(PMFMM_EUNSUPPORTED, "adjoint not available in this build");
-    (void)stream;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const pmfmm::Plan& pl = ctx->plan;
+    const int64_t n = pl.n;
+    HIP_TRY(ctx->w64.ensure((size_t)n * 32));
+    HIP_TRY(ctx->w32.ensure((size_t)n * 16));
+    HIP_TRY(pmfmm::launch_gather_w(w, ctx->perm.as<int32_t>(), ctx->w64.as<double4>(), ctx->w32.as<float4>(),
+                                   (int32_t)n, s));
+    HIP_TRY(pmfmm::launch_zero_i32(ctx->counter.as<int32_t>(), 1, s));
+    const bool timing = ctx->p.timing != 0;
+    if (timing) {
+        int rc = ensure_events(ctx);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(ctx->ev[4], s));
+    }
+    pmfmm::AdjArgs a{};
+    a.x64 = ctx->x64.as<double4>();
+    a.x32 = ctx->x32.as<float4>();
+    a.w64 = ctx->w64.as<double4>();
+    a.w32 = ctx->w32.as<float4>();
+    a.leaf = ctx->leaf.as<int4>();
+    a.leafc = ctx->leafc.as<double4>();
+    a.p2p_js = ctx->js.as<int32_t>();
+    a.items = ctx->items.as<int4>();
+    a.queue = ctx->queue.as<int32_t>();
+    a.n_items = (int32_t)pl.items.size();
+    a.counter = ctx->counter.as<int32_t>();
+    a.partial = ctx->partial.as<double>();
+    a.boxes = ctx->boxes.as<pmfmm::BoxDev>();
+    const int mode = mode_of(ctx->p);
+    const int wg = ctx->p.wg_waves > 0 ? ctx->p.wg_waves : 4;
+    int grid = ctx->p.grid_wgs;
+    if (grid <= 0) grid = ctx->n_cu * pmfmm::adjoint_blocks_per_cu(mode, wg, 0);
+    HIP_TRY(pmfmm::launch_adjoint(mode, a, wg, grid, 0, s));
+    if (timing) {
+        HIP_TRY(hipEventRecord(ctx->ev[5], s));
+        ctx->timed_adj = true;
+    }
+    pmfmm::AdjReduceArgs r{ctx->leaf.as<int4>(), ctx->leaf_slot.as<int32_t>(), ctx->partial.as<double>(),
+                           ctx->perm.as<int32_t>(), ctx->boxes.as<pmfmm::BoxDev>(), grad_pos, grad_mass,
+                           (int32_t)pl.leaf_count.size()};
+    HIP_TRY(pmfmm::launch_adj_reduce(r, s));
+    return PMFMM_OK;
 }
 
 }  // extern "C"

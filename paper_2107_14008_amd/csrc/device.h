@@ -94,6 +94,7 @@ struct AdjArgs {
     const double4* x64;
     const float4* x32;
     const double4* w64;         // (w, 0) per particle, leaf order
+    const float4* w32;          // the same in float32
     const int4* leaf;
     const double4* leafc;
     const int32_t* p2p_js;
@@ -126,7 +127,7 @@ hipError_t launch_p2p(int mode, const P2PArgs& a, int wg_waves, int grid_wgs,
                       size_t lds_bytes, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_gather_w(const double* w, const int32_t* perm, double4* w64,
-                           int32_t n, hipStream_t s);
+                           float4* w32, int32_t n, hipStream_t s);
 hipError_t launch_adjoint(int mode, const AdjArgs& a, int wg_waves, int grid_wgs,
                           size_t lds_bytes, hipStream_t s);
 hipError_t launch_adj_reduce(const AdjReduceArgs& a, hipStream_t s);

@@ -103,9 +103,19 @@ _lib = None
 
 
 def library():
-    """Load libpmfmm.so once; raise if it has not been built."""
+    """Load libpmfmm.so once; raise if it has not been built.
+
+    torch is imported first when it is installed: torch carries its own HIP
+    runtime, and the library must bind to that same runtime (its dependency
+    is resolved by soname to the copy already in the process).  Two HIP
+    runtimes in one process do not share devices or memory.
+    """
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(
                 f"{LIB_PATH} is missing: build it with "

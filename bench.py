@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--table-size", type=int, default=512)
     ap.add_argument("--table-level", type=int, default=2)
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run one plain device copy of this many MiB "
+                         "(scale reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the multi-GPU decomposition is "
@@ -113,6 +116,14 @@ def main():
     mass = torch.tensor(w.mass, device=dev)
     out = torch.empty((n, 3), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
+
+    if args.calib_copy_mb > 0:
+        nel = args.calib_copy_mb * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize(dev)
+        del src, dst
 
     forms = {
         "fp32": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,

@@ -17,7 +17,10 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <future>
 #include <thread>
@@ -232,12 +235,25 @@ void keys_to_csr(std::vector<uint64_t>& keys, int64_t n_rows, int threads,
     }
 }
 
+struct PhaseClock {
+    bool on = std::getenv("PMFMM_PLAN_TIMING") != nullptr;
+    std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    void lap(const char* what) {
+        if (!on) return;
+        auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[pmfmm plan] %-10s %8.2f ms\n", what,
+                     std::chrono::duration<double, std::milli>(now - t).count());
+        t = now;
+    }
+};
+
 }  // namespace
 
 std::string make_plan(Plan& plan, const std::vector<BoxParams>& boxes,
                       const std::vector<int64_t>& counts, const double* pos,
                       const double* mass, int threads) {
     if (threads <= 0) threads = (int)std::max(1u, std::thread::hardware_concurrency());
+    PhaseClock clk;
     const int nbox = (int)boxes.size();
     plan = Plan();
     plan.boxes = boxes;
@@ -267,6 +283,7 @@ std::string make_plan(Plan& plan, const std::vector<BoxParams>& boxes,
         }
     }
 
+    clk.lap("wrap");
     // ---- tree shapes and global numbering
     std::vector<Shape> shapes(nbox);
     plan.box_first_leaf.assign(nbox + 1, 0);
@@ -324,6 +341,7 @@ std::string make_plan(Plan& plan, const std::vector<BoxParams>& boxes,
             for (auto& t : th) t.join();
         }
     }
+    clk.lap("orb");
     plan.leaf_first.resize(n_leaves);
     plan.leaf_count.resize(n_leaves);
     plan.leaf_box.resize(n_leaves);
@@ -407,10 +425,12 @@ std::string make_plan(Plan& plan, const std::vector<BoxParams>& boxes,
             std::vector<uint64_t>().swap(tm[t]);
         }
     }
+    clk.lap("walk");
     plan.far_field = !m2l_keys.empty();
     keys_to_csr(p2p_keys, n_leaves, threads, plan.p2p_row, plan.p2p_j, plan.p2p_shift);
     keys_to_csr(m2l_keys, n_cells, threads, plan.m2l_row, plan.m2l_src, plan.m2l_shift);
 
+    clk.lap("csr");
     int64_t cand = 0;
     for (int64_t i = 0; i < n_leaves; ++i)
         for (int32_t t = plan.p2p_row[i]; t < plan.p2p_row[i + 1]; ++t)
@@ -441,6 +461,7 @@ std::string make_plan(Plan& plan, const std::vector<BoxParams>& boxes,
         std::vector<int32_t> fill(plan.depth_begin.begin(), plan.depth_begin.end() - 1);
         for (int64_t k = 0; k < n_cells; ++k) plan.cells_by_depth[fill[plan.cells[k].depth]++] = (int32_t)k;
     }
+    clk.lap("views");
     return std::string();
 }
 

@@ -46,6 +46,26 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 
 
+def measured_traffic(kernel_tag="p2p_fp32_t2_clustered_2m"):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the P2P source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        line = line.split("#")[0].strip()
+        if "=" in line:
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2107_14008_amd", "csrc", "p2p.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if kv.get("p2p_source_sha256_16") != sha:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
 def cpu_baseline(w, cand_per_particle, target_seconds=12.0):
     """Oracle brute force on a bounded random sample of target particles."""
     from oracle import direct
@@ -202,7 +222,8 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "B per launch",
             "kernel": "p2p_kernel<FP32 table, level 2>",
             "flops_per_pair": FLOPS_PER_PAIR_F32_T2,
             "kernel_ms": r32["p2p_ms"],

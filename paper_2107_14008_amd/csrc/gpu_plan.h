@@ -1,0 +1,110 @@
+// Device buffers of a context and the on-GPU planner (ORB tree, dual walk,
+// TaskGroup CSR and work items built from particles already in HBM).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+
+#include "device.h"
+#include "plan.h"
+
+namespace pmfmm {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t want) {
+        if (want <= bytes && p != nullptr) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (want == 0) want = 16;
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) bytes = want;
+        return e;
+    }
+    // Grow keeping the first `keep` bytes.
+    hipError_t grow(size_t want, size_t keep, hipStream_t s) {
+        if (want <= bytes && p != nullptr) return hipSuccess;
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, want);
+        if (e != hipSuccess) return e;
+        if (p && keep) {
+            e = hipMemcpyAsync(q, p, keep, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) { (void)hipFree(q); return e; }
+            e = hipStreamSynchronize(s);
+            if (e != hipSuccess) { (void)hipFree(q); return e; }
+        }
+        if (p) (void)hipFree(p);
+        p = q;
+        bytes = want;
+        return hipSuccess;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+// Everything the kernels of one context read or write.
+struct DevPlan {
+    // used by the forward / adjoint passes
+    DevBuf perm, leaf, leafc, js, items, queue, leaf_slot, partial, counter, boxes, table;
+    DevBuf x64, x32, stage_pos, stage_mass, far;
+    DevBuf cell, cell_aux, cellc, M, Lc, m2l_row, m2l_src, m2l_shift, level_cells;
+    DevBuf w64, w32;
+    // on-GPU planner scratch
+    DevBuf p2p_row, wpos, keys, keys_tmp, plist, plist_tmp, hist, flag, fsc, fsc_out, tile_sums;
+    DevBuf pc, pc_tmp, clo, chi, chs, box_first, walkbox, front, front_next, p2p_keys,
+        p2p_keys_tmp, m2l_keys, m2l_keys_tmp, wcount, cost, cost_keys, cost_keys_tmp, queue_tmp,
+        item_count, cell_axis;
+
+    void release_all() {
+        for (DevBuf* b : {&perm, &leaf, &leafc, &js, &items, &queue, &leaf_slot, &partial, &counter,
+                          &boxes, &table, &x64, &x32, &stage_pos, &stage_mass, &far, &cell,
+                          &cell_aux, &cellc, &M, &Lc, &m2l_row, &m2l_src, &m2l_shift, &level_cells,
+                          &w64, &w32, &p2p_row, &wpos, &keys, &keys_tmp, &plist, &plist_tmp, &hist,
+                          &flag, &fsc, &fsc_out, &tile_sums, &pc, &pc_tmp, &clo, &chi, &chs,
+                          &box_first, &walkbox, &front, &front_next, &p2p_keys, &p2p_keys_tmp,
+                          &m2l_keys, &m2l_keys_tmp, &wcount, &cost, &cost_keys, &cost_keys_tmp,
+                          &queue_tmp, &item_count, &cell_axis})
+            b->release();
+    }
+};
+
+// Counts the host needs after a device plan.
+struct PlanCounts {
+    int64_t n_p2p = 0, n_m2l = 0, n_items = 0, candidate_pairs = 0;
+};
+
+// Sort / scan primitives (gpu_sort.hip).
+int64_t sort_tiles(int64_t n);
+hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals,
+                          uint32_t* hist, int64_t n, int bit_begin, int bit_end, hipStream_t s,
+                          bool* result_in_tmp);
+hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, uint32_t* tile_sums,
+                              hipStream_t s);
+
+// Uploads the tree shape of `topo` (cells, leaves, depth levels) and the
+// per-box constants.
+hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, hipStream_t s);
+
+// Builds the plan on the device from caller-order particles `pos` (n, 3) and
+// `mass` (n) in device memory, for the shape uploaded by upload_topology.
+// Fills perm, cell bounds and centres, x64 / x32, the P2P and M2L CSR, the
+// work items and queue.  Synchronises `s` (the list sizes come back to the
+// host).  Returns an error message ("" on success).
+std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, const double* mass,
+                           int chunk, hipStream_t s, PlanCounts& out);
+
+// Re-cuts the work items for a new chunk size from the device CSR.
+std::string gpu_make_items(DevPlan& d, const Plan& topo, int64_t n_p2p, int chunk, hipStream_t s,
+                           PlanCounts& out);
+
+}  // namespace pmfmm

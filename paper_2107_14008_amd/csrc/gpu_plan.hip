@@ -1,0 +1,665 @@
+// On-GPU planner: the ORB tree (Sec. 2), the dual walk into P2P and M2L
+// task lists (Sec. 3) and the TaskGroup / GroupIdx CSR with its work items
+// (Sec. 3.2), built from particles already in HBM.  Same readings as the
+// host planner (plan.cpp), and the same results bit for bit: every geometry
+// decision is the same rounded float64 operation in the same order.
+//
+// ORB without per-cell sorting: the particles are sorted once per axis by
+// (coordinate, caller index) with a stable radix sort; the shape of the tree
+// (which cell holds which range of positions) depends on the particle count
+// alone and comes from the host.  Level by level, each splitting cell reads
+// its bounds from the ends of its three sorted ranges, marks the floor(n/2)
+// first particles of its split axis as "left", and every axis list is
+// partitioned stably (prefix sums of the left marks), which keeps each child
+// range sorted on every axis.
+//
+// Dual walk: level-synchronous over a frontier of cell pairs; one thread per
+// pair classifies it and appends P2P keys, M2L keys or child pairs with one
+// atomic per wavefront.  The keys (i << 32 | j << 5 | shift) are then sorted,
+// which yields the canonical (i, j, shift) order and the CSR rows.
+#include <algorithm>
+#include <vector>
+
+#include "gpu_plan.h"
+
+namespace pmfmm {
+namespace {
+
+constexpr double kGuard = 0x1p-40;
+
+struct WalkBox {
+    double L, rc2_drop, rc2_m2l, th2;
+    int32_t use_m2l, pad0;
+    double pad1;
+};
+
+__device__ __forceinline__ double wrap_coord(double x, double L) {
+#pragma clang fp contract(off)
+    if (x >= 0.0 && x < L) return x;
+    double y = x - L * floor(x / L);
+    if (y >= L) y -= L;
+    if (y < 0.0) y += L;
+    if (!(y >= 0.0 && y < L)) y = 0.0;
+    return y;
+}
+
+__device__ __forceinline__ int box_of(const int32_t* __restrict__ bf, int nbox, int i) {
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bf[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Order-preserving key of a non-negative double (+0 and -0 equal).
+__device__ __forceinline__ uint64_t coord_key(double x) {
+    return x == 0.0 ? 0ull : (uint64_t)__double_as_longlong(x);
+}
+
+__global__ void k_wrap_keys(const double* __restrict__ pos, int64_t n, const int32_t* __restrict__ bf,
+                            int nbox, const BoxDev* __restrict__ boxes, double* __restrict__ wpos,
+                            uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double L = boxes[box_of(bf, nbox, (int)i)].L;
+    for (int a = 0; a < 3; ++a) {
+        const double x = wrap_coord(pos[3 * i + a], L);
+        wpos[3 * i + a] = x;
+        keys[a * n + i] = coord_key(x);
+        vals[a * n + i] = (uint32_t)i;
+    }
+}
+
+__global__ void k_box_keys(const uint32_t* __restrict__ vals, int64_t n, const int32_t* __restrict__ bf,
+                           int nbox, uint64_t* __restrict__ keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = (uint64_t)box_of(bf, nbox, (int)vals[i]);
+}
+
+__global__ void k_init_pc(int64_t n, const int32_t* __restrict__ bf, const int32_t* __restrict__ bfc,
+                          int nbox, int32_t* __restrict__ pc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    pc[i] = bfc[box_of(bf, nbox, (int)i)];
+}
+
+// Bounds of every cell of one depth from the ends of its sorted ranges.
+__global__ void k_cells_level(const int32_t* __restrict__ level, int nd, const int4* __restrict__ cell,
+                              const int4* __restrict__ aux, const uint32_t* __restrict__ plist,
+                              int64_t n, const double* __restrict__ wpos, double* __restrict__ clo,
+                              double* __restrict__ chi, int32_t* __restrict__ axis_out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nd) return;
+    const int c = level[k];
+    const int4 ci = cell[c];
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = wpos[3 * (size_t)plist[a * n + ci.x] + a];
+        hi[a] = wpos[3 * (size_t)plist[a * n + ci.x + ci.y - 1] + a];
+        clo[3 * (size_t)c + a] = lo[a];
+        chi[3 * (size_t)c + a] = hi[a];
+    }
+    if (aux[c].x >= 0) {
+#pragma clang fp contract(off)
+        const double e0 = hi[0] - lo[0], e1 = hi[1] - lo[1], e2 = hi[2] - lo[2];
+        int axis = 0;
+        double best = e0;
+        if (e1 > best) { axis = 1; best = e1; }
+        if (e2 > best) axis = 2;
+        axis_out[c] = axis;
+    }
+}
+
+__global__ void k_flag(int64_t n, const int32_t* __restrict__ pc, const int4* __restrict__ cell,
+                       const int4* __restrict__ aux, const int32_t* __restrict__ axis,
+                       const uint32_t* __restrict__ plist, int32_t* __restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = pc[i];
+    if (aux[c].x < 0) return;
+    const int4 ci = cell[c];
+    const int ax = axis[c];
+    flag[plist[ax * n + i]] = (i - ci.x < ci.y / 2) ? 1 : 0;
+}
+
+__global__ void k_marks(int64_t n, const int32_t* __restrict__ pc, const int4* __restrict__ aux,
+                        const uint32_t* __restrict__ plist, const int32_t* __restrict__ flag,
+                        int32_t* __restrict__ f) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool split = aux[pc[i]].x >= 0;
+    for (int a = 0; a < 3; ++a) f[a * n + i] = split ? flag[plist[a * n + i]] : 0;
+}
+
+__global__ void k_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __restrict__ pc_out,
+                       const int4* __restrict__ cell, const int4* __restrict__ aux,
+                       const uint32_t* __restrict__ plist, uint32_t* __restrict__ pout,
+                       const int32_t* __restrict__ flag, const int32_t* __restrict__ scan) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = pc[i];
+    const int4 ax = aux[c];
+    if (ax.x < 0) {
+        for (int a = 0; a < 3; ++a) pout[a * n + i] = plist[a * n + i];
+        pc_out[i] = c;
+        return;
+    }
+    const int4 ci = cell[c];
+    const int64_t first = ci.x, nl = ci.y / 2;
+    for (int a = 0; a < 3; ++a) {
+        const uint32_t p = plist[a * n + i];
+        const int64_t lr = scan[a * n + i] - scan[a * n + first];
+        const int64_t pos = flag[p] ? first + lr : first + nl + (i - first - lr);
+        pout[a * n + pos] = p;
+    }
+    pc_out[i] = (i - first < nl) ? ax.x : ax.y;
+}
+
+// One wavefront per leaf: its particles in ascending caller index.
+__global__ void __launch_bounds__(256)
+k_leaf_perm(int nl, const int4* __restrict__ leaf, const uint32_t* __restrict__ plist,
+            int32_t* __restrict__ perm) {
+    const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (l >= nl) return;
+    const int4 li = leaf[l];
+    if (lane >= li.y) return;
+    const uint32_t id = plist[li.x + lane];
+    int rank = 0;
+    for (int k = 0; k < li.y; ++k) rank += plist[li.x + k] < id ? 1 : 0;
+    perm[li.x + rank] = (int32_t)id;
+}
+
+// Centre, half size and radius of every cell (the host planner's formulas).
+__global__ void k_geom(int nc, const double* __restrict__ clo, const double* __restrict__ chi,
+                       const int4* __restrict__ cell, double4* __restrict__ cellc,
+                       double4* __restrict__ chs, double4* __restrict__ leafc) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    double cc[3], h[3];
+    double rad;
+    {
+#pragma clang fp contract(off)
+        for (int a = 0; a < 3; ++a) {
+            const double lo = clo[3 * (size_t)c + a], hi = chi[3 * (size_t)c + a];
+            cc[a] = 0.5 * (lo + hi);
+            h[a] = 0.5 * (hi - lo);
+        }
+        rad = sqrt((h[0] * h[0] + h[1] * h[1]) + h[2] * h[2]);
+    }
+    cellc[c] = make_double4(cc[0], cc[1], cc[2], rad);
+    chs[c] = make_double4(h[0], h[1], h[2], 0.0);
+    const int lf = cell[c].w;
+    if (lf >= 0) leafc[lf] = make_double4(cc[0], cc[1], cc[2], 0.0);
+}
+
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t* total) {
+    const int lane = threadIdx.x & 63;
+    uint32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    *total = __shfl(x, 63);
+    return x - v;
+}
+
+// Appends `cnt` items per lane at one atomic per wavefront; returns the
+// lane's first slot.
+__device__ __forceinline__ uint32_t wave_append(uint32_t cnt, uint32_t* counter) {
+    uint32_t total;
+    const uint32_t off = wave_excl_scan(cnt, &total);
+    uint32_t base = 0;
+    if (total != 0) {
+        if ((threadIdx.x & 63) == 0) base = atomicAdd(counter, total);
+        base = __shfl(base, 0);
+    }
+    return base + off;
+}
+
+__global__ void __launch_bounds__(256)
+k_walk(const int2* __restrict__ front, int nf, int2* __restrict__ next,
+       const WalkBox* __restrict__ wbox, const double4* __restrict__ cellc,
+       const double4* __restrict__ chs, const int4* __restrict__ cell, const int4* __restrict__ aux,
+       uint32_t* __restrict__ counters, uint64_t* __restrict__ p2p_keys,
+       uint64_t* __restrict__ m2l_keys) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t n_child = 0, n_p2p = 0, n_m2l = 0;
+    int2 child[4];
+    uint64_t key = 0;
+    if (k < nf) {
+        const int2 pr = front[k];
+        const int t = pr.x, u = pr.y >> 5, s = pr.y & 31;
+        const int4 at = aux[t], au = aux[u];
+        const WalkBox wb = wbox[at.z];
+        const double4 ct = cellc[t], cu = cellc[u], ht = chs[t], hu = chs[u];
+        const double sL[3] = {(double)(s % 3 - 1) * wb.L, (double)((s / 3) % 3 - 1) * wb.L,
+                              (double)(s / 9 - 1) * wb.L};
+        const double cta[3] = {ct.x, ct.y, ct.z}, cua[3] = {cu.x, cu.y, cu.z};
+        const double hta[3] = {ht.x, ht.y, ht.z}, hua[3] = {hu.x, hu.y, hu.z};
+        double R[3], A[3], H[3], gp[3], gap2, dmax2 = 0.0, R2 = 0.0, lhs = 0.0;
+        {
+#pragma clang fp contract(off)
+            for (int a = 0; a < 3; ++a) {
+                R[a] = (cua[a] - cta[a]) + sL[a];
+                A[a] = fabs(R[a]);
+                H[a] = hta[a] + hua[a];
+                const double g = A[a] - H[a];
+                gp[a] = g > 0.0 ? g : 0.0;
+            }
+            gap2 = (gp[0] * gp[0] + gp[1] * gp[1]) + gp[2] * gp[2];
+            if (wb.use_m2l) {
+                const double d0 = A[0] + H[0], d1 = A[1] + H[1], d2 = A[2] + H[2];
+                dmax2 = (d0 * d0 + d1 * d1) + d2 * d2;
+                R2 = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2];
+                lhs = ct.w + cu.w;
+                lhs = lhs * lhs;
+                R2 = wb.th2 * R2;
+            }
+        }
+        if (gap2 < wb.rc2_drop) {
+            if (wb.use_m2l && dmax2 < wb.rc2_m2l && lhs < R2) {
+                n_m2l = 1;
+                key = ((uint64_t)(uint32_t)t << 32) | ((uint64_t)(uint32_t)u << 5) | (uint64_t)s;
+            } else {
+                const int lt = cell[t].w, lu = cell[u].w;
+                const double rt = ct.w, ru = cu.w;
+                if (lt >= 0 && lu >= 0) {
+                    n_p2p = 1;
+                    key = ((uint64_t)(uint32_t)lt << 32) | ((uint64_t)(uint32_t)lu << 5) | (uint64_t)s;
+                } else if (lt < 0 && (lu >= 0 || rt > ru)) {
+                    child[0] = make_int2(at.x, pr.y);
+                    child[1] = make_int2(at.y, pr.y);
+                    n_child = 2;
+                } else if (lu < 0 && (lt >= 0 || ru > rt)) {
+                    child[0] = make_int2(t, (au.x << 5) | s);
+                    child[1] = make_int2(t, (au.y << 5) | s);
+                    n_child = 2;
+                } else {
+                    child[0] = make_int2(at.x, (au.x << 5) | s);
+                    child[1] = make_int2(at.x, (au.y << 5) | s);
+                    child[2] = make_int2(at.y, (au.x << 5) | s);
+                    child[3] = make_int2(at.y, (au.y << 5) | s);
+                    n_child = 4;
+                }
+            }
+        }
+    }
+    const uint32_t cslot = wave_append(n_child, &counters[0]);
+    for (uint32_t q = 0; q < n_child; ++q) next[cslot + q] = child[q];
+    const uint32_t pslot = wave_append(n_p2p, &counters[1]);
+    if (n_p2p) p2p_keys[pslot] = key;
+    const uint32_t mslot = wave_append(n_m2l, &counters[2]);
+    if (n_m2l) m2l_keys[mslot] = key;
+}
+
+__global__ void k_zero_u32(uint32_t* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+__global__ void k_csr_rows(const uint64_t* __restrict__ keys, int64_t nk, int nrows,
+                           int32_t* __restrict__ row) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > nrows) return;
+    const uint64_t target = (uint64_t)(uint32_t)r << 32;
+    int64_t lo = 0, hi = nk;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < target) lo = mid + 1; else hi = mid;
+    }
+    row[r] = (int32_t)lo;
+}
+
+__global__ void k_split_p2p(const uint64_t* __restrict__ keys, int64_t nk, int32_t* __restrict__ js) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nk) js[k] = (int32_t)(keys[k] & 0xffffffffull);
+}
+
+__global__ void k_split_m2l(const uint64_t* __restrict__ keys, int64_t nk, int32_t* __restrict__ src,
+                            int32_t* __restrict__ shift) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nk) return;
+    const uint32_t low = (uint32_t)(keys[k] & 0xffffffffull);
+    src[k] = (int32_t)(low >> 5);
+    shift[k] = (int32_t)(low & 31u);
+}
+
+__global__ void k_item_count(int nl, const int32_t* __restrict__ row, int chunk,
+                             int32_t* __restrict__ cnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > nl) return;
+    if (i == nl) { cnt[i] = 0; return; }
+    const int len = row[i + 1] - row[i];
+    cnt[i] = (len + chunk - 1) / chunk;
+}
+
+__global__ void k_items(int nl, const int32_t* __restrict__ row, const int32_t* __restrict__ js,
+                        const int4* __restrict__ leaf, int chunk, const int32_t* __restrict__ slot0,
+                        int4* __restrict__ items, uint64_t* __restrict__ cost_keys,
+                        uint32_t* __restrict__ slots, unsigned long long* __restrict__ cand) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nl) return;
+    const int r0 = row[i], len = row[i + 1] - r0;
+    if (len == 0) return;
+    const int parts = (len + chunk - 1) / chunk;
+    const int base = len / parts, extra = len % parts;
+    const int ni = leaf[i].y;
+    int t = r0;
+    unsigned long long total = 0;
+    for (int k = 0; k < parts; ++k) {
+        const int sz = base + (k < extra ? 1 : 0);
+        unsigned long long c = 0;
+        for (int q = t; q < t + sz; ++q) c += (unsigned long long)leaf[js[q] >> 5].y;
+        c *= (unsigned long long)ni;
+        total += c;
+        const int s = slot0[i] + k;
+        items[s] = make_int4(i, t, t + sz, s);
+        const uint32_t c32 = c > 0xffffffffull ? 0xffffffffu : (uint32_t)c;
+        cost_keys[s] = (uint64_t)(0xffffffffu - c32);
+        slots[s] = (uint32_t)s;
+        t += sz;
+    }
+    atomicAdd(cand, total);
+}
+
+inline unsigned grid_of(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+int bits_for(uint64_t maxv) {
+    int b = 0;
+    while (b < 64 && (maxv >> b) != 0) ++b;
+    return b;
+}
+
+#define TRY(expr)                                                                   \
+    do {                                                                            \
+        hipError_t e_ = (expr);                                                     \
+        if (e_ != hipSuccess) return std::string(#expr) + ": " + hipGetErrorString(e_); \
+    } while (0)
+
+template <class T>
+hipError_t up(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
+    hipError_t e = b.ensure(std::max<size_t>(16, v.size() * sizeof(T)));
+    if (e != hipSuccess || v.empty()) return e;
+    return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+// Sorts keys (and values) in place; swaps in the scratch buffers when the
+// number of passes leaves the result there.
+std::string sort_in_place(DevBuf& keys, DevBuf* vals, DevBuf& ktmp, DevBuf* vtmp, DevBuf& hist,
+                          int64_t n, int bit_end, hipStream_t s) {
+    if (n <= 1) return std::string();
+    bit_end = std::min(64, (bit_end + 7) / 8 * 8);
+    TRY(ktmp.ensure(n * 8));
+    if (vals) TRY(vtmp->ensure(n * 4));
+    TRY(hist.ensure((size_t)256 * sort_tiles(n) * 4));
+    bool in_tmp = false;
+    TRY(radix_sort_u64(keys.as<uint64_t>(), vals ? vals->as<uint32_t>() : nullptr, ktmp.as<uint64_t>(),
+                       vtmp ? vtmp->as<uint32_t>() : nullptr, hist.as<uint32_t>(), n, 0, bit_end, s,
+                       &in_tmp));
+    if (in_tmp) {
+        std::swap(keys, ktmp);
+        if (vals) std::swap(*vals, *vtmp);
+    }
+    return std::string();
+}
+
+}  // namespace
+
+hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, hipStream_t s) {
+    const int64_t nc = (int64_t)topo.cells.size(), nl = (int64_t)topo.leaf_cell.size();
+    std::vector<int32_t> cell(4 * nc), aux(4 * nc), leaf(4 * nl);
+    for (int64_t k = 0; k < nc; ++k) {
+        const Cell& c = topo.cells[k];
+        cell[4 * k] = c.first;
+        cell[4 * k + 1] = c.count;
+        cell[4 * k + 2] = c.parent;
+        cell[4 * k + 3] = c.leaf;
+        aux[4 * k] = c.child[0];
+        aux[4 * k + 1] = c.child[1];
+        aux[4 * k + 2] = c.box;
+        aux[4 * k + 3] = c.depth;
+    }
+    for (int64_t l = 0; l < nl; ++l) {
+        const Cell& c = topo.cells[topo.leaf_cell[l]];
+        leaf[4 * l] = c.first;
+        leaf[4 * l + 1] = c.count;
+        leaf[4 * l + 2] = c.box;
+        leaf[4 * l + 3] = topo.leaf_cell[l];
+    }
+    const int nbox = (int)topo.boxes.size();
+    std::vector<WalkBox> wb(nbox);
+    std::vector<BoxDev> bd(boxdev, boxdev + nbox);
+    for (int b = 0; b < nbox; ++b) {
+        const BoxParams& p = topo.boxes[b];
+        const double rc2 = p.r_cut * p.r_cut;
+        wb[b].L = p.box;
+        wb[b].rc2_drop = rc2 * (1.0 + kGuard);
+        wb[b].rc2_m2l = rc2 * (1.0 - kGuard);
+        wb[b].th2 = p.theta * p.theta;
+        wb[b].use_m2l = (p.order >= 0 && p.theta > 0.0) ? 1 : 0;
+        wb[b].pad0 = 0;
+        wb[b].pad1 = 0.0;
+    }
+    std::vector<int32_t> bfc(topo.box_first_cell.begin(), topo.box_first_cell.end());
+    hipError_t e;
+    if ((e = up(d.cell, cell, s)) != hipSuccess) return e;
+    if ((e = up(d.cell_aux, aux, s)) != hipSuccess) return e;
+    if ((e = up(d.leaf, leaf, s)) != hipSuccess) return e;
+    if ((e = up(d.level_cells, topo.cells_by_depth, s)) != hipSuccess) return e;
+    if ((e = up(d.box_first, topo.box_first_particle, s)) != hipSuccess) return e;
+    if ((e = up(d.walkbox, wb, s)) != hipSuccess) return e;
+    if ((e = up(d.boxes, bd, s)) != hipSuccess) return e;
+    if ((e = up(d.item_count, bfc, s)) != hipSuccess) return e;   // box -> root cell (scratch reuse)
+    return hipStreamSynchronize(s);
+}
+
+std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, const double* mass,
+                           int chunk, hipStream_t s, PlanCounts& out) {
+    const int64_t n = topo.n;
+    const int nbox = (int)topo.boxes.size();
+    const int64_t nc = (int64_t)topo.cells.size(), nl = (int64_t)topo.leaf_cell.size();
+    const int nd = (int)topo.depth_begin.size() - 1;
+
+    // ---- wrap, sort each axis by (coordinate, caller index)
+    TRY(d.wpos.ensure(n * 24));
+    TRY(d.keys.ensure(n * 24));
+    TRY(d.plist.ensure(n * 12));
+    TRY(d.plist_tmp.ensure(n * 12));
+    TRY(d.keys_tmp.ensure(n * 8));
+    hipLaunchKernelGGL(k_wrap_keys, dim3(grid_of(n)), dim3(256), 0, s, pos, n,
+                       d.box_first.as<int32_t>(), nbox, d.boxes.as<BoxDev>(), d.wpos.as<double>(),
+                       d.keys.as<uint64_t>(), d.plist.as<uint32_t>());
+    TRY(hipGetLastError());
+    TRY(d.hist.ensure((size_t)256 * sort_tiles(n) * 4 + 16));
+    for (int a = 0; a < 3; ++a) {
+        uint64_t* k = d.keys.as<uint64_t>() + a * n;
+        uint32_t* v = d.plist.as<uint32_t>() + a * n;
+        uint64_t* kt = d.keys_tmp.as<uint64_t>();
+        uint32_t* vt = d.plist_tmp.as<uint32_t>();
+        bool in_tmp = false;
+        if (n > 1) {
+            TRY(radix_sort_u64(k, v, kt, vt, d.hist.as<uint32_t>(), n, 0, 64, s, &in_tmp));
+            if (in_tmp) {
+                TRY(hipMemcpyAsync(k, kt, n * 8, hipMemcpyDeviceToDevice, s));
+                TRY(hipMemcpyAsync(v, vt, n * 4, hipMemcpyDeviceToDevice, s));
+            }
+            if (nbox > 1) {
+                hipLaunchKernelGGL(k_box_keys, dim3(grid_of(n)), dim3(256), 0, s, v, n,
+                                   d.box_first.as<int32_t>(), nbox, k);
+                TRY(hipGetLastError());
+                TRY(radix_sort_u64(k, v, kt, vt, d.hist.as<uint32_t>(), n, 0, bits_for(nbox - 1) + 1,
+                                   s, &in_tmp));
+                if (in_tmp) TRY(hipMemcpyAsync(v, vt, n * 4, hipMemcpyDeviceToDevice, s));
+            }
+        }
+    }
+
+    // ---- ORB levels
+    TRY(d.pc.ensure(n * 4));
+    TRY(d.pc_tmp.ensure(n * 4));
+    TRY(d.flag.ensure(n * 4));
+    TRY(d.fsc.ensure(n * 12));
+    TRY(d.fsc_out.ensure(n * 12));
+    TRY(d.tile_sums.ensure(sort_tiles(n) * 4 + 16));
+    TRY(d.clo.ensure(nc * 24));
+    TRY(d.chi.ensure(nc * 24));
+    TRY(d.cell_axis.ensure(nc * 4));
+    hipLaunchKernelGGL(k_init_pc, dim3(grid_of(n)), dim3(256), 0, s, n, d.box_first.as<int32_t>(),
+                       d.item_count.as<int32_t>(), nbox, d.pc.as<int32_t>());
+    TRY(hipGetLastError());
+    for (int dep = 0; dep < nd; ++dep) {
+        const int c0 = topo.depth_begin[dep], ncd = topo.depth_begin[dep + 1] - c0;
+        hipLaunchKernelGGL(k_cells_level, dim3(grid_of(ncd)), dim3(256), 0, s,
+                           d.level_cells.as<int32_t>() + c0, ncd, d.cell.as<int4>(),
+                           d.cell_aux.as<int4>(), d.plist.as<uint32_t>(), n, d.wpos.as<double>(),
+                           d.clo.as<double>(), d.chi.as<double>(), d.cell_axis.as<int32_t>());
+        TRY(hipGetLastError());
+        if (dep == nd - 1) break;      // the deepest level holds leaves only
+        hipLaunchKernelGGL(k_flag, dim3(grid_of(n)), dim3(256), 0, s, n, d.pc.as<int32_t>(),
+                           d.cell.as<int4>(), d.cell_aux.as<int4>(), d.cell_axis.as<int32_t>(),
+                           d.plist.as<uint32_t>(), d.flag.as<int32_t>());
+        hipLaunchKernelGGL(k_marks, dim3(grid_of(n)), dim3(256), 0, s, n, d.pc.as<int32_t>(),
+                           d.cell_aux.as<int4>(), d.plist.as<uint32_t>(), d.flag.as<int32_t>(),
+                           d.fsc.as<int32_t>());
+        TRY(hipGetLastError());
+        for (int a = 0; a < 3; ++a)
+            TRY(exclusive_scan_i32(d.fsc.as<int32_t>() + a * n, d.fsc_out.as<int32_t>() + a * n, n,
+                                   d.tile_sums.as<uint32_t>(), s));
+        hipLaunchKernelGGL(k_move, dim3(grid_of(n)), dim3(256), 0, s, n, d.pc.as<int32_t>(),
+                           d.pc_tmp.as<int32_t>(), d.cell.as<int4>(), d.cell_aux.as<int4>(),
+                           d.plist.as<uint32_t>(), d.plist_tmp.as<uint32_t>(), d.flag.as<int32_t>(),
+                           d.fsc_out.as<int32_t>());
+        TRY(hipGetLastError());
+        std::swap(d.plist, d.plist_tmp);
+        std::swap(d.pc, d.pc_tmp);
+    }
+
+    // ---- leaf order, geometry, particle records
+    TRY(d.perm.ensure(n * 4));
+    TRY(d.leafc.ensure(nl * 32));
+    TRY(d.cellc.ensure(nc * 32));
+    TRY(d.chs.ensure(nc * 32));
+    hipLaunchKernelGGL(k_leaf_perm, dim3(grid_of(nl, 4)), dim3(256), 0, s, (int)nl, d.leaf.as<int4>(),
+                       d.plist.as<uint32_t>(), d.perm.as<int32_t>());
+    hipLaunchKernelGGL(k_geom, dim3(grid_of(nc)), dim3(256), 0, s, (int)nc, d.clo.as<double>(),
+                       d.chi.as<double>(), d.cell.as<int4>(), d.cellc.as<double4>(),
+                       d.chs.as<double4>(), d.leafc.as<double4>());
+    TRY(hipGetLastError());
+    TRY(d.x64.ensure(n * 32));
+    TRY(d.x32.ensure(n * 16));
+    GatherArgs g{pos, mass, d.perm.as<int32_t>(), d.leaf.as<int4>(), d.leafc.as<double4>(),
+                 d.boxes.as<BoxDev>(), d.x64.as<double4>(), d.x32.as<float4>(), (int32_t)nl};
+    TRY(launch_gather(g, nullptr, s));
+
+    // ---- dual walk
+    TRY(d.wcount.ensure(64));
+    int64_t nf = 27 * (int64_t)nbox;
+    {
+        std::vector<int32_t> f0(2 * nf);
+        for (int b = 0; b < nbox; ++b)
+            for (int q = 0; q < 27; ++q) {
+                const int root = topo.box_first_cell[b];
+                f0[2 * (27 * b + q)] = root;
+                f0[2 * (27 * b + q) + 1] = (root << 5) | q;
+            }
+        TRY(d.front.ensure(std::max<size_t>(f0.size() * 4, 4096)));
+        TRY(hipMemcpyAsync(d.front.p, f0.data(), f0.size() * 4, hipMemcpyHostToDevice, s));
+    }
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, d.wcount.as<uint32_t>(), 4);
+    int64_t n_p2p = 0, n_m2l = 0;
+    if (d.p2p_keys.bytes < 16) TRY(d.p2p_keys.ensure(1 << 20));
+    if (d.m2l_keys.bytes < 16) TRY(d.m2l_keys.ensure(1 << 16));
+    uint32_t hc[4] = {0, 0, 0, 0};
+    while (nf > 0) {
+        TRY(d.front_next.grow((size_t)4 * nf * 8, 0, s));
+        if ((size_t)(n_p2p + nf) * 8 > d.p2p_keys.bytes)
+            TRY(d.p2p_keys.grow((size_t)(n_p2p + nf) * 8 * 2, (size_t)n_p2p * 8, s));
+        if ((size_t)(n_m2l + nf) * 8 > d.m2l_keys.bytes)
+            TRY(d.m2l_keys.grow((size_t)(n_m2l + nf) * 8 * 2, (size_t)n_m2l * 8, s));
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, d.wcount.as<uint32_t>(), 1);
+        hipLaunchKernelGGL(k_walk, dim3(grid_of(nf)), dim3(256), 0, s, d.front.as<int2>(), (int)nf,
+                           d.front_next.as<int2>(), d.walkbox.as<WalkBox>(), d.cellc.as<double4>(),
+                           d.chs.as<double4>(), d.cell.as<int4>(), d.cell_aux.as<int4>(),
+                           d.wcount.as<uint32_t>(), d.p2p_keys.as<uint64_t>(),
+                           d.m2l_keys.as<uint64_t>());
+        TRY(hipGetLastError());
+        TRY(hipMemcpyAsync(hc, d.wcount.p, 16, hipMemcpyDeviceToHost, s));
+        TRY(hipStreamSynchronize(s));
+        nf = hc[0];
+        n_p2p = hc[1];
+        n_m2l = hc[2];
+        std::swap(d.front, d.front_next);
+    }
+
+    // ---- canonical order and CSR
+    const int p2p_bits = 32 + bits_for((uint64_t)std::max<int64_t>(1, nl - 1));
+    std::string err = sort_in_place(d.p2p_keys, nullptr, d.p2p_keys_tmp, nullptr, d.hist, n_p2p,
+                                    p2p_bits, s);
+    if (!err.empty()) return err;
+    TRY(d.p2p_row.ensure((nl + 1) * 4));
+    TRY(d.js.ensure(std::max<int64_t>(1, n_p2p) * 4));
+    hipLaunchKernelGGL(k_csr_rows, dim3(grid_of(nl + 1)), dim3(256), 0, s, d.p2p_keys.as<uint64_t>(),
+                       n_p2p, (int)nl, d.p2p_row.as<int32_t>());
+    if (n_p2p > 0)
+        hipLaunchKernelGGL(k_split_p2p, dim3(grid_of(n_p2p)), dim3(256), 0, s,
+                           d.p2p_keys.as<uint64_t>(), n_p2p, d.js.as<int32_t>());
+    TRY(hipGetLastError());
+    const int m2l_bits = 32 + bits_for((uint64_t)std::max<int64_t>(1, nc - 1));
+    err = sort_in_place(d.m2l_keys, nullptr, d.m2l_keys_tmp, nullptr, d.hist, n_m2l, m2l_bits, s);
+    if (!err.empty()) return err;
+    TRY(d.m2l_row.ensure((nc + 1) * 4));
+    TRY(d.m2l_src.ensure(std::max<int64_t>(1, n_m2l) * 4));
+    TRY(d.m2l_shift.ensure(std::max<int64_t>(1, n_m2l) * 4));
+    hipLaunchKernelGGL(k_csr_rows, dim3(grid_of(nc + 1)), dim3(256), 0, s, d.m2l_keys.as<uint64_t>(),
+                       n_m2l, (int)nc, d.m2l_row.as<int32_t>());
+    if (n_m2l > 0)
+        hipLaunchKernelGGL(k_split_m2l, dim3(grid_of(n_m2l)), dim3(256), 0, s,
+                           d.m2l_keys.as<uint64_t>(), n_m2l, d.m2l_src.as<int32_t>(),
+                           d.m2l_shift.as<int32_t>());
+    TRY(hipGetLastError());
+    out.n_p2p = n_p2p;
+    out.n_m2l = n_m2l;
+    return gpu_make_items(d, topo, n_p2p, chunk, s, out);
+}
+
+std::string gpu_make_items(DevPlan& d, const Plan& topo, int64_t n_p2p, int chunk, hipStream_t s,
+                           PlanCounts& out) {
+    const int64_t nl = (int64_t)topo.leaf_cell.size();
+    if (chunk <= 0) chunk = (int)std::max<int64_t>(4, (n_p2p + 16383) / 16384);
+    TRY(d.cost.ensure((nl + 1) * 4));
+    TRY(d.leaf_slot.ensure((nl + 1) * 4));
+    TRY(d.tile_sums.ensure(sort_tiles(nl + 1) * 4 + 16));
+    hipLaunchKernelGGL(k_item_count, dim3(grid_of(nl + 1)), dim3(256), 0, s, (int)nl,
+                       d.p2p_row.as<int32_t>(), chunk, d.cost.as<int32_t>());
+    TRY(hipGetLastError());
+    TRY(exclusive_scan_i32(d.cost.as<int32_t>(), d.leaf_slot.as<int32_t>(), nl + 1,
+                           d.tile_sums.as<uint32_t>(), s));
+    int32_t n_items = 0;
+    TRY(hipMemcpyAsync(&n_items, d.leaf_slot.as<int32_t>() + nl, 4, hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    TRY(d.items.ensure(std::max<int64_t>(1, n_items) * 16));
+    TRY(d.cost_keys.ensure(std::max<int64_t>(1, n_items) * 8));
+    TRY(d.queue.ensure(std::max<int64_t>(1, n_items) * 4));
+    TRY(d.partial.ensure(std::max<int64_t>(1, n_items) * 4 * 64 * 8));
+    TRY(d.wcount.ensure(64));
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, d.wcount.as<uint32_t>(), 16);
+    hipLaunchKernelGGL(k_items, dim3(grid_of(nl)), dim3(256), 0, s, (int)nl, d.p2p_row.as<int32_t>(),
+                       d.js.as<int32_t>(), d.leaf.as<int4>(), chunk, d.leaf_slot.as<int32_t>(),
+                       d.items.as<int4>(), d.cost_keys.as<uint64_t>(), d.queue.as<uint32_t>(),
+                       reinterpret_cast<unsigned long long*>(d.wcount.as<uint32_t>() + 8));
+    TRY(hipGetLastError());
+    std::string err = sort_in_place(d.cost_keys, &d.queue, d.cost_keys_tmp, &d.queue_tmp, d.hist,
+                                    n_items, 32, s);
+    if (!err.empty()) return err;
+    unsigned long long cand = 0;
+    TRY(hipMemcpyAsync(&cand, d.wcount.as<uint32_t>() + 8, 8, hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    out.n_items = n_items;
+    out.candidate_pairs = (int64_t)cand;
+    return std::string();
+}
+
+}  // namespace pmfmm

@@ -1,0 +1,195 @@
+// Device primitives of the on-GPU planner: a stable LSD radix sort of 64-bit
+// keys (optionally carrying 32-bit values) and an exclusive prefix sum of
+// 32-bit integers.
+//
+// Radix sort: 8-bit digits, tiles of 4096 elements (256 threads x 16
+// rounds).  Per pass: (1) per-tile digit histogram in LDS, (2) one exclusive
+// scan over the digit-major [256][tiles] table, (3) scatter: inside a tile
+// the 256 elements of a round are ranked per digit with wavefront ballots
+// (eight ballots give each lane the mask of lanes holding its digit) and a
+// running per-digit count in LDS, so the order of equal digits is kept
+// (stable), which makes the sort stable across passes.
+#include "gpu_plan.h"
+
+namespace pmfmm {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kRounds = 16;
+constexpr int kTile = kThreads * kRounds;  // 4096
+
+__global__ void __launch_bounds__(kThreads)
+rs_hist(const uint64_t* __restrict__ keys, int64_t n, int shift, uint32_t* __restrict__ hist,
+        int tiles) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t i = base + r * kThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of m 32-bit values by one workgroup of 1024 threads.
+__global__ void __launch_bounds__(1024) scan_single(uint32_t* __restrict__ a, int64_t m) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (m + 1023) / 1024;
+    const int64_t b = t * per, e = min(m, b + per);
+    uint32_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += a[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = t == 0 ? 0u : part[t - 1];
+    for (int64_t i = b; i < e; ++i) {
+        const uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+}
+
+template <bool VALS>
+__global__ void __launch_bounds__(kThreads)
+rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+           uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n, int shift,
+           const uint32_t* __restrict__ offs, int tiles) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wc[kThreads / 64][256];
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    run[t] = offs[(size_t)t * tiles + blockIdx.x];
+    for (int w = 0; w < kThreads / 64; ++w) wc[w][t] = 0;
+    __syncthreads();
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t i = base + r * kThreads + t;
+        const bool valid = i < n;
+        uint64_t key = 0;
+        uint32_t val = 0;
+        uint32_t d = 0;
+        if (valid) {
+            key = kin[i];
+            if (VALS) val = vin[i];
+            d = (uint32_t)(key >> shift) & 255u;
+        }
+        uint64_t m = __ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        const uint32_t rank = (uint32_t)__popcll(m & below);
+        if (valid && rank == 0) wc[wave][d] = (uint32_t)__popcll(m);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[d] + rank;
+            for (int w = 0; w < wave; ++w) pos += wc[w][d];
+            kout[pos] = key;
+            if (VALS) vout[pos] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int w = 0; w < kThreads / 64; ++w) {
+            add += wc[w][t];
+            wc[w][t] = 0;
+        }
+        run[t] += add;
+        __syncthreads();
+    }
+}
+
+// ---- exclusive scan of int32 (tiles of 4096)
+__global__ void __launch_bounds__(kThreads)
+scan_tile_sums(const int32_t* __restrict__ in, int64_t n, uint32_t* __restrict__ sums) {
+    __shared__ int32_t red[kThreads];
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kRounds;
+    int32_t s = 0;
+    for (int r = 0; r < kRounds; ++r)
+        if (base + r < n) s += in[base + r];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = kThreads / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = (uint32_t)red[0];
+}
+
+__global__ void __launch_bounds__(kThreads)
+scan_tile_apply(const int32_t* __restrict__ in, int32_t* __restrict__ out, int64_t n,
+                const uint32_t* __restrict__ sums) {
+    __shared__ int32_t part[kThreads];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)t * kRounds;
+    int32_t v[kRounds];
+    int32_t s = 0;
+    for (int r = 0; r < kRounds; ++r) {
+        v[r] = base + r < n ? in[base + r] : 0;
+        s += v[r];
+    }
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < kThreads; off <<= 1) {
+        int32_t x = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    int32_t run = (int32_t)sums[blockIdx.x] + (t == 0 ? 0 : part[t - 1]);
+    for (int r = 0; r < kRounds; ++r) {
+        if (base + r < n) out[base + r] = run;
+        run += v[r];
+    }
+}
+
+}  // namespace
+
+int64_t sort_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
+
+hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals,
+                          uint32_t* hist, int64_t n, int bit_begin, int bit_end, hipStream_t s,
+                          bool* result_in_tmp) {
+    *result_in_tmp = false;
+    if (n <= 1) return hipSuccess;
+    const int tiles = (int)sort_tiles(n);
+    uint64_t* ka = keys;
+    uint64_t* kb = tmp_keys;
+    uint32_t* va = vals;
+    uint32_t* vb = tmp_vals;
+    for (int shift = bit_begin; shift < bit_end; shift += 8) {
+        hipLaunchKernelGGL(rs_hist, dim3(tiles), dim3(kThreads), 0, s, ka, n, shift, hist, tiles);
+        hipLaunchKernelGGL(scan_single, dim3(1), dim3(1024), 0, s, hist, (int64_t)256 * tiles);
+        if (vals)
+            hipLaunchKernelGGL(rs_scatter<true>, dim3(tiles), dim3(kThreads), 0, s, ka, va, kb, vb, n,
+                               shift, hist, tiles);
+        else
+            hipLaunchKernelGGL(rs_scatter<false>, dim3(tiles), dim3(kThreads), 0, s, ka, va, kb, vb, n,
+                               shift, hist, tiles);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+        *result_in_tmp = !*result_in_tmp;
+    }
+    return hipGetLastError();
+}
+
+hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, uint32_t* tile_sums,
+                              hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int tiles = (int)sort_tiles(n);
+    hipLaunchKernelGGL(scan_tile_sums, dim3(tiles), dim3(kThreads), 0, s, in, n, tile_sums);
+    hipLaunchKernelGGL(scan_single, dim3(1), dim3(1024), 0, s, tile_sums, (int64_t)tiles);
+    hipLaunchKernelGGL(scan_tile_apply, dim3(tiles), dim3(kThreads), 0, s, in, out, n, tile_sums);
+    return hipGetLastError();
+}
+
+}  // namespace pmfmm

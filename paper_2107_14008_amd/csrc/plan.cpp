@@ -465,6 +465,86 @@ std::string make_plan(Plan& plan, const std::vector<BoxParams>& boxes,
     return std::string();
 }
 
+namespace {
+
+struct TopoBuilder {
+    const Shape* shape;
+    int64_t ml;
+    Cell* cells;
+    int32_t* leaf_cell;
+    int32_t box;
+    void build(int64_t n, int32_t cell, int32_t leaf, int32_t first, int32_t parent, int depth) {
+        Cell& c = cells[cell];
+        for (int d = 0; d < 3; ++d) c.lo[d] = c.hi[d] = 0.0;
+        c.first = first;
+        c.count = (int32_t)n;
+        c.child[0] = c.child[1] = -1;
+        c.parent = parent;
+        c.depth = depth;
+        c.leaf = -1;
+        c.box = box;
+        if (n <= ml) {
+            c.leaf = leaf;
+            leaf_cell[leaf] = cell;
+            return;
+        }
+        const int64_t nl = n / 2;
+        const auto ls = shape->get(nl);
+        const int32_t lc = cell + 1, rc = cell + 1 + (int32_t)ls.first;
+        c.child[0] = lc;
+        c.child[1] = rc;
+        build(nl, lc, leaf, first, cell, depth + 1);
+        build(n - nl, rc, leaf + (int32_t)ls.second, first + (int32_t)nl, cell, depth + 1);
+    }
+};
+
+}  // namespace
+
+void make_topology(Plan& plan, const std::vector<BoxParams>& boxes,
+                   const std::vector<int64_t>& counts) {
+    const int nbox = (int)boxes.size();
+    plan.boxes = boxes;
+    plan.box_first_particle.assign(nbox + 1, 0);
+    plan.box_first_leaf.assign(nbox + 1, 0);
+    plan.box_first_cell.assign(nbox + 1, 0);
+    std::vector<Shape> shapes(nbox);
+    for (int b = 0; b < nbox; ++b) {
+        shapes[b].ml = boxes[b].max_leaf;
+        auto s = shapes[b].fill(counts[b]);
+        plan.box_first_particle[b + 1] = plan.box_first_particle[b] + (int32_t)counts[b];
+        plan.box_first_cell[b + 1] = plan.box_first_cell[b] + (int32_t)s.first;
+        plan.box_first_leaf[b + 1] = plan.box_first_leaf[b] + (int32_t)s.second;
+    }
+    plan.n = plan.box_first_particle[nbox];
+    const int64_t nc = plan.box_first_cell[nbox], nl = plan.box_first_leaf[nbox];
+    plan.cells.assign(nc, Cell{});
+    plan.leaf_cell.assign(nl, 0);
+    for (int b = 0; b < nbox; ++b) {
+        TopoBuilder tb{&shapes[b], boxes[b].max_leaf, plan.cells.data(), plan.leaf_cell.data(), b};
+        tb.build(counts[b], plan.box_first_cell[b], plan.box_first_leaf[b], plan.box_first_particle[b], -1, 0);
+    }
+    plan.leaf_first.resize(nl);
+    plan.leaf_count.resize(nl);
+    plan.leaf_box.resize(nl);
+    for (int64_t l = 0; l < nl; ++l) {
+        const Cell& c = plan.cells[plan.leaf_cell[l]];
+        plan.leaf_first[l] = c.first;
+        plan.leaf_count[l] = c.count;
+        plan.leaf_box[l] = c.box;
+    }
+    int max_depth = 0;
+    for (const Cell& c : plan.cells) max_depth = std::max(max_depth, c.depth);
+    plan.depth_begin.assign(max_depth + 2, 0);
+    for (const Cell& c : plan.cells) plan.depth_begin[c.depth + 1]++;
+    for (int d = 0; d <= max_depth; ++d) plan.depth_begin[d + 1] += plan.depth_begin[d];
+    plan.cells_by_depth.resize(nc);
+    std::vector<int32_t> fill(plan.depth_begin.begin(), plan.depth_begin.end() - 1);
+    for (int64_t k = 0; k < nc; ++k) plan.cells_by_depth[fill[plan.cells[k].depth]++] = (int32_t)k;
+    plan.max_order = -1;
+    for (const auto& b : boxes)
+        if (b.order >= 0 && b.theta > 0.0) plan.max_order = std::max<int>(plan.max_order, b.order);
+}
+
 void make_items(Plan& plan, int chunk) {
     const int64_t n_leaves = (int64_t)plan.leaf_count.size();
     const int64_t n_tasks = (int64_t)plan.p2p_j.size();

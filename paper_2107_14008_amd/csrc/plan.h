@@ -65,6 +65,12 @@ std::string make_plan(Plan& plan, const std::vector<BoxParams>& boxes,
                       const std::vector<int64_t>& counts, const double* pos,
                       const double* mass, int threads);
 
+// Tree shape only (no particles): cells with first / count / children /
+// parent / depth / leaf / box, the leaf table, cells grouped by depth.  The
+// ORB shape depends on the particle counts and MAXLEAF alone.
+void make_topology(Plan& plan, const std::vector<BoxParams>& boxes,
+                   const std::vector<int64_t>& counts);
+
 // (Re)cuts the P2P rows into work items of at most `chunk` tasks
 // (0 = automatic) and orders the queue by decreasing pair count.
 void make_items(Plan& plan, int chunk);

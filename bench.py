@@ -211,6 +211,7 @@ def main():
                         "+ 20% in 200 Plummer halos, L=100, N_PM=128, "
                         "r_s=1.2 dg, r_cut=4.5 r_s, leaf<=64, p=4",
             "n": n, "theta": args.theta, "order": args.order,
+            "planner": "gpu",
             "candidate_pairs_per_step": cand,
             "fp32_form": f"float32 cell-relative pairs, {args.table_size}-node "
                          f"T_[{args.table_level}] table, float64 accumulation",

@@ -76,7 +76,8 @@ typedef struct pmfmm_params {
     int32_t wg_waves;    /* wavefronts per workgroup of the P2P launch, 0 = auto  */
     int32_t grid_wgs;    /* workgroups of the persistent launch, 0 = auto         */
     int32_t timing;      /* 1: time each phase with HIP events (see get_timings)  */
-    int32_t threads;     /* host threads for the tree build, 0 = all              */
+    int32_t threads;     /* host threads of the host planner, 0 = all             */
+    int32_t planner;     /* pmfmm_build: 0 = plan on the GPU, 1 = on the host     */
 } pmfmm_params;
 
 typedef struct pmfmm_ctx pmfmm_ctx;
@@ -115,10 +116,14 @@ int pmfmm_plan_batch(pmfmm_ctx* ctx, int32_t nbox,
                      const pmfmm_params* per_box, const int64_t* counts,
                      const double* pos, const double* mass);
 
-/* pmfmm_plan followed by the upload of everything the kernels read.
- * on_device = 0: pos and mass are host pointers; 1: device pointers (they
- * are copied to the host for the tree, synchronously on `stream`).  The
- * particles are then gathered into leaf order on the device.  The caller
+/* Plan and upload everything the kernels read.  With params.planner = 0
+ * (default) the tree, task lists and work items are built on the GPU from
+ * the particles (the same lists as pmfmm_plan, integer for integer); with
+ * planner = 1 they are built by pmfmm_plan on the host and uploaded.
+ * on_device = 0: pos and mass are host pointers (copied to the device);
+ * 1: device pointers (the host planner copies them to the host first).  The
+ * particles are gathered into leaf order on the device.  Synchronises
+ * `stream` before returning (list sizes come back to the host).  The caller
  * may free or change pos and mass when the call returns.
  * Errors: those of pmfmm_plan, EDEVICE, ENOMEM. */
 int pmfmm_build(pmfmm_ctx* ctx, int64_t n, const double* pos,

@@ -41,6 +41,7 @@ class Params(C.Structure):
         ("table_round", C.c_int32), ("chunk", C.c_int32),
         ("wg_waves", C.c_int32), ("grid_wgs", C.c_int32),
         ("timing", C.c_int32), ("threads", C.c_int32),
+        ("planner", C.c_int32),
     ]
 
 

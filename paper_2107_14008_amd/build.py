@@ -34,6 +34,8 @@ SOURCES = [
     ("p2p.hip", "hip"),
     ("far.hip", "hip"),
     ("adjoint.hip", "hip"),
+    ("gpu_sort.hip", "hip"),
+    ("gpu_plan.hip", "hip"),
 ]
 
 
@@ -42,7 +44,8 @@ def _cmd(src, kind, obj):
     if kind == "gxx":
         return ["g++", *COMMON, *HOST, "-c", path, "-o", obj]
     if kind == "hip-host":
-        return [HIPCC, *COMMON, *HOST, "-c", path, "-o", obj]
+        return [HIPCC, *COMMON, *HOST, f"--offload-arch={ARCH}",
+                "--offload-host-only", "-c", path, "-o", obj]
     return [HIPCC, *COMMON, *HIP, "-c", path, "-o", obj]
 
 

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "device.h"
+#include "gpu_plan.h"
 #include "plan.h"
 
 namespace {
@@ -31,27 +32,7 @@ int fail(int code, const std::string& msg) {
                         std::string(#expr) + ": " + hipGetErrorString(e_));           \
     } while (0)
 
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    hipError_t ensure(size_t want) {
-        if (want <= bytes && p != nullptr) return hipSuccess;
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-        if (want == 0) want = 16;
-        hipError_t e = hipMalloc(&p, want);
-        if (e == hipSuccess) bytes = want;
-        return e;
-    }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    template <class T>
-    T* as() const { return static_cast<T*>(p); }
-};
+using pmfmm::DevBuf;
 
 bool valid_geometry(const pmfmm_params& p, std::string& why) {
     if (!(std::isfinite(p.box) && p.box > 0.0)) { why = "box must be finite and > 0"; return false; }
@@ -145,20 +126,25 @@ std::vector<unsigned char> build_table(const pmfmm_params& p) {
 
 struct pmfmm_ctx {
     pmfmm_params p{};
-    pmfmm::Plan plan;
+    // Host plan (host planner), or tree shape + lists copied back on demand
+    // (GPU planner).
+    mutable pmfmm::Plan plan;
     bool planned = false;
     bool built = false;
+    bool gpu_planned = false;
+    mutable bool lists_fresh = false;
     int device = -1;
     int n_cu = 0;
-    // device buffers
-    DevBuf perm, leaf, leafc, js, items, queue, leaf_slot, partial, counter, boxes, table;
-    DevBuf x64, x32, stage_pos, stage_mass, far;
-    DevBuf cell, cell_aux, cellc, M, Lc, m2l_row, m2l_src, m2l_shift, level_cells;
-    DevBuf w64, w32;
+    pmfmm::DevPlan d;
     std::vector<unsigned char> table_host;
     bool table_dirty = true;
-    int last_mode = -1;
-    size_t lds_bytes = 0;
+    // sizes of the current plan
+    int64_t n_items = 0, n_p2p = 0, n_m2l = 0, cand = 0;
+    bool far = false;
+    // tree shape uploaded for the GPU planner
+    std::vector<int64_t> topo_counts;
+    std::vector<pmfmm::BoxParams> topo_boxes;
+    bool topo_on_device = false;
     // timing
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     bool timed_fwd = false, timed_adj = false;
@@ -168,10 +154,7 @@ struct pmfmm_ctx {
             (void)hipSetDevice(device);
             (void)hipDeviceSynchronize();
         }
-        for (DevBuf* b : {&perm, &leaf, &leafc, &js, &items, &queue, &leaf_slot, &partial, &counter,
-                          &boxes, &table, &x64, &x32, &stage_pos, &stage_mass, &far, &cell, &cell_aux,
-                          &cellc, &M, &Lc, &m2l_row, &m2l_src, &m2l_shift, &level_cells, &w64, &w32})
-            b->release();
+        d.release_all();
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
     }
@@ -198,6 +181,14 @@ int do_plan(pmfmm_ctx* ctx, const std::vector<pmfmm::BoxParams>& boxes,
     }
     if (!msg.empty()) return fail(PMFMM_EINVAL, msg);
     ctx->planned = true;
+    ctx->gpu_planned = false;
+    ctx->lists_fresh = true;
+    ctx->topo_on_device = false;
+    ctx->n_items = (int64_t)ctx->plan.items.size();
+    ctx->n_p2p = (int64_t)ctx->plan.p2p_j.size();
+    ctx->n_m2l = (int64_t)ctx->plan.m2l_src.size();
+    ctx->cand = ctx->plan.candidate_pairs;
+    ctx->far = ctx->plan.far_field;
     return PMFMM_OK;
 }
 
@@ -235,10 +226,10 @@ int upload_items(pmfmm_ctx* ctx, hipStream_t s) {
         it[4 * k + 3] = pl.items[k].slot;
     }
     int rc;
-    if ((rc = upload(ctx->items, it, s))) return rc;
-    if ((rc = upload(ctx->queue, pl.queue, s))) return rc;
-    if ((rc = upload(ctx->leaf_slot, pl.leaf_slot_begin, s))) return rc;
-    HIP_TRY(ctx->partial.ensure(std::max<size_t>(1, pl.items.size()) * 4 * 64 * sizeof(double)));
+    if ((rc = upload(ctx->d.items, it, s))) return rc;
+    if ((rc = upload(ctx->d.queue, pl.queue, s))) return rc;
+    if ((rc = upload(ctx->d.leaf_slot, pl.leaf_slot_begin, s))) return rc;
+    HIP_TRY(ctx->d.partial.ensure(std::max<size_t>(1, pl.items.size()) * 4 * 64 * sizeof(double)));
     HIP_TRY(hipStreamSynchronize(s));
     return PMFMM_OK;
 }
@@ -246,7 +237,7 @@ int upload_items(pmfmm_ctx* ctx, hipStream_t s) {
 int upload_table(pmfmm_ctx* ctx, hipStream_t s) {
     if (!ctx->table_dirty) return PMFMM_OK;
     ctx->table_host = build_table(ctx->p);
-    int rc = upload(ctx->table, ctx->table_host, s);
+    int rc = upload(ctx->d.table, ctx->table_host, s);
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(s));
     ctx->table_dirty = false;
@@ -290,25 +281,25 @@ int do_upload(pmfmm_ctx* ctx, const double* pos, const double* mass, int32_t on_
     std::vector<int32_t> js(pl.p2p_j.size());
     for (size_t t = 0; t < js.size(); ++t) js[t] = (pl.p2p_j[t] << 5) | pl.p2p_shift[t];
     int rc;
-    if ((rc = upload(ctx->perm, pl.perm, s))) return rc;
-    if ((rc = upload(ctx->leaf, leaf, s))) return rc;
-    if ((rc = upload(ctx->leafc, leafc, s))) return rc;
-    if ((rc = upload(ctx->js, js, s))) return rc;
-    if ((rc = upload(ctx->boxes, box_table(ctx), s))) return rc;
-    HIP_TRY(ctx->counter.ensure(64));
-    HIP_TRY(ctx->x64.ensure((size_t)n * 32));
-    HIP_TRY(ctx->x32.ensure((size_t)n * 16));
+    if ((rc = upload(ctx->d.perm, pl.perm, s))) return rc;
+    if ((rc = upload(ctx->d.leaf, leaf, s))) return rc;
+    if ((rc = upload(ctx->d.leafc, leafc, s))) return rc;
+    if ((rc = upload(ctx->d.js, js, s))) return rc;
+    if ((rc = upload(ctx->d.boxes, box_table(ctx), s))) return rc;
+    HIP_TRY(ctx->d.counter.ensure(64));
+    HIP_TRY(ctx->d.x64.ensure((size_t)n * 32));
+    HIP_TRY(ctx->d.x32.ensure((size_t)n * 16));
     const double* src_pos = pos;
     const double* src_mass = mass;
     if (!on_device) {
-        if ((rc = upload(ctx->stage_pos, pl.pos, s))) return rc;
-        if ((rc = upload(ctx->stage_mass, pl.mass, s))) return rc;
-        src_pos = ctx->stage_pos.as<double>();
-        src_mass = ctx->stage_mass.as<double>();
+        if ((rc = upload(ctx->d.stage_pos, pl.pos, s))) return rc;
+        if ((rc = upload(ctx->d.stage_mass, pl.mass, s))) return rc;
+        src_pos = ctx->d.stage_pos.as<double>();
+        src_mass = ctx->d.stage_mass.as<double>();
     }
-    pmfmm::GatherArgs g{src_pos, src_mass, ctx->perm.as<int32_t>(), ctx->leaf.as<int4>(),
-                        ctx->leafc.as<double4>(), ctx->boxes.as<pmfmm::BoxDev>(), ctx->x64.as<double4>(),
-                        ctx->x32.as<float4>(), (int32_t)nl};
+    pmfmm::GatherArgs g{src_pos, src_mass, ctx->d.perm.as<int32_t>(), ctx->d.leaf.as<int4>(),
+                        ctx->d.leafc.as<double4>(), ctx->d.boxes.as<pmfmm::BoxDev>(), ctx->d.x64.as<double4>(),
+                        ctx->d.x32.as<float4>(), (int32_t)nl};
     HIP_TRY(pmfmm::launch_gather(g, nullptr, s));
     if ((rc = upload_items(ctx, s))) return rc;
     ctx->table_dirty = true;
@@ -331,17 +322,17 @@ int do_upload(pmfmm_ctx* ctx, const double* pos, const double* mass, int32_t on_
             for (int a = 0; a < 3; ++a) cc[4 * k + a] = 0.5 * (c.lo[a] + c.hi[a]);
             cc[4 * k + 3] = 0.0;
         }
-        if ((rc = upload(ctx->cell, cell, s))) return rc;
-        if ((rc = upload(ctx->cell_aux, aux, s))) return rc;
-        if ((rc = upload(ctx->cellc, cc, s))) return rc;
-        if ((rc = upload(ctx->m2l_row, pl.m2l_row, s))) return rc;
-        if ((rc = upload(ctx->m2l_src, pl.m2l_src, s))) return rc;
-        if ((rc = upload(ctx->m2l_shift, pl.m2l_shift, s))) return rc;
-        if ((rc = upload(ctx->level_cells, pl.cells_by_depth, s))) return rc;
+        if ((rc = upload(ctx->d.cell, cell, s))) return rc;
+        if ((rc = upload(ctx->d.cell_aux, aux, s))) return rc;
+        if ((rc = upload(ctx->d.cellc, cc, s))) return rc;
+        if ((rc = upload(ctx->d.m2l_row, pl.m2l_row, s))) return rc;
+        if ((rc = upload(ctx->d.m2l_src, pl.m2l_src, s))) return rc;
+        if ((rc = upload(ctx->d.m2l_shift, pl.m2l_shift, s))) return rc;
+        if ((rc = upload(ctx->d.level_cells, pl.cells_by_depth, s))) return rc;
         const int nco = pmfmm::n_coef(pl.max_order);
-        HIP_TRY(ctx->M.ensure((size_t)nc * nco * sizeof(double)));
-        HIP_TRY(ctx->Lc.ensure((size_t)nc * nco * sizeof(double)));
-        HIP_TRY(ctx->far.ensure((size_t)n * 3 * sizeof(double)));
+        HIP_TRY(ctx->d.M.ensure((size_t)nc * nco * sizeof(double)));
+        HIP_TRY(ctx->d.Lc.ensure((size_t)nc * nco * sizeof(double)));
+        HIP_TRY(ctx->d.far.ensure((size_t)n * 3 * sizeof(double)));
     }
     HIP_TRY(hipStreamSynchronize(s));
     ctx->built = true;
@@ -356,19 +347,19 @@ int run_far(pmfmm_ctx* ctx, hipStream_t s) {
     const pmfmm::Plan& pl = ctx->plan;
     const int64_t nc = (int64_t)pl.cells.size();
     pmfmm::FarArgs f{};
-    f.x64 = ctx->x64.as<double4>();
-    f.leaf = ctx->leaf.as<int4>();
-    f.leafc = ctx->leafc.as<double4>();
-    f.cell = ctx->cell.as<int4>();
-    f.cell_aux = ctx->cell_aux.as<int4>();
-    f.cellc = ctx->cellc.as<double4>();
-    f.m2l_row = ctx->m2l_row.as<int32_t>();
-    f.m2l_src = ctx->m2l_src.as<int32_t>();
-    f.m2l_shift = ctx->m2l_shift.as<int32_t>();
-    f.boxes = ctx->boxes.as<pmfmm::BoxDev>();
-    f.M = ctx->M.as<double>();
-    f.Lc = ctx->Lc.as<double>();
-    f.far = ctx->far.as<double>();
+    f.x64 = ctx->d.x64.as<double4>();
+    f.leaf = ctx->d.leaf.as<int4>();
+    f.leafc = ctx->d.leafc.as<double4>();
+    f.cell = ctx->d.cell.as<int4>();
+    f.cell_aux = ctx->d.cell_aux.as<int4>();
+    f.cellc = ctx->d.cellc.as<double4>();
+    f.m2l_row = ctx->d.m2l_row.as<int32_t>();
+    f.m2l_src = ctx->d.m2l_src.as<int32_t>();
+    f.m2l_shift = ctx->d.m2l_shift.as<int32_t>();
+    f.boxes = ctx->d.boxes.as<pmfmm::BoxDev>();
+    f.M = ctx->d.M.as<double>();
+    f.Lc = ctx->d.Lc.as<double>();
+    f.far = ctx->d.far.as<double>();
     f.n_cells = (int32_t)nc;
     f.n_leaves = (int32_t)pl.leaf_count.size();
     f.order = pl.max_order;
@@ -377,13 +368,13 @@ int run_far(pmfmm_ctx* ctx, hipStream_t s) {
     HIP_TRY(pmfmm::launch_p2m(f, s));
     const int nd = (int)pl.depth_begin.size() - 1;
     for (int d = nd - 2; d >= 0; --d) {   // parents of the deepest level first
-        f.level_cells = ctx->level_cells.as<int32_t>() + pl.depth_begin[d];
+        f.level_cells = ctx->d.level_cells.as<int32_t>() + pl.depth_begin[d];
         f.n_level = pl.depth_begin[d + 1] - pl.depth_begin[d];
         HIP_TRY(pmfmm::launch_m2m_level(f, s));
     }
     HIP_TRY(pmfmm::launch_m2l(f, s));
     for (int d = 1; d < nd; ++d) {
-        f.level_cells = ctx->level_cells.as<int32_t>() + pl.depth_begin[d];
+        f.level_cells = ctx->d.level_cells.as<int32_t>() + pl.depth_begin[d];
         f.n_level = pl.depth_begin[d + 1] - pl.depth_begin[d];
         HIP_TRY(pmfmm::launch_l2l_level(f, s));
     }
@@ -394,6 +385,134 @@ int run_far(pmfmm_ctx* ctx, hipStream_t s) {
 int ensure_events(pmfmm_ctx* ctx) {
     for (auto& e : ctx->ev)
         if (!e) HIP_TRY(hipEventCreate(&e));
+    return PMFMM_OK;
+}
+
+bool same_boxes(const std::vector<pmfmm::BoxParams>& a, const std::vector<pmfmm::BoxParams>& b) {
+    if (a.size() != b.size()) return false;
+    for (size_t k = 0; k < a.size(); ++k)
+        if (a[k].box != b[k].box || a[k].r_s != b[k].r_s || a[k].r_cut != b[k].r_cut || a[k].G != b[k].G ||
+            a[k].theta != b[k].theta || a[k].max_leaf != b[k].max_leaf || a[k].order != b[k].order)
+            return false;
+    return true;
+}
+
+int ensure_device(pmfmm_ctx* ctx) {
+    HIP_TRY(hipGetDevice(&ctx->device));
+    HIP_TRY(hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    return PMFMM_OK;
+}
+
+// Plan on the GPU from particles (device or host pointers).
+int gpu_build(pmfmm_ctx* ctx, const std::vector<pmfmm::BoxParams>& boxes, const std::vector<int64_t>& cnt,
+              const double* pos, const double* mass, int32_t on_device, hipStream_t s) {
+    ctx->planned = false;
+    ctx->built = false;
+    int rc = ensure_device(ctx);
+    if (rc) return rc;
+    int64_t n = 0;
+    for (int64_t c : cnt) n += c;
+    if (n > (int64_t)INT32_MAX) return fail(PMFMM_EINVAL, "too many particles (limit 2^31 - 1)");
+    const double* dp = pos;
+    const double* dm = mass;
+    if (!on_device) {
+        HIP_TRY(ctx->d.stage_pos.ensure((size_t)n * 24));
+        HIP_TRY(ctx->d.stage_mass.ensure((size_t)n * 8));
+        HIP_TRY(hipMemcpyAsync(ctx->d.stage_pos.p, pos, (size_t)n * 24, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ctx->d.stage_mass.p, mass, (size_t)n * 8, hipMemcpyHostToDevice, s));
+        dp = ctx->d.stage_pos.as<double>();
+        dm = ctx->d.stage_mass.as<double>();
+    }
+    std::string err = pmfmm::gpu_check_inputs(ctx->d, dp, dm, n, s);
+    if (!err.empty()) return fail(PMFMM_EINVAL, err);
+    const bool same = ctx->topo_on_device && ctx->topo_counts == cnt && same_boxes(ctx->topo_boxes, boxes);
+    if (!same) {
+        try {
+            pmfmm::make_topology(ctx->plan, boxes, cnt);
+        } catch (const std::bad_alloc&) {
+            return fail(PMFMM_ENOMEM, "host allocation failed while shaping the tree");
+        }
+        if ((int64_t)ctx->plan.cells.size() >= ((int64_t)1 << 27))
+            return fail(PMFMM_EINVAL, "too many tree cells (limit 2^27)");
+        const std::vector<pmfmm::BoxDev> bt = box_table(ctx);
+        HIP_TRY(pmfmm::upload_topology(ctx->d, ctx->plan, bt.data(), s));
+        ctx->topo_counts = cnt;
+        ctx->topo_boxes = boxes;
+        ctx->topo_on_device = true;
+    } else {
+        if ((rc = upload(ctx->d.boxes, box_table(ctx), s))) return rc;
+    }
+    pmfmm::PlanCounts pc;
+    err = pmfmm::gpu_build_plan(ctx->d, ctx->plan, dp, dm, ctx->p.chunk, s, pc);
+    if (!err.empty()) return fail(PMFMM_EDEVICE, err);
+    ctx->n_p2p = pc.n_p2p;
+    ctx->n_m2l = pc.n_m2l;
+    ctx->n_items = pc.n_items;
+    ctx->cand = pc.candidate_pairs;
+    ctx->far = pc.n_m2l > 0;
+    ctx->plan.far_field = ctx->far;
+    ctx->plan.candidate_pairs = pc.candidate_pairs;
+    HIP_TRY(ctx->d.counter.ensure(64));
+    if (ctx->far) {
+        const int64_t nc = (int64_t)ctx->plan.cells.size();
+        const int nco = pmfmm::n_coef(ctx->plan.max_order);
+        HIP_TRY(ctx->d.M.ensure((size_t)nc * nco * sizeof(double)));
+        HIP_TRY(ctx->d.Lc.ensure((size_t)nc * nco * sizeof(double)));
+        HIP_TRY(ctx->d.far.ensure((size_t)n * 3 * sizeof(double)));
+    }
+    ctx->table_dirty = true;
+    if ((rc = upload_table(ctx, s))) return rc;
+    ctx->planned = true;
+    ctx->built = true;
+    ctx->gpu_planned = true;
+    ctx->lists_fresh = false;
+    return PMFMM_OK;
+}
+
+// Copies the device-built lists back into the host plan views.
+int download_lists(const pmfmm_ctx* ctx) {
+    pmfmm::Plan& pl = ctx->plan;
+    const pmfmm::DevPlan& d = ctx->d;
+    const int64_t n = pl.n, nc = (int64_t)pl.cells.size(), nl = (int64_t)pl.leaf_cell.size();
+    pl.perm.resize(n);
+    pl.cell_lo.resize(3 * nc);
+    pl.cell_hi.resize(3 * nc);
+    pl.p2p_row.resize(nl + 1);
+    std::vector<int32_t> js(ctx->n_p2p);
+    pl.m2l_row.resize(nc + 1);
+    pl.m2l_src.resize(ctx->n_m2l);
+    pl.m2l_shift.resize(ctx->n_m2l);
+    HIP_TRY(hipMemcpy(pl.perm.data(), d.perm.p, n * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(pl.cell_lo.data(), d.clo.p, nc * 24, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(pl.cell_hi.data(), d.chi.p, nc * 24, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(pl.p2p_row.data(), d.p2p_row.p, (nl + 1) * 4, hipMemcpyDeviceToHost));
+    if (ctx->n_p2p) HIP_TRY(hipMemcpy(js.data(), d.js.p, ctx->n_p2p * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(pl.m2l_row.data(), d.m2l_row.p, (nc + 1) * 4, hipMemcpyDeviceToHost));
+    if (ctx->n_m2l) {
+        HIP_TRY(hipMemcpy(pl.m2l_src.data(), d.m2l_src.p, ctx->n_m2l * 4, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(pl.m2l_shift.data(), d.m2l_shift.p, ctx->n_m2l * 4, hipMemcpyDeviceToHost));
+    }
+    pl.p2p_j.resize(ctx->n_p2p);
+    pl.p2p_shift.resize(ctx->n_p2p);
+    for (int64_t t = 0; t < ctx->n_p2p; ++t) {
+        pl.p2p_j[t] = js[t] >> 5;
+        pl.p2p_shift[t] = js[t] & 31;
+    }
+    pl.cell_first.resize(nc);
+    pl.cell_count.resize(nc);
+    pl.cell_child.resize(2 * nc);
+    for (int64_t k = 0; k < nc; ++k) {
+        pmfmm::Cell& c = pl.cells[k];
+        for (int a = 0; a < 3; ++a) {
+            c.lo[a] = pl.cell_lo[3 * k + a];
+            c.hi[a] = pl.cell_hi[3 * k + a];
+        }
+        pl.cell_first[k] = c.first;
+        pl.cell_count[k] = c.count;
+        pl.cell_child[2 * k] = c.child[0];
+        pl.cell_child[2 * k + 1] = c.child[1];
+    }
+    ctx->lists_fresh = true;
     return PMFMM_OK;
 }
 
@@ -457,6 +576,7 @@ static int build_common(pmfmm_ctx* ctx, const std::vector<pmfmm::BoxParams>& box
                         const std::vector<int64_t>& cnt, const double* pos, const double* mass,
                         int32_t on_device, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ctx->p.planner == 0) return gpu_build(ctx, boxes, cnt, pos, mass, on_device, s);
     int64_t n = 0;
     for (int64_t c : cnt) n += c;
     const double* hp = pos;
@@ -513,15 +633,23 @@ int pmfmm_set_eval(pmfmm_ctx* ctx, const pmfmm_params* p) {
     ctx->p.timing = p->timing;
     if (table_change) ctx->table_dirty = true;
     if (ctx->planned && chunk_change) {
-        pmfmm::make_items(ctx->plan, ctx->p.chunk);
-        if (ctx->built) {
-            int rc = upload_items(ctx, nullptr);
-            if (rc) return rc;
+        if (ctx->gpu_planned) {
+            pmfmm::PlanCounts pc;
+            std::string err = pmfmm::gpu_make_items(ctx->d, ctx->plan, ctx->n_p2p, ctx->p.chunk, nullptr, pc);
+            if (!err.empty()) return fail(PMFMM_EDEVICE, err);
+            ctx->n_items = pc.n_items;
+        } else {
+            pmfmm::make_items(ctx->plan, ctx->p.chunk);
+            ctx->n_items = (int64_t)ctx->plan.items.size();
+            if (ctx->built) {
+                int rc = upload_items(ctx, nullptr);
+                if (rc) return rc;
+            }
         }
     }
     if (ctx->built) {
         // per-box constants depend on table_size
-        int rc = upload(ctx->boxes, box_table(ctx), nullptr);
+        int rc = upload(ctx->d.boxes, box_table(ctx), nullptr);
         if (rc) return rc;
         HIP_TRY(hipStreamSynchronize(nullptr));
     }
@@ -541,24 +669,24 @@ int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream) {
         if ((rc = ensure_events(ctx))) return rc;
         HIP_TRY(hipEventRecord(ctx->ev[0], s));
     }
-    if (pl.far_field) {
+    if (ctx->far) {
         if ((rc = run_far(ctx, s))) return rc;
     }
-    HIP_TRY(pmfmm::launch_zero_i32(ctx->counter.as<int32_t>(), 1, s));
+    HIP_TRY(pmfmm::launch_zero_i32(ctx->d.counter.as<int32_t>(), 1, s));
     if (timing) HIP_TRY(hipEventRecord(ctx->ev[1], s));
     pmfmm::P2PArgs a{};
-    a.x64 = ctx->x64.as<double4>();
-    a.x32 = ctx->x32.as<float4>();
-    a.leaf = ctx->leaf.as<int4>();
-    a.leafc = ctx->leafc.as<double4>();
-    a.p2p_js = ctx->js.as<int32_t>();
-    a.items = ctx->items.as<int4>();
-    a.queue = ctx->queue.as<int32_t>();
-    a.n_items = (int32_t)pl.items.size();
-    a.counter = ctx->counter.as<int32_t>();
-    a.partial = ctx->partial.as<double>();
-    a.boxes = ctx->boxes.as<pmfmm::BoxDev>();
-    a.table = ctx->table.p;
+    a.x64 = ctx->d.x64.as<double4>();
+    a.x32 = ctx->d.x32.as<float4>();
+    a.leaf = ctx->d.leaf.as<int4>();
+    a.leafc = ctx->d.leafc.as<double4>();
+    a.p2p_js = ctx->d.js.as<int32_t>();
+    a.items = ctx->d.items.as<int4>();
+    a.queue = ctx->d.queue.as<int32_t>();
+    a.n_items = (int32_t)ctx->n_items;
+    a.counter = ctx->d.counter.as<int32_t>();
+    a.partial = ctx->d.partial.as<double>();
+    a.boxes = ctx->d.boxes.as<pmfmm::BoxDev>();
+    a.table = ctx->d.table.p;
     a.n_tab = ctx->p.table_size;
     a.level = ctx->p.table_level;
     a.round_floor = ctx->p.table_round == PMFMM_ROUND_FLOOR;
@@ -569,9 +697,9 @@ int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream) {
     if (grid <= 0) grid = ctx->n_cu * pmfmm::p2p_blocks_per_cu(mode, wg, lds);
     HIP_TRY(pmfmm::launch_p2p(mode, a, wg, grid, lds, s));
     if (timing) HIP_TRY(hipEventRecord(ctx->ev[2], s));
-    pmfmm::ReduceArgs r{ctx->leaf.as<int4>(), ctx->leaf_slot.as<int32_t>(), ctx->partial.as<double>(),
-                        pl.far_field ? ctx->far.as<double>() : nullptr, ctx->perm.as<int32_t>(),
-                        ctx->boxes.as<pmfmm::BoxDev>(), acc, (int32_t)pl.leaf_count.size()};
+    pmfmm::ReduceArgs r{ctx->d.leaf.as<int4>(), ctx->d.leaf_slot.as<int32_t>(), ctx->d.partial.as<double>(),
+                        ctx->far ? ctx->d.far.as<double>() : nullptr, ctx->d.perm.as<int32_t>(),
+                        ctx->d.boxes.as<pmfmm::BoxDev>(), acc, (int32_t)pl.leaf_count.size()};
     HIP_TRY(pmfmm::launch_reduce(r, s));
     if (timing) {
         HIP_TRY(hipEventRecord(ctx->ev[3], s));
@@ -583,15 +711,19 @@ int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream) {
 int pmfmm_get_lists(const pmfmm_ctx* ctx, pmfmm_lists* out) {
     if (!ctx || !out) return fail(PMFMM_EINVAL, "null argument");
     if (!ctx->planned) return fail(PMFMM_ESTATE, "no plan");
+    if (!ctx->lists_fresh) {
+        int rc = download_lists(ctx);
+        if (rc) return rc;
+    }
     const pmfmm::Plan& pl = ctx->plan;
     out->n = pl.n;
     out->n_boxes = (int64_t)pl.boxes.size();
     out->n_leaves = (int64_t)pl.leaf_count.size();
     out->n_cells = (int64_t)pl.cells.size();
-    out->n_p2p = (int64_t)pl.p2p_j.size();
-    out->n_m2l = (int64_t)pl.m2l_src.size();
-    out->n_items = (int64_t)pl.items.size();
-    out->candidate_pairs = pl.candidate_pairs;
+    out->n_p2p = ctx->n_p2p;
+    out->n_m2l = ctx->n_m2l;
+    out->n_items = ctx->n_items;
+    out->candidate_pairs = ctx->cand;
     out->perm = pl.perm.data();
     out->box_first_leaf = pl.box_first_leaf.data();
     out->box_first_cell = pl.box_first_cell.data();
@@ -639,15 +771,15 @@ int pmfmm_get_timings(const pmfmm_ctx* ctx, pmfmm_timings* out) {
 int pmfmm_adjoint(pmfmm_ctx* ctx, const double* w, double* grad_pos, double* grad_mass, void* stream) {
     if (!ctx || !w || !grad_pos || !grad_mass) return fail(PMFMM_EINVAL, "null argument");
     if (!ctx->built) return fail(PMFMM_ESTATE, "adjoint before build");
-    if (ctx->plan.far_field) return fail(PMFMM_EUNSUPPORTED, "adjoint covers the P2P-only force (far field off)");
+    if (ctx->far) return fail(PMFMM_EUNSUPPORTED, "adjoint covers the P2P-only force (far field off)");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const pmfmm::Plan& pl = ctx->plan;
     const int64_t n = pl.n;
-    HIP_TRY(ctx->w64.ensure((size_t)n * 32));
-    HIP_TRY(ctx->w32.ensure((size_t)n * 16));
-    HIP_TRY(pmfmm::launch_gather_w(w, ctx->perm.as<int32_t>(), ctx->w64.as<double4>(), ctx->w32.as<float4>(),
+    HIP_TRY(ctx->d.w64.ensure((size_t)n * 32));
+    HIP_TRY(ctx->d.w32.ensure((size_t)n * 16));
+    HIP_TRY(pmfmm::launch_gather_w(w, ctx->d.perm.as<int32_t>(), ctx->d.w64.as<double4>(), ctx->d.w32.as<float4>(),
                                    (int32_t)n, s));
-    HIP_TRY(pmfmm::launch_zero_i32(ctx->counter.as<int32_t>(), 1, s));
+    HIP_TRY(pmfmm::launch_zero_i32(ctx->d.counter.as<int32_t>(), 1, s));
     const bool timing = ctx->p.timing != 0;
     if (timing) {
         int rc = ensure_events(ctx);
@@ -655,19 +787,19 @@ int pmfmm_adjoint(pmfmm_ctx* ctx, const double* w, double* grad_pos, double* gra
         HIP_TRY(hipEventRecord(ctx->ev[4], s));
     }
     pmfmm::AdjArgs a{};
-    a.x64 = ctx->x64.as<double4>();
-    a.x32 = ctx->x32.as<float4>();
-    a.w64 = ctx->w64.as<double4>();
-    a.w32 = ctx->w32.as<float4>();
-    a.leaf = ctx->leaf.as<int4>();
-    a.leafc = ctx->leafc.as<double4>();
-    a.p2p_js = ctx->js.as<int32_t>();
-    a.items = ctx->items.as<int4>();
-    a.queue = ctx->queue.as<int32_t>();
-    a.n_items = (int32_t)pl.items.size();
-    a.counter = ctx->counter.as<int32_t>();
-    a.partial = ctx->partial.as<double>();
-    a.boxes = ctx->boxes.as<pmfmm::BoxDev>();
+    a.x64 = ctx->d.x64.as<double4>();
+    a.x32 = ctx->d.x32.as<float4>();
+    a.w64 = ctx->d.w64.as<double4>();
+    a.w32 = ctx->d.w32.as<float4>();
+    a.leaf = ctx->d.leaf.as<int4>();
+    a.leafc = ctx->d.leafc.as<double4>();
+    a.p2p_js = ctx->d.js.as<int32_t>();
+    a.items = ctx->d.items.as<int4>();
+    a.queue = ctx->d.queue.as<int32_t>();
+    a.n_items = (int32_t)ctx->n_items;
+    a.counter = ctx->d.counter.as<int32_t>();
+    a.partial = ctx->d.partial.as<double>();
+    a.boxes = ctx->d.boxes.as<pmfmm::BoxDev>();
     const int mode = mode_of(ctx->p);
     const int wg = ctx->p.wg_waves > 0 ? ctx->p.wg_waves : 4;
     int grid = ctx->p.grid_wgs;
@@ -677,8 +809,8 @@ int pmfmm_adjoint(pmfmm_ctx* ctx, const double* w, double* grad_pos, double* gra
         HIP_TRY(hipEventRecord(ctx->ev[5], s));
         ctx->timed_adj = true;
     }
-    pmfmm::AdjReduceArgs r{ctx->leaf.as<int4>(), ctx->leaf_slot.as<int32_t>(), ctx->partial.as<double>(),
-                           ctx->perm.as<int32_t>(), ctx->boxes.as<pmfmm::BoxDev>(), grad_pos, grad_mass,
+    pmfmm::AdjReduceArgs r{ctx->d.leaf.as<int4>(), ctx->d.leaf_slot.as<int32_t>(), ctx->d.partial.as<double>(),
+                           ctx->d.perm.as<int32_t>(), ctx->d.boxes.as<pmfmm::BoxDev>(), grad_pos, grad_mass,
                            (int32_t)pl.leaf_count.size()};
     HIP_TRY(pmfmm::launch_adj_reduce(r, s));
     return PMFMM_OK;

@@ -91,6 +91,11 @@ hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, ui
 hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, uint32_t* tile_sums,
                               hipStream_t s);
 
+// Checks device particles: finite positions, finite non-negative masses.
+// Returns "" or a message naming the first offending particle.
+std::string gpu_check_inputs(DevPlan& d, const double* pos, const double* mass, int64_t n,
+                             hipStream_t s);
+
 // Uploads the tree shape of `topo` (cells, leaves, depth levels) and the
 // per-box constants.
 hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, hipStream_t s);

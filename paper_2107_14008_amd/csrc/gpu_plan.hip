@@ -365,6 +365,20 @@ __global__ void k_items(int nl, const int32_t* __restrict__ row, const int32_t* 
     atomicAdd(cand, total);
 }
 
+__global__ void k_check(const double* __restrict__ pos, const double* __restrict__ mass, int64_t n,
+                        int* __restrict__ bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2], m = mass[i];
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) atomicMin(&bad[0], (int)i);
+    if (!(isfinite(m) && m >= 0.0)) atomicMin(&bad[1], (int)i);
+}
+
+__global__ void k_fill_i32(int* p, int n, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 inline unsigned grid_of(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
 int bits_for(uint64_t maxv) {
@@ -407,6 +421,22 @@ std::string sort_in_place(DevBuf& keys, DevBuf* vals, DevBuf& ktmp, DevBuf* vtmp
 }
 
 }  // namespace
+
+std::string gpu_check_inputs(DevPlan& d, const double* pos, const double* mass, int64_t n,
+                             hipStream_t s) {
+    TRY(d.wcount.ensure(64));
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int*>(d.wcount.p), 2,
+                       0x7fffffff);
+    hipLaunchKernelGGL(k_check, dim3(grid_of(n)), dim3(256), 0, s, pos, mass, n,
+                       reinterpret_cast<int*>(d.wcount.p));
+    TRY(hipGetLastError());
+    int bad[2] = {0, 0};
+    TRY(hipMemcpyAsync(bad, d.wcount.p, 8, hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    if (bad[0] != 0x7fffffff) return "non-finite position at particle " + std::to_string(bad[0]);
+    if (bad[1] != 0x7fffffff) return "negative or non-finite mass at particle " + std::to_string(bad[1]);
+    return std::string();
+}
 
 hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, hipStream_t s) {
     const int64_t nc = (int64_t)topo.cells.size(), nl = (int64_t)topo.leaf_cell.size();

@@ -1,0 +1,121 @@
+"""The on-GPU planner (pmfmm_build with planner = 0) yields the same tree
+and task lists as the oracle's independent builder, bit for bit, and the same
+work items as the host planner."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2107_14008_amd import binding as B
+from paper_2107_14008_amd import inputs
+from test_lists import assert_same, oracle_lists
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_lists(pos, mass, box, r_s, r_cut, max_leaf, order, theta, **kw):
+    ctx = B.Context(box=box, r_s=r_s, r_cut=r_cut, max_leaf=max_leaf,
+                    order=order, theta=theta, planner=0, **kw)
+    ctx.build(torch.tensor(pos, device="cuda"), torch.tensor(mass, device="cuda"))
+    return ctx.lists(), ctx
+
+
+def test_uniform_32k():
+    w = inputs.uniform_32k()
+    print("case: gpu plan uniform 32^3", flush=True)
+    L, _ = gpu_lists(w.pos, w.mass, w.box, w.r_s, w.r_cut, w.max_leaf, -1, 0.0)
+    tree, lists = oracle_lists(w.pos, w.box, w.r_cut, w.max_leaf, -1, 0.0)
+    assert_same(L, tree, lists)
+
+
+@pytest.mark.parametrize("theta", [0.25, 0.5])
+def test_clustered_with_far_field(theta):
+    w = inputs.clustered_small(20, 41, halo_frac=0.4, n_halos=5, max_leaf=24)
+    print(f"case: gpu plan clustered 20^3 theta {theta}", flush=True)
+    L, _ = gpu_lists(w.pos, w.mass, w.box, w.r_s, w.r_cut, 24, 4, theta)
+    tree, lists = oracle_lists(w.pos, w.box, w.r_cut, 24, 4, theta)
+    assert len(lists.m2l) > 0
+    assert_same(L, tree, lists)
+
+
+@pytest.mark.parametrize("n,max_leaf", [(1, 8), (2, 1), (7, 8), (9, 8),
+                                        (1000, 1), (1001, 64), (4095, 33)])
+def test_ragged_sizes(n, max_leaf):
+    rng = np.random.default_rng(n)
+    pos = rng.uniform(0, 20.0, (n, 3))
+    m = rng.uniform(0.1, 1.0, n)
+    print(f"case: gpu plan ragged n={n} leaf={max_leaf}", flush=True)
+    L, _ = gpu_lists(pos, m, 20.0, 0.6, 2.7, max_leaf, 3, 0.4)
+    tree, lists = oracle_lists(pos, 20.0, 2.7, max_leaf, 3, 0.4)
+    assert_same(L, tree, lists)
+
+
+def test_ties_duplicates_and_unwrapped():
+    rng = np.random.default_rng(5)
+    g = np.arange(8) * 2.5
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    pos = np.concatenate([pos, pos[:40], rng.uniform(0, 20, (30, 3))])
+    m = np.ones(len(pos))
+    shifted = pos + rng.integers(-1, 2, pos.shape) * 20.0
+    print("case: gpu plan ties/duplicates", flush=True)
+    L, _ = gpu_lists(shifted, m, 20.0, 0.7, 3.15, 8, 4, 0.5)
+    tree, lists = oracle_lists(pos, 20.0, 3.15, 8, 4, 0.5)
+    assert_same(L, tree, lists)
+
+
+def test_matches_host_planner_clustered_2m_items():
+    w = inputs.clustered_2m()
+    print("case: gpu plan vs host plan 128^3", flush=True)
+    L, ctx = gpu_lists(w.pos, w.mass, w.box, w.r_s, w.r_cut, 64, 4, 0.25)
+    host = B.Context(box=w.box, r_s=w.r_s, r_cut=w.r_cut, max_leaf=64,
+                     order=4, theta=0.25)
+    host.plan(w.pos, w.mass)
+    H = host.lists()
+    for k in ("perm", "cell_lo", "cell_hi", "p2p_row", "p2p_j", "p2p_shift",
+              "m2l_row", "m2l_src", "m2l_shift", "leaf_first", "leaf_count"):
+        assert np.array_equal(L[k], H[k]), k
+    for k in ("n_p2p", "n_m2l", "n_items", "candidate_pairs"):
+        assert L[k] == H[k], k
+
+
+def test_batch_matches_per_box():
+    boxes = [inputs.clustered_small(n, 100 + n, max_leaf=32, order=-1)
+             for n in (12, 16, 14)]
+    ctx = B.Context(planner=0)
+    per_box = [B.make_params(box=w.box, r_s=w.r_s, r_cut=w.r_cut,
+                             max_leaf=w.max_leaf, order=-1, theta=0.0)
+               for w in boxes]
+    counts = [len(w.mass) for w in boxes]
+    pos = torch.tensor(np.concatenate([w.pos for w in boxes]), device="cuda")
+    mass = torch.tensor(np.concatenate([w.mass for w in boxes]), device="cuda")
+    print("case: gpu plan batch of 3", flush=True)
+    ctx.build_batch(per_box, counts, pos, mass)
+    L = ctx.lists()
+    host = B.Context()
+    host.plan_batch(per_box, counts, pos.cpu().numpy(), mass.cpu().numpy())
+    H = host.lists()
+    for k in ("perm", "cell_lo", "cell_hi", "p2p_row", "p2p_j", "p2p_shift",
+              "cell_child", "leaf_first"):
+        assert np.array_equal(L[k], H[k]), k
+
+
+def test_rebuild_reuses_shape_and_rejects_bad_input():
+    rng = np.random.default_rng(8)
+    pos = rng.uniform(0, 20.0, (3000, 3))
+    m = np.ones(3000)
+    ctx = B.Context(box=20.0, r_s=0.6, r_cut=2.7, max_leaf=16, order=-1)
+    for k in range(3):
+        p = pos + 0.01 * k
+        ctx.build(torch.tensor(p, device="cuda"), torch.tensor(m, device="cuda"))
+        L = ctx.lists()
+        tree, lists = oracle_lists(inputs.wrap(p, 20.0), 20.0, 2.7, 16, -1, 0.0)
+        assert np.array_equal(L["p2p_j"], lists.p2p[:, 1])
+    bad = pos.copy()
+    bad[17, 2] = np.inf
+    with pytest.raises(B.PmfmmError, match="particle 17"):
+        ctx.build(torch.tensor(bad, device="cuda"), torch.tensor(m, device="cuda"))
+    mm = m.copy()
+    mm[5] = -1.0
+    with pytest.raises(B.PmfmmError, match="mass"):
+        ctx.build(torch.tensor(pos, device="cuda"), torch.tensor(mm, device="cuda"))

@@ -262,6 +262,8 @@ std::vector<pmfmm::BoxDev> box_table(const pmfmm_ctx* ctx) {
     return out;
 }
 
+int prepare_far(pmfmm_ctx* ctx, hipStream_t s);
+
 int do_upload(pmfmm_ctx* ctx, const double* pos, const double* mass, int32_t on_device, hipStream_t s) {
     const pmfmm::Plan& pl = ctx->plan;
     HIP_TRY(hipGetDevice(&ctx->device));
@@ -333,6 +335,7 @@ int do_upload(pmfmm_ctx* ctx, const double* pos, const double* mass, int32_t on_
         HIP_TRY(ctx->d.M.ensure((size_t)nc * nco * sizeof(double)));
         HIP_TRY(ctx->d.Lc.ensure((size_t)nc * nco * sizeof(double)));
         HIP_TRY(ctx->d.far.ensure((size_t)n * 3 * sizeof(double)));
+        if ((rc = prepare_far(ctx, s))) return rc;
     }
     HIP_TRY(hipStreamSynchronize(s));
     ctx->built = true;
@@ -343,7 +346,7 @@ int default_wg_waves(int mode) {
     return mode == pmfmm::kFP64Table ? 16 : 4;
 }
 
-int run_far(pmfmm_ctx* ctx, hipStream_t s) {
+pmfmm::FarArgs far_args(pmfmm_ctx* ctx) {
     const pmfmm::Plan& pl = ctx->plan;
     const int64_t nc = (int64_t)pl.cells.size();
     pmfmm::FarArgs f{};
@@ -360,11 +363,26 @@ int run_far(pmfmm_ctx* ctx, hipStream_t s) {
     f.M = ctx->d.M.as<double>();
     f.Lc = ctx->d.Lc.as<double>();
     f.far = ctx->d.far.as<double>();
+    f.needM = ctx->d.farflag.as<int32_t>();
+    f.needL = ctx->d.farflag.as<int32_t>() + 2 * nc;
     f.n_cells = (int32_t)nc;
     f.n_leaves = (int32_t)pl.leaf_count.size();
     f.order = pl.max_order;
     f.ncoef = pmfmm::n_coef(pl.max_order);
-    HIP_TRY(pmfmm::launch_zero_f64(f.M, nc * f.ncoef, s));
+    return f;
+}
+
+// Per-plan marks of the cells the far field touches.
+int prepare_far(pmfmm_ctx* ctx, hipStream_t s) {
+    const int64_t nc = (int64_t)ctx->plan.cells.size();
+    HIP_TRY(ctx->d.farflag.ensure((size_t)4 * nc * sizeof(int32_t)));
+    HIP_TRY(pmfmm::launch_far_flags(far_args(ctx), s));
+    return PMFMM_OK;
+}
+
+int run_far(pmfmm_ctx* ctx, hipStream_t s) {
+    const pmfmm::Plan& pl = ctx->plan;
+    pmfmm::FarArgs f = far_args(ctx);
     HIP_TRY(pmfmm::launch_p2m(f, s));
     const int nd = (int)pl.depth_begin.size() - 1;
     for (int d = nd - 2; d >= 0; --d) {   // parents of the deepest level first
@@ -459,6 +477,7 @@ int gpu_build(pmfmm_ctx* ctx, const std::vector<pmfmm::BoxParams>& boxes, const 
         HIP_TRY(ctx->d.M.ensure((size_t)nc * nco * sizeof(double)));
         HIP_TRY(ctx->d.Lc.ensure((size_t)nc * nco * sizeof(double)));
         HIP_TRY(ctx->d.far.ensure((size_t)n * 3 * sizeof(double)));
+        if ((rc = prepare_far(ctx, s))) return rc;
     }
     ctx->table_dirty = true;
     if ((rc = upload_table(ctx, s))) return rc;

@@ -87,6 +87,8 @@ struct FarArgs {
     double* M;                  // (n_cells, ncoef)
     double* Lc;                 // (n_cells, ncoef)
     double* far;                // (n, 3) leaf order
+    int32_t* needM;             // per cell: multipole needed (M2L source subtree)
+    int32_t* needL;             // per cell: local expansion needed (M2L target subtree)
     int32_t n_cells, n_leaves, order, ncoef;
 };
 
@@ -139,6 +141,9 @@ hipError_t launch_m2l(const FarArgs& a, hipStream_t s);
 hipError_t launch_l2l_level(const FarArgs& a, hipStream_t s);
 hipError_t launch_l2p(const FarArgs& a, hipStream_t s);
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t s);
+// Marks the cells whose expansions the far field needs (sources and targets
+// of M2L tasks and their subtrees).
+hipError_t launch_far_flags(const FarArgs& a, hipStream_t s);
 
 // Occupancy helpers: max resident workgroups per CU of the P2P kernel.
 int p2p_blocks_per_cu(int mode, int wg_waves, size_t lds_bytes);

@@ -101,10 +101,11 @@ __device__ double d_entry(int a, int b, int c, const double R[3], const double* 
 __global__ void __launch_bounds__(64)
 p2m_kernel(const double4* __restrict__ x64, const int4* __restrict__ leaf,
            const double4* __restrict__ cellc, const BoxDev* __restrict__ boxes,
-           double* __restrict__ M, int n_leaves, int ncoef) {
+           const int32_t* __restrict__ needM, double* __restrict__ M, int n_leaves, int ncoef) {
     const int l = blockIdx.x;
     if (l >= n_leaves) return;
     const int4 li = leaf[l];
+    if (!needM[li.w]) return;
     const int p = boxes[li.z].order;
     if (p < 0) return;
     const int nc = ncoef_of(p);
@@ -125,10 +126,11 @@ p2m_kernel(const double4* __restrict__ x64, const int4* __restrict__ leaf,
 __global__ void __launch_bounds__(64)
 m2m_kernel(const int32_t* __restrict__ level_cells, int n_level, const int4* __restrict__ cell,
            const int4* __restrict__ aux, const double4* __restrict__ cellc,
-           const BoxDev* __restrict__ boxes, double* __restrict__ M, int ncoef) {
+           const BoxDev* __restrict__ boxes, const int32_t* __restrict__ needM,
+           double* __restrict__ M, int ncoef) {
     if ((int)blockIdx.x >= n_level) return;
     const int P = level_cells[blockIdx.x];
-    if (cell[P].w >= 0) return;                       // leaf: P2M already did it
+    if (cell[P].w >= 0 || !needM[P]) return;          // leaf: P2M already did it
     const int4 ax = aux[P];
     const int p = boxes[ax.z].order;
     if (p < 0) return;
@@ -161,10 +163,12 @@ __global__ void __launch_bounds__(64)
 m2l_kernel(const int32_t* __restrict__ row, const int32_t* __restrict__ src,
            const int32_t* __restrict__ shift, const int4* __restrict__ aux,
            const double4* __restrict__ cellc, const BoxDev* __restrict__ boxes,
-           const double* __restrict__ M, double* __restrict__ Lc, int n_cells, int ncoef) {
+           const int32_t* __restrict__ needL, const double* __restrict__ M,
+           double* __restrict__ Lc, int n_cells, int ncoef) {
     __shared__ double Dsh[kMaxNC];
     const int t = blockIdx.x;
     if (t >= n_cells) return;
+    if (!needL[t]) return;
     const int r0 = row[t], r1 = row[t + 1];
     const int lane = threadIdx.x;
     if (r0 == r1) {
@@ -211,11 +215,12 @@ m2l_kernel(const int32_t* __restrict__ row, const int32_t* __restrict__ src,
 __global__ void __launch_bounds__(64)
 l2l_kernel(const int32_t* __restrict__ level_cells, int n_level, const int4* __restrict__ cell,
            const int4* __restrict__ aux, const double4* __restrict__ cellc,
-           const BoxDev* __restrict__ boxes, double* __restrict__ Lc, int ncoef) {
+           const BoxDev* __restrict__ boxes, const int32_t* __restrict__ needL,
+           double* __restrict__ Lc, int ncoef) {
     if ((int)blockIdx.x >= n_level) return;
     const int C = level_cells[blockIdx.x];
     const int P = cell[C].z;
-    if (P < 0) return;
+    if (P < 0 || !needL[C] || !needL[P]) return;
     const int p = boxes[aux[C].z].order;
     if (p < 0) return;
     const int nc = ncoef_of(p);
@@ -243,7 +248,8 @@ l2l_kernel(const int32_t* __restrict__ level_cells, int n_level, const int4* __r
 __global__ void __launch_bounds__(64)
 l2p_kernel(const double4* __restrict__ x64, const int4* __restrict__ leaf,
            const double4* __restrict__ cellc, const BoxDev* __restrict__ boxes,
-           const double* __restrict__ Lc, double* __restrict__ far, int n_leaves, int ncoef) {
+           const int32_t* __restrict__ needL, const double* __restrict__ Lc,
+           double* __restrict__ far, int n_leaves, int ncoef) {
     const int l = blockIdx.x;
     if (l >= n_leaves) return;
     const int4 li = leaf[l];
@@ -252,7 +258,7 @@ l2p_kernel(const double4* __restrict__ x64, const int4* __restrict__ leaf,
     const int k = li.x + lane;
     const int p = boxes[li.z].order;
     double ax = 0.0, ay = 0.0, az = 0.0;
-    if (p >= 0) {
+    if (p >= 0 && needL[li.w]) {
         const int nc = ncoef_of(p);
         const double4 c = cellc[li.w];
         const double4 q = x64[k];
@@ -276,6 +282,39 @@ l2p_kernel(const double4* __restrict__ x64, const int4* __restrict__ leaf,
     far[3 * (size_t)k + 2] = az;
 }
 
+// Sources and targets of M2L rows.
+__global__ void far_mark_kernel(const int32_t* __restrict__ row, const int32_t* __restrict__ src,
+                                int n_cells, int32_t* __restrict__ needM,
+                                int32_t* __restrict__ needL) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    const int r0 = row[c], r1 = row[c + 1];
+    if (r0 == r1) return;
+    needL[c] = 1;
+    for (int q = r0; q < r1; ++q) needM[src[q]] = 1;
+}
+
+// A cell needs an expansion when it or an ancestor was marked.
+__global__ void far_spread_kernel(const int4* __restrict__ cell, int n_cells,
+                                  const int32_t* __restrict__ markM,
+                                  const int32_t* __restrict__ markL, int32_t* __restrict__ needM,
+                                  int32_t* __restrict__ needL) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    int m = 0, l = 0;
+    for (int a = c; a >= 0; a = cell[a].z) {
+        m |= markM[a];
+        l |= markL[a];
+    }
+    needM[c] = m;
+    needL[c] = l;
+}
+
+__global__ void zero_i32_n(int32_t* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 __global__ void zero_f64_kernel(double* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.0;
@@ -291,38 +330,54 @@ hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+// needM / needL hold 2 n_cells ints each: marks first, then the spread flags.
+hipError_t launch_far_flags(const FarArgs& a, hipStream_t s) {
+    const int64_t nc = a.n_cells;
+    int32_t* markM = a.needM + nc;
+    int32_t* markL = a.needL + nc;
+    const unsigned g = (unsigned)((nc + 255) / 256);
+    hipLaunchKernelGGL(zero_i32_n, dim3(g), dim3(256), 0, s, markM, nc);
+    hipLaunchKernelGGL(zero_i32_n, dim3(g), dim3(256), 0, s, markL, nc);
+    hipLaunchKernelGGL(far_mark_kernel, dim3(g), dim3(256), 0, s, a.m2l_row, a.m2l_src, (int)nc, markM,
+                       markL);
+    hipLaunchKernelGGL(far_spread_kernel, dim3(g), dim3(256), 0, s, a.cell, (int)nc, markM, markL,
+                       a.needM, a.needL);
+    return hipGetLastError();
+}
+
 hipError_t launch_p2m(const FarArgs& a, hipStream_t s) {
     if (a.n_leaves == 0) return hipSuccess;
     hipLaunchKernelGGL(p2m_kernel, dim3(a.n_leaves), dim3(64), 0, s, a.x64, a.leaf, a.cellc,
-                       a.boxes, a.M, a.n_leaves, a.ncoef);
+                       a.boxes, a.needM, a.M, a.n_leaves, a.ncoef);
     return hipGetLastError();
 }
 
 hipError_t launch_m2m_level(const FarArgs& a, hipStream_t s) {
     if (a.n_level == 0) return hipSuccess;
     hipLaunchKernelGGL(m2m_kernel, dim3(a.n_level), dim3(64), 0, s, a.level_cells, a.n_level,
-                       a.cell, a.cell_aux, a.cellc, a.boxes, a.M, a.ncoef);
+                       a.cell, a.cell_aux, a.cellc, a.boxes, a.needM, a.M, a.ncoef);
     return hipGetLastError();
 }
 
 hipError_t launch_m2l(const FarArgs& a, hipStream_t s) {
     if (a.n_cells == 0) return hipSuccess;
     hipLaunchKernelGGL(m2l_kernel, dim3(a.n_cells), dim3(64), 0, s, a.m2l_row, a.m2l_src,
-                       a.m2l_shift, a.cell_aux, a.cellc, a.boxes, a.M, a.Lc, a.n_cells, a.ncoef);
+                       a.m2l_shift, a.cell_aux, a.cellc, a.boxes, a.needL, a.M, a.Lc, a.n_cells,
+                       a.ncoef);
     return hipGetLastError();
 }
 
 hipError_t launch_l2l_level(const FarArgs& a, hipStream_t s) {
     if (a.n_level == 0) return hipSuccess;
     hipLaunchKernelGGL(l2l_kernel, dim3(a.n_level), dim3(64), 0, s, a.level_cells, a.n_level,
-                       a.cell, a.cell_aux, a.cellc, a.boxes, a.Lc, a.ncoef);
+                       a.cell, a.cell_aux, a.cellc, a.boxes, a.needL, a.Lc, a.ncoef);
     return hipGetLastError();
 }
 
 hipError_t launch_l2p(const FarArgs& a, hipStream_t s) {
     if (a.n_leaves == 0) return hipSuccess;
     hipLaunchKernelGGL(l2p_kernel, dim3(a.n_leaves), dim3(64), 0, s, a.x64, a.leaf, a.cellc,
-                       a.boxes, a.Lc, a.far, a.n_leaves, a.ncoef);
+                       a.boxes, a.needL, a.Lc, a.far, a.n_leaves, a.ncoef);
     return hipGetLastError();
 }
 

@@ -63,7 +63,7 @@ struct DevPlan {
     DevBuf p2p_row, wpos, keys, keys_tmp, plist, plist_tmp, hist, flag, fsc, fsc_out, tile_sums;
     DevBuf pc, pc_tmp, clo, chi, chs, box_first, walkbox, front, front_next, p2p_keys,
         p2p_keys_tmp, m2l_keys, m2l_keys_tmp, wcount, cost, cost_keys, cost_keys_tmp, queue_tmp,
-        item_count, cell_axis;
+        item_count, cell_axis, farflag;
 
     void release_all() {
         for (DevBuf* b : {&perm, &leaf, &leafc, &js, &items, &queue, &leaf_slot, &partial, &counter,
@@ -73,7 +73,7 @@ struct DevPlan {
                           &flag, &fsc, &fsc_out, &tile_sums, &pc, &pc_tmp, &clo, &chi, &chs,
                           &box_first, &walkbox, &front, &front_next, &p2p_keys, &p2p_keys_tmp,
                           &m2l_keys, &m2l_keys_tmp, &wcount, &cost, &cost_keys, &cost_keys_tmp,
-                          &queue_tmp, &item_count, &cell_axis})
+                          &queue_tmp, &item_count, &cell_axis, &farflag})
             b->release();
     }
 };

@@ -60,7 +60,9 @@ def test_ties_duplicates_and_unwrapped():
     shifted = pos + rng.integers(-1, 2, pos.shape) * 20.0
     print("case: gpu plan ties/duplicates", flush=True)
     L, _ = gpu_lists(shifted, m, 20.0, 0.7, 3.15, 8, 4, 0.5)
-    tree, lists = oracle_lists(pos, 20.0, 3.15, 8, 4, 0.5)
+    # the oracle sees the same wrapped coordinates (x + 20 - 20 can differ
+    # from x in the last bit)
+    tree, lists = oracle_lists(inputs.wrap(shifted, 20.0), 20.0, 3.15, 8, 4, 0.5)
     assert_same(L, tree, lists)
 
 

@@ -98,12 +98,43 @@ std::vector<unsigned char> build_table(const pmfmm_params& p) {
     }
     std::vector<unsigned char> out;
     if (p.precision == PMFMM_FP32) {
-        out.resize((size_t)20 * n + 16);
+        // one node past x = 3; for the nearest node the polynomial is
+        // re-expanded in e' = e + 1/2 in [0, 1):  c'_j = sum_k c_k C(k,j) (-1/2)^(k-j)
+        const int m = n + 1;
+        std::vector<double> a(5 * (size_t)m);
+        for (int i = 0; i < m; ++i) {
+            const double x = i * h, x2 = x * x;
+            const double E = -4.0 * std::exp(-x2) * inv_sqrt_pi;
+            const double b[5] = {std::erfc(x) - x * E / 2.0, x2 * E, -x * (x2 - 1.0) * E,
+                                 ((2.0 / 3.0) * x2 * x2 - (5.0 / 3.0) * x2 + 1.0 / 3.0) * E,
+                                 -x * ((1.0 / 3.0) * x2 * x2 - 1.5 * x2 + 1.0) * E};
+            double hk = 1.0;
+            double ck[5];
+            for (int k = 0; k < 5; ++k) {
+                ck[k] = b[k] * hk;
+                hk *= h;
+            }
+            const int level = p.table_level;
+            for (int k = level + 1; k < 5; ++k) ck[k] = 0.0;   // truncate before shifting
+            if (p.table_round == PMFMM_ROUND_NEAREST) {
+                static const double binom[5][5] = {{1, 0, 0, 0, 0}, {1, 1, 0, 0, 0}, {1, 2, 1, 0, 0},
+                                                   {1, 3, 3, 1, 0}, {1, 4, 6, 4, 1}};
+                double sh[5];
+                for (int j = 0; j < 5; ++j) {
+                    double acc = 0.0;
+                    for (int k = j; k < 5; ++k) acc += ck[k] * binom[k][j] * std::pow(-0.5, k - j);
+                    sh[j] = acc;
+                }
+                for (int k = 0; k < 5; ++k) ck[k] = sh[k];
+            }
+            for (int k = 0; k < 5; ++k) a[5 * (size_t)i + k] = ck[k];
+        }
+        out.resize((size_t)20 * m + 16);
         float* f4 = reinterpret_cast<float*>(out.data());
-        float* f1 = reinterpret_cast<float*>(out.data() + 16 * (size_t)n);
-        for (int i = 0; i < n; ++i) {
-            for (int k = 0; k < 4; ++k) f4[4 * i + k] = (float)c[k][i];
-            f1[i] = (float)c[4][i];
+        float* f1 = reinterpret_cast<float*>(out.data() + 16 * (size_t)m);
+        for (int i = 0; i < m; ++i) {
+            for (int k = 0; k < 4; ++k) f4[4 * i + k] = (float)a[5 * (size_t)i + k];
+            f1[i] = (float)a[5 * (size_t)i + 4];
         }
     } else {
         out.resize((size_t)40 * n + 16);
@@ -639,7 +670,8 @@ int pmfmm_set_eval(pmfmm_ctx* ctx, const pmfmm_params* p) {
     if (p->trunc == PMFMM_TRUNC_TABLE && ctx->planned)
         for (const auto& b : ctx->plan.boxes)
             if (b.r_cut / (2.0 * b.r_s) > 3.0) return fail(PMFMM_EINVAL, "the table covers r <= 6 r_s only");
-    const bool table_change = p->precision != ctx->p.precision || p->table_size != ctx->p.table_size;
+    const bool table_change = p->precision != ctx->p.precision || p->table_size != ctx->p.table_size ||
+                              p->table_round != ctx->p.table_round || p->table_level != ctx->p.table_level;
     const bool chunk_change = p->chunk != ctx->p.chunk;
     ctx->p.precision = p->precision;
     ctx->p.trunc = p->trunc;

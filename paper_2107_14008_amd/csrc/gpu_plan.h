@@ -85,6 +85,8 @@ struct PlanCounts {
 
 // Sort / scan primitives (gpu_sort.hip).
 int64_t sort_tiles(int64_t n);
+// 32-bit words of the `hist` scratch radix_sort_u64 needs for n keys.
+int64_t sort_hist_words(int64_t n);
 hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals,
                           uint32_t* hist, int64_t n, int bit_begin, int bit_end, hipStream_t s,
                           bool* result_in_tmp);

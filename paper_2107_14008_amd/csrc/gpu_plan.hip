@@ -18,6 +18,9 @@
 // atomic per wavefront.  The keys (i << 32 | j << 5 | shift) are then sorted,
 // which yields the canonical (i, j, shift) order and the CSR rows.
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "gpu_plan.h"
@@ -408,7 +411,7 @@ std::string sort_in_place(DevBuf& keys, DevBuf* vals, DevBuf& ktmp, DevBuf* vtmp
     bit_end = std::min(64, (bit_end + 7) / 8 * 8);
     TRY(ktmp.ensure(n * 8));
     if (vals) TRY(vtmp->ensure(n * 4));
-    TRY(hist.ensure((size_t)256 * sort_tiles(n) * 4));
+    TRY(hist.ensure((size_t)sort_hist_words(n) * 4));
     bool in_tmp = false;
     TRY(radix_sort_u64(keys.as<uint64_t>(), vals ? vals->as<uint32_t>() : nullptr, ktmp.as<uint64_t>(),
                        vtmp ? vtmp->as<uint32_t>() : nullptr, hist.as<uint32_t>(), n, 0, bit_end, s,
@@ -419,6 +422,23 @@ std::string sort_in_place(DevBuf& keys, DevBuf* vals, DevBuf& ktmp, DevBuf* vtmp
     }
     return std::string();
 }
+
+// Wall-clock phases of the device planner, printed to stderr when the
+// environment variable PMFMM_PLAN_TIMING is set (synchronises each phase).
+struct PhaseTimer {
+    bool on = std::getenv("PMFMM_PLAN_TIMING") != nullptr;
+    hipStream_t s;
+    std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    explicit PhaseTimer(hipStream_t st) : s(st) {}
+    void lap(const char* what) {
+        if (!on) return;
+        (void)hipStreamSynchronize(s);
+        auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[pmfmm gpu plan] %-10s %8.3f ms\n", what,
+                     std::chrono::duration<double, std::milli>(now - t).count());
+        t = now;
+    }
+};
 
 }  // namespace
 
@@ -492,6 +512,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     const int nbox = (int)topo.boxes.size();
     const int64_t nc = (int64_t)topo.cells.size(), nl = (int64_t)topo.leaf_cell.size();
     const int nd = (int)topo.depth_begin.size() - 1;
+    PhaseTimer clk(s);
 
     // ---- wrap, sort each axis by (coordinate, caller index)
     TRY(d.wpos.ensure(n * 24));
@@ -503,7 +524,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                        d.box_first.as<int32_t>(), nbox, d.boxes.as<BoxDev>(), d.wpos.as<double>(),
                        d.keys.as<uint64_t>(), d.plist.as<uint32_t>());
     TRY(hipGetLastError());
-    TRY(d.hist.ensure((size_t)256 * sort_tiles(n) * 4 + 16));
+    TRY(d.hist.ensure((size_t)sort_hist_words(n) * 4));
     for (int a = 0; a < 3; ++a) {
         uint64_t* k = d.keys.as<uint64_t>() + a * n;
         uint32_t* v = d.plist.as<uint32_t>() + a * n;
@@ -527,6 +548,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         }
     }
 
+    clk.lap("sort");
     // ---- ORB levels
     TRY(d.pc.ensure(n * 4));
     TRY(d.pc_tmp.ensure(n * 4));
@@ -567,6 +589,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         std::swap(d.pc, d.pc_tmp);
     }
 
+    clk.lap("levels");
     // ---- leaf order, geometry, particle records
     TRY(d.perm.ensure(n * 4));
     TRY(d.leafc.ensure(nl * 32));
@@ -584,6 +607,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                  d.boxes.as<BoxDev>(), d.x64.as<double4>(), d.x32.as<float4>(), (int32_t)nl};
     TRY(launch_gather(g, nullptr, s));
 
+    clk.lap("records");
     // ---- dual walk
     TRY(d.wcount.ensure(64));
     int64_t nf = 27 * (int64_t)nbox;
@@ -624,6 +648,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         std::swap(d.front, d.front_next);
     }
 
+    clk.lap("walk");
     // ---- canonical order and CSR
     const int p2p_bits = 32 + bits_for((uint64_t)std::max<int64_t>(1, nl - 1));
     std::string err = sort_in_place(d.p2p_keys, nullptr, d.p2p_keys_tmp, nullptr, d.hist, n_p2p,
@@ -652,7 +677,10 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     TRY(hipGetLastError());
     out.n_p2p = n_p2p;
     out.n_m2l = n_m2l;
-    return gpu_make_items(d, topo, n_p2p, chunk, s, out);
+    clk.lap("csr");
+    std::string e2 = gpu_make_items(d, topo, n_p2p, chunk, s, out);
+    clk.lap("items");
+    return e2;
 }
 
 std::string gpu_make_items(DevPlan& d, const Plan& topo, int64_t n_p2p, int chunk, hipStream_t s,

@@ -154,7 +154,15 @@ scan_tile_apply(const int32_t* __restrict__ in, int32_t* __restrict__ out, int64
 
 }  // namespace
 
+hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, uint32_t* tile_sums,
+                              hipStream_t s);
+
 int64_t sort_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
+
+int64_t sort_hist_words(int64_t n) {
+    const int64_t m = 256 * sort_tiles(n);
+    return 2 * m + sort_tiles(m) + 16;
+}
 
 hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals,
                           uint32_t* hist, int64_t n, int bit_begin, int bit_end, hipStream_t s,
@@ -166,15 +174,21 @@ hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, ui
     uint64_t* kb = tmp_keys;
     uint32_t* va = vals;
     uint32_t* vb = tmp_vals;
+    // scratch layout: counts [m], their exclusive scan [m], tile sums
+    const int64_t m = (int64_t)256 * tiles;
+    uint32_t* offs = hist + m;
+    uint32_t* scan_scratch = hist + 2 * m;
     for (int shift = bit_begin; shift < bit_end; shift += 8) {
         hipLaunchKernelGGL(rs_hist, dim3(tiles), dim3(kThreads), 0, s, ka, n, shift, hist, tiles);
-        hipLaunchKernelGGL(scan_single, dim3(1), dim3(1024), 0, s, hist, (int64_t)256 * tiles);
+        const hipError_t e = exclusive_scan_i32(reinterpret_cast<const int32_t*>(hist),
+                                                reinterpret_cast<int32_t*>(offs), m, scan_scratch, s);
+        if (e != hipSuccess) return e;
         if (vals)
             hipLaunchKernelGGL(rs_scatter<true>, dim3(tiles), dim3(kThreads), 0, s, ka, va, kb, vb, n,
-                               shift, hist, tiles);
+                               shift, offs, tiles);
         else
             hipLaunchKernelGGL(rs_scatter<false>, dim3(tiles), dim3(kThreads), 0, s, ka, va, kb, vb, n,
-                               shift, hist, tiles);
+                               shift, offs, tiles);
         std::swap(ka, kb);
         std::swap(va, vb);
         *result_in_tmp = !*result_in_tmp;

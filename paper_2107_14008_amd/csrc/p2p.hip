@@ -126,16 +126,22 @@ __device__ __forceinline__ void pair_f64_table(const double4 q, double xi, doubl
 }
 
 // float32 on cell-relative offsets: (px, py, pz) = target offset minus the
-// source leaf's offset, so d = q.xyz - p.
+// source leaf's offset, so d = q.xyz - p.  r^2 is clamped into
+// [kTinyR2, r_cut^2] before 1/r: pairs outside the cutoff are masked out
+// anyway, the clamp keeps the table index in range, and a coincident pair
+// (d = 0) then contributes g * 0 = 0 with a finite g, which is what the
+// r^2 > 0 test of the definition gives.
+constexpr float kTinyR2 = 1e-20f;
+
 __device__ __forceinline__ void pair_f32_exact(const float4 q, float px, float py, float pz,
                                                float rc2, float alpha, float& ax, float& ay,
                                                float& az) {
     const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    const bool ok = (r2 > 0.f) & (r2 < rc2);
-    const float r2s = ok ? r2 : 1.f;
-    const float idr = rsqrtf(r2s);
-    const float x = r2s * idr * alpha;
+    const bool ok = r2 < rc2;
+    const float r2c = __builtin_amdgcn_fmed3f(r2, kTinyR2, rc2);
+    const float idr = __builtin_amdgcn_rsqf(r2c);
+    const float x = r2c * idr * alpha;
     const float T = erfcf(x) + kTwoOverSqrtPiF * x * expf(-x * x);
     const float g = ok ? q.w * T * (idr * idr * idr) : 0.f;
     ax = fmaf(g, dx, ax);
@@ -143,21 +149,25 @@ __device__ __forceinline__ void pair_f32_exact(const float4 q, float px, float p
     az = fmaf(g, dz, az);
 }
 
+// Table form: u = x n_tab / 3 + rnd with rnd = 1/2 (nearest node) or 0
+// (node below); node d = floor(u), offset e = frac(u) in [0, 1).  The host
+// stores each node's Eq. (int) polynomial re-expanded in e (for the nearest
+// node it is centred at u = d + 1/2), so no clamp or float conversion of d
+// is needed; the table carries one node past x = 3.
 template <int LEVEL>
 __device__ __forceinline__ void pair_f32_table(const float4 q, float px, float py, float pz,
-                                               float rc2, float scale, float rnd, int dmax,
+                                               float rc2, float scale, float rnd,
                                                const float4* __restrict__ t03,
                                                const float* __restrict__ t4, float& ax, float& ay,
                                                float& az) {
     const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    const bool ok = (r2 > 0.f) & (r2 < rc2);
-    const float r2s = ok ? r2 : 1.f;
-    const float idr = rsqrtf(r2s);
-    const float u = r2s * idr * scale;
-    int d = (int)(u + rnd);
-    d = min(d, dmax);
-    const float e = u - (float)d;
+    const bool ok = r2 < rc2;
+    const float r2c = __builtin_amdgcn_fmed3f(r2, kTinyR2, rc2);
+    const float idr = __builtin_amdgcn_rsqf(r2c);
+    const float u = fmaf(r2c * idr, scale, rnd);
+    const int d = (int)u;
+    const float e = __builtin_amdgcn_fractf(u);
     const float4 c = t03[d];
     float T;
     if constexpr (LEVEL == 0) {
@@ -178,7 +188,7 @@ __device__ __forceinline__ void pair_f32_table(const float4 q, float px, float p
 }
 
 // LDS table layouts (bytes), matching the host builder in abi.cpp:
-//   float32: float4 c0..c3 [n_tab], then float c4 [n_tab]
+//   float32: float4 c0..c3 [n_tab + 1], then float c4 [n_tab + 1]
 //   float64: double2 (c0, c1) [n_tab], double2 (c2, c3) [n_tab], double c4 [n_tab]
 __device__ __forceinline__ void load_table(unsigned char* lds, const void* __restrict__ table,
                                            int bytes) {
@@ -223,7 +233,7 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
             const float rc2 = bx.rc2_f;
             const float rnd = round_floor ? 0.f : 0.5f;
             const float4* t03 = reinterpret_cast<const float4*>(lds);
-            const float* t4 = reinterpret_cast<const float*>(lds + 16 * n_tab);
+            const float* t4 = reinterpret_cast<const float*>(lds + 16 * (n_tab + 1));
             for (int t = t0; t < t1; ++t) {
                 const int js = uni(p2p_js[t]);
                 const int jl = js >> 5;
@@ -243,8 +253,8 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                 } else {
 #pragma unroll 4
                     for (int k = 0; k < nj; ++k)
-                        pair_f32_table<LEVEL>(src[k], px, py, pz, rc2, bx.tab_scale_f, rnd, dmax,
-                                              t03, t4, fx, fy, fz);
+                        pair_f32_table<LEVEL>(src[k], px, py, pz, rc2, bx.tab_scale_f, rnd, t03,
+                                              t4, fx, fy, fz);
                 }
                 ax += (double)fx;
                 ay += (double)fy;

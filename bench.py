@@ -46,6 +46,17 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 
 
+def error_summary(acc, ref):
+    """Median / 99.9th percentile / max of |a - a_ref| / |a_ref| per particle."""
+    num = np.linalg.norm(np.asarray(acc) - ref, axis=1)
+    den = np.linalg.norm(ref, axis=1)
+    ok = den > 1e-6 * np.median(den)
+    e = num[ok] / den[ok]
+    return dict(n=int(e.size), median=float(np.quantile(e, 0.5, method="higher")),
+                p999=float(np.quantile(e, 0.999, method="higher")),
+                max=float(e.max()))
+
+
 def measured_traffic(kernel_tag="p2p_fp32_t2_clustered_2m"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the P2P source has changed since the counters were taken."""
@@ -93,6 +104,165 @@ def cpu_baseline(w, cand_per_particle, target_seconds=12.0):
                 seconds=t_used), idx, ref
 
 
+def _timed_steps(ctx, build, out, stream, steps, warmup):
+    """Whole steps (build + forward); returns ms per step and mean phase times."""
+    import torch
+    for _ in range(warmup):
+        build()
+        ctx.forward(out, stream)
+    torch.cuda.synchronize()
+    ph = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        build()
+        ctx.forward(out, stream)
+        ph.append(ctx.timings())
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    return ms, {k: float(np.mean([p[k] for p in ph])) for k in ph[0]}
+
+
+def secondary(args):
+    """The other workloads: 32^3 uniform, 256^3 clustered (exact vs table
+    forms), the 64-box batch with autotuned schedule, and the 64^3 gradient
+    case.  Same JSON keys as the headline line."""
+    import torch
+    from paper_2107_14008_amd import binding as B
+    from paper_2107_14008_amd import tune
+    dev = torch.device("cuda:0")
+    line = {"metric": "short-range pair interactions/s", "unit": "interactions/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic"}
+    if args.config == "batch64":
+        boxes = inputs.batch_64()
+        refs = {}
+        if not args.no_cpu_baseline:       # oracle before the GPU is touched
+            for b in range(0, len(boxes), 16):
+                _, idx, ref = cpu_baseline(boxes[b], 1.0, target_seconds=2.0)
+                refs[b] = (idx, ref)
+        stream = torch.cuda.current_stream(dev)
+        counts = [len(w.mass) for w in boxes]
+        per_box = [B.make_params(box=w.box, r_s=w.r_s, r_cut=w.r_cut,
+                                 max_leaf=w.max_leaf, order=-1, theta=0.0)
+                   for w in boxes]
+        pos = torch.tensor(np.concatenate([w.pos for w in boxes]), device=dev)
+        mass = torch.tensor(np.concatenate([w.mass for w in boxes]), device=dev)
+        n = int(sum(counts))
+        out = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        ctx = B.Context(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
+                        table_size=512, table_level=2, timing=1)
+
+        def build():
+            ctx.build_batch(per_box, counts, pos, mass, stream)
+        build()
+        best, res = tune.autotune(ctx, out, stream, use_cache=False)
+        cand = int(ctx.lists()["candidate_pairs"])
+        ms, ph = _timed_steps(ctx, build, out, stream, args.steps, args.warmup)
+        errs = []
+        acc = out.cpu().numpy()
+        starts = np.concatenate([[0], np.cumsum(counts)])
+        for b, (idx, ref) in refs.items():
+            errs.append(error_summary(acc[starts[b] + idx], ref))
+        line.update(value=cand / (ms / 1e3), ms_per_step=ms,
+                    config={"workload": f"batch64: {len(boxes)} clustered boxes, "
+                            f"N = n_side^3 with n_side log-uniform in [16, 96] "
+                            f"(total {n}), one persistent launch, float32 "
+                            f"512-node T_[2] table", "n": n,
+                            "candidate_pairs_per_step": cand,
+                            "schedule": best, "phases_ms": ph,
+                            "p2p_interactions_per_s": cand / (ph["p2p_ms"] / 1e3),
+                            "tuning_ms": {f"{k[0]},{k[1]},{k[2]}": v
+                                          for k, v in res.items()},
+                            "err_sampled_boxes": errs})
+        return line
+    if args.config == "adjoint262k":
+        w = inputs.clustered_262k()
+        stream = torch.cuda.current_stream(dev)
+        n = len(w.mass)
+        pos = torch.tensor(w.pos, device=dev)
+        mass = torch.tensor(w.mass, device=dev)
+        wv = torch.tensor(inputs.cotangent(n), device=dev)
+        out = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        gp = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        gm = torch.empty((n,), dtype=torch.float64, device=dev)
+        ctx = B.Context(box=w.box, r_s=w.r_s, r_cut=w.r_cut, max_leaf=64,
+                        order=-1, precision=B.PMFMM_FP32, trunc=B.TRUNC_EXACT,
+                        timing=1)
+        ctx.build(pos, mass, stream)
+        cand = int(ctx.lists()["candidate_pairs"])
+        for _ in range(args.warmup):
+            ctx.forward(out, stream)
+            ctx.adjoint(wv, gp, gm, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fw, ad = [], []
+        for _ in range(args.steps):
+            ctx.build(pos, mass, stream)
+            ctx.forward(out, stream)
+            fw.append(ctx.timings()["p2p_ms"])
+            ctx.adjoint(wv, gp, gm, stream)
+            ad.append(ctx.timings()["adjoint_ms"])
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        line.update(value=cand / (ms / 1e3), ms_per_step=ms,
+                    config={"workload": "adjoint262k: 64^3 clustered (Zel'dovich "
+                            "+ 20% Plummer), N_PM=64, float32 exact T, "
+                            "forward + adjoint per step", "n": n,
+                            "candidate_pairs_per_step": cand,
+                            "p2p_ms": float(np.mean(fw)),
+                            "adjoint_ms": float(np.mean(ad))})
+        return line
+    if args.config == "uniform_32k":
+        w = inputs.uniform_32k()
+        forms = {"fp64_exact": dict(precision=B.PMFMM_FP64, trunc=B.TRUNC_EXACT),
+                 "fp32_t2_512": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
+                                     table_size=512, table_level=2)}
+        order, theta = -1, 0.0
+    else:
+        w = inputs.clustered_16m()
+        forms = {"fp32_exact": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_EXACT),
+                 "fp32_t1_2048": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
+                                      table_size=2048, table_level=1),
+                 "fp32_t3_2048": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
+                                      table_size=2048, table_level=3),
+                 "fp32_t2_512": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
+                                     table_size=512, table_level=2)}
+        order, theta = args.order, args.theta
+    n = len(w.mass)
+    res = {}
+    base = idx = ref = None
+    if not args.no_cpu_baseline:           # oracle before the GPU is touched
+        base, idx, ref = cpu_baseline(w, 1.0, target_seconds=6.0)
+    stream = torch.cuda.current_stream(dev)
+    pos = torch.tensor(w.pos, device=dev)
+    mass = torch.tensor(w.mass, device=dev)
+    out = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    cand = None
+    for name, ev in forms.items():
+        ctx = B.Context(box=w.box, r_s=w.r_s, r_cut=w.r_cut, max_leaf=w.max_leaf,
+                        order=order, theta=theta, timing=1, **ev)
+
+        def build():
+            ctx.build(pos, mass, stream)
+        ms, ph = _timed_steps(ctx, build, out, stream, args.steps, args.warmup)
+        cand = int(ctx.lists()["candidate_pairs"])
+        err = error_summary(out.cpu().numpy()[idx], ref) if idx is not None else None
+        res[name] = dict(ms_per_step=ms, phases_ms=ph,
+                         p2p_interactions_per_s=cand / (ph["p2p_ms"] / 1e3),
+                         err=err)
+        ctx.close()
+    first = next(iter(res))
+    if base is not None:
+        base["value"] = base["value"] * cand / n    # candidate pairs per particle
+    line.update(value=cand / (res[first]["ms_per_step"] / 1e3),
+                ms_per_step=res[first]["ms_per_step"],
+                config={"workload": w.name, "n": n, "theta": theta, "order": order,
+                        "candidate_pairs_per_step": cand, "forms": res},
+                cpu_baseline=base)
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +274,11 @@ def main():
     ap.add_argument("--table-size", type=int, default=512)
     ap.add_argument("--table-level", type=int, default=2)
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--config", default="clustered_2m",
+                    choices=["clustered_2m", "clustered_16m", "batch64",
+                             "adjoint262k", "uniform_32k"],
+                    help="clustered_2m is the headline; the others are "
+                         "secondary measurements of the other workloads")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB "
                          "(scale reference for hardware byte counters)")
@@ -112,6 +287,9 @@ def main():
         print("bench.py runs on one GPU only: the multi-GPU decomposition is "
               "designed but not built (see the design notes)", file=sys.stderr)
         sys.exit(2)
+    if args.config != "clustered_2m":
+        print(json.dumps(secondary(args)), flush=True)
+        return
 
     w = inputs.clustered_2m()
     n = len(w.mass)
@@ -130,7 +308,6 @@ def main():
         base, sample_idx, sample_ref = cpu_baseline(w, cand / n)
 
     import torch
-    from oracle import metrics
     dev = torch.device("cuda:0")
     pos = torch.tensor(w.pos, device=dev)
     mass = torch.tensor(w.mass, device=dev)
@@ -179,7 +356,7 @@ def main():
         acc = out.cpu().numpy()
         err = None
         if sample_idx is not None:
-            err = metrics.error_summary(acc[sample_idx], sample_ref)
+            err = error_summary(acc[sample_idx], sample_ref)
         lists = ctx.lists()
         results[name] = dict(
             ms_per_step=1e3 * elapsed / args.steps,

@@ -63,7 +63,10 @@ struct DevPlan {
     DevBuf p2p_row, wpos, keys, keys_tmp, plist, plist_tmp, hist, flag, fsc, fsc_out, tile_sums;
     DevBuf pc, pc_tmp, clo, chi, chs, box_first, walkbox, front, front_next, p2p_keys,
         p2p_keys_tmp, m2l_keys, m2l_keys_tmp, wcount, cost, cost_keys, cost_keys_tmp, queue_tmp,
-        item_count, cell_axis, farflag;
+        item_count, cell_axis, farflag, walk_ctl;
+    // walk sizes seen on the last level-by-level build of this tree shape
+    uint32_t walk_cap_front = 0, walk_cap_p2p = 0, walk_cap_m2l = 0;
+    int walk_levels = 0;
 
     void release_all() {
         for (DevBuf* b : {&perm, &leaf, &leafc, &js, &items, &queue, &leaf_slot, &partial, &counter,
@@ -73,7 +76,7 @@ struct DevPlan {
                           &flag, &fsc, &fsc_out, &tile_sums, &pc, &pc_tmp, &clo, &chi, &chs,
                           &box_first, &walkbox, &front, &front_next, &p2p_keys, &p2p_keys_tmp,
                           &m2l_keys, &m2l_keys_tmp, &wcount, &cost, &cost_keys, &cost_keys_tmp,
-                          &queue_tmp, &item_count, &cell_axis, &farflag})
+                          &queue_tmp, &item_count, &cell_axis, &farflag, &walk_ctl})
             b->release();
     }
 };

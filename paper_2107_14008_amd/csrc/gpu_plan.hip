@@ -222,6 +222,75 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t cnt, uint32_t* counter)
     return base + off;
 }
 
+// Classification of one cell pair (the dual-walk rules of the host planner).
+struct WalkOut {
+    uint32_t n_child, n_p2p, n_m2l;
+    int2 child[4];
+    uint64_t key;
+};
+
+__device__ __forceinline__ void walk_classify(const int2 pr, const WalkBox* __restrict__ wbox,
+                                              const double4* __restrict__ cellc,
+                                              const double4* __restrict__ chs,
+                                              const int4* __restrict__ cell,
+                                              const int4* __restrict__ aux, WalkOut& o) {
+    const int t = pr.x, u = pr.y >> 5, s = pr.y & 31;
+    const int4 at = aux[t], au = aux[u];
+    const WalkBox wb = wbox[at.z];
+    const double4 ct = cellc[t], cu = cellc[u], ht = chs[t], hu = chs[u];
+    const double sL[3] = {(double)(s % 3 - 1) * wb.L, (double)((s / 3) % 3 - 1) * wb.L,
+                          (double)(s / 9 - 1) * wb.L};
+    const double cta[3] = {ct.x, ct.y, ct.z}, cua[3] = {cu.x, cu.y, cu.z};
+    const double hta[3] = {ht.x, ht.y, ht.z}, hua[3] = {hu.x, hu.y, hu.z};
+    double R[3], A[3], H[3], gp[3], gap2, dmax2 = 0.0, R2 = 0.0, lhs = 0.0;
+    {
+#pragma clang fp contract(off)
+        for (int a = 0; a < 3; ++a) {
+            R[a] = (cua[a] - cta[a]) + sL[a];
+            A[a] = fabs(R[a]);
+            H[a] = hta[a] + hua[a];
+            const double g = A[a] - H[a];
+            gp[a] = g > 0.0 ? g : 0.0;
+        }
+        gap2 = (gp[0] * gp[0] + gp[1] * gp[1]) + gp[2] * gp[2];
+        if (wb.use_m2l) {
+            const double d0 = A[0] + H[0], d1 = A[1] + H[1], d2 = A[2] + H[2];
+            dmax2 = (d0 * d0 + d1 * d1) + d2 * d2;
+            R2 = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2];
+            lhs = ct.w + cu.w;
+            lhs = lhs * lhs;
+            R2 = wb.th2 * R2;
+        }
+    }
+    if (!(gap2 < wb.rc2_drop)) return;
+    if (wb.use_m2l && dmax2 < wb.rc2_m2l && lhs < R2) {
+        o.n_m2l = 1;
+        o.key = ((uint64_t)(uint32_t)t << 32) | ((uint64_t)(uint32_t)u << 5) | (uint64_t)s;
+        return;
+    }
+    const int lt = cell[t].w, lu = cell[u].w;
+    const double rt = ct.w, ru = cu.w;
+    if (lt >= 0 && lu >= 0) {
+        o.n_p2p = 1;
+        o.key = ((uint64_t)(uint32_t)lt << 32) | ((uint64_t)(uint32_t)lu << 5) | (uint64_t)s;
+    } else if (lt < 0 && (lu >= 0 || rt > ru)) {
+        o.child[0] = make_int2(at.x, pr.y);
+        o.child[1] = make_int2(at.y, pr.y);
+        o.n_child = 2;
+    } else if (lu < 0 && (lt >= 0 || ru > rt)) {
+        o.child[0] = make_int2(t, (au.x << 5) | s);
+        o.child[1] = make_int2(t, (au.y << 5) | s);
+        o.n_child = 2;
+    } else {
+        o.child[0] = make_int2(at.x, (au.x << 5) | s);
+        o.child[1] = make_int2(at.x, (au.y << 5) | s);
+        o.child[2] = make_int2(at.y, (au.x << 5) | s);
+        o.child[3] = make_int2(at.y, (au.y << 5) | s);
+        o.n_child = 4;
+    }
+}
+
+// One level of the walk, frontier size known on the host.
 __global__ void __launch_bounds__(256)
 k_walk(const int2* __restrict__ front, int nf, int2* __restrict__ next,
        const WalkBox* __restrict__ wbox, const double4* __restrict__ cellc,
@@ -229,73 +298,52 @@ k_walk(const int2* __restrict__ front, int nf, int2* __restrict__ next,
        uint32_t* __restrict__ counters, uint64_t* __restrict__ p2p_keys,
        uint64_t* __restrict__ m2l_keys) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t n_child = 0, n_p2p = 0, n_m2l = 0;
-    int2 child[4];
-    uint64_t key = 0;
-    if (k < nf) {
-        const int2 pr = front[k];
-        const int t = pr.x, u = pr.y >> 5, s = pr.y & 31;
-        const int4 at = aux[t], au = aux[u];
-        const WalkBox wb = wbox[at.z];
-        const double4 ct = cellc[t], cu = cellc[u], ht = chs[t], hu = chs[u];
-        const double sL[3] = {(double)(s % 3 - 1) * wb.L, (double)((s / 3) % 3 - 1) * wb.L,
-                              (double)(s / 9 - 1) * wb.L};
-        const double cta[3] = {ct.x, ct.y, ct.z}, cua[3] = {cu.x, cu.y, cu.z};
-        const double hta[3] = {ht.x, ht.y, ht.z}, hua[3] = {hu.x, hu.y, hu.z};
-        double R[3], A[3], H[3], gp[3], gap2, dmax2 = 0.0, R2 = 0.0, lhs = 0.0;
-        {
-#pragma clang fp contract(off)
-            for (int a = 0; a < 3; ++a) {
-                R[a] = (cua[a] - cta[a]) + sL[a];
-                A[a] = fabs(R[a]);
-                H[a] = hta[a] + hua[a];
-                const double g = A[a] - H[a];
-                gp[a] = g > 0.0 ? g : 0.0;
-            }
-            gap2 = (gp[0] * gp[0] + gp[1] * gp[1]) + gp[2] * gp[2];
-            if (wb.use_m2l) {
-                const double d0 = A[0] + H[0], d1 = A[1] + H[1], d2 = A[2] + H[2];
-                dmax2 = (d0 * d0 + d1 * d1) + d2 * d2;
-                R2 = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2];
-                lhs = ct.w + cu.w;
-                lhs = lhs * lhs;
-                R2 = wb.th2 * R2;
-            }
+    WalkOut o{0u, 0u, 0u, {}, 0ull};
+    if (k < nf) walk_classify(front[k], wbox, cellc, chs, cell, aux, o);
+    const uint32_t cslot = wave_append(o.n_child, &counters[0]);
+    for (uint32_t q = 0; q < o.n_child; ++q) next[cslot + q] = o.child[q];
+    const uint32_t pslot = wave_append(o.n_p2p, &counters[1]);
+    if (o.n_p2p) p2p_keys[pslot] = o.key;
+    const uint32_t mslot = wave_append(o.n_m2l, &counters[2]);
+    if (o.n_m2l) m2l_keys[mslot] = o.key;
+}
+
+// One level of the walk with the frontier size read on the device (no host
+// round trip between levels).  Capacities are checked; an overflow is
+// reported and the host then redoes the walk level by level.
+// ctl: [0] p2p total, [1] m2l total, [2] overflow flag, [3] largest frontier;
+// sizes[it] = frontier size of level it.
+__global__ void __launch_bounds__(256)
+k_walk_dev(const int2* __restrict__ front, int2* __restrict__ next, int it,
+           uint32_t* __restrict__ sizes, uint32_t* __restrict__ ctl, uint32_t cap_front,
+           uint32_t cap_p2p, uint32_t cap_m2l, const WalkBox* __restrict__ wbox,
+           const double4* __restrict__ cellc, const double4* __restrict__ chs,
+           const int4* __restrict__ cell, const int4* __restrict__ aux,
+           uint64_t* __restrict__ p2p_keys, uint64_t* __restrict__ m2l_keys) {
+    const uint32_t nf = sizes[it];
+    if (nf > cap_front) return;
+    const int lane = threadIdx.x & 63;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < nf; base += stride) {
+        const uint32_t k = base + lane;
+        WalkOut o{0u, 0u, 0u, {}, 0ull};
+        if (k < nf) walk_classify(front[k], wbox, cellc, chs, cell, aux, o);
+        const uint32_t cslot = wave_append(o.n_child, &sizes[it + 1]);
+        if (cslot + o.n_child <= cap_front) {
+            for (uint32_t q = 0; q < o.n_child; ++q) next[cslot + q] = o.child[q];
+        } else if (o.n_child) {
+            ctl[2] = 1u;
         }
-        if (gap2 < wb.rc2_drop) {
-            if (wb.use_m2l && dmax2 < wb.rc2_m2l && lhs < R2) {
-                n_m2l = 1;
-                key = ((uint64_t)(uint32_t)t << 32) | ((uint64_t)(uint32_t)u << 5) | (uint64_t)s;
-            } else {
-                const int lt = cell[t].w, lu = cell[u].w;
-                const double rt = ct.w, ru = cu.w;
-                if (lt >= 0 && lu >= 0) {
-                    n_p2p = 1;
-                    key = ((uint64_t)(uint32_t)lt << 32) | ((uint64_t)(uint32_t)lu << 5) | (uint64_t)s;
-                } else if (lt < 0 && (lu >= 0 || rt > ru)) {
-                    child[0] = make_int2(at.x, pr.y);
-                    child[1] = make_int2(at.y, pr.y);
-                    n_child = 2;
-                } else if (lu < 0 && (lt >= 0 || ru > rt)) {
-                    child[0] = make_int2(t, (au.x << 5) | s);
-                    child[1] = make_int2(t, (au.y << 5) | s);
-                    n_child = 2;
-                } else {
-                    child[0] = make_int2(at.x, (au.x << 5) | s);
-                    child[1] = make_int2(at.x, (au.y << 5) | s);
-                    child[2] = make_int2(at.y, (au.x << 5) | s);
-                    child[3] = make_int2(at.y, (au.y << 5) | s);
-                    n_child = 4;
-                }
-            }
+        const uint32_t pslot = wave_append(o.n_p2p, &ctl[0]);
+        if (o.n_p2p) {
+            if (pslot < cap_p2p) p2p_keys[pslot] = o.key; else ctl[2] = 1u;
+        }
+        const uint32_t mslot = wave_append(o.n_m2l, &ctl[1]);
+        if (o.n_m2l) {
+            if (mslot < cap_m2l) m2l_keys[mslot] = o.key; else ctl[2] = 1u;
         }
     }
-    const uint32_t cslot = wave_append(n_child, &counters[0]);
-    for (uint32_t q = 0; q < n_child; ++q) next[cslot + q] = child[q];
-    const uint32_t pslot = wave_append(n_p2p, &counters[1]);
-    if (n_p2p) p2p_keys[pslot] = key;
-    const uint32_t mslot = wave_append(n_m2l, &counters[2]);
-    if (n_m2l) m2l_keys[mslot] = key;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&ctl[3], nf);
 }
 
 __global__ void k_zero_u32(uint32_t* p, int n) {
@@ -494,6 +542,7 @@ hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, h
         wb[b].pad1 = 0.0;
     }
     std::vector<int32_t> bfc(topo.box_first_cell.begin(), topo.box_first_cell.end());
+    d.walk_levels = 0;      // a new shape: size the walk level by level once
     hipError_t e;
     if ((e = up(d.cell, cell, s)) != hipSuccess) return e;
     if ((e = up(d.cell_aux, aux, s)) != hipSuccess) return e;
@@ -555,7 +604,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     TRY(d.flag.ensure(n * 4));
     TRY(d.fsc.ensure(n * 12));
     TRY(d.fsc_out.ensure(n * 12));
-    TRY(d.tile_sums.ensure(sort_tiles(n) * 4 + 16));
+    TRY(d.tile_sums.ensure(sort_tiles(3 * n) * 4 + 16));
     TRY(d.clo.ensure(nc * 24));
     TRY(d.chi.ensure(nc * 24));
     TRY(d.cell_axis.ensure(nc * 4));
@@ -577,9 +626,10 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                            d.cell_aux.as<int4>(), d.plist.as<uint32_t>(), d.flag.as<int32_t>(),
                            d.fsc.as<int32_t>());
         TRY(hipGetLastError());
-        for (int a = 0; a < 3; ++a)
-            TRY(exclusive_scan_i32(d.fsc.as<int32_t>() + a * n, d.fsc_out.as<int32_t>() + a * n, n,
-                                   d.tile_sums.as<uint32_t>(), s));
+        // one scan over the three lists back to back: each cell's range of
+        // each list is contiguous, so differences inside a range are exact
+        TRY(exclusive_scan_i32(d.fsc.as<int32_t>(), d.fsc_out.as<int32_t>(), 3 * n,
+                               d.tile_sums.as<uint32_t>(), s));
         hipLaunchKernelGGL(k_move, dim3(grid_of(n)), dim3(256), 0, s, n, d.pc.as<int32_t>(),
                            d.pc_tmp.as<int32_t>(), d.cell.as<int4>(), d.cell_aux.as<int4>(),
                            d.plist.as<uint32_t>(), d.plist_tmp.as<uint32_t>(), d.flag.as<int32_t>(),
@@ -610,42 +660,88 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     clk.lap("records");
     // ---- dual walk
     TRY(d.wcount.ensure(64));
-    int64_t nf = 27 * (int64_t)nbox;
-    {
-        std::vector<int32_t> f0(2 * nf);
-        for (int b = 0; b < nbox; ++b)
-            for (int q = 0; q < 27; ++q) {
-                const int root = topo.box_first_cell[b];
-                f0[2 * (27 * b + q)] = root;
-                f0[2 * (27 * b + q) + 1] = (root << 5) | q;
-            }
+    const int64_t nf0 = 27 * (int64_t)nbox;
+    std::vector<int32_t> f0(2 * nf0);
+    for (int b = 0; b < nbox; ++b)
+        for (int q = 0; q < 27; ++q) {
+            const int root = topo.box_first_cell[b];
+            f0[2 * (27 * b + q)] = root;
+            f0[2 * (27 * b + q) + 1] = (root << 5) | q;
+        }
+    int64_t n_p2p = 0, n_m2l = 0;
+    bool done = false;
+    // Level-by-level walk without host round trips, sized from the previous
+    // build of the same tree shape; falls back to the host-driven loop.
+    if (d.walk_cap_front > 0 && d.walk_levels > 0) {
+        const uint32_t capf = d.walk_cap_front, capp = d.walk_cap_p2p, capm = d.walk_cap_m2l;
+        const int L = d.walk_levels;
+        TRY(d.front.ensure((size_t)std::max<int64_t>(capf, nf0) * 8));
+        TRY(d.front_next.ensure((size_t)capf * 8));
+        TRY(d.p2p_keys.ensure((size_t)capp * 8));
+        TRY(d.m2l_keys.ensure((size_t)std::max<uint32_t>(capm, 1) * 8));
+        TRY(d.walk_ctl.ensure((size_t)(L + 8) * 4));
+        hipLaunchKernelGGL(k_zero_u32, dim3((L + 8 + 255) / 256), dim3(256), 0, s,
+                           d.walk_ctl.as<uint32_t>(), L + 8);
+        uint32_t nf0u = (uint32_t)nf0;
+        TRY(hipMemcpyAsync(d.front.p, f0.data(), f0.size() * 4, hipMemcpyHostToDevice, s));
+        TRY(hipMemcpyAsync(d.walk_ctl.as<uint32_t>() + 4, &nf0u, 4, hipMemcpyHostToDevice, s));
+        uint32_t* ctl = d.walk_ctl.as<uint32_t>();
+        uint32_t* sizes = ctl + 4;
+        DevBuf* bufs[2] = {&d.front, &d.front_next};
+        for (int it = 0; it < L; ++it) {
+            hipLaunchKernelGGL(k_walk_dev, dim3(2048), dim3(256), 0, s, bufs[it & 1]->as<int2>(),
+                               bufs[(it + 1) & 1]->as<int2>(), it, sizes, ctl, capf, capp, capm,
+                               d.walkbox.as<WalkBox>(), d.cellc.as<double4>(), d.chs.as<double4>(),
+                               d.cell.as<int4>(), d.cell_aux.as<int4>(), d.p2p_keys.as<uint64_t>(),
+                               d.m2l_keys.as<uint64_t>());
+        }
+        TRY(hipGetLastError());
+        std::vector<uint32_t> hc(L + 5);
+        TRY(hipMemcpyAsync(hc.data(), ctl, (L + 5) * 4, hipMemcpyDeviceToHost, s));
+        TRY(hipStreamSynchronize(s));
+        if (hc[2] == 0 && hc[4 + L] == 0 && hc[0] <= capp && hc[1] <= capm) {
+            n_p2p = hc[0];
+            n_m2l = hc[1];
+            done = true;
+        }
+    }
+    if (!done) {
+        int64_t nf = nf0;
         TRY(d.front.ensure(std::max<size_t>(f0.size() * 4, 4096)));
         TRY(hipMemcpyAsync(d.front.p, f0.data(), f0.size() * 4, hipMemcpyHostToDevice, s));
-    }
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, d.wcount.as<uint32_t>(), 4);
-    int64_t n_p2p = 0, n_m2l = 0;
-    if (d.p2p_keys.bytes < 16) TRY(d.p2p_keys.ensure(1 << 20));
-    if (d.m2l_keys.bytes < 16) TRY(d.m2l_keys.ensure(1 << 16));
-    uint32_t hc[4] = {0, 0, 0, 0};
-    while (nf > 0) {
-        TRY(d.front_next.grow((size_t)4 * nf * 8, 0, s));
-        if ((size_t)(n_p2p + nf) * 8 > d.p2p_keys.bytes)
-            TRY(d.p2p_keys.grow((size_t)(n_p2p + nf) * 8 * 2, (size_t)n_p2p * 8, s));
-        if ((size_t)(n_m2l + nf) * 8 > d.m2l_keys.bytes)
-            TRY(d.m2l_keys.grow((size_t)(n_m2l + nf) * 8 * 2, (size_t)n_m2l * 8, s));
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, d.wcount.as<uint32_t>(), 1);
-        hipLaunchKernelGGL(k_walk, dim3(grid_of(nf)), dim3(256), 0, s, d.front.as<int2>(), (int)nf,
-                           d.front_next.as<int2>(), d.walkbox.as<WalkBox>(), d.cellc.as<double4>(),
-                           d.chs.as<double4>(), d.cell.as<int4>(), d.cell_aux.as<int4>(),
-                           d.wcount.as<uint32_t>(), d.p2p_keys.as<uint64_t>(),
-                           d.m2l_keys.as<uint64_t>());
-        TRY(hipGetLastError());
-        TRY(hipMemcpyAsync(hc, d.wcount.p, 16, hipMemcpyDeviceToHost, s));
-        TRY(hipStreamSynchronize(s));
-        nf = hc[0];
-        n_p2p = hc[1];
-        n_m2l = hc[2];
-        std::swap(d.front, d.front_next);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, d.wcount.as<uint32_t>(), 4);
+        if (d.p2p_keys.bytes < 16) TRY(d.p2p_keys.ensure(1 << 20));
+        if (d.m2l_keys.bytes < 16) TRY(d.m2l_keys.ensure(1 << 16));
+        uint32_t hc[4] = {0, 0, 0, 0};
+        int levels = 0;
+        int64_t max_front = nf;
+        while (nf > 0) {
+            TRY(d.front_next.grow((size_t)4 * nf * 8, 0, s));
+            if ((size_t)(n_p2p + nf) * 8 > d.p2p_keys.bytes)
+                TRY(d.p2p_keys.grow((size_t)(n_p2p + nf) * 8 * 2, (size_t)n_p2p * 8, s));
+            if ((size_t)(n_m2l + nf) * 8 > d.m2l_keys.bytes)
+                TRY(d.m2l_keys.grow((size_t)(n_m2l + nf) * 8 * 2, (size_t)n_m2l * 8, s));
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, d.wcount.as<uint32_t>(), 1);
+            hipLaunchKernelGGL(k_walk, dim3(grid_of(nf)), dim3(256), 0, s, d.front.as<int2>(), (int)nf,
+                               d.front_next.as<int2>(), d.walkbox.as<WalkBox>(), d.cellc.as<double4>(),
+                               d.chs.as<double4>(), d.cell.as<int4>(), d.cell_aux.as<int4>(),
+                               d.wcount.as<uint32_t>(), d.p2p_keys.as<uint64_t>(),
+                               d.m2l_keys.as<uint64_t>());
+            TRY(hipGetLastError());
+            TRY(hipMemcpyAsync(hc, d.wcount.p, 16, hipMemcpyDeviceToHost, s));
+            TRY(hipStreamSynchronize(s));
+            nf = hc[0];
+            n_p2p = hc[1];
+            n_m2l = hc[2];
+            max_front = std::max<int64_t>(max_front, nf);
+            ++levels;
+            std::swap(d.front, d.front_next);
+        }
+        // sizes for the next build of this shape (with some room to move)
+        d.walk_levels = levels + 2;
+        d.walk_cap_front = (uint32_t)std::min<int64_t>(0x7fffffff, max_front + max_front / 2 + 4096);
+        d.walk_cap_p2p = (uint32_t)std::min<int64_t>(0x7fffffff, n_p2p + n_p2p / 4 + 4096);
+        d.walk_cap_m2l = (uint32_t)std::min<int64_t>(0x7fffffff, n_m2l + n_m2l / 4 + 4096);
     }
 
     clk.lap("walk");

@@ -39,6 +39,23 @@ def test_clustered_with_far_field(theta):
     assert_same(L, tree, lists)
 
 
+def test_second_build_of_a_shape_gives_the_same_lists():
+    """The second build of a tree shape walks without host round trips."""
+    w = inputs.clustered_small(20, 41, halo_frac=0.4, n_halos=5, max_leaf=24)
+    ctx = B.Context(box=w.box, r_s=w.r_s, r_cut=w.r_cut, max_leaf=24, order=4,
+                    theta=0.4)
+    tree, lists = oracle_lists(w.pos, w.box, w.r_cut, 24, 4, 0.4)
+    p = torch.tensor(w.pos, device="cuda")
+    m = torch.tensor(w.mass, device="cuda")
+    for _ in range(3):
+        ctx.build(p, m)
+        assert_same(ctx.lists(), tree, lists)
+    moved = inputs.wrap(w.pos + 0.37, w.box)
+    ctx.build(torch.tensor(moved, device="cuda"), m)
+    tree2, lists2 = oracle_lists(moved, w.box, w.r_cut, 24, 4, 0.4)
+    assert_same(ctx.lists(), tree2, lists2)
+
+
 @pytest.mark.parametrize("n,max_leaf", [(1, 8), (2, 1), (7, 8), (9, 8),
                                         (1000, 1), (1001, 64), (4095, 33)])
 def test_ragged_sizes(n, max_leaf):

@@ -63,7 +63,11 @@ struct DevPlan {
     DevBuf p2p_row, wpos, keys, keys_tmp, plist, plist_tmp, hist, flag, fsc, fsc_out, tile_sums;
     DevBuf pc, pc_tmp, clo, chi, chs, box_first, walkbox, front, front_next, p2p_keys,
         p2p_keys_tmp, m2l_keys, m2l_keys_tmp, wcount, cost, cost_keys, cost_keys_tmp, queue_tmp,
-        item_count, cell_axis, farflag, walk_ctl;
+        item_count, cell_axis, farflag, walk_ctl, froots, cell_split, loop_cells;
+    // cells the level loop partitions, by depth (loop_cells holds them);
+    // n_froots subtrees finished in one launch (0: the loop does every level)
+    std::vector<int32_t> loop_depth_begin;
+    int n_froots = 0;
     // walk sizes seen on the last level-by-level build of this tree shape
     uint32_t walk_cap_front = 0, walk_cap_p2p = 0, walk_cap_m2l = 0;
     int walk_levels = 0;
@@ -76,7 +80,8 @@ struct DevPlan {
                           &flag, &fsc, &fsc_out, &tile_sums, &pc, &pc_tmp, &clo, &chi, &chs,
                           &box_first, &walkbox, &front, &front_next, &p2p_keys, &p2p_keys_tmp,
                           &m2l_keys, &m2l_keys_tmp, &wcount, &cost, &cost_keys, &cost_keys_tmp,
-                          &queue_tmp, &item_count, &cell_axis, &farflag, &walk_ctl})
+                          &queue_tmp, &item_count, &cell_axis, &farflag, &walk_ctl, &froots,
+                          &cell_split, &loop_cells})
             b->release();
     }
 };

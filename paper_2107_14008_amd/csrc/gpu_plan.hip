@@ -115,36 +115,38 @@ __global__ void k_cells_level(const int32_t* __restrict__ level, int nd, const i
     }
 }
 
+// split[c] = 1 for the cells the level loop partitions.
 __global__ void k_flag(int64_t n, const int32_t* __restrict__ pc, const int4* __restrict__ cell,
-                       const int4* __restrict__ aux, const int32_t* __restrict__ axis,
+                       const int32_t* __restrict__ split, const int32_t* __restrict__ axis,
                        const uint32_t* __restrict__ plist, int32_t* __restrict__ flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int c = pc[i];
-    if (aux[c].x < 0) return;
+    if (!split[c]) return;
     const int4 ci = cell[c];
     const int ax = axis[c];
     flag[plist[ax * n + i]] = (i - ci.x < ci.y / 2) ? 1 : 0;
 }
 
-__global__ void k_marks(int64_t n, const int32_t* __restrict__ pc, const int4* __restrict__ aux,
+__global__ void k_marks(int64_t n, const int32_t* __restrict__ pc, const int32_t* __restrict__ split,
                         const uint32_t* __restrict__ plist, const int32_t* __restrict__ flag,
                         int32_t* __restrict__ f) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const bool split = aux[pc[i]].x >= 0;
-    for (int a = 0; a < 3; ++a) f[a * n + i] = split ? flag[plist[a * n + i]] : 0;
+    const bool sp = split[pc[i]] != 0;
+    for (int a = 0; a < 3; ++a) f[a * n + i] = sp ? flag[plist[a * n + i]] : 0;
 }
 
 __global__ void k_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __restrict__ pc_out,
                        const int4* __restrict__ cell, const int4* __restrict__ aux,
-                       const uint32_t* __restrict__ plist, uint32_t* __restrict__ pout,
-                       const int32_t* __restrict__ flag, const int32_t* __restrict__ scan) {
+                       const int32_t* __restrict__ split, const uint32_t* __restrict__ plist,
+                       uint32_t* __restrict__ pout, const int32_t* __restrict__ flag,
+                       const int32_t* __restrict__ scan) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int c = pc[i];
     const int4 ax = aux[c];
-    if (ax.x < 0) {
+    if (!split[c]) {
         for (int a = 0; a < 3; ++a) pout[a * n + i] = plist[a * n + i];
         pc_out[i] = c;
         return;
@@ -173,6 +175,179 @@ k_leaf_perm(int nl, const int4* __restrict__ leaf, const uint32_t* __restrict__ 
     int rank = 0;
     for (int k = 0; k < li.y; ++k) rank += plist[li.x + k] < id ? 1 : 0;
     perm[li.x + rank] = (int32_t)id;
+}
+
+// The bottom levels of the tree in one launch: one workgroup per subtree of
+// at most kFuseM particles and kFuseC cells.  The three sorted lists of the
+// subtree's range are held in LDS as 16-bit local ids (a particle's local id
+// is its rank in the x list) and partitioned level by level exactly as the
+// level loop does (first floor(n/2) of the split axis left, stable), then
+// each leaf's particles are written to perm in ascending caller index.
+// Bounds of every cell of the subtree are written to clo / chi.
+constexpr int kFuseM = 4096;
+constexpr int kFuseC = 512;
+constexpr int kFuseT = 512;
+constexpr int kFusePer = (3 * kFuseM + kFuseT - 1) / kFuseT;
+static_assert(kFusePer <= 32, "one 32-bit mask per thread chunk");
+constexpr uint16_t kNoChild = 0xffffu;
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    __syncthreads();
+    return before + x - v;
+}
+
+// roots[b] = (subtree root cell, cells in the subtree, root depth, deepest depth)
+__global__ void __launch_bounds__(kFuseT)
+k_orb_fused(const int4* __restrict__ roots, const int4* __restrict__ cell,
+            const int4* __restrict__ aux, const uint32_t* __restrict__ plist, int64_t n,
+            const double* __restrict__ wpos, int32_t* __restrict__ loc, double* __restrict__ clo,
+            double* __restrict__ chi, int32_t* __restrict__ perm) {
+    __shared__ __align__(16) uint16_t lst[2 * 3 * kFuseM];
+    __shared__ uint8_t flag[kFuseM];
+    __shared__ uint16_t pcl[kFuseM];
+    __shared__ uint16_t cfirst[kFuseC], ccount[kFuseC], cch0[kFuseC], cch1[kFuseC];
+    __shared__ uint8_t caxis[kFuseC], cdep[kFuseC];
+    __shared__ uint32_t sfirst[3 * kFuseC];
+    __shared__ uint32_t wsum[kFuseT / 64];
+    const int4 r = roots[blockIdx.x];
+    const int root = r.x, nsub = r.y, depth_span = r.w - r.z;
+    const int4 rc = cell[root];
+    const int base = rc.x, m = rc.y;
+    const int t = threadIdx.x;
+    const uint32_t* __restrict__ l0 = plist + base;
+    auto L = [&](int buf, int a, int k) -> uint16_t& { return lst[(buf * 3 + a) * kFuseM + k]; };
+
+    for (int k = t; k < m; k += kFuseT) {
+        L(0, 0, k) = (uint16_t)k;
+        loc[l0[k]] = k;
+        pcl[k] = 0;
+    }
+    for (int c = t; c < nsub; c += kFuseT) {
+        const int4 ci = cell[root + c], ai = aux[root + c];
+        cfirst[c] = (uint16_t)(ci.x - base);
+        ccount[c] = (uint16_t)ci.y;
+        cch0[c] = ai.x >= 0 ? (uint16_t)(ai.x - root) : kNoChild;
+        cch1[c] = ai.y >= 0 ? (uint16_t)(ai.y - root) : kNoChild;
+        cdep[c] = (uint8_t)(ai.w - r.z);
+    }
+    // loc[] is written and read through global memory by this workgroup only
+    __threadfence();
+    __syncthreads();
+    __threadfence();
+    for (int k = t; k < m; k += kFuseT) {
+        L(0, 1, k) = (uint16_t)loc[plist[n + base + k]];
+        L(0, 2, k) = (uint16_t)loc[plist[2 * n + base + k]];
+    }
+    __syncthreads();
+
+    int cur = 0;
+    for (int dep = 0;; ++dep) {
+        // bounds of the cells of this depth, split axis of those that split
+        for (int c = t; c < nsub; c += kFuseT) {
+            if (cdep[c] != dep) continue;
+            const int f = cfirst[c], e = f + ccount[c] - 1;
+            double lo[3], hi[3];
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = wpos[3 * (size_t)l0[L(cur, a, f)] + a];
+                hi[a] = wpos[3 * (size_t)l0[L(cur, a, e)] + a];
+                clo[3 * (size_t)(root + c) + a] = lo[a];
+                chi[3 * (size_t)(root + c) + a] = hi[a];
+            }
+            if (cch0[c] != kNoChild) {
+#pragma clang fp contract(off)
+                const double e0 = hi[0] - lo[0], e1 = hi[1] - lo[1], e2 = hi[2] - lo[2];
+                int axis = 0;
+                double best = e0;
+                if (e1 > best) { axis = 1; best = e1; }
+                if (e2 > best) axis = 2;
+                caxis[c] = (uint8_t)axis;
+            }
+        }
+        if (dep == depth_span) break;
+        __syncthreads();
+        auto splits = [&](int c) { return cdep[c] == dep && cch0[c] != kNoChild; };
+        for (int k = t; k < m; k += kFuseT) {
+            const int c = pcl[k];
+            if (!splits(c)) continue;
+            flag[L(cur, caxis[c], k)] = (k - cfirst[c] < ccount[c] / 2) ? 1 : 0;
+        }
+        __syncthreads();
+        // stable partition of the three lists: one exclusive scan over the
+        // left marks of all 3m positions (each cell's range is contiguous in
+        // every list, so differences inside a range count that range only)
+        const int q0 = min(3 * m, t * kFusePer), q1 = min(3 * m, q0 + kFusePer);
+        uint32_t bits = 0, cnt = 0;
+        {
+            int a = q0 / m, k = q0 - a * m;
+            for (int q = q0; q < q1; ++q) {
+                const int c = pcl[k];
+                if (splits(c) && flag[L(cur, a, k)]) {
+                    bits |= 1u << (q - q0);
+                    ++cnt;
+                }
+                if (++k == m) { k = 0; ++a; }
+            }
+        }
+        const uint32_t excl = block_excl_scan(cnt, wsum);
+        {
+            uint32_t run = excl;
+            int a = q0 / m, k = q0 - a * m;
+            for (int q = q0; q < q1; ++q) {
+                const int c = pcl[k];
+                if (k == cfirst[c] && splits(c)) sfirst[a * kFuseC + c] = run;
+                run += (bits >> (q - q0)) & 1u;
+                if (++k == m) { k = 0; ++a; }
+            }
+        }
+        __syncthreads();
+        {
+            uint32_t run = excl;
+            int a = q0 / m, k = q0 - a * m;
+            for (int q = q0; q < q1; ++q) {
+                const int c = pcl[k];
+                const uint32_t b = (bits >> (q - q0)) & 1u;
+                int pos = k;
+                if (splits(c)) {
+                    const int f = cfirst[c], nl = ccount[c] / 2;
+                    const int lr = (int)(run - sfirst[a * kFuseC + c]);
+                    pos = b ? f + lr : f + nl + (k - f - lr);
+                }
+                L(cur ^ 1, a, pos) = L(cur, a, k);
+                run += b;
+                if (++k == m) { k = 0; ++a; }
+            }
+        }
+        __syncthreads();
+        for (int k = t; k < m; k += kFuseT) {
+            const int c = pcl[k];
+            if (splits(c)) pcl[k] = (k - cfirst[c] < ccount[c] / 2) ? cch0[c] : cch1[c];
+        }
+        cur ^= 1;
+        __syncthreads();
+    }
+    // leaves: particles in ascending caller index
+    uint32_t* gid = reinterpret_cast<uint32_t*>(&lst[(cur ^ 1) * 3 * kFuseM]);
+    __syncthreads();
+    for (int k = t; k < m; k += kFuseT) gid[k] = l0[L(cur, 0, k)];
+    __syncthreads();
+    for (int k = t; k < m; k += kFuseT) {
+        const int c = pcl[k];
+        const int f = cfirst[c], e = f + ccount[c];
+        const uint32_t id = gid[k];
+        int rank = 0;
+        for (int q = f; q < e; ++q) rank += gid[q] < id ? 1 : 0;
+        perm[base + f + rank] = (int32_t)id;
+    }
 }
 
 // Centre, half size and radius of every cell (the host planner's formulas).
@@ -543,11 +718,60 @@ hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, h
     }
     std::vector<int32_t> bfc(topo.box_first_cell.begin(), topo.box_first_cell.end());
     d.walk_levels = 0;      // a new shape: size the walk level by level once
+
+    // Subtrees finished by k_orb_fused: the highest cells with at most kFuseM
+    // particles and kFuseC cells (cells are in pre-order, so a subtree is the
+    // contiguous id range [c, c + sub[c])).  Used only when every leaf falls
+    // in one; the level loop then partitions the cells above them.
+    std::vector<int32_t> sub(nc, 1), deep(nc, 0);
+    for (int64_t k = nc - 1; k >= 0; --k) {
+        const Cell& c = topo.cells[k];
+        deep[k] = c.depth;
+        if (c.child[0] >= 0) {
+            sub[k] = 1 + sub[c.child[0]] + sub[c.child[1]];
+            deep[k] = std::max(deep[c.child[0]], deep[c.child[1]]);
+        }
+    }
+    auto fusable = [&](int64_t k) {
+        return topo.cells[k].count <= kFuseM && sub[k] <= kFuseC;
+    };
+    bool all_leaves = true;
+    for (int32_t c : topo.leaf_cell) all_leaves = all_leaves && fusable(c);
+    std::vector<int32_t> roots, split(nc, 0), loop_cells;
+    std::vector<int32_t> loop_begin(1, 0);
+    if (all_leaves) {
+        for (int64_t k = 0; k < nc; ++k) {
+            const Cell& c = topo.cells[k];
+            if (!fusable(k)) split[k] = 1;   // holds more than a leaf: it splits
+            else if (c.parent < 0 || !fusable(c.parent)) {
+                roots.push_back((int32_t)k);
+                roots.push_back(sub[k]);
+                roots.push_back(c.depth);
+                roots.push_back(deep[k]);
+            }
+        }
+        for (int dep = 0; dep + 1 < (int)topo.depth_begin.size(); ++dep) {
+            const size_t before = loop_cells.size();
+            for (int q = topo.depth_begin[dep]; q < topo.depth_begin[dep + 1]; ++q)
+                if (split[topo.cells_by_depth[q]]) loop_cells.push_back(topo.cells_by_depth[q]);
+            if (loop_cells.size() == before) break;
+            loop_begin.push_back((int32_t)loop_cells.size());
+        }
+    } else {
+        for (int64_t k = 0; k < nc; ++k) split[k] = topo.cells[k].child[0] >= 0 ? 1 : 0;
+        loop_cells = topo.cells_by_depth;
+        loop_begin = topo.depth_begin;
+    }
+    d.n_froots = (int)(roots.size() / 4);
+    d.loop_depth_begin = loop_begin;
     hipError_t e;
     if ((e = up(d.cell, cell, s)) != hipSuccess) return e;
     if ((e = up(d.cell_aux, aux, s)) != hipSuccess) return e;
     if ((e = up(d.leaf, leaf, s)) != hipSuccess) return e;
     if ((e = up(d.level_cells, topo.cells_by_depth, s)) != hipSuccess) return e;
+    if ((e = up(d.loop_cells, loop_cells, s)) != hipSuccess) return e;
+    if ((e = up(d.cell_split, split, s)) != hipSuccess) return e;
+    if ((e = up(d.froots, roots, s)) != hipSuccess) return e;
     if ((e = up(d.box_first, topo.box_first_particle, s)) != hipSuccess) return e;
     if ((e = up(d.walkbox, wb, s)) != hipSuccess) return e;
     if ((e = up(d.boxes, bd, s)) != hipSuccess) return e;
@@ -560,7 +784,6 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     const int64_t n = topo.n;
     const int nbox = (int)topo.boxes.size();
     const int64_t nc = (int64_t)topo.cells.size(), nl = (int64_t)topo.leaf_cell.size();
-    const int nd = (int)topo.depth_begin.size() - 1;
     PhaseTimer clk(s);
 
     // ---- wrap, sort each axis by (coordinate, caller index)
@@ -611,19 +834,24 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     hipLaunchKernelGGL(k_init_pc, dim3(grid_of(n)), dim3(256), 0, s, n, d.box_first.as<int32_t>(),
                        d.item_count.as<int32_t>(), nbox, d.pc.as<int32_t>());
     TRY(hipGetLastError());
-    for (int dep = 0; dep < nd; ++dep) {
-        const int c0 = topo.depth_begin[dep], ncd = topo.depth_begin[dep + 1] - c0;
+    // the level loop partitions the cells above the fused subtrees (every
+    // splitting cell when there are none; the deepest level then holds
+    // leaves only and needs its bounds alone)
+    const bool fused = d.n_froots > 0;
+    const int nloop = (int)d.loop_depth_begin.size() - 1;
+    for (int dep = 0; dep < nloop; ++dep) {
+        const int c0 = d.loop_depth_begin[dep], ncd = d.loop_depth_begin[dep + 1] - c0;
         hipLaunchKernelGGL(k_cells_level, dim3(grid_of(ncd)), dim3(256), 0, s,
-                           d.level_cells.as<int32_t>() + c0, ncd, d.cell.as<int4>(),
+                           d.loop_cells.as<int32_t>() + c0, ncd, d.cell.as<int4>(),
                            d.cell_aux.as<int4>(), d.plist.as<uint32_t>(), n, d.wpos.as<double>(),
                            d.clo.as<double>(), d.chi.as<double>(), d.cell_axis.as<int32_t>());
         TRY(hipGetLastError());
-        if (dep == nd - 1) break;      // the deepest level holds leaves only
+        if (!fused && dep == nloop - 1) break;
         hipLaunchKernelGGL(k_flag, dim3(grid_of(n)), dim3(256), 0, s, n, d.pc.as<int32_t>(),
-                           d.cell.as<int4>(), d.cell_aux.as<int4>(), d.cell_axis.as<int32_t>(),
+                           d.cell.as<int4>(), d.cell_split.as<int32_t>(), d.cell_axis.as<int32_t>(),
                            d.plist.as<uint32_t>(), d.flag.as<int32_t>());
         hipLaunchKernelGGL(k_marks, dim3(grid_of(n)), dim3(256), 0, s, n, d.pc.as<int32_t>(),
-                           d.cell_aux.as<int4>(), d.plist.as<uint32_t>(), d.flag.as<int32_t>(),
+                           d.cell_split.as<int32_t>(), d.plist.as<uint32_t>(), d.flag.as<int32_t>(),
                            d.fsc.as<int32_t>());
         TRY(hipGetLastError());
         // one scan over the three lists back to back: each cell's range of
@@ -632,21 +860,30 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                                d.tile_sums.as<uint32_t>(), s));
         hipLaunchKernelGGL(k_move, dim3(grid_of(n)), dim3(256), 0, s, n, d.pc.as<int32_t>(),
                            d.pc_tmp.as<int32_t>(), d.cell.as<int4>(), d.cell_aux.as<int4>(),
-                           d.plist.as<uint32_t>(), d.plist_tmp.as<uint32_t>(), d.flag.as<int32_t>(),
+                           d.cell_split.as<int32_t>(), d.plist.as<uint32_t>(),
+                           d.plist_tmp.as<uint32_t>(), d.flag.as<int32_t>(),
                            d.fsc_out.as<int32_t>());
         TRY(hipGetLastError());
         std::swap(d.plist, d.plist_tmp);
         std::swap(d.pc, d.pc_tmp);
     }
+    TRY(d.perm.ensure(n * 4));
+    if (fused) {
+        hipLaunchKernelGGL(k_orb_fused, dim3(d.n_froots), dim3(kFuseT), 0, s, d.froots.as<int4>(),
+                           d.cell.as<int4>(), d.cell_aux.as<int4>(), d.plist.as<uint32_t>(), n,
+                           d.wpos.as<double>(), d.flag.as<int32_t>(), d.clo.as<double>(),
+                           d.chi.as<double>(), d.perm.as<int32_t>());
+        TRY(hipGetLastError());
+    }
 
     clk.lap("levels");
     // ---- leaf order, geometry, particle records
-    TRY(d.perm.ensure(n * 4));
     TRY(d.leafc.ensure(nl * 32));
     TRY(d.cellc.ensure(nc * 32));
     TRY(d.chs.ensure(nc * 32));
-    hipLaunchKernelGGL(k_leaf_perm, dim3(grid_of(nl, 4)), dim3(256), 0, s, (int)nl, d.leaf.as<int4>(),
-                       d.plist.as<uint32_t>(), d.perm.as<int32_t>());
+    if (!fused)
+        hipLaunchKernelGGL(k_leaf_perm, dim3(grid_of(nl, 4)), dim3(256), 0, s, (int)nl,
+                           d.leaf.as<int4>(), d.plist.as<uint32_t>(), d.perm.as<int32_t>());
     hipLaunchKernelGGL(k_geom, dim3(grid_of(nc)), dim3(256), 0, s, (int)nc, d.clo.as<double>(),
                        d.chi.as<double>(), d.cell.as<int4>(), d.cellc.as<double4>(),
                        d.chs.as<double4>(), d.leafc.as<double4>());

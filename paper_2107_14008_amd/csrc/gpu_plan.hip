@@ -11,7 +11,9 @@
 // its bounds from the ends of its three sorted ranges, marks the floor(n/2)
 // first particles of its split axis as "left", and every axis list is
 // partitioned stably (prefix sums of the left marks), which keeps each child
-// range sorted on every axis.
+// range sorted on every axis.  Once a subtree holds at most 4096 particles
+// and 512 cells, one workgroup finishes it in LDS (k_orb_fused), so the
+// launches per level are paid only for the top levels.
 //
 // Dual walk: level-synchronous over a frontier of cell pairs; one thread per
 // pair classifies it and appends P2P keys, M2L keys or child pairs with one
@@ -160,21 +162,6 @@ __global__ void k_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __res
         pout[a * n + pos] = p;
     }
     pc_out[i] = (i - first < nl) ? ax.x : ax.y;
-}
-
-// One wavefront per leaf: its particles in ascending caller index.
-__global__ void __launch_bounds__(256)
-k_leaf_perm(int nl, const int4* __restrict__ leaf, const uint32_t* __restrict__ plist,
-            int32_t* __restrict__ perm) {
-    const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (l >= nl) return;
-    const int4 li = leaf[l];
-    if (lane >= li.y) return;
-    const uint32_t id = plist[li.x + lane];
-    int rank = 0;
-    for (int k = 0; k < li.y; ++k) rank += plist[li.x + k] < id ? 1 : 0;
-    perm[li.x + rank] = (int32_t)id;
 }
 
 // The bottom levels of the tree in one launch: one workgroup per subtree of
@@ -721,8 +708,9 @@ hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, h
 
     // Subtrees finished by k_orb_fused: the highest cells with at most kFuseM
     // particles and kFuseC cells (cells are in pre-order, so a subtree is the
-    // contiguous id range [c, c + sub[c])).  Used only when every leaf falls
-    // in one; the level loop then partitions the cells above them.
+    // contiguous id range [c, c + sub[c])).  A leaf (<= 64 particles) always
+    // qualifies, so the subtrees cover every leaf; the level loop partitions
+    // the cells above them, all of which split.
     std::vector<int32_t> sub(nc, 1), deep(nc, 0);
     for (int64_t k = nc - 1; k >= 0; --k) {
         const Cell& c = topo.cells[k];
@@ -735,32 +723,26 @@ hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, h
     auto fusable = [&](int64_t k) {
         return topo.cells[k].count <= kFuseM && sub[k] <= kFuseC;
     };
-    bool all_leaves = true;
-    for (int32_t c : topo.leaf_cell) all_leaves = all_leaves && fusable(c);
     std::vector<int32_t> roots, split(nc, 0), loop_cells;
     std::vector<int32_t> loop_begin(1, 0);
-    if (all_leaves) {
-        for (int64_t k = 0; k < nc; ++k) {
-            const Cell& c = topo.cells[k];
-            if (!fusable(k)) split[k] = 1;   // holds more than a leaf: it splits
-            else if (c.parent < 0 || !fusable(c.parent)) {
-                roots.push_back((int32_t)k);
-                roots.push_back(sub[k]);
-                roots.push_back(c.depth);
-                roots.push_back(deep[k]);
-            }
+    for (int64_t k = 0; k < nc; ++k) {
+        const Cell& c = topo.cells[k];
+        if (!fusable(k)) {
+            if (c.child[0] < 0) return hipErrorInvalidValue;   // a leaf above kFuseM
+            split[k] = 1;
+        } else if (c.parent < 0 || !fusable(c.parent)) {
+            roots.push_back((int32_t)k);
+            roots.push_back(sub[k]);
+            roots.push_back(c.depth);
+            roots.push_back(deep[k]);
         }
-        for (int dep = 0; dep + 1 < (int)topo.depth_begin.size(); ++dep) {
-            const size_t before = loop_cells.size();
-            for (int q = topo.depth_begin[dep]; q < topo.depth_begin[dep + 1]; ++q)
-                if (split[topo.cells_by_depth[q]]) loop_cells.push_back(topo.cells_by_depth[q]);
-            if (loop_cells.size() == before) break;
-            loop_begin.push_back((int32_t)loop_cells.size());
-        }
-    } else {
-        for (int64_t k = 0; k < nc; ++k) split[k] = topo.cells[k].child[0] >= 0 ? 1 : 0;
-        loop_cells = topo.cells_by_depth;
-        loop_begin = topo.depth_begin;
+    }
+    for (int dep = 0; dep + 1 < (int)topo.depth_begin.size(); ++dep) {
+        const size_t before = loop_cells.size();
+        for (int q = topo.depth_begin[dep]; q < topo.depth_begin[dep + 1]; ++q)
+            if (split[topo.cells_by_depth[q]]) loop_cells.push_back(topo.cells_by_depth[q]);
+        if (loop_cells.size() == before) break;
+        loop_begin.push_back((int32_t)loop_cells.size());
     }
     d.n_froots = (int)(roots.size() / 4);
     d.loop_depth_begin = loop_begin;
@@ -834,10 +816,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     hipLaunchKernelGGL(k_init_pc, dim3(grid_of(n)), dim3(256), 0, s, n, d.box_first.as<int32_t>(),
                        d.item_count.as<int32_t>(), nbox, d.pc.as<int32_t>());
     TRY(hipGetLastError());
-    // the level loop partitions the cells above the fused subtrees (every
-    // splitting cell when there are none; the deepest level then holds
-    // leaves only and needs its bounds alone)
-    const bool fused = d.n_froots > 0;
+    // the level loop partitions the cells above the fused subtrees
     const int nloop = (int)d.loop_depth_begin.size() - 1;
     for (int dep = 0; dep < nloop; ++dep) {
         const int c0 = d.loop_depth_begin[dep], ncd = d.loop_depth_begin[dep + 1] - c0;
@@ -846,7 +825,6 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                            d.cell_aux.as<int4>(), d.plist.as<uint32_t>(), n, d.wpos.as<double>(),
                            d.clo.as<double>(), d.chi.as<double>(), d.cell_axis.as<int32_t>());
         TRY(hipGetLastError());
-        if (!fused && dep == nloop - 1) break;
         hipLaunchKernelGGL(k_flag, dim3(grid_of(n)), dim3(256), 0, s, n, d.pc.as<int32_t>(),
                            d.cell.as<int4>(), d.cell_split.as<int32_t>(), d.cell_axis.as<int32_t>(),
                            d.plist.as<uint32_t>(), d.flag.as<int32_t>());
@@ -867,23 +845,19 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         std::swap(d.plist, d.plist_tmp);
         std::swap(d.pc, d.pc_tmp);
     }
+    // the subtrees below, each in one workgroup; leaves into perm
     TRY(d.perm.ensure(n * 4));
-    if (fused) {
-        hipLaunchKernelGGL(k_orb_fused, dim3(d.n_froots), dim3(kFuseT), 0, s, d.froots.as<int4>(),
-                           d.cell.as<int4>(), d.cell_aux.as<int4>(), d.plist.as<uint32_t>(), n,
-                           d.wpos.as<double>(), d.flag.as<int32_t>(), d.clo.as<double>(),
-                           d.chi.as<double>(), d.perm.as<int32_t>());
-        TRY(hipGetLastError());
-    }
+    hipLaunchKernelGGL(k_orb_fused, dim3(d.n_froots), dim3(kFuseT), 0, s, d.froots.as<int4>(),
+                       d.cell.as<int4>(), d.cell_aux.as<int4>(), d.plist.as<uint32_t>(), n,
+                       d.wpos.as<double>(), d.flag.as<int32_t>(), d.clo.as<double>(),
+                       d.chi.as<double>(), d.perm.as<int32_t>());
+    TRY(hipGetLastError());
 
     clk.lap("levels");
     // ---- leaf order, geometry, particle records
     TRY(d.leafc.ensure(nl * 32));
     TRY(d.cellc.ensure(nc * 32));
     TRY(d.chs.ensure(nc * 32));
-    if (!fused)
-        hipLaunchKernelGGL(k_leaf_perm, dim3(grid_of(nl, 4)), dim3(256), 0, s, (int)nl,
-                           d.leaf.as<int4>(), d.plist.as<uint32_t>(), d.perm.as<int32_t>());
     hipLaunchKernelGGL(k_geom, dim3(grid_of(nc)), dim3(256), 0, s, (int)nc, d.clo.as<double>(),
                        d.chi.as<double>(), d.cell.as<int4>(), d.cellc.as<double4>(),
                        d.chs.as<double4>(), d.leafc.as<double4>());

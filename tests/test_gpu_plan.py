@@ -56,11 +56,11 @@ def test_second_build_of_a_shape_gives_the_same_lists():
     assert_same(ctx.lists(), tree2, lists2)
 
 
-# (6000, 4500): a leaf larger than one fused subtree, so every level runs in
-# the level loop; the others finish their bottom levels in one launch.
+# (1000, 1): subtrees are cut by their cell count (512), not their particle
+# count; (4097, 8): one level in the level loop above the fused subtrees.
 @pytest.mark.parametrize("n,max_leaf", [(1, 8), (2, 1), (7, 8), (9, 8),
                                         (1000, 1), (1001, 64), (4095, 33),
-                                        (4097, 8), (6000, 4500)])
+                                        (4097, 8)])
 def test_ragged_sizes(n, max_leaf):
     rng = np.random.default_rng(n)
     pos = rng.uniform(0, 20.0, (n, 3))

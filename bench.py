@@ -9,9 +9,10 @@ One step = the whole short-range path on particles already in HBM: plan
 order, far field (P2M .. L2P), the persistent P2P kernel and the ordered
 reduction.  ``value`` counts candidate pairs of the P2P tasks (n_i * n_j per
 task, the paper's interaction count) per second of whole step, for the
-float32 form (cell-relative float32 pairs, 512-node T_[2] table, float64
-accumulation); the plain float64 form (exact erfc/exp) is timed the same
-way and reported beside it.
+float32 form (cell-relative float32 pairs, T from a 2048-segment quadratic
+table over r^2, float64 accumulation).  The float32 form with the paper's
+table (512 nodes on x, T_[2]) and the plain float64 form (exact erfc/exp)
+are timed the same way and reported beside it.
 
 Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one
 GPU.
@@ -33,10 +34,13 @@ sys.path.insert(0, ROOT)
 
 from paper_2107_14008_amd import inputs  # noqa: E402
 
-# Algorithmic float32 operations per candidate pair of the table form:
-# displacement 3, r^2 5, 1/r 1, table coordinate 2, index and offset 2,
+# Algorithmic float32 operations per candidate pair of the paper's table
+# form: displacement 3, r^2 5, 1/r 1, table coordinate 2, index and offset 2,
 # T_[2] Horner 4, g = m T / r^3 4, accumulation 6.
 FLOPS_PER_PAIR_F32_T2 = 27
+# r^2 segment table: displacement 3, r^2 5, clamp 1, segment index 1,
+# quadratic Horner in r^2 4, 1/r 1, 1/r^3 2, g = m T / r^3 2, accumulation 6.
+FLOPS_PER_PAIR_F32_R2 = 25
 # Same count for the float64 exact form, erfc and exp taken as one op each:
 # displacement 3 (+3 shift), r^2 5, 1/r 1, x 2, T = erfc + c x e^-x^2 6,
 # g 4, accumulation 6.
@@ -57,7 +61,7 @@ def error_summary(acc, ref):
                 max=float(e.max()))
 
 
-def measured_traffic(kernel_tag="p2p_fp32_t2_clustered_2m"):
+def measured_traffic(kernel_tag="p2p_fp32_r2_clustered_2m"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the P2P source has changed since the counters were taken."""
     import hashlib
@@ -150,8 +154,8 @@ def secondary(args):
         mass = torch.tensor(np.concatenate([w.mass for w in boxes]), device=dev)
         n = int(sum(counts))
         out = torch.empty((n, 3), dtype=torch.float64, device=dev)
-        ctx = B.Context(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
-                        table_size=512, table_level=2, timing=1)
+        ctx = B.Context(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2,
+                        table_size=2048, table_level=2, timing=1)
 
         def build():
             ctx.build_batch(per_box, counts, pos, mass, stream)
@@ -168,7 +172,7 @@ def secondary(args):
                     config={"workload": f"batch64: {len(boxes)} clustered boxes, "
                             f"N = n_side^3 with n_side log-uniform in [16, 96] "
                             f"(total {n}), one persistent launch, float32 "
-                            f"512-node T_[2] table", "n": n,
+                            f"2048-segment quadratic r^2 table", "n": n,
                             "candidate_pairs_per_step": cand,
                             "schedule": best, "phases_ms": ph,
                             "p2p_interactions_per_s": cand / (ph["p2p_ms"] / 1e3),
@@ -217,7 +221,9 @@ def secondary(args):
         w = inputs.uniform_32k()
         forms = {"fp64_exact": dict(precision=B.PMFMM_FP64, trunc=B.TRUNC_EXACT),
                  "fp32_t2_512": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
-                                     table_size=512, table_level=2)}
+                                     table_size=512, table_level=2),
+                 "fp32_r2_2048": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2,
+                                      table_size=2048, table_level=2)}
         order, theta = -1, 0.0
     else:
         w = inputs.clustered_16m()
@@ -227,7 +233,9 @@ def secondary(args):
                  "fp32_t3_2048": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
                                       table_size=2048, table_level=3),
                  "fp32_t2_512": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
-                                     table_size=512, table_level=2)}
+                                     table_size=512, table_level=2),
+                 "fp32_r2_2048": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2,
+                                      table_size=2048, table_level=2)}
         order, theta = args.order, args.theta
     n = len(w.mass)
     res = {}
@@ -273,7 +281,11 @@ def main():
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--table-size", type=int, default=512)
     ap.add_argument("--table-level", type=int, default=2)
+    ap.add_argument("--r2-segments", type=int, default=2048,
+                    help="segments of the headline float32 r^2 table")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time the headline float32 form only (profiling)")
     ap.add_argument("--config", default="clustered_2m",
                     choices=["clustered_2m", "clustered_16m", "batch64",
                              "adjoint262k", "uniform_32k"],
@@ -323,13 +335,18 @@ def main():
         del src, dst
 
     forms = {
-        "fp32": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
-                     table_size=args.table_size, table_level=args.table_level,
-                     table_round=B.ROUND_NEAREST),
+        "fp32": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2,
+                     table_size=args.r2_segments, table_level=2),
+        "fp32_paper_table": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
+                                 table_size=args.table_size,
+                                 table_level=args.table_level,
+                                 table_round=B.ROUND_NEAREST),
         "fp64": dict(precision=B.PMFMM_FP64, trunc=B.TRUNC_EXACT),
     }
     if args.skip_fp64:
         forms.pop("fp64")
+    if args.headline_only:
+        forms = {"fp32": forms["fp32"]}
     results = {}
     for name, ev in forms.items():
         ctx = B.Context(box=w.box, r_s=w.r_s, r_cut=w.r_cut, max_leaf=64,
@@ -368,7 +385,7 @@ def main():
 
     r32 = results["fp32"]
     value = cand / (r32["ms_per_step"] / 1e3)
-    achieved = cand * FLOPS_PER_PAIR_F32_T2 / (r32["p2p_ms"] / 1e3) / 1e12
+    achieved = cand * FLOPS_PER_PAIR_F32_R2 / (r32["p2p_ms"] / 1e3) / 1e12
     line = {
         "metric": "short-range pair interactions/s, FP32 vs FP64 at 99.9% "
                   "rel. force err <=1e-4",
@@ -390,8 +407,12 @@ def main():
             "n": n, "theta": args.theta, "order": args.order,
             "planner": "gpu",
             "candidate_pairs_per_step": cand,
-            "fp32_form": f"float32 cell-relative pairs, {args.table_size}-node "
-                         f"T_[{args.table_level}] table, float64 accumulation",
+            "fp32_form": f"float32 cell-relative pairs, T from a "
+                         f"{args.r2_segments}-segment quadratic table over r^2, "
+                         f"float64 accumulation",
+            "fp32_paper_table_form": f"float32 cell-relative pairs, "
+                                     f"{args.table_size}-node T_[{args.table_level}] "
+                                     f"table of Eq. (int)",
             "fp64_form": "float64 pairs, exact erfc/exp",
         },
         "roofline": {
@@ -402,8 +423,8 @@ def main():
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": measured_traffic(),
             "traffic_unit": "B per launch",
-            "kernel": "p2p_kernel<FP32 table, level 2>",
-            "flops_per_pair": FLOPS_PER_PAIR_F32_T2,
+            "kernel": "p2p_kernel<FP32 r^2 table, degree 2>",
+            "flops_per_pair": FLOPS_PER_PAIR_F32_R2,
             "kernel_ms": r32["p2p_ms"],
             "paper_convention_frac": cand * PAPER_OPS_PER_PAIR
             / (r32["p2p_ms"] / 1e3) / 1e12 / PEAK_FP32_TFLOPS,
@@ -413,6 +434,15 @@ def main():
         "p2p_interactions_per_s": {k: cand / (v["p2p_ms"] / 1e3)
                                    for k, v in results.items()},
     }
+    if "fp32_paper_table" in results:
+        rt = results["fp32_paper_table"]
+        line["fp32_paper_table"] = {
+            "value": cand / (rt["ms_per_step"] / 1e3),
+            "ms_per_step": rt["ms_per_step"],
+            "p2p_tflops": cand * FLOPS_PER_PAIR_F32_T2 / (rt["p2p_ms"] / 1e3) / 1e12,
+            "frac_of_fp32_peak": cand * FLOPS_PER_PAIR_F32_T2
+            / (rt["p2p_ms"] / 1e3) / 1e12 / PEAK_FP32_TFLOPS,
+        }
     if "fp64" in results:
         r64 = results["fp64"]
         line["fp64"] = {

@@ -14,7 +14,7 @@ import torch
 from . import binding as B
 
 _PREC = {"fp64": B.PMFMM_FP64, "fp32": B.PMFMM_FP32}
-_TRUNC = {"exact": B.TRUNC_EXACT, "table": B.TRUNC_TABLE}
+_TRUNC = {"exact": B.TRUNC_EXACT, "table": B.TRUNC_TABLE, "r2": B.TRUNC_R2}
 _ROUND = {"nearest": B.ROUND_NEAREST, "floor": B.ROUND_FLOOR}
 
 

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpmfmm.so")
 
 PMFMM_FP64, PMFMM_FP32 = 0, 1
-TRUNC_EXACT, TRUNC_TABLE = 0, 1
+TRUNC_EXACT, TRUNC_TABLE, TRUNC_R2 = 0, 1, 2
 ROUND_NEAREST, ROUND_FLOOR = 0, 1
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE",

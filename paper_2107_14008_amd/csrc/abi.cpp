@@ -53,7 +53,15 @@ bool valid_geometry(const pmfmm_params& p, std::string& why) {
 
 bool valid_eval(const pmfmm_params& p, std::string& why) {
     if (p.precision != PMFMM_FP64 && p.precision != PMFMM_FP32) { why = "precision must be FP64 or FP32"; return false; }
-    if (p.trunc != PMFMM_TRUNC_EXACT && p.trunc != PMFMM_TRUNC_TABLE) { why = "trunc must be EXACT or TABLE"; return false; }
+    if (p.trunc != PMFMM_TRUNC_EXACT && p.trunc != PMFMM_TRUNC_TABLE && p.trunc != PMFMM_TRUNC_R2) {
+        why = "trunc must be EXACT, TABLE or R2";
+        return false;
+    }
+    if (p.trunc == PMFMM_TRUNC_R2) {
+        if (p.precision != PMFMM_FP32) { why = "the r^2 segment table is a float32 form"; return false; }
+        if (p.table_level < 1 || p.table_level > 3) { why = "table_level (degree) must be in 1..3 for R2"; return false; }
+        if (p.table_size < 64 || p.table_size > 4096) { why = "table_size (segments) must be in 64..4096 for R2"; return false; }
+    }
     if (p.table_level < 0 || p.table_level > 4) { why = "table_level must be in 0..4"; return false; }
     if (p.table_round != PMFMM_ROUND_NEAREST && p.table_round != PMFMM_ROUND_FLOOR) { why = "table_round must be NEAREST or FLOOR"; return false; }
     const int max_tab = p.precision == PMFMM_FP64 ? 2048 : 4096;
@@ -70,7 +78,76 @@ bool valid_eval(const pmfmm_params& p, std::string& why) {
 
 int mode_of(const pmfmm_params& p) {
     if (p.precision == PMFMM_FP64) return p.trunc == PMFMM_TRUNC_TABLE ? pmfmm::kFP64Table : pmfmm::kFP64Exact;
+    if (p.trunc == PMFMM_TRUNC_R2) return pmfmm::kFP32R2;
     return p.trunc == PMFMM_TRUNC_TABLE ? pmfmm::kFP32Table : pmfmm::kFP32Exact;
+}
+
+bool uses_r2(const pmfmm_params& p) { return p.precision == PMFMM_FP32 && p.trunc == PMFMM_TRUNC_R2; }
+
+// x_c = r_cut / 2 r_s, which the r^2 table needs to be one for all boxes
+// (up to rounding: r_cut = 4.5 r_s over many r_s gives x_c within an ulp).
+bool same_xc(double rc_a, double rs_a, double rc_b, double rs_b) {
+    const double a = rc_a / (2.0 * rs_a), b = rc_b / (2.0 * rs_b);
+    return std::fabs(a - b) <= 1e-12 * std::fabs(a);
+}
+
+bool one_xc(const std::vector<pmfmm::BoxParams>& boxes) {
+    for (const auto& b : boxes)
+        if (!same_xc(b.r_cut, b.r_s, boxes[0].r_cut, boxes[0].r_s)) return false;
+    return true;
+}
+
+double truncation_T(double x) {
+    return std::erfc(x) + 1.12837916709551257390 * x * std::exp(-x * x);
+}
+
+// Table of the float32 r^2 form: segment k covers s = r'^2 in [k, k + 1),
+// i.e. x^2 in [k kappa, (k + 1) kappa) with kappa = x_c^2 / n; on it T is
+// the polynomial of degree `deg` interpolating T at the Chebyshev nodes of
+// t = s - k in [0, 1], re-expanded in s itself (the kernel evaluates it at
+// s with no segment offset).  Row n (beyond the cutoff) is zero.
+std::vector<unsigned char> build_r2_table(int n, int deg, double xc) {
+    const double kappa = xc * xc / n;
+    std::vector<unsigned char> out((size_t)16 * (n + 1) + 16, 0);
+    float* f = reinterpret_cast<float*>(out.data());
+    const int m = deg + 1;
+    for (int k = 0; k < n; ++k) {
+        double V[4][5];
+        for (int i = 0; i < m; ++i) {
+            const double t = 0.5 - 0.5 * std::cos(M_PI * (i + 0.5) / m);
+            double tp = 1.0;
+            for (int j = 0; j < m; ++j) {
+                V[i][j] = tp;
+                tp *= t;
+            }
+            V[i][m] = truncation_T(std::sqrt((k + t) * kappa));
+        }
+        // Gaussian elimination with partial pivoting on the (m x m) system
+        for (int c = 0; c < m; ++c) {
+            int piv = c;
+            for (int r = c + 1; r < m; ++r)
+                if (std::fabs(V[r][c]) > std::fabs(V[piv][c])) piv = r;
+            for (int j = 0; j <= m; ++j) std::swap(V[c][j], V[piv][j]);
+            for (int r = c + 1; r < m; ++r) {
+                const double q = V[r][c] / V[c][c];
+                for (int j = c; j <= m; ++j) V[r][j] -= q * V[c][j];
+            }
+        }
+        double cl[4] = {0, 0, 0, 0};
+        for (int c = m - 1; c >= 0; --c) {
+            double acc = V[c][m];
+            for (int j = c + 1; j < m; ++j) acc -= V[c][j] * cl[j];
+            cl[c] = acc / V[c][c];
+        }
+        // p(s) = sum_j cl_j (s - k)^j = sum_i a_i s^i
+        static const double binom[4][4] = {{1, 0, 0, 0}, {1, 1, 0, 0}, {1, 2, 1, 0}, {1, 3, 3, 1}};
+        for (int i = 0; i < 4; ++i) {
+            double acc = 0.0;
+            for (int j = i; j < m; ++j) acc += cl[j] * binom[j][i] * std::pow(-(double)k, j - i);
+            f[4 * k + i] = i < m ? (float)acc : 0.0f;
+        }
+    }
+    return out;
 }
 
 // Coefficients of Eq. (int) in table units e = (x - x_i) / h:
@@ -78,7 +155,8 @@ int mode_of(const pmfmm_params& p) {
 //   a_1 = x_i^2 E_i, a_2 = -x_i (x_i^2 - 1) E_i,
 //   a_3 = (2/3 x_i^4 - 5/3 x_i^2 + 1/3) E_i, a_4 = -x_i (x_i^4 / 3 - 3/2 x_i^2 + 1) E_i,
 //   E_i = -4 exp(-x_i^2) / sqrt(pi), x_i = i h, h = 3 / n_tab.
-std::vector<unsigned char> build_table(const pmfmm_params& p) {
+std::vector<unsigned char> build_table(const pmfmm_params& p, double xc) {
+    if (uses_r2(p)) return build_r2_table(p.table_size, p.table_level, xc);
     const int n = p.table_size;
     const double h = 3.0 / n;
     const double inv_sqrt_pi = 0.56418958354775628695;
@@ -232,6 +310,9 @@ int check_box_params(int32_t nbox, const pmfmm_params* per_box, const int64_t* c
         if (!valid_geometry(per_box[b], why)) return fail(PMFMM_EINVAL, "box " + std::to_string(b) + ": " + why);
         if (eval.trunc == PMFMM_TRUNC_TABLE && per_box[b].r_cut / (2.0 * per_box[b].r_s) > 3.0)
             return fail(PMFMM_EINVAL, "box " + std::to_string(b) + ": the table covers r <= 6 r_s only");
+        if (uses_r2(eval) && !same_xc(per_box[b].r_cut, per_box[b].r_s, per_box[0].r_cut, per_box[0].r_s))
+            return fail(PMFMM_EINVAL, "box " + std::to_string(b) +
+                                          ": the r^2 table needs one r_cut / r_s for all boxes");
         if (counts[b] < 1) return fail(PMFMM_EINVAL, "box " + std::to_string(b) + ": needs at least one particle");
         const pmfmm_params& q = per_box[b];
         boxes.push_back(pmfmm::BoxParams{q.box, q.r_s, q.r_cut, q.G, q.theta, q.max_leaf, q.order});
@@ -267,7 +348,9 @@ int upload_items(pmfmm_ctx* ctx, hipStream_t s) {
 
 int upload_table(pmfmm_ctx* ctx, hipStream_t s) {
     if (!ctx->table_dirty) return PMFMM_OK;
-    ctx->table_host = build_table(ctx->p);
+    const double xc = ctx->plan.boxes.empty() ? ctx->p.r_cut / (2.0 * ctx->p.r_s)
+                                              : ctx->plan.boxes[0].r_cut / (2.0 * ctx->plan.boxes[0].r_s);
+    ctx->table_host = build_table(ctx->p, xc);
     int rc = upload(ctx->d.table, ctx->table_host, s);
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(s));
@@ -283,10 +366,14 @@ std::vector<pmfmm::BoxDev> box_table(const pmfmm_ctx* ctx) {
         d.alpha = 1.0 / (2.0 * b.r_s);
         d.rc2 = b.r_cut * b.r_cut;
         d.G = b.G;
-        d.alpha_f = (float)d.alpha;
-        d.rc2_f = (float)d.rc2;
+        // float32 offsets in units of 1 / sigma (see BoxDev)
+        const bool r2 = uses_r2(ctx->p);
+        d.sigma = r2 ? std::sqrt(ctx->p.table_size / d.rc2) : 1.0;
+        d.alpha_f = (float)(d.alpha / d.sigma);
+        d.rc2_f = r2 ? (float)ctx->p.table_size : (float)d.rc2;
+        d.tiny_f = d.rc2_f * 1e-14f;
         d.tab_scale = d.alpha * (ctx->p.table_size / 3.0);
-        d.tab_scale_f = (float)d.tab_scale;
+        d.tab_scale_f = (float)(d.tab_scale / d.sigma);
         d.order = (b.order >= 0 && b.theta > 0.0) ? b.order : -1;
         out.push_back(d);
     }
@@ -373,8 +460,10 @@ int do_upload(pmfmm_ctx* ctx, const double* pos, const double* mass, int32_t on_
     return PMFMM_OK;
 }
 
+// Table forms: 16 waves share one LDS copy of the table (a 2048-segment r^2
+// table is 33 KB; with 4-wave groups LDS would cap a CU at 16 waves).
 int default_wg_waves(int mode) {
-    return mode == pmfmm::kFP64Table ? 16 : 4;
+    return (mode == pmfmm::kFP64Table || mode == pmfmm::kFP32Table || mode == pmfmm::kFP32R2) ? 16 : 4;
 }
 
 pmfmm::FarArgs far_args(pmfmm_ctx* ctx) {
@@ -670,8 +759,14 @@ int pmfmm_set_eval(pmfmm_ctx* ctx, const pmfmm_params* p) {
     if (p->trunc == PMFMM_TRUNC_TABLE && ctx->planned)
         for (const auto& b : ctx->plan.boxes)
             if (b.r_cut / (2.0 * b.r_s) > 3.0) return fail(PMFMM_EINVAL, "the table covers r <= 6 r_s only");
+    if (uses_r2(*p) && ctx->planned && !one_xc(ctx->plan.boxes))
+        return fail(PMFMM_EINVAL, "the r^2 table needs one r_cut / r_s for all boxes");
     const bool table_change = p->precision != ctx->p.precision || p->table_size != ctx->p.table_size ||
-                              p->table_round != ctx->p.table_round || p->table_level != ctx->p.table_level;
+                              p->table_round != ctx->p.table_round || p->table_level != ctx->p.table_level ||
+                              p->trunc != ctx->p.trunc;
+    // the float32 offsets' scale (x32) depends on these
+    const bool sigma_change = uses_r2(*p) != uses_r2(ctx->p) ||
+                              (uses_r2(*p) && p->table_size != ctx->p.table_size);
     const bool chunk_change = p->chunk != ctx->p.chunk;
     ctx->p.precision = p->precision;
     ctx->p.trunc = p->trunc;
@@ -702,6 +797,11 @@ int pmfmm_set_eval(pmfmm_ctx* ctx, const pmfmm_params* p) {
         // per-box constants depend on table_size
         int rc = upload(ctx->d.boxes, box_table(ctx), nullptr);
         if (rc) return rc;
+        if (sigma_change)
+            HIP_TRY(pmfmm::launch_rescale_x32(ctx->d.leaf.as<int4>(), ctx->d.leafc.as<double4>(),
+                                              ctx->d.boxes.as<pmfmm::BoxDev>(), ctx->d.x64.as<double4>(),
+                                              ctx->d.x32.as<float4>(), (int32_t)ctx->plan.leaf_count.size(),
+                                              nullptr));
         HIP_TRY(hipStreamSynchronize(nullptr));
     }
     return PMFMM_OK;
@@ -741,7 +841,7 @@ int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream) {
     a.n_tab = ctx->p.table_size;
     a.level = ctx->p.table_level;
     a.round_floor = ctx->p.table_round == PMFMM_ROUND_FLOOR;
-    const bool tab = mode == pmfmm::kFP32Table || mode == pmfmm::kFP64Table;
+    const bool tab = mode == pmfmm::kFP32Table || mode == pmfmm::kFP64Table || mode == pmfmm::kFP32R2;
     const size_t lds = tab ? ctx->table_host.size() : 0;
     const int wg = ctx->p.wg_waves > 0 ? ctx->p.wg_waves : default_wg_waves(mode);
     int grid = ctx->p.grid_wgs;

@@ -61,6 +61,9 @@ __device__ __forceinline__ void adj_pair_f64(const double4 q, const double4 wl, 
     gm -= g * dwl;
 }
 
+// Offsets in units of 1 / sigma (see BoxDev): g and h come out as
+// sigma^-3 g and sigma^-5 h, d as sigma d, so A and B carry a factor
+// sigma^-3 and gm sigma^-2, which the caller takes back out.
 __device__ __forceinline__ void adj_pair_f32(const float4 q, const float4 wl, float px, float py,
                                              float pz, float4 wk, float rc2, float alpha,
                                              float* A, float* Bv, float& gm) {
@@ -122,9 +125,9 @@ adjoint_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                 const double4 cj = leafc[jl];
                 const double sx = (double)(s % 3 - 1) * bx.L, sy = (double)((s / 3) % 3 - 1) * bx.L,
                              sz = (double)(s / 9 - 1) * bx.L;
-                const float px = pv.x - (float)((cj.x - ci.x) + sx);
-                const float py = pv.y - (float)((cj.y - ci.y) + sy);
-                const float pz = pv.z - (float)((cj.z - ci.z) + sz);
+                const float px = pv.x - (float)(((cj.x - ci.x) + sx) * bx.sigma);
+                const float py = pv.y - (float)(((cj.y - ci.y) + sy) * bx.sigma);
+                const float pz = pv.z - (float)(((cj.z - ci.z) + sz) * bx.sigma);
                 const float4* __restrict__ src = x32 + uni(lj.x);
                 const float4* __restrict__ wsrc = w32 + uni(lj.x);
                 const int nj = uni(lj.y);
@@ -137,6 +140,12 @@ adjoint_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                 }
                 gm += (double)g;
             }
+            const double s2 = bx.sigma * bx.sigma, s3 = s2 * bx.sigma;
+            for (int c = 0; c < 3; ++c) {
+                A[c] *= s3;
+                Bv[c] *= s3;
+            }
+            gm *= s2;
         } else {
             const double4 pv = x64[pk];
             const double4 wk = w64[pk];
@@ -225,7 +234,7 @@ hipError_t launch_gather_w(const double* w, const int32_t* perm, double4* w64, f
 hipError_t launch_adjoint(int mode, const AdjArgs& a, int wg_waves, int grid_wgs, size_t,
                           hipStream_t s) {
     if (a.n_items == 0) return hipSuccess;
-    if (mode == kFP32Exact || mode == kFP32Table)
+    if (is_fp32(mode))
         hipLaunchKernelGGL(adjoint_kernel<true>, dim3(grid_wgs), dim3(64 * wg_waves), 0, s, a.x64,
                            a.x32, a.w64, a.w32, a.leaf, a.leafc, a.p2p_js, a.items, a.queue,
                            a.n_items, a.counter, a.partial, a.boxes);
@@ -245,8 +254,7 @@ hipError_t launch_adj_reduce(const AdjReduceArgs& a, hipStream_t s) {
 }
 
 int adjoint_blocks_per_cu(int mode, int wg_waves, size_t) {
-    return (mode == kFP32Exact || mode == kFP32Table) ? occ_adj<true>(wg_waves)
-                                                      : occ_adj<false>(wg_waves);
+    return is_fp32(mode) ? occ_adj<true>(wg_waves) : occ_adj<false>(wg_waves);
 }
 
 }  // namespace pmfmm

@@ -2,7 +2,8 @@
 //
 // Layout in HBM (all arrays global over a batch of boxes):
 //   x64[k]  double4 (x, y, z, m)            particle k in leaf order
-//   x32[k]  float4  (x - c_leaf, m)         single-precision cell-relative form
+//   x32[k]  float4  ((x - c_leaf) sigma, m) single-precision cell-relative form,
+//                                           in units of 1 / sigma of its box
 //   leaf[l] int4    (first, count, box, cell)
 //   leafc[l] double4 (centre x, y, z, 0)    expansion / offset centre
 //   p2p_row[l] .. p2p_row[l+1]              TaskGroup rows of i leaf l
@@ -17,17 +18,35 @@
 
 namespace pmfmm {
 
-enum Mode : int { kFP64Exact = 0, kFP64Table = 1, kFP32Exact = 2, kFP32Table = 3 };
+enum Mode : int {
+    kFP64Exact = 0,
+    kFP64Table = 1,
+    kFP32Exact = 2,
+    kFP32Table = 3,
+    kFP32R2 = 4     // float32, segment table over r^2 (cutoff at the last row)
+};
 
+constexpr bool is_fp32(int mode) { return mode >= kFP32Exact; }
+
+// Per-box constants.  The float32 forms work on offsets scaled by sigma
+// (x32 and the per-task centre offsets): sigma = 1, except for the r^2
+// segment table, where sigma^2 = n_seg / r_cut^2 puts segment k of the
+// table at r'^2 in [k, k + 1) and the cutoff at r'^2 = n_seg.  The float
+// constants below are in those units; results are scaled back by sigma^2
+// (forces) or sigma^3 / sigma^2 (adjoint).
 struct BoxDev {
     double L;        // box side
     double alpha;    // 1 / (2 r_s)
     double rc2;      // r_cut * r_cut
     double G;
-    float alpha_f, rc2_f, tab_scale_f, pad_f;
+    float alpha_f;   // alpha / sigma
+    float rc2_f;     // r_cut^2 sigma^2 (exactly n_seg for the r^2 table)
+    float tab_scale_f;  // tab_scale / sigma
+    float tiny_f;    // rc2_f * 1e-14: float32 r^2 clamp below (coincident pairs)
     double tab_scale;  // n_tab / 3 / (2 r_s): x-table units per unit distance
     int32_t order;     // expansion order p of this box (< 0: no far field)
     int32_t pad;
+    double sigma;      // scale of the float32 offsets
 };
 
 struct P2PArgs {
@@ -128,6 +147,9 @@ hipError_t launch_zero_i32(int32_t* p, int32_t n, hipStream_t s);
 hipError_t launch_p2p(int mode, const P2PArgs& a, int wg_waves, int grid_wgs,
                       size_t lds_bytes, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+// Recomputes x32 from x64 and the leaf centres with the boxes' current sigma.
+hipError_t launch_rescale_x32(const int4* leaf, const double4* leafc, const BoxDev* boxes,
+                              const double4* x64, float4* x32, int32_t n_leaves, hipStream_t s);
 hipError_t launch_gather_w(const double* w, const int32_t* perm, double4* w64,
                            float4* w32, int32_t n, hipStream_t s);
 hipError_t launch_adjoint(int mode, const AdjArgs& a, int wg_waves, int grid_wgs,

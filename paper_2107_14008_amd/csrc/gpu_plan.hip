@@ -993,7 +993,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
 std::string gpu_make_items(DevPlan& d, const Plan& topo, int64_t n_p2p, int chunk, hipStream_t s,
                            PlanCounts& out) {
     const int64_t nl = (int64_t)topo.leaf_cell.size();
-    if (chunk <= 0) chunk = (int)std::max<int64_t>(4, (n_p2p + 16383) / 16384);
+    if (chunk <= 0) chunk = kAutoChunk;
     TRY(d.cost.ensure((nl + 1) * 4));
     TRY(d.leaf_slot.ensure((nl + 1) * 4));
     TRY(d.tile_sums.ensure(sort_tiles(nl + 1) * 4 + 16));

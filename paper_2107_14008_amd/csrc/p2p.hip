@@ -127,19 +127,18 @@ __device__ __forceinline__ void pair_f64_table(const double4 q, double xi, doubl
 
 // float32 on cell-relative offsets: (px, py, pz) = target offset minus the
 // source leaf's offset, so d = q.xyz - p.  r^2 is clamped into
-// [kTinyR2, r_cut^2] before 1/r: pairs outside the cutoff are masked out
+// [tiny, r_cut^2] before 1/r (tiny = 1e-14 r_cut^2, below float32
+// resolution of the offsets): pairs outside the cutoff are masked out
 // anyway, the clamp keeps the table index in range, and a coincident pair
 // (d = 0) then contributes g * 0 = 0 with a finite g, which is what the
 // r^2 > 0 test of the definition gives.
-constexpr float kTinyR2 = 1e-20f;
-
 __device__ __forceinline__ void pair_f32_exact(const float4 q, float px, float py, float pz,
-                                               float rc2, float alpha, float& ax, float& ay,
-                                               float& az) {
+                                               float rc2, float tiny, float alpha, float& ax,
+                                               float& ay, float& az) {
     const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
     const bool ok = r2 < rc2;
-    const float r2c = __builtin_amdgcn_fmed3f(r2, kTinyR2, rc2);
+    const float r2c = __builtin_amdgcn_fmed3f(r2, tiny, rc2);
     const float idr = __builtin_amdgcn_rsqf(r2c);
     const float x = r2c * idr * alpha;
     const float T = erfcf(x) + kTwoOverSqrtPiF * x * expf(-x * x);
@@ -156,14 +155,14 @@ __device__ __forceinline__ void pair_f32_exact(const float4 q, float px, float p
 // is needed; the table carries one node past x = 3.
 template <int LEVEL>
 __device__ __forceinline__ void pair_f32_table(const float4 q, float px, float py, float pz,
-                                               float rc2, float scale, float rnd,
+                                               float rc2, float tiny, float scale, float rnd,
                                                const float4* __restrict__ t03,
                                                const float* __restrict__ t4, float& ax, float& ay,
                                                float& az) {
     const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
     const bool ok = r2 < rc2;
-    const float r2c = __builtin_amdgcn_fmed3f(r2, kTinyR2, rc2);
+    const float r2c = __builtin_amdgcn_fmed3f(r2, tiny, rc2);
     const float idr = __builtin_amdgcn_rsqf(r2c);
     const float u = fmaf(r2c * idr, scale, rnd);
     const int d = (int)u;
@@ -187,7 +186,39 @@ __device__ __forceinline__ void pair_f32_table(const float4 q, float px, float p
     az = fmaf(g, dz, az);
 }
 
+// Segment table over r^2 (not the paper's table; see the host builder in
+// abi.cpp): offsets are in units where r_cut^2 = n_seg, so s = r'^2 indexes
+// the segment directly, k = floor(s), and each row holds the polynomial of T
+// on [k, k + 1) in s itself (no offset inside the segment).  Row n_seg is
+// zero, and s is clamped to at most n_seg, so a pair beyond the cutoff gets
+// T = 0 with no compare.  T depends on r only through s, so 1/r is needed
+// only for 1/r^3.
+template <int LEVEL>
+__device__ __forceinline__ void pair_f32_r2(const float4 q, float px, float py, float pz,
+                                            float smax, float tiny,
+                                            const float4* __restrict__ tab, float& ax,
+                                            float& ay, float& az) {
+    const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const float sc = __builtin_amdgcn_fmed3f(r2, tiny, smax);
+    const float4 c = tab[(int)sc];
+    float T;
+    if constexpr (LEVEL == 1) {
+        T = fmaf(c.y, sc, c.x);
+    } else if constexpr (LEVEL == 2) {
+        T = fmaf(fmaf(c.z, sc, c.y), sc, c.x);
+    } else {
+        T = fmaf(fmaf(fmaf(c.w, sc, c.z), sc, c.y), sc, c.x);
+    }
+    const float idr = __builtin_amdgcn_rsqf(sc);
+    const float g = q.w * T * (idr * idr * idr);
+    ax = fmaf(g, dx, ax);
+    ay = fmaf(g, dy, ay);
+    az = fmaf(g, dz, az);
+}
+
 // LDS table layouts (bytes), matching the host builder in abi.cpp:
+//   float32 r^2 segments: float4 (c0, c1, c2, c3) [n_seg + 1]
 //   float32: float4 c0..c3 [n_tab + 1], then float c4 [n_tab + 1]
 //   float64: double2 (c0, c1) [n_tab], double2 (c2, c3) [n_tab], double c4 [n_tab]
 __device__ __forceinline__ void load_table(unsigned char* lds, const void* __restrict__ table,
@@ -208,7 +239,7 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
            const void* __restrict__ table, int32_t n_tab, int32_t table_bytes,
            int32_t round_floor) {
     extern __shared__ __align__(16) unsigned char lds[];
-    constexpr bool kTable = (MODE == kFP64Table) || (MODE == kFP32Table);
+    constexpr bool kTable = (MODE == kFP64Table) || (MODE == kFP32Table) || (MODE == kFP32R2);
     if constexpr (kTable) load_table(lds, table, table_bytes);
     const int lane = threadIdx.x & 63;
     const int dmax = n_tab - 1;
@@ -228,9 +259,10 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
         const double4 ci = leafc[il];
         double ax = 0.0, ay = 0.0, az = 0.0;
 
-        if constexpr (MODE == kFP32Exact || MODE == kFP32Table) {
+        if constexpr (is_fp32(MODE)) {
             const float4 pv = x32[pi];
-            const float rc2 = bx.rc2_f;
+            const float rc2 = bx.rc2_f, tiny = bx.tiny_f;
+            const double sig = bx.sigma;
             const float rnd = round_floor ? 0.f : 0.5f;
             const float4* t03 = reinterpret_cast<const float4*>(lds);
             const float* t4 = reinterpret_cast<const float*>(lds + 16 * (n_tab + 1));
@@ -241,25 +273,33 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                 const double4 cj = leafc[jl];
                 double sx, sy, sz;
                 shift_of(js & 31, bx.L, sx, sy, sz);
-                const float px = pv.x - (float)((cj.x - ci.x) + sx);
-                const float py = pv.y - (float)((cj.y - ci.y) + sy);
-                const float pz = pv.z - (float)((cj.z - ci.z) + sz);
+                const float px = pv.x - (float)(((cj.x - ci.x) + sx) * sig);
+                const float py = pv.y - (float)(((cj.y - ci.y) + sy) * sig);
+                const float pz = pv.z - (float)(((cj.z - ci.z) + sz) * sig);
                 const float4* __restrict__ src = x32 + uni(lj.x);
                 const int nj = uni(lj.y);
                 float fx = 0.f, fy = 0.f, fz = 0.f;
                 if constexpr (MODE == kFP32Exact) {
                     for (int k = 0; k < nj; ++k)
-                        pair_f32_exact(src[k], px, py, pz, rc2, bx.alpha_f, fx, fy, fz);
+                        pair_f32_exact(src[k], px, py, pz, rc2, tiny, bx.alpha_f, fx, fy, fz);
+                } else if constexpr (MODE == kFP32Table) {
+#pragma unroll 4
+                    for (int k = 0; k < nj; ++k)
+                        pair_f32_table<LEVEL>(src[k], px, py, pz, rc2, tiny, bx.tab_scale_f, rnd,
+                                              t03, t4, fx, fy, fz);
                 } else {
 #pragma unroll 4
                     for (int k = 0; k < nj; ++k)
-                        pair_f32_table<LEVEL>(src[k], px, py, pz, rc2, bx.tab_scale_f, rnd, t03,
-                                              t4, fx, fy, fz);
+                        pair_f32_r2<LEVEL>(src[k], px, py, pz, rc2, tiny, t03, fx, fy, fz);
                 }
                 ax += (double)fx;
                 ay += (double)fy;
                 az += (double)fz;
             }
+            const double s2 = sig * sig;
+            ax *= s2;
+            ay *= s2;
+            az *= s2;
         } else {
             const double4 pv = x64[pi];
             const double rc2 = bx.rc2;
@@ -360,7 +400,27 @@ gather_kernel(const double* __restrict__ pos_in, const double* __restrict__ mass
     const double m = mass_in[o];
     x64[k] = make_double4(x, y, z, m);
     const double4 c = leafc[l];
-    x32[k] = make_float4((float)(x - c.x), (float)(y - c.y), (float)(z - c.z), (float)m);
+    const double sig = boxes[li.z].sigma;
+    x32[k] = make_float4((float)((x - c.x) * sig), (float)((y - c.y) * sig),
+                         (float)((z - c.z) * sig), (float)m);
+}
+
+// x32 again from x64 after the boxes' sigma changed.
+__global__ void __launch_bounds__(256)
+rescale_x32_kernel(const int4* __restrict__ leaf, const double4* __restrict__ leafc,
+                   const BoxDev* __restrict__ boxes, const double4* __restrict__ x64,
+                   float4* __restrict__ x32, int32_t n_leaves) {
+    const int l = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (l >= n_leaves) return;
+    const int4 li = leaf[l];
+    if (lane >= li.y) return;
+    const int k = li.x + lane;
+    const double4 p = x64[k];
+    const double4 c = leafc[l];
+    const double sig = boxes[li.z].sigma;
+    x32[k] = make_float4((float)((p.x - c.x) * sig), (float)((p.y - c.y) * sig),
+                         (float)((p.z - c.z) * sig), (float)p.w);
 }
 
 __global__ void zero_i32_kernel(int32_t* p, int32_t n) {
@@ -402,6 +462,12 @@ hipError_t launch_p2p(int mode, const P2PArgs& a, int wg_waves, int grid_wgs, si
                 case 3: return launch_one<kFP32Table, 3>(a, wg_waves, grid_wgs, lds, s);
                 default: return launch_one<kFP32Table, 4>(a, wg_waves, grid_wgs, lds, s);
             }
+        case kFP32R2:
+            switch (a.level) {
+                case 1: return launch_one<kFP32R2, 1>(a, wg_waves, grid_wgs, lds, s);
+                case 2: return launch_one<kFP32R2, 2>(a, wg_waves, grid_wgs, lds, s);
+                default: return launch_one<kFP32R2, 3>(a, wg_waves, grid_wgs, lds, s);
+            }
         case kFP64Table:
             switch (a.level) {
                 case 0: return launch_one<kFP64Table, 0>(a, wg_waves, grid_wgs, lds, s);
@@ -419,6 +485,7 @@ int p2p_blocks_per_cu(int mode, int wg_waves, size_t lds) {
         case kFP64Exact: return occ_one<kFP64Exact, 0>(wg_waves, 0);
         case kFP32Exact: return occ_one<kFP32Exact, 0>(wg_waves, 0);
         case kFP32Table: return occ_one<kFP32Table, 2>(wg_waves, lds);
+        case kFP32R2: return occ_one<kFP32R2, 2>(wg_waves, lds);
         default: return occ_one<kFP64Table, 4>(wg_waves, lds);
     }
 }
@@ -436,6 +503,14 @@ hipError_t launch_gather(const GatherArgs& a, const double* /*unused*/, hipStrea
     const int wgs = (a.n_leaves + 3) / 4;
     hipLaunchKernelGGL(gather_kernel, dim3(wgs), dim3(256), 0, s, a.pos_in, a.mass_in, a.perm,
                        a.leaf, a.leafc, a.boxes, a.x64, a.x32, a.n_leaves);
+    return hipGetLastError();
+}
+
+hipError_t launch_rescale_x32(const int4* leaf, const double4* leafc, const BoxDev* boxes,
+                              const double4* x64, float4* x32, int32_t n_leaves, hipStream_t s) {
+    if (n_leaves == 0) return hipSuccess;
+    hipLaunchKernelGGL(rescale_x32_kernel, dim3((n_leaves + 3) / 4), dim3(256), 0, s, leaf, leafc,
+                       boxes, x64, x32, n_leaves);
     return hipGetLastError();
 }
 

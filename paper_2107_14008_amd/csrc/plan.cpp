@@ -548,10 +548,7 @@ void make_topology(Plan& plan, const std::vector<BoxParams>& boxes,
 void make_items(Plan& plan, int chunk) {
     const int64_t n_leaves = (int64_t)plan.leaf_count.size();
     const int64_t n_tasks = (int64_t)plan.p2p_j.size();
-    if (chunk <= 0) {
-        const int64_t target = 16384;
-        chunk = (int)std::max<int64_t>(4, (n_tasks + target - 1) / target);
-    }
+    if (chunk <= 0) chunk = kAutoChunk;
     plan.items.clear();
     plan.leaf_slot_begin.assign(n_leaves + 1, 0);
     std::vector<int64_t> cost;

@@ -71,6 +71,12 @@ std::string make_plan(Plan& plan, const std::vector<BoxParams>& boxes,
 void make_topology(Plan& plan, const std::vector<BoxParams>& boxes,
                    const std::vector<int64_t>& counts);
 
+// Tasks per work item when the caller leaves the choice to the library: an
+// item then holds at most 16 x 64 x 64 pair evaluations, a few percent of a
+// wavefront's share of a large launch, so the longest-first queue ends with
+// little idle time (measured best at 128^3 for all float32 forms).
+constexpr int kAutoChunk = 16;
+
 // (Re)cuts the P2P rows into work items of at most `chunk` tasks
 // (0 = automatic) and orders the queue by decreasing pair count.
 void make_items(Plan& plan, int chunk);

@@ -61,6 +61,29 @@ def test_fp64_table_size_limit():
     B.Context(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE, table_size=4096).close()
 
 
+def test_r2_table_is_a_float32_form():
+    for bad in (dict(precision=B.PMFMM_FP64, trunc=B.TRUNC_R2),
+                dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_level=0),
+                dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_level=4),
+                dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_size=32)):
+        with pytest.raises(B.PmfmmError):
+            B.Context(**bad)
+    B.Context(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_size=2048,
+              table_level=2).close()
+
+
+def test_r2_table_needs_one_cutoff_ratio():
+    ctx = B.Context(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_size=1024,
+                    table_level=2)
+    a = B.make_params(box=10.0, r_s=0.5, r_cut=2.25, max_leaf=8)
+    b = B.make_params(box=12.0, r_s=0.6, r_cut=2.7, max_leaf=8)     # same x_c
+    c = B.make_params(box=12.0, r_s=0.6, r_cut=3.0, max_leaf=8)
+    pos = np.random.default_rng(0).uniform(0, 10, (30, 3))
+    with pytest.raises(B.PmfmmError, match="r_cut / r_s"):
+        ctx.plan_batch([a, c], [10, 20], pos, np.ones(30))
+    ctx.plan_batch([a, b], [10, 20], pos, np.ones(30))
+
+
 def test_plan_rejects_bad_particles():
     ctx = B.Context(box=10.0, r_s=0.5, r_cut=2.25, max_leaf=8)
     pos = np.random.default_rng(0).uniform(0, 10, (50, 3))

@@ -36,7 +36,8 @@ def run_batch(boxes, **ev):
 
 @pytest.mark.parametrize("prec,trunc", [(B.PMFMM_FP64, B.TRUNC_EXACT),
                                         (B.PMFMM_FP32, B.TRUNC_TABLE),
-                                        (B.PMFMM_FP32, B.TRUNC_EXACT)])
+                                        (B.PMFMM_FP32, B.TRUNC_EXACT),
+                                        (B.PMFMM_FP32, B.TRUNC_R2)])
 def test_batch_against_oracle(boxes, prec, trunc):
     print(f"case: batch of {len(boxes)} boxes prec {prec} trunc {trunc}",
           flush=True)

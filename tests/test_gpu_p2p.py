@@ -104,6 +104,37 @@ def test_fp32_table(c1, level, n_tab, rnd):
     check_fp32(acc, ref)
 
 
+@pytest.mark.parametrize("level,n_seg", [(2, 2048), (1, 4096), (3, 512),
+                                         (2, 1024)])
+def test_fp32_r2_table(c1, level, n_seg):
+    w, ref = c1
+    print(f"case: uniform 32^3 fp32 r^2 table {n_seg} degree {level}",
+          flush=True)
+    acc, _ = gpu_forward(w.pos, w.mass, w.box, w.r_s, w.r_cut, w.max_leaf,
+                         precision=B.PMFMM_FP32, trunc=B.TRUNC_R2,
+                         table_size=n_seg, table_level=level)
+    check_fp32(acc, ref)
+
+
+def test_fp32_r2_table_clustered_and_coincident(clustered):
+    w, ref = clustered
+    print("case: clustered 24^3 fp32 r^2 table 2048 degree 2", flush=True)
+    acc, _ = gpu_forward(w.pos, w.mass, w.box, w.r_s, w.r_cut, 64,
+                         precision=B.PMFMM_FP32, trunc=B.TRUNC_R2,
+                         table_size=2048, table_level=2)
+    check_fp32(acc, ref)
+    rng = np.random.default_rng(19)
+    pos = rng.uniform(0, 20.0, (2001, 3))
+    pos[50:90] = pos[0]                         # coincident particles
+    m = rng.uniform(0.2, 1.0, 2001) * 1e9       # large masses stay finite
+    print("case: ragged 2001 coincident, fp32 r^2 table", flush=True)
+    acc, _ = gpu_forward(pos, m, 20.0, 0.6, 2.7, 16, precision=B.PMFMM_FP32,
+                         trunc=B.TRUNC_R2, table_size=2048, table_level=2)
+    ref2, _ = direct.all_pairs(pos, m, 20.0, 0.6, 2.7)
+    assert np.all(np.isfinite(acc))
+    check_fp32(acc, ref2)
+
+
 def test_fp32_exact_and_table_clustered(clustered):
     w, ref = clustered
     for trunc in (B.TRUNC_EXACT, B.TRUNC_TABLE):
@@ -130,9 +161,15 @@ def test_reused_context_switching_modes(clustered):
     w, ref = clustered
     acc, ctx = gpu_forward(w.pos, w.mass, w.box, w.r_s, w.r_cut, 64)
     out = torch.empty((len(w.mass), 3), dtype=torch.float64, device="cuda")
+    # the r^2 table works on rescaled float32 offsets: switching into and out
+    # of it rescales them
     for prec, trunc in [(B.PMFMM_FP32, B.TRUNC_TABLE), (B.PMFMM_FP64,
                                                         B.TRUNC_EXACT),
-                        (B.PMFMM_FP32, B.TRUNC_EXACT)]:
+                        (B.PMFMM_FP32, B.TRUNC_R2), (B.PMFMM_FP32,
+                                                     B.TRUNC_EXACT),
+                        (B.PMFMM_FP32, B.TRUNC_R2), (B.PMFMM_FP64,
+                                                     B.TRUNC_EXACT),
+                        (B.PMFMM_FP32, B.TRUNC_TABLE)]:
         ctx.set_eval(precision=prec, trunc=trunc, table_size=1024,
                      table_level=2, chunk=7)
         ctx.forward(out, torch.cuda.current_stream())
@@ -217,7 +254,8 @@ def test_full_size_clustered_2m_sampled(c2):
     out = torch.empty((len(w.mass), 3), dtype=torch.float64, device="cuda")
     for trunc, level, n_tab in [(B.TRUNC_TABLE, 2, 512),
                                 (B.TRUNC_TABLE, 1, 2048),
-                                (B.TRUNC_EXACT, 0, 2048)]:
+                                (B.TRUNC_EXACT, 0, 2048),
+                                (B.TRUNC_R2, 2, 2048)]:
         print(f"case: clustered 128^3 fp32 trunc {trunc} {n_tab} {level}",
               flush=True)
         ctx.set_eval(precision=B.PMFMM_FP32, trunc=trunc, table_size=n_tab,

@@ -247,6 +247,8 @@ struct pmfmm_ctx {
     pmfmm::DevPlan d;
     std::vector<unsigned char> table_host;
     bool table_dirty = true;
+    double table_xc = -1.0;   // r_cut / 2 r_s the r^2 table was built for
+    std::vector<pmfmm::BoxDev> boxes_on_device;   // last upload of d.boxes
     // sizes of the current plan
     int64_t n_items = 0, n_p2p = 0, n_m2l = 0, cand = 0;
     bool far = false;
@@ -346,10 +348,13 @@ int upload_items(pmfmm_ctx* ctx, hipStream_t s) {
     return PMFMM_OK;
 }
 
+// (Re)builds the table when the evaluation parameters changed, or, for the
+// r^2 table, the boxes' r_cut / r_s.
 int upload_table(pmfmm_ctx* ctx, hipStream_t s) {
-    if (!ctx->table_dirty) return PMFMM_OK;
     const double xc = ctx->plan.boxes.empty() ? ctx->p.r_cut / (2.0 * ctx->p.r_s)
                                               : ctx->plan.boxes[0].r_cut / (2.0 * ctx->plan.boxes[0].r_s);
+    if (!ctx->table_dirty && (!uses_r2(ctx->p) || xc == ctx->table_xc)) return PMFMM_OK;
+    ctx->table_xc = xc;
     ctx->table_host = build_table(ctx->p, xc);
     int rc = upload(ctx->d.table, ctx->table_host, s);
     if (rc) return rc;
@@ -380,6 +385,19 @@ std::vector<pmfmm::BoxDev> box_table(const pmfmm_ctx* ctx) {
     return out;
 }
 
+// Uploads the per-box constants unless the device already holds them.
+int upload_boxes(pmfmm_ctx* ctx, hipStream_t s) {
+    std::vector<pmfmm::BoxDev> bt = box_table(ctx);
+    const bool same = ctx->d.boxes.p != nullptr && bt.size() == ctx->boxes_on_device.size() &&
+                      std::memcmp(bt.data(), ctx->boxes_on_device.data(),
+                                  bt.size() * sizeof(pmfmm::BoxDev)) == 0;
+    if (same) return PMFMM_OK;
+    int rc = upload(ctx->d.boxes, bt, s);
+    if (rc) return rc;
+    ctx->boxes_on_device = std::move(bt);
+    return PMFMM_OK;
+}
+
 int prepare_far(pmfmm_ctx* ctx, hipStream_t s);
 
 int do_upload(pmfmm_ctx* ctx, const double* pos, const double* mass, int32_t on_device, hipStream_t s) {
@@ -405,7 +423,7 @@ int do_upload(pmfmm_ctx* ctx, const double* pos, const double* mass, int32_t on_
     if ((rc = upload(ctx->d.leaf, leaf, s))) return rc;
     if ((rc = upload(ctx->d.leafc, leafc, s))) return rc;
     if ((rc = upload(ctx->d.js, js, s))) return rc;
-    if ((rc = upload(ctx->d.boxes, box_table(ctx), s))) return rc;
+    if ((rc = upload_boxes(ctx, s))) return rc;
     HIP_TRY(ctx->d.counter.ensure(64));
     HIP_TRY(ctx->d.x64.ensure((size_t)n * 32));
     HIP_TRY(ctx->d.x32.ensure((size_t)n * 16));
@@ -422,7 +440,6 @@ int do_upload(pmfmm_ctx* ctx, const double* pos, const double* mass, int32_t on_
                         ctx->d.x32.as<float4>(), (int32_t)nl};
     HIP_TRY(pmfmm::launch_gather(g, nullptr, s));
     if ((rc = upload_items(ctx, s))) return rc;
-    ctx->table_dirty = true;
     if ((rc = upload_table(ctx, s))) return rc;
     if (pl.far_field) {
         // far-field arrays
@@ -574,11 +591,12 @@ int gpu_build(pmfmm_ctx* ctx, const std::vector<pmfmm::BoxParams>& boxes, const 
             return fail(PMFMM_EINVAL, "too many tree cells (limit 2^27)");
         const std::vector<pmfmm::BoxDev> bt = box_table(ctx);
         HIP_TRY(pmfmm::upload_topology(ctx->d, ctx->plan, bt.data(), s));
+        ctx->boxes_on_device = bt;
         ctx->topo_counts = cnt;
         ctx->topo_boxes = boxes;
         ctx->topo_on_device = true;
     } else {
-        if ((rc = upload(ctx->d.boxes, box_table(ctx), s))) return rc;
+        if ((rc = upload_boxes(ctx, s))) return rc;
     }
     pmfmm::PlanCounts pc;
     err = pmfmm::gpu_build_plan(ctx->d, ctx->plan, dp, dm, ctx->p.chunk, s, pc);
@@ -599,7 +617,6 @@ int gpu_build(pmfmm_ctx* ctx, const std::vector<pmfmm::BoxParams>& boxes, const 
         HIP_TRY(ctx->d.far.ensure((size_t)n * 3 * sizeof(double)));
         if ((rc = prepare_far(ctx, s))) return rc;
     }
-    ctx->table_dirty = true;
     if ((rc = upload_table(ctx, s))) return rc;
     ctx->planned = true;
     ctx->built = true;
@@ -795,7 +812,7 @@ int pmfmm_set_eval(pmfmm_ctx* ctx, const pmfmm_params* p) {
     }
     if (ctx->built) {
         // per-box constants depend on table_size
-        int rc = upload(ctx->d.boxes, box_table(ctx), nullptr);
+        int rc = upload_boxes(ctx, nullptr);
         if (rc) return rc;
         if (sigma_change)
             HIP_TRY(pmfmm::launch_rescale_x32(ctx->d.leaf.as<int4>(), ctx->d.leafc.as<double4>(),

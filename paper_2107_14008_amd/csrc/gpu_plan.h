@@ -93,11 +93,15 @@ struct PlanCounts {
 
 // Sort / scan primitives (gpu_sort.hip).
 int64_t sort_tiles(int64_t n);
-// 32-bit words of the `hist` scratch radix_sort_u64 needs for n keys.
-int64_t sort_hist_words(int64_t n);
+// 32-bit words of the `hist` scratch radix_sort_u64 needs for nseg
+// segments of n keys.
+int64_t sort_hist_words(int64_t n, int nseg = 1);
+// Stable sort of keys[seg n .. (seg + 1) n) (and vals alongside) for each of
+// the nseg segments, by bits [bit_begin, bit_end) in 8-bit passes; the
+// result ends in the tmp buffers when the pass count is odd.
 hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals,
                           uint32_t* hist, int64_t n, int bit_begin, int bit_end, hipStream_t s,
-                          bool* result_in_tmp);
+                          bool* result_in_tmp, int nseg = 1);
 hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, uint32_t* tile_sums,
                               hipStream_t s);
 

@@ -15,9 +15,10 @@
 // and 512 cells, one workgroup finishes it in LDS (k_orb_fused), so the
 // launches per level are paid only for the top levels.
 //
-// Dual walk: level-synchronous over a frontier of cell pairs; one thread per
-// pair classifies it and appends P2P keys, M2L keys or child pairs with one
-// atomic per wavefront.  The keys (i << 32 | j << 5 | shift) are then sorted,
+// Dual walk: level-synchronous over a frontier of cell pairs (the canonical
+// half of the symmetric walk); one thread per pair classifies it and appends
+// P2P keys, M2L keys (each with its mirror) or child pairs with one atomic
+// per wavefront.  The keys (i << 32 | j << 5 | shift) are then sorted,
 // which yields the canonical (i, j, shift) order and the CSR rows.
 #include <algorithm>
 #include <chrono>
@@ -118,9 +119,11 @@ __global__ void k_cells_level(const int32_t* __restrict__ level, int nd, const i
 }
 
 // split[c] = 1 for the cells the level loop partitions.
+// Marks are bytes indexed by particle: the level's random reads of them then
+// stay in L2.
 __global__ void k_flag(int64_t n, const int32_t* __restrict__ pc, const int4* __restrict__ cell,
                        const int32_t* __restrict__ split, const int32_t* __restrict__ axis,
-                       const uint32_t* __restrict__ plist, int32_t* __restrict__ flag) {
+                       const uint32_t* __restrict__ plist, uint8_t* __restrict__ flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int c = pc[i];
@@ -131,7 +134,7 @@ __global__ void k_flag(int64_t n, const int32_t* __restrict__ pc, const int4* __
 }
 
 __global__ void k_marks(int64_t n, const int32_t* __restrict__ pc, const int32_t* __restrict__ split,
-                        const uint32_t* __restrict__ plist, const int32_t* __restrict__ flag,
+                        const uint32_t* __restrict__ plist, const uint8_t* __restrict__ flag,
                         int32_t* __restrict__ f) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -142,7 +145,7 @@ __global__ void k_marks(int64_t n, const int32_t* __restrict__ pc, const int32_t
 __global__ void k_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __restrict__ pc_out,
                        const int4* __restrict__ cell, const int4* __restrict__ aux,
                        const int32_t* __restrict__ split, const uint32_t* __restrict__ plist,
-                       uint32_t* __restrict__ pout, const int32_t* __restrict__ flag,
+                       uint32_t* __restrict__ pout, const uint8_t* __restrict__ flag,
                        const int32_t* __restrict__ scan) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -385,17 +388,33 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t cnt, uint32_t* counter)
 }
 
 // Classification of one cell pair (the dual-walk rules of the host planner).
+//
+// Only half of the walk is visited: every rule is symmetric under
+// (t, u, s) -> (u, t, s') with s' = 26 - s the opposite image (R changes
+// sign exactly, |R| and the half sizes do not change, and a tie splits both
+// cells), so the pairs with s > 13, or s = 13 and t <= u, are walked and
+// each result is also emitted mirrored.  Cells are in pre-order, so two
+// different cells of a walked pair have disjoint subtrees and the order of
+// t and u carries over to all their descendants; only a self pair (t, t, 13)
+// drops its child pair (c1, c0), the mirror of (c0, c1).
 struct WalkOut {
     uint32_t n_child, n_p2p, n_m2l;
     int2 child[4];
-    uint64_t key;
+    uint64_t key[2];
 };
+
+// Task key (a << ks) | (b << 5) | s with ks = 5 + bits of the largest id:
+// sorting it gives the canonical (a, b, s) order with as few radix passes
+// as the ids need.
+__device__ __forceinline__ uint64_t walk_key(int a, int b, int s, int ks) {
+    return ((uint64_t)(uint32_t)a << ks) | ((uint64_t)(uint32_t)b << 5) | (uint64_t)s;
+}
 
 __device__ __forceinline__ void walk_classify(const int2 pr, const WalkBox* __restrict__ wbox,
                                               const double4* __restrict__ cellc,
                                               const double4* __restrict__ chs,
                                               const int4* __restrict__ cell,
-                                              const int4* __restrict__ aux, WalkOut& o) {
+                                              const int4* __restrict__ aux, int2 ks, WalkOut& o) {
     const int t = pr.x, u = pr.y >> 5, s = pr.y & 31;
     const int4 at = aux[t], au = aux[u];
     const WalkBox wb = wbox[at.z];
@@ -425,16 +444,24 @@ __device__ __forceinline__ void walk_classify(const int2 pr, const WalkBox* __re
         }
     }
     if (!(gap2 < wb.rc2_drop)) return;
+    const bool self = (t == u) && (s == 13);
     if (wb.use_m2l && dmax2 < wb.rc2_m2l && lhs < R2) {
-        o.n_m2l = 1;
-        o.key = ((uint64_t)(uint32_t)t << 32) | ((uint64_t)(uint32_t)u << 5) | (uint64_t)s;
+        o.n_m2l = self ? 1 : 2;
+        o.key[0] = walk_key(t, u, s, ks.y);
+        o.key[1] = walk_key(u, t, 26 - s, ks.y);
         return;
     }
     const int lt = cell[t].w, lu = cell[u].w;
     const double rt = ct.w, ru = cu.w;
     if (lt >= 0 && lu >= 0) {
-        o.n_p2p = 1;
-        o.key = ((uint64_t)(uint32_t)lt << 32) | ((uint64_t)(uint32_t)lu << 5) | (uint64_t)s;
+        o.n_p2p = self ? 1 : 2;
+        o.key[0] = walk_key(lt, lu, s, ks.x);
+        o.key[1] = walk_key(lu, lt, 26 - s, ks.x);
+    } else if (self) {
+        o.child[0] = make_int2(at.x, (at.x << 5) | s);
+        o.child[1] = make_int2(at.x, (at.y << 5) | s);
+        o.child[2] = make_int2(at.y, (at.y << 5) | s);
+        o.n_child = 3;
     } else if (lt < 0 && (lu >= 0 || rt > ru)) {
         o.child[0] = make_int2(at.x, pr.y);
         o.child[1] = make_int2(at.y, pr.y);
@@ -457,17 +484,17 @@ __global__ void __launch_bounds__(256)
 k_walk(const int2* __restrict__ front, int nf, int2* __restrict__ next,
        const WalkBox* __restrict__ wbox, const double4* __restrict__ cellc,
        const double4* __restrict__ chs, const int4* __restrict__ cell, const int4* __restrict__ aux,
-       uint32_t* __restrict__ counters, uint64_t* __restrict__ p2p_keys,
+       int2 ks, uint32_t* __restrict__ counters, uint64_t* __restrict__ p2p_keys,
        uint64_t* __restrict__ m2l_keys) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    WalkOut o{0u, 0u, 0u, {}, 0ull};
-    if (k < nf) walk_classify(front[k], wbox, cellc, chs, cell, aux, o);
+    WalkOut o{0u, 0u, 0u, {}, {0ull, 0ull}};
+    if (k < nf) walk_classify(front[k], wbox, cellc, chs, cell, aux, ks, o);
     const uint32_t cslot = wave_append(o.n_child, &counters[0]);
     for (uint32_t q = 0; q < o.n_child; ++q) next[cslot + q] = o.child[q];
     const uint32_t pslot = wave_append(o.n_p2p, &counters[1]);
-    if (o.n_p2p) p2p_keys[pslot] = o.key;
+    for (uint32_t q = 0; q < o.n_p2p; ++q) p2p_keys[pslot + q] = o.key[q];
     const uint32_t mslot = wave_append(o.n_m2l, &counters[2]);
-    if (o.n_m2l) m2l_keys[mslot] = o.key;
+    for (uint32_t q = 0; q < o.n_m2l; ++q) m2l_keys[mslot + q] = o.key[q];
 }
 
 // One level of the walk with the frontier size read on the device (no host
@@ -480,7 +507,7 @@ k_walk_dev(const int2* __restrict__ front, int2* __restrict__ next, int it,
            uint32_t* __restrict__ sizes, uint32_t* __restrict__ ctl, uint32_t cap_front,
            uint32_t cap_p2p, uint32_t cap_m2l, const WalkBox* __restrict__ wbox,
            const double4* __restrict__ cellc, const double4* __restrict__ chs,
-           const int4* __restrict__ cell, const int4* __restrict__ aux,
+           const int4* __restrict__ cell, const int4* __restrict__ aux, int2 ks,
            uint64_t* __restrict__ p2p_keys, uint64_t* __restrict__ m2l_keys) {
     const uint32_t nf = sizes[it];
     if (nf > cap_front) return;
@@ -488,8 +515,8 @@ k_walk_dev(const int2* __restrict__ front, int2* __restrict__ next, int it,
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < nf; base += stride) {
         const uint32_t k = base + lane;
-        WalkOut o{0u, 0u, 0u, {}, 0ull};
-        if (k < nf) walk_classify(front[k], wbox, cellc, chs, cell, aux, o);
+        WalkOut o{0u, 0u, 0u, {}, {0ull, 0ull}};
+        if (k < nf) walk_classify(front[k], wbox, cellc, chs, cell, aux, ks, o);
         const uint32_t cslot = wave_append(o.n_child, &sizes[it + 1]);
         if (cslot + o.n_child <= cap_front) {
             for (uint32_t q = 0; q < o.n_child; ++q) next[cslot + q] = o.child[q];
@@ -497,12 +524,12 @@ k_walk_dev(const int2* __restrict__ front, int2* __restrict__ next, int it,
             ctl[2] = 1u;
         }
         const uint32_t pslot = wave_append(o.n_p2p, &ctl[0]);
-        if (o.n_p2p) {
-            if (pslot < cap_p2p) p2p_keys[pslot] = o.key; else ctl[2] = 1u;
+        for (uint32_t q = 0; q < o.n_p2p; ++q) {
+            if (pslot + q < cap_p2p) p2p_keys[pslot + q] = o.key[q]; else ctl[2] = 1u;
         }
         const uint32_t mslot = wave_append(o.n_m2l, &ctl[1]);
-        if (o.n_m2l) {
-            if (mslot < cap_m2l) m2l_keys[mslot] = o.key; else ctl[2] = 1u;
+        for (uint32_t q = 0; q < o.n_m2l; ++q) {
+            if (mslot + q < cap_m2l) m2l_keys[mslot + q] = o.key[q]; else ctl[2] = 1u;
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&ctl[3], nf);
@@ -513,11 +540,11 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
     if (i < n) p[i] = 0u;
 }
 
-__global__ void k_csr_rows(const uint64_t* __restrict__ keys, int64_t nk, int nrows,
+__global__ void k_csr_rows(const uint64_t* __restrict__ keys, int64_t nk, int nrows, int ks,
                            int32_t* __restrict__ row) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r > nrows) return;
-    const uint64_t target = (uint64_t)(uint32_t)r << 32;
+    const uint64_t target = (uint64_t)(uint32_t)r << ks;
     int64_t lo = 0, hi = nk;
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
@@ -526,16 +553,17 @@ __global__ void k_csr_rows(const uint64_t* __restrict__ keys, int64_t nk, int nr
     row[r] = (int32_t)lo;
 }
 
-__global__ void k_split_p2p(const uint64_t* __restrict__ keys, int64_t nk, int32_t* __restrict__ js) {
+__global__ void k_split_p2p(const uint64_t* __restrict__ keys, int64_t nk, int ks,
+                            int32_t* __restrict__ js) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < nk) js[k] = (int32_t)(keys[k] & 0xffffffffull);
+    if (k < nk) js[k] = (int32_t)(keys[k] & ((1ull << ks) - 1));
 }
 
-__global__ void k_split_m2l(const uint64_t* __restrict__ keys, int64_t nk, int32_t* __restrict__ src,
-                            int32_t* __restrict__ shift) {
+__global__ void k_split_m2l(const uint64_t* __restrict__ keys, int64_t nk, int ks,
+                            int32_t* __restrict__ src, int32_t* __restrict__ shift) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nk) return;
-    const uint32_t low = (uint32_t)(keys[k] & 0xffffffffull);
+    const uint32_t low = (uint32_t)(keys[k] & ((1ull << ks) - 1));
     src[k] = (int32_t)(low >> 5);
     shift[k] = (int32_t)(low & 31u);
 }
@@ -549,10 +577,14 @@ __global__ void k_item_count(int nl, const int32_t* __restrict__ row, int chunk,
     cnt[i] = (len + chunk - 1) / chunk;
 }
 
+// Work items of each TaskGroup row; the queue key is 255 - (pair count >>
+// cshift), one radix pass, so the queue is longest first up to 1/256 of the
+// largest item.
 __global__ void k_items(int nl, const int32_t* __restrict__ row, const int32_t* __restrict__ js,
-                        const int4* __restrict__ leaf, int chunk, const int32_t* __restrict__ slot0,
-                        int4* __restrict__ items, uint64_t* __restrict__ cost_keys,
-                        uint32_t* __restrict__ slots, unsigned long long* __restrict__ cand) {
+                        const int4* __restrict__ leaf, int chunk, int cshift,
+                        const int32_t* __restrict__ slot0, int4* __restrict__ items,
+                        uint64_t* __restrict__ cost_keys, uint32_t* __restrict__ slots,
+                        unsigned long long* __restrict__ cand) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nl) return;
     const int r0 = row[i], len = row[i + 1] - r0;
@@ -570,8 +602,8 @@ __global__ void k_items(int nl, const int32_t* __restrict__ row, const int32_t* 
         total += c;
         const int s = slot0[i] + k;
         items[s] = make_int4(i, t, t + sz, s);
-        const uint32_t c32 = c > 0xffffffffull ? 0xffffffffu : (uint32_t)c;
-        cost_keys[s] = (uint64_t)(0xffffffffu - c32);
+        const unsigned long long b = c >> cshift;
+        cost_keys[s] = (uint64_t)(255u - (b > 255ull ? 255u : (uint32_t)b));
         slots[s] = (uint32_t)s;
         t += sz;
     }
@@ -773,32 +805,32 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     TRY(d.keys.ensure(n * 24));
     TRY(d.plist.ensure(n * 12));
     TRY(d.plist_tmp.ensure(n * 12));
-    TRY(d.keys_tmp.ensure(n * 8));
+    TRY(d.keys_tmp.ensure(n * 24));
     hipLaunchKernelGGL(k_wrap_keys, dim3(grid_of(n)), dim3(256), 0, s, pos, n,
                        d.box_first.as<int32_t>(), nbox, d.boxes.as<BoxDev>(), d.wpos.as<double>(),
                        d.keys.as<uint64_t>(), d.plist.as<uint32_t>());
     TRY(hipGetLastError());
-    TRY(d.hist.ensure((size_t)sort_hist_words(n) * 4));
-    for (int a = 0; a < 3; ++a) {
-        uint64_t* k = d.keys.as<uint64_t>() + a * n;
-        uint32_t* v = d.plist.as<uint32_t>() + a * n;
+    // the three axis lists are three segments of one sort
+    TRY(d.hist.ensure((size_t)sort_hist_words(n, 3) * 4));
+    if (n > 1) {
+        uint64_t* k = d.keys.as<uint64_t>();
+        uint32_t* v = d.plist.as<uint32_t>();
         uint64_t* kt = d.keys_tmp.as<uint64_t>();
         uint32_t* vt = d.plist_tmp.as<uint32_t>();
         bool in_tmp = false;
-        if (n > 1) {
-            TRY(radix_sort_u64(k, v, kt, vt, d.hist.as<uint32_t>(), n, 0, 64, s, &in_tmp));
-            if (in_tmp) {
-                TRY(hipMemcpyAsync(k, kt, n * 8, hipMemcpyDeviceToDevice, s));
-                TRY(hipMemcpyAsync(v, vt, n * 4, hipMemcpyDeviceToDevice, s));
-            }
-            if (nbox > 1) {
-                hipLaunchKernelGGL(k_box_keys, dim3(grid_of(n)), dim3(256), 0, s, v, n,
-                                   d.box_first.as<int32_t>(), nbox, k);
-                TRY(hipGetLastError());
-                TRY(radix_sort_u64(k, v, kt, vt, d.hist.as<uint32_t>(), n, 0, bits_for(nbox - 1) + 1,
-                                   s, &in_tmp));
-                if (in_tmp) TRY(hipMemcpyAsync(v, vt, n * 4, hipMemcpyDeviceToDevice, s));
-            }
+        TRY(radix_sort_u64(k, v, kt, vt, d.hist.as<uint32_t>(), n, 0, 64, s, &in_tmp, 3));
+        if (in_tmp) {
+            TRY(hipMemcpyAsync(k, kt, n * 24, hipMemcpyDeviceToDevice, s));
+            TRY(hipMemcpyAsync(v, vt, n * 12, hipMemcpyDeviceToDevice, s));
+        }
+        if (nbox > 1) {
+            // then stably by box: each box's particles in coordinate order
+            hipLaunchKernelGGL(k_box_keys, dim3(grid_of(3 * n)), dim3(256), 0, s, v, 3 * n,
+                               d.box_first.as<int32_t>(), nbox, k);
+            TRY(hipGetLastError());
+            TRY(radix_sort_u64(k, v, kt, vt, d.hist.as<uint32_t>(), n, 0, bits_for(nbox - 1) + 1, s,
+                               &in_tmp, 3));
+            if (in_tmp) TRY(hipMemcpyAsync(v, vt, n * 12, hipMemcpyDeviceToDevice, s));
         }
     }
 
@@ -827,9 +859,9 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         TRY(hipGetLastError());
         hipLaunchKernelGGL(k_flag, dim3(grid_of(n)), dim3(256), 0, s, n, d.pc.as<int32_t>(),
                            d.cell.as<int4>(), d.cell_split.as<int32_t>(), d.cell_axis.as<int32_t>(),
-                           d.plist.as<uint32_t>(), d.flag.as<int32_t>());
+                           d.plist.as<uint32_t>(), d.flag.as<uint8_t>());
         hipLaunchKernelGGL(k_marks, dim3(grid_of(n)), dim3(256), 0, s, n, d.pc.as<int32_t>(),
-                           d.cell_split.as<int32_t>(), d.plist.as<uint32_t>(), d.flag.as<int32_t>(),
+                           d.cell_split.as<int32_t>(), d.plist.as<uint32_t>(), d.flag.as<uint8_t>(),
                            d.fsc.as<int32_t>());
         TRY(hipGetLastError());
         // one scan over the three lists back to back: each cell's range of
@@ -839,7 +871,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         hipLaunchKernelGGL(k_move, dim3(grid_of(n)), dim3(256), 0, s, n, d.pc.as<int32_t>(),
                            d.pc_tmp.as<int32_t>(), d.cell.as<int4>(), d.cell_aux.as<int4>(),
                            d.cell_split.as<int32_t>(), d.plist.as<uint32_t>(),
-                           d.plist_tmp.as<uint32_t>(), d.flag.as<int32_t>(),
+                           d.plist_tmp.as<uint32_t>(), d.flag.as<uint8_t>(),
                            d.fsc_out.as<int32_t>());
         TRY(hipGetLastError());
         std::swap(d.plist, d.plist_tmp);
@@ -871,16 +903,20 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     clk.lap("records");
     // ---- dual walk
     TRY(d.wcount.ensure(64));
-    const int64_t nf0 = 27 * (int64_t)nbox;
+    // the canonical half of (root, root, s): the zero shift and the 13
+    // shifts with code > 13
+    const int64_t nf0 = 14 * (int64_t)nbox;
     std::vector<int32_t> f0(2 * nf0);
     for (int b = 0; b < nbox; ++b)
-        for (int q = 0; q < 27; ++q) {
+        for (int q = 0; q < 14; ++q) {
             const int root = topo.box_first_cell[b];
-            f0[2 * (27 * b + q)] = root;
-            f0[2 * (27 * b + q) + 1] = (root << 5) | q;
+            f0[2 * (14 * b + q)] = root;
+            f0[2 * (14 * b + q) + 1] = (root << 5) | (13 + q);
         }
     int64_t n_p2p = 0, n_m2l = 0;
     bool done = false;
+    const int2 ks = make_int2(5 + bits_for((uint64_t)std::max<int64_t>(1, nl - 1)),
+                              5 + bits_for((uint64_t)std::max<int64_t>(1, nc - 1)));
     // Level-by-level walk without host round trips, sized from the previous
     // build of the same tree shape; falls back to the host-driven loop.
     if (d.walk_cap_front > 0 && d.walk_levels > 0) {
@@ -903,8 +939,8 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
             hipLaunchKernelGGL(k_walk_dev, dim3(2048), dim3(256), 0, s, bufs[it & 1]->as<int2>(),
                                bufs[(it + 1) & 1]->as<int2>(), it, sizes, ctl, capf, capp, capm,
                                d.walkbox.as<WalkBox>(), d.cellc.as<double4>(), d.chs.as<double4>(),
-                               d.cell.as<int4>(), d.cell_aux.as<int4>(), d.p2p_keys.as<uint64_t>(),
-                               d.m2l_keys.as<uint64_t>());
+                               d.cell.as<int4>(), d.cell_aux.as<int4>(), ks,
+                               d.p2p_keys.as<uint64_t>(), d.m2l_keys.as<uint64_t>());
         }
         TRY(hipGetLastError());
         std::vector<uint32_t> hc(L + 5);
@@ -928,14 +964,15 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         int64_t max_front = nf;
         while (nf > 0) {
             TRY(d.front_next.grow((size_t)4 * nf * 8, 0, s));
-            if ((size_t)(n_p2p + nf) * 8 > d.p2p_keys.bytes)
-                TRY(d.p2p_keys.grow((size_t)(n_p2p + nf) * 8 * 2, (size_t)n_p2p * 8, s));
-            if ((size_t)(n_m2l + nf) * 8 > d.m2l_keys.bytes)
-                TRY(d.m2l_keys.grow((size_t)(n_m2l + nf) * 8 * 2, (size_t)n_m2l * 8, s));
+            // each pair adds at most 4 children and 2 keys (itself and mirror)
+            if ((size_t)(n_p2p + 2 * nf) * 8 > d.p2p_keys.bytes)
+                TRY(d.p2p_keys.grow((size_t)(n_p2p + 2 * nf) * 8 * 2, (size_t)n_p2p * 8, s));
+            if ((size_t)(n_m2l + 2 * nf) * 8 > d.m2l_keys.bytes)
+                TRY(d.m2l_keys.grow((size_t)(n_m2l + 2 * nf) * 8 * 2, (size_t)n_m2l * 8, s));
             hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, d.wcount.as<uint32_t>(), 1);
             hipLaunchKernelGGL(k_walk, dim3(grid_of(nf)), dim3(256), 0, s, d.front.as<int2>(), (int)nf,
                                d.front_next.as<int2>(), d.walkbox.as<WalkBox>(), d.cellc.as<double4>(),
-                               d.chs.as<double4>(), d.cell.as<int4>(), d.cell_aux.as<int4>(),
+                               d.chs.as<double4>(), d.cell.as<int4>(), d.cell_aux.as<int4>(), ks,
                                d.wcount.as<uint32_t>(), d.p2p_keys.as<uint64_t>(),
                                d.m2l_keys.as<uint64_t>());
             TRY(hipGetLastError());
@@ -957,29 +994,29 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
 
     clk.lap("walk");
     // ---- canonical order and CSR
-    const int p2p_bits = 32 + bits_for((uint64_t)std::max<int64_t>(1, nl - 1));
+    const int p2p_bits = ks.x + bits_for((uint64_t)std::max<int64_t>(1, nl - 1));
     std::string err = sort_in_place(d.p2p_keys, nullptr, d.p2p_keys_tmp, nullptr, d.hist, n_p2p,
                                     p2p_bits, s);
     if (!err.empty()) return err;
     TRY(d.p2p_row.ensure((nl + 1) * 4));
     TRY(d.js.ensure(std::max<int64_t>(1, n_p2p) * 4));
     hipLaunchKernelGGL(k_csr_rows, dim3(grid_of(nl + 1)), dim3(256), 0, s, d.p2p_keys.as<uint64_t>(),
-                       n_p2p, (int)nl, d.p2p_row.as<int32_t>());
+                       n_p2p, (int)nl, ks.x, d.p2p_row.as<int32_t>());
     if (n_p2p > 0)
         hipLaunchKernelGGL(k_split_p2p, dim3(grid_of(n_p2p)), dim3(256), 0, s,
-                           d.p2p_keys.as<uint64_t>(), n_p2p, d.js.as<int32_t>());
+                           d.p2p_keys.as<uint64_t>(), n_p2p, ks.x, d.js.as<int32_t>());
     TRY(hipGetLastError());
-    const int m2l_bits = 32 + bits_for((uint64_t)std::max<int64_t>(1, nc - 1));
+    const int m2l_bits = ks.y + bits_for((uint64_t)std::max<int64_t>(1, nc - 1));
     err = sort_in_place(d.m2l_keys, nullptr, d.m2l_keys_tmp, nullptr, d.hist, n_m2l, m2l_bits, s);
     if (!err.empty()) return err;
     TRY(d.m2l_row.ensure((nc + 1) * 4));
     TRY(d.m2l_src.ensure(std::max<int64_t>(1, n_m2l) * 4));
     TRY(d.m2l_shift.ensure(std::max<int64_t>(1, n_m2l) * 4));
     hipLaunchKernelGGL(k_csr_rows, dim3(grid_of(nc + 1)), dim3(256), 0, s, d.m2l_keys.as<uint64_t>(),
-                       n_m2l, (int)nc, d.m2l_row.as<int32_t>());
+                       n_m2l, (int)nc, ks.y, d.m2l_row.as<int32_t>());
     if (n_m2l > 0)
         hipLaunchKernelGGL(k_split_m2l, dim3(grid_of(n_m2l)), dim3(256), 0, s,
-                           d.m2l_keys.as<uint64_t>(), n_m2l, d.m2l_src.as<int32_t>(),
+                           d.m2l_keys.as<uint64_t>(), n_m2l, ks.y, d.m2l_src.as<int32_t>(),
                            d.m2l_shift.as<int32_t>());
     TRY(hipGetLastError());
     out.n_p2p = n_p2p;
@@ -1011,13 +1048,15 @@ std::string gpu_make_items(DevPlan& d, const Plan& topo, int64_t n_p2p, int chun
     TRY(d.partial.ensure(std::max<int64_t>(1, n_items) * 4 * 64 * 8));
     TRY(d.wcount.ensure(64));
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, d.wcount.as<uint32_t>(), 16);
+    // largest item: chunk tasks of at most 64 x 64 pairs
+    const int cshift = std::max(0, bits_for((uint64_t)chunk * 64 * 64) - 8);
     hipLaunchKernelGGL(k_items, dim3(grid_of(nl)), dim3(256), 0, s, (int)nl, d.p2p_row.as<int32_t>(),
-                       d.js.as<int32_t>(), d.leaf.as<int4>(), chunk, d.leaf_slot.as<int32_t>(),
+                       d.js.as<int32_t>(), d.leaf.as<int4>(), chunk, cshift, d.leaf_slot.as<int32_t>(),
                        d.items.as<int4>(), d.cost_keys.as<uint64_t>(), d.queue.as<uint32_t>(),
                        reinterpret_cast<unsigned long long*>(d.wcount.as<uint32_t>() + 8));
     TRY(hipGetLastError());
     std::string err = sort_in_place(d.cost_keys, &d.queue, d.cost_keys_tmp, &d.queue_tmp, d.hist,
-                                    n_items, 32, s);
+                                    n_items, 8, s);
     if (!err.empty()) return err;
     unsigned long long cand = 0;
     TRY(hipMemcpyAsync(&cand, d.wcount.as<uint32_t>() + 8, 8, hipMemcpyDeviceToHost, s));

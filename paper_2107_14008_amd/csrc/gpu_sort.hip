@@ -1,14 +1,16 @@
 // Device primitives of the on-GPU planner: a stable LSD radix sort of 64-bit
-// keys (optionally carrying 32-bit values) and an exclusive prefix sum of
-// 32-bit integers.
+// keys (optionally carrying 32-bit values), also of several equal-length
+// segments at once, and an exclusive prefix sum of 32-bit integers.
 //
 // Radix sort: 8-bit digits, tiles of 4096 elements (256 threads x 16
-// rounds).  Per pass: (1) per-tile digit histogram in LDS, (2) one exclusive
-// scan over the digit-major [256][tiles] table, (3) scatter: inside a tile
-// the 256 elements of a round are ranked per digit with wavefront ballots
-// (eight ballots give each lane the mask of lanes holding its digit) and a
-// running per-digit count in LDS, so the order of equal digits is kept
-// (stable), which makes the sort stable across passes.
+// rounds); a tile never straddles two segments.  Per pass: (1) per-tile
+// digit histogram in LDS, (2) one exclusive scan over the
+// [segment][digit][tile] table (segment-major, so segment s lands in
+// [s n, (s + 1) n)), (3) scatter: inside a tile the 256 elements of a round
+// are ranked per digit with wavefront ballots (eight ballots give each lane
+// the mask of lanes holding its digit) and a running per-digit count in
+// LDS, so the order of equal digits is kept (stable), which makes the sort
+// stable across passes.
 #include "gpu_plan.h"
 
 namespace pmfmm {
@@ -18,19 +20,35 @@ constexpr int kThreads = 256;
 constexpr int kRounds = 16;
 constexpr int kTile = kThreads * kRounds;  // 4096
 
+// Block b handles tile (b % tiles) of segment (b / tiles); its elements are
+// [seg n + tile kTile, min(seg n + (tile + 1) kTile, (seg + 1) n)).
+struct TileRange {
+    int64_t begin, end;
+    size_t col;   // (seg * 256) * tiles + tile: add digit * tiles
+};
+
+__device__ __forceinline__ TileRange tile_range(int64_t n, int tiles) {
+    const int seg = blockIdx.x / tiles, tile = blockIdx.x - seg * tiles;
+    TileRange t;
+    t.begin = (int64_t)seg * n + (int64_t)tile * kTile;
+    t.end = min((int64_t)seg * n + n, t.begin + kTile);
+    t.col = (size_t)seg * 256 * tiles + tile;
+    return t;
+}
+
 __global__ void __launch_bounds__(kThreads)
 rs_hist(const uint64_t* __restrict__ keys, int64_t n, int shift, uint32_t* __restrict__ hist,
         int tiles) {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const TileRange tr = tile_range(n, tiles);
     for (int r = 0; r < kRounds; ++r) {
-        const int64_t i = base + r * kThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        const int64_t i = tr.begin + r * kThreads + threadIdx.x;
+        if (i < tr.end) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    hist[(size_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
+    hist[tr.col + (size_t)threadIdx.x * tiles] = h[threadIdx.x];
 }
 
 // Exclusive scan of m 32-bit values by one workgroup of 1024 threads.
@@ -66,14 +84,14 @@ rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     __shared__ uint32_t wc[kThreads / 64][256];
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
-    run[t] = offs[(size_t)t * tiles + blockIdx.x];
+    const TileRange tr = tile_range(n, tiles);
+    run[t] = offs[tr.col + (size_t)t * tiles];
     for (int w = 0; w < kThreads / 64; ++w) wc[w][t] = 0;
     __syncthreads();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t base = (int64_t)blockIdx.x * kTile;
     for (int r = 0; r < kRounds; ++r) {
-        const int64_t i = base + r * kThreads + t;
-        const bool valid = i < n;
+        const int64_t i = tr.begin + r * kThreads + t;
+        const bool valid = i < tr.end;
         uint64_t key = 0;
         uint32_t val = 0;
         uint32_t d = 0;
@@ -159,36 +177,37 @@ hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, uint32
 
 int64_t sort_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
 
-int64_t sort_hist_words(int64_t n) {
-    const int64_t m = 256 * sort_tiles(n);
+int64_t sort_hist_words(int64_t n, int nseg) {
+    const int64_t m = (int64_t)nseg * 256 * sort_tiles(n);
     return 2 * m + sort_tiles(m) + 16;
 }
 
 hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals,
                           uint32_t* hist, int64_t n, int bit_begin, int bit_end, hipStream_t s,
-                          bool* result_in_tmp) {
+                          bool* result_in_tmp, int nseg) {
     *result_in_tmp = false;
-    if (n <= 1) return hipSuccess;
+    if (n <= 1 || nseg < 1) return hipSuccess;
     const int tiles = (int)sort_tiles(n);
+    const int blocks = nseg * tiles;
     uint64_t* ka = keys;
     uint64_t* kb = tmp_keys;
     uint32_t* va = vals;
     uint32_t* vb = tmp_vals;
     // scratch layout: counts [m], their exclusive scan [m], tile sums
-    const int64_t m = (int64_t)256 * tiles;
+    const int64_t m = (int64_t)nseg * 256 * tiles;
     uint32_t* offs = hist + m;
     uint32_t* scan_scratch = hist + 2 * m;
     for (int shift = bit_begin; shift < bit_end; shift += 8) {
-        hipLaunchKernelGGL(rs_hist, dim3(tiles), dim3(kThreads), 0, s, ka, n, shift, hist, tiles);
+        hipLaunchKernelGGL(rs_hist, dim3(blocks), dim3(kThreads), 0, s, ka, n, shift, hist, tiles);
         const hipError_t e = exclusive_scan_i32(reinterpret_cast<const int32_t*>(hist),
                                                 reinterpret_cast<int32_t*>(offs), m, scan_scratch, s);
         if (e != hipSuccess) return e;
         if (vals)
-            hipLaunchKernelGGL(rs_scatter<true>, dim3(tiles), dim3(kThreads), 0, s, ka, va, kb, vb, n,
-                               shift, offs, tiles);
+            hipLaunchKernelGGL(rs_scatter<true>, dim3(blocks), dim3(kThreads), 0, s, ka, va, kb, vb,
+                               n, shift, offs, tiles);
         else
-            hipLaunchKernelGGL(rs_scatter<false>, dim3(tiles), dim3(kThreads), 0, s, ka, va, kb, vb, n,
-                               shift, offs, tiles);
+            hipLaunchKernelGGL(rs_scatter<false>, dim3(blocks), dim3(kThreads), 0, s, ka, va, kb, vb,
+                               n, shift, offs, tiles);
         std::swap(ka, kb);
         std::swap(va, vb);
         *result_in_tmp = !*result_in_tmp;

@@ -469,6 +469,7 @@ int do_upload(pmfmm_ctx* ctx, const double* pos, const double* mass, int32_t on_
         const int nco = pmfmm::n_coef(pl.max_order);
         HIP_TRY(ctx->d.M.ensure((size_t)nc * nco * sizeof(double)));
         HIP_TRY(ctx->d.Lc.ensure((size_t)nc * nco * sizeof(double)));
+        HIP_TRY(ctx->d.Lt.ensure((size_t)std::max<int64_t>(1, ctx->n_m2l) * nco * sizeof(double)));
         HIP_TRY(ctx->d.far.ensure((size_t)n * 3 * sizeof(double)));
         if ((rc = prepare_far(ctx, s))) return rc;
     }
@@ -499,6 +500,8 @@ pmfmm::FarArgs far_args(pmfmm_ctx* ctx) {
     f.boxes = ctx->d.boxes.as<pmfmm::BoxDev>();
     f.M = ctx->d.M.as<double>();
     f.Lc = ctx->d.Lc.as<double>();
+    f.Lt = ctx->d.Lt.as<double>();
+    f.n_m2l = (int32_t)ctx->n_m2l;
     f.far = ctx->d.far.as<double>();
     f.needM = ctx->d.farflag.as<int32_t>();
     f.needL = ctx->d.farflag.as<int32_t>() + 2 * nc;
@@ -614,6 +617,7 @@ int gpu_build(pmfmm_ctx* ctx, const std::vector<pmfmm::BoxParams>& boxes, const 
         const int nco = pmfmm::n_coef(ctx->plan.max_order);
         HIP_TRY(ctx->d.M.ensure((size_t)nc * nco * sizeof(double)));
         HIP_TRY(ctx->d.Lc.ensure((size_t)nc * nco * sizeof(double)));
+        HIP_TRY(ctx->d.Lt.ensure((size_t)std::max<int64_t>(1, ctx->n_m2l) * nco * sizeof(double)));
         HIP_TRY(ctx->d.far.ensure((size_t)n * 3 * sizeof(double)));
         if ((rc = prepare_far(ctx, s))) return rc;
     }

@@ -105,6 +105,8 @@ struct FarArgs {
     const BoxDev* boxes;
     double* M;                  // (n_cells, ncoef)
     double* Lc;                 // (n_cells, ncoef)
+    double* Lt;                 // (n_m2l, ncoef): each M2L task's contribution
+    int32_t n_m2l;
     double* far;                // (n, 3) leaf order
     int32_t* needM;             // per cell: multipole needed (M2L source subtree)
     int32_t* needL;             // per cell: local expansion needed (M2L target subtree)

@@ -157,58 +157,67 @@ m2m_kernel(const int32_t* __restrict__ level_cells, int n_level, const int4* __r
     }
 }
 
-// ---- M2L: one wavefront per target cell over its M2L row; the D tensor of
-// each source is built in LDS by the lanes, then lane n accumulates L_n.
+// ---- M2L: one wavefront per task (t, u, s) of the M2L list; the D tensor
+// of the task is built in LDS by the lanes, lane n then computes the task's
+// contribution to L_n(z_t) into its own row of Lt (no ordering between
+// tasks is needed); m2l_sum_kernel adds each target's rows in list order.
 __global__ void __launch_bounds__(64)
-m2l_kernel(const int32_t* __restrict__ row, const int32_t* __restrict__ src,
-           const int32_t* __restrict__ shift, const int4* __restrict__ aux,
-           const double4* __restrict__ cellc, const BoxDev* __restrict__ boxes,
-           const int32_t* __restrict__ needL, const double* __restrict__ M,
-           double* __restrict__ Lc, int n_cells, int ncoef) {
+m2l_task_kernel(const int32_t* __restrict__ row, const int32_t* __restrict__ src,
+                const int32_t* __restrict__ shift, const int4* __restrict__ aux,
+                const double4* __restrict__ cellc, const BoxDev* __restrict__ boxes,
+                const double* __restrict__ M, double* __restrict__ Lt, int n_cells, int ncoef) {
     __shared__ double Dsh[kMaxNC];
-    const int t = blockIdx.x;
-    if (t >= n_cells) return;
-    if (!needL[t]) return;
-    const int r0 = row[t], r1 = row[t + 1];
+    const int q = blockIdx.x;
     const int lane = threadIdx.x;
-    if (r0 == r1) {
-        for (int n = lane; n < ncoef; n += 64) Lc[(size_t)t * ncoef + n] = 0.0;
-        return;
+    // target cell of task q: the row holding it
+    int lo = 0, hi = n_cells - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row[mid] <= q) lo = mid; else hi = mid - 1;
     }
+    const int t = lo;
     const BoxDev bx = boxes[aux[t].z];
     const int p = bx.order;
     const int nc = ncoef_of(p);
     const double4 ct = cellc[t];
-    double acc0 = 0.0, acc1 = 0.0;
-    for (int q = r0; q < r1; ++q) {
-        const int u = src[q];
-        const int s = shift[q];
-        const double4 cu = cellc[u];
-        const double R[3] = {ct.x - (cu.x + (double)(s % 3 - 1) * bx.L),
-                             ct.y - (cu.y + (double)((s / 3) % 3 - 1) * bx.L),
-                             ct.z - (cu.z + (double)(s / 9 - 1) * bx.L)};
-        const double r = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
-        double f[kMaxP + 1];
-        radial_f(r, bx.alpha, p, f);
-        for (int k = lane; k < nc; k += 64) Dsh[k] = d_entry(c_mi.a[k], c_mi.b[k], c_mi.c[k], R, f);
-        __syncthreads();
-        const double* Mu = M + (size_t)u * ncoef;
-        for (int half = 0; half < 2; ++half) {
-            const int n = lane + 64 * half;
-            if (n >= nc) break;
+    const int u = src[q];
+    const int s = shift[q];
+    const double4 cu = cellc[u];
+    const double R[3] = {ct.x - (cu.x + (double)(s % 3 - 1) * bx.L),
+                         ct.y - (cu.y + (double)((s / 3) % 3 - 1) * bx.L),
+                         ct.z - (cu.z + (double)(s / 9 - 1) * bx.L)};
+    const double r = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+    double f[kMaxP + 1];
+    radial_f(r, bx.alpha, p, f);
+    for (int k = lane; k < nc; k += 64) Dsh[k] = d_entry(c_mi.a[k], c_mi.b[k], c_mi.c[k], R, f);
+    __syncthreads();
+    const double* Mu = M + (size_t)u * ncoef;
+    double* out = Lt + (size_t)q * ncoef;
+    for (int n = lane; n < ncoef; n += 64) {
+        double acc = 0.0;
+        if (n < nc) {
             const int n0 = c_mi.a[n], n1 = c_mi.b[n], n2 = c_mi.c[n];
-            const int rem = p - (n0 + n1 + n2);
-            const int mend = ncoef_of(rem);
-            double s_acc = 0.0;
+            const int mend = ncoef_of(p - (n0 + n1 + n2));
             for (int m = 0; m < mend; ++m)
-                s_acc += Mu[m] * Dsh[c_mi.idx[n0 + c_mi.a[m]][n1 + c_mi.b[m]][n2 + c_mi.c[m]]];
-            if (half == 0) acc0 += s_acc; else acc1 += s_acc;
+                acc += Mu[m] * Dsh[c_mi.idx[n0 + c_mi.a[m]][n1 + c_mi.b[m]][n2 + c_mi.c[m]]];
         }
-        __syncthreads();
+        out[n] = acc;
     }
-    if (lane < nc) Lc[(size_t)t * ncoef + lane] = acc0;
-    if (lane + 64 < nc) Lc[(size_t)t * ncoef + lane + 64] = acc1;
-    for (int n = nc + lane; n < ncoef; n += 64) Lc[(size_t)t * ncoef + n] = 0.0;
+}
+
+// L of every cell that needs one: the sum of its tasks' rows in list order
+// (zero without tasks).
+__global__ void __launch_bounds__(64)
+m2l_sum_kernel(const int32_t* __restrict__ row, const int32_t* __restrict__ needL,
+               const double* __restrict__ Lt, double* __restrict__ Lc, int n_cells, int ncoef) {
+    const int t = blockIdx.x;
+    if (t >= n_cells || !needL[t]) return;
+    const int r0 = row[t], r1 = row[t + 1];
+    for (int n = threadIdx.x; n < ncoef; n += 64) {
+        double acc = 0.0;
+        for (int q = r0; q < r1; ++q) acc += Lt[(size_t)q * ncoef + n];
+        Lc[(size_t)t * ncoef + n] = acc;
+    }
 }
 
 // ---- L2L for the cells of one depth (>= 1): add the parent's shifted local.
@@ -361,9 +370,12 @@ hipError_t launch_m2m_level(const FarArgs& a, hipStream_t s) {
 
 hipError_t launch_m2l(const FarArgs& a, hipStream_t s) {
     if (a.n_cells == 0) return hipSuccess;
-    hipLaunchKernelGGL(m2l_kernel, dim3(a.n_cells), dim3(64), 0, s, a.m2l_row, a.m2l_src,
-                       a.m2l_shift, a.cell_aux, a.cellc, a.boxes, a.needL, a.M, a.Lc, a.n_cells,
-                       a.ncoef);
+    if (a.n_m2l > 0)
+        hipLaunchKernelGGL(m2l_task_kernel, dim3(a.n_m2l), dim3(64), 0, s, a.m2l_row, a.m2l_src,
+                           a.m2l_shift, a.cell_aux, a.cellc, a.boxes, a.M, a.Lt, a.n_cells,
+                           a.ncoef);
+    hipLaunchKernelGGL(m2l_sum_kernel, dim3(a.n_cells), dim3(64), 0, s, a.m2l_row, a.needL, a.Lt,
+                       a.Lc, a.n_cells, a.ncoef);
     return hipGetLastError();
 }
 

@@ -57,10 +57,10 @@ struct DevPlan {
     // used by the forward / adjoint passes
     DevBuf perm, leaf, leafc, js, items, queue, leaf_slot, partial, counter, boxes, table;
     DevBuf x64, x32, stage_pos, stage_mass, far;
-    DevBuf cell, cell_aux, cellc, M, Lc, m2l_row, m2l_src, m2l_shift, level_cells;
+    DevBuf cell, cell_aux, cellc, M, Lc, Lt, m2l_row, m2l_src, m2l_shift, level_cells;
     DevBuf w64, w32;
     // on-GPU planner scratch
-    DevBuf p2p_row, wpos, keys, keys_tmp, plist, plist_tmp, hist, flag, fsc, fsc_out, tile_sums;
+    DevBuf p2p_row, wpos, keys, keys_tmp, plist, plist_tmp, hist, flag, lv_first, tile_sums;
     DevBuf pc, pc_tmp, clo, chi, chs, box_first, walkbox, front, front_next, p2p_keys,
         p2p_keys_tmp, m2l_keys, m2l_keys_tmp, wcount, cost, cost_keys, cost_keys_tmp, queue_tmp,
         item_count, cell_axis, farflag, walk_ctl, froots, cell_split, loop_cells;
@@ -75,9 +75,9 @@ struct DevPlan {
     void release_all() {
         for (DevBuf* b : {&perm, &leaf, &leafc, &js, &items, &queue, &leaf_slot, &partial, &counter,
                           &boxes, &table, &x64, &x32, &stage_pos, &stage_mass, &far, &cell,
-                          &cell_aux, &cellc, &M, &Lc, &m2l_row, &m2l_src, &m2l_shift, &level_cells,
+                          &cell_aux, &cellc, &M, &Lc, &Lt, &m2l_row, &m2l_src, &m2l_shift, &level_cells,
                           &w64, &w32, &p2p_row, &wpos, &keys, &keys_tmp, &plist, &plist_tmp, &hist,
-                          &flag, &fsc, &fsc_out, &tile_sums, &pc, &pc_tmp, &clo, &chi, &chs,
+                          &flag, &lv_first, &tile_sums, &pc, &pc_tmp, &clo, &chi, &chs,
                           &box_first, &walkbox, &front, &front_next, &p2p_keys, &p2p_keys_tmp,
                           &m2l_keys, &m2l_keys_tmp, &wcount, &cost, &cost_keys, &cost_keys_tmp,
                           &queue_tmp, &item_count, &cell_axis, &farflag, &walk_ctl, &froots,
@@ -104,6 +104,8 @@ hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, ui
                           bool* result_in_tmp, int nseg = 1);
 hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, uint32_t* tile_sums,
                               hipStream_t s);
+// In-place exclusive scan by one workgroup (for a few thousand values).
+hipError_t exclusive_scan_u32_one_block(uint32_t* a, int64_t m, hipStream_t s);
 
 // Checks device particles: finite positions, finite non-negative masses.
 // Returns "" or a message naming the first offending particle.

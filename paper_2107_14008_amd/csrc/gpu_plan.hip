@@ -133,38 +133,131 @@ __global__ void k_flag(int64_t n, const int32_t* __restrict__ pc, const int4* __
     flag[plist[ax * n + i]] = (i - ci.x < ci.y / 2) ? 1 : 0;
 }
 
-__global__ void k_marks(int64_t n, const int32_t* __restrict__ pc, const int32_t* __restrict__ split,
-                        const uint32_t* __restrict__ plist, const uint8_t* __restrict__ flag,
-                        int32_t* __restrict__ f) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const bool sp = split[pc[i]] != 0;
-    for (int a = 0; a < 3; ++a) f[a * n + i] = sp ? flag[plist[a * n + i]] : 0;
+// The stable partition of one level, with the left marks of the three lists
+// (3n positions, list a at [a n, (a + 1) n)) computed where they are used
+// instead of stored: a position's mark is flag[particle] if its cell splits
+// at this level, else 0.  Tiles of 4096 positions: k_level_sums counts each
+// tile's marks, an exclusive scan of the counts gives the tile offsets,
+// k_level_firsts the exclusive prefix at each splitting cell's first
+// position of each list, and k_level_move the prefix of every position
+// (tile offset + in-tile scan) and from it the position's destination.
+constexpr int kLvThreads = 256;
+constexpr int kLvRounds = 16;
+constexpr int kLvTile = kLvThreads * kLvRounds;   // 4096
+
+__device__ __forceinline__ uint32_t level_mark(int64_t q, int64_t n, const int32_t* __restrict__ pc,
+                                               const int32_t* __restrict__ split,
+                                               const uint32_t* __restrict__ plist,
+                                               const uint8_t* __restrict__ flag) {
+    const int64_t i = q >= n ? (q >= 2 * n ? q - 2 * n : q - n) : q;
+    return split[pc[i]] ? (uint32_t)flag[plist[q]] : 0u;
 }
 
-__global__ void k_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __restrict__ pc_out,
-                       const int4* __restrict__ cell, const int4* __restrict__ aux,
-                       const int32_t* __restrict__ split, const uint32_t* __restrict__ plist,
-                       uint32_t* __restrict__ pout, const uint8_t* __restrict__ flag,
-                       const int32_t* __restrict__ scan) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int c = pc[i];
-    const int4 ax = aux[c];
-    if (!split[c]) {
-        for (int a = 0; a < 3; ++a) pout[a * n + i] = plist[a * n + i];
-        pc_out[i] = c;
-        return;
+__global__ void __launch_bounds__(kLvThreads)
+k_level_sums(int64_t n, const int32_t* __restrict__ pc, const int32_t* __restrict__ split,
+             const uint32_t* __restrict__ plist, const uint8_t* __restrict__ flag,
+             uint32_t* __restrict__ tile_sums) {
+    __shared__ uint32_t wsum[kLvThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kLvTile;
+    uint32_t c = 0;
+    for (int r = 0; r < kLvRounds; ++r) {
+        const int64_t q = base + r * kLvThreads + threadIdx.x;
+        if (q < 3 * n) c += level_mark(q, n, pc, split, plist, flag);
     }
-    const int4 ci = cell[c];
-    const int64_t first = ci.x, nl = ci.y / 2;
-    for (int a = 0; a < 3; ++a) {
-        const uint32_t p = plist[a * n + i];
-        const int64_t lr = scan[a * n + i] - scan[a * n + first];
-        const int64_t pos = flag[p] ? first + lr : first + nl + (i - first - lr);
-        pout[a * n + pos] = p;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kLvThreads / 64; ++w) t += wsum[w];
+        tile_sums[blockIdx.x] = t;
     }
-    pc_out[i] = (i - first < nl) ? ax.x : ax.y;
+}
+
+// One wavefront per (splitting cell of this level, list): the exclusive
+// prefix of the marks at the cell's first position of that list.
+__global__ void __launch_bounds__(256)
+k_level_firsts(const int32_t* __restrict__ level, int nd, int64_t n, const int4* __restrict__ cell,
+               const int32_t* __restrict__ pc, const int32_t* __restrict__ split,
+               const uint32_t* __restrict__ plist, const uint8_t* __restrict__ flag,
+               const uint32_t* __restrict__ tile_off, int nc, int32_t* __restrict__ pfirst) {
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (w >= 3 * nd) return;
+    const int k = w / 3, a = w - 3 * k;
+    const int c = level[k];
+    const int64_t qf = (int64_t)a * n + cell[c].x;
+    const int64_t t0 = qf / kLvTile * kLvTile;
+    uint32_t cnt = 0;
+    for (int64_t q = t0 + lane; q < qf; q += 64) cnt += level_mark(q, n, pc, split, plist, flag);
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off);
+    if (lane == 0) pfirst[(size_t)a * nc + c] = (int32_t)(tile_off[qf / kLvTile] + cnt);
+}
+
+__global__ void __launch_bounds__(kLvThreads)
+k_level_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __restrict__ pc_out,
+             const int4* __restrict__ cell, const int4* __restrict__ aux,
+             const int32_t* __restrict__ split, const uint32_t* __restrict__ plist,
+             uint32_t* __restrict__ pout, const uint8_t* __restrict__ flag,
+             const uint32_t* __restrict__ tile_off, int nc, const int32_t* __restrict__ pfirst) {
+    __shared__ uint8_t mk[kLvTile];
+    __shared__ uint16_t pre[kLvTile];
+    __shared__ uint32_t wsum[kLvThreads / 64];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kLvTile;
+    uint32_t pv[kLvRounds];
+    int32_t cv[kLvRounds];
+    for (int r = 0; r < kLvRounds; ++r) {
+        const int64_t q = base + r * kLvThreads + t;
+        uint8_t f = 0;
+        pv[r] = 0u;
+        cv[r] = -1;
+        if (q < 3 * n) {
+            const int64_t i = q >= n ? (q >= 2 * n ? q - 2 * n : q - n) : q;
+            pv[r] = plist[q];
+            cv[r] = pc[i];
+            f = split[cv[r]] ? flag[pv[r]] : (uint8_t)0;
+        }
+        mk[r * kLvThreads + t] = f;
+    }
+    __syncthreads();
+    // in-tile exclusive prefix: thread t owns positions [16 t, 16 t + 16)
+    uint32_t own = 0;
+    for (int j = 0; j < kLvRounds; ++j) own += mk[kLvRounds * t + j];
+    uint32_t x = own;
+    const int lane = t & 63, wave = t >> 6;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    uint32_t run = x - own;
+    for (int w = 0; w < wave; ++w) run += wsum[w];
+    for (int j = 0; j < kLvRounds; ++j) {
+        pre[kLvRounds * t + j] = (uint16_t)run;
+        run += mk[kLvRounds * t + j];
+    }
+    __syncthreads();
+    const uint32_t toff = tile_off[blockIdx.x];
+    for (int r = 0; r < kLvRounds; ++r) {
+        const int64_t q = base + r * kLvThreads + t;
+        if (q >= 3 * n) continue;
+        const int a = q >= n ? (q >= 2 * n ? 2 : 1) : 0;
+        const int64_t i = q - (int64_t)a * n;
+        const int c = cv[r];
+        if (!split[c]) {
+            pout[q] = pv[r];
+            if (a == 0) pc_out[i] = c;
+            continue;
+        }
+        const int4 ci = cell[c];
+        const int64_t first = ci.x, nl = ci.y / 2;
+        const int64_t lr = (int64_t)(toff + pre[r * kLvThreads + t]) - pfirst[(size_t)a * nc + c];
+        const int64_t pos = mk[r * kLvThreads + t] ? first + lr : first + nl + (i - first - lr);
+        pout[(int64_t)a * n + pos] = pv[r];
+        if (a == 0) pc_out[i] = (i - first < nl) ? aux[c].x : aux[c].y;
+    }
 }
 
 // The bottom levels of the tree in one launch: one workgroup per subtree of
@@ -839,9 +932,9 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     TRY(d.pc.ensure(n * 4));
     TRY(d.pc_tmp.ensure(n * 4));
     TRY(d.flag.ensure(n * 4));
-    TRY(d.fsc.ensure(n * 12));
-    TRY(d.fsc_out.ensure(n * 12));
-    TRY(d.tile_sums.ensure(sort_tiles(3 * n) * 4 + 16));
+    const int64_t lv_tiles = (3 * n + kLvTile - 1) / kLvTile;
+    TRY(d.lv_first.ensure(3 * nc * 4));
+    TRY(d.tile_sums.ensure(lv_tiles * 4 + 16));
     TRY(d.clo.ensure(nc * 24));
     TRY(d.chi.ensure(nc * 24));
     TRY(d.cell_axis.ensure(nc * 4));
@@ -860,19 +953,21 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         hipLaunchKernelGGL(k_flag, dim3(grid_of(n)), dim3(256), 0, s, n, d.pc.as<int32_t>(),
                            d.cell.as<int4>(), d.cell_split.as<int32_t>(), d.cell_axis.as<int32_t>(),
                            d.plist.as<uint32_t>(), d.flag.as<uint8_t>());
-        hipLaunchKernelGGL(k_marks, dim3(grid_of(n)), dim3(256), 0, s, n, d.pc.as<int32_t>(),
-                           d.cell_split.as<int32_t>(), d.plist.as<uint32_t>(), d.flag.as<uint8_t>(),
-                           d.fsc.as<int32_t>());
+        hipLaunchKernelGGL(k_level_sums, dim3(lv_tiles), dim3(kLvThreads), 0, s, n,
+                           d.pc.as<int32_t>(), d.cell_split.as<int32_t>(), d.plist.as<uint32_t>(),
+                           d.flag.as<uint8_t>(), d.tile_sums.as<uint32_t>());
         TRY(hipGetLastError());
-        // one scan over the three lists back to back: each cell's range of
-        // each list is contiguous, so differences inside a range are exact
-        TRY(exclusive_scan_i32(d.fsc.as<int32_t>(), d.fsc_out.as<int32_t>(), 3 * n,
-                               d.tile_sums.as<uint32_t>(), s));
-        hipLaunchKernelGGL(k_move, dim3(grid_of(n)), dim3(256), 0, s, n, d.pc.as<int32_t>(),
-                           d.pc_tmp.as<int32_t>(), d.cell.as<int4>(), d.cell_aux.as<int4>(),
-                           d.cell_split.as<int32_t>(), d.plist.as<uint32_t>(),
+        TRY(exclusive_scan_u32_one_block(d.tile_sums.as<uint32_t>(), lv_tiles, s));
+        hipLaunchKernelGGL(k_level_firsts, dim3((3 * ncd + 3) / 4), dim3(256), 0, s,
+                           d.loop_cells.as<int32_t>() + c0, ncd, n, d.cell.as<int4>(),
+                           d.pc.as<int32_t>(), d.cell_split.as<int32_t>(), d.plist.as<uint32_t>(),
+                           d.flag.as<uint8_t>(), d.tile_sums.as<uint32_t>(), (int)nc,
+                           d.lv_first.as<int32_t>());
+        hipLaunchKernelGGL(k_level_move, dim3(lv_tiles), dim3(kLvThreads), 0, s, n,
+                           d.pc.as<int32_t>(), d.pc_tmp.as<int32_t>(), d.cell.as<int4>(),
+                           d.cell_aux.as<int4>(), d.cell_split.as<int32_t>(), d.plist.as<uint32_t>(),
                            d.plist_tmp.as<uint32_t>(), d.flag.as<uint8_t>(),
-                           d.fsc_out.as<int32_t>());
+                           d.tile_sums.as<uint32_t>(), (int)nc, d.lv_first.as<int32_t>());
         TRY(hipGetLastError());
         std::swap(d.plist, d.plist_tmp);
         std::swap(d.pc, d.pc_tmp);

@@ -2,7 +2,7 @@
 // keys (optionally carrying 32-bit values), also of several equal-length
 // segments at once, and an exclusive prefix sum of 32-bit integers.
 //
-// Radix sort: 8-bit digits, tiles of 4096 elements (256 threads x 16
+// Radix sort: 8-bit digits, tiles of 2048 elements (256 threads x 8
 // rounds); a tile never straddles two segments.  Per pass: (1) per-tile
 // digit histogram in LDS, (2) one exclusive scan over the
 // [segment][digit][tile] table (segment-major, so segment s lands in
@@ -10,15 +10,15 @@
 // are ranked per digit with wavefront ballots (eight ballots give each lane
 // the mask of lanes holding its digit) and a running per-digit count in
 // LDS, so the order of equal digits is kept (stable), which makes the sort
-// stable across passes.
+// stable across passes; the tile is ordered in LDS and written out in runs.
 #include "gpu_plan.h"
 
 namespace pmfmm {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kRounds = 16;
-constexpr int kTile = kThreads * kRounds;  // 4096
+constexpr int kRounds = 8;
+constexpr int kTile = kThreads * kRounds;  // 2048
 
 // Block b handles tile (b % tiles) of segment (b / tiles); its elements are
 // [seg n + tile kTile, min(seg n + (tile + 1) kTile, (seg + 1) n)).
@@ -75,18 +75,51 @@ __global__ void __launch_bounds__(1024) scan_single(uint32_t* __restrict__ a, in
     }
 }
 
+// Scatter of one pass.  The tile is first put in digit order in LDS (local
+// position = the digit's start in the tile + the element's stable rank among
+// the tile's elements of that digit), then written out position by
+// position: consecutive positions of one digit go to consecutive addresses,
+// so the global writes come in runs instead of one element per line.
 template <bool VALS>
 __global__ void __launch_bounds__(kThreads)
 rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
            uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n, int shift,
-           const uint32_t* __restrict__ offs, int tiles) {
-    __shared__ uint32_t run[256];
+           const uint32_t* __restrict__ hist, const uint32_t* __restrict__ offs, int tiles) {
+    __shared__ uint64_t ks[kTile];
+    __shared__ uint32_t vs[VALS ? kTile : 1];
+    __shared__ uint32_t start[256];     // digit start inside the tile
+    __shared__ uint32_t goff[256];      // digit start in the output
+    __shared__ uint32_t run[256];       // elements of each digit placed so far
     __shared__ uint32_t wc[kThreads / 64][256];
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const TileRange tr = tile_range(n, tiles);
-    run[t] = offs[tr.col + (size_t)t * tiles];
-    for (int w = 0; w < kThreads / 64; ++w) wc[w][t] = 0;
+    // exclusive scan of the tile's digit counts (one wave scans 4 per lane)
+    {
+        const uint32_t c = hist[tr.col + (size_t)t * tiles];
+        goff[t] = offs[tr.col + (size_t)t * tiles];
+        run[t] = 0;
+        start[t] = c;
+        for (int w = 0; w < kThreads / 64; ++w) wc[w][t] = 0;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        uint32_t v[4], tot = 0;
+        for (int j = 0; j < 4; ++j) {
+            v[j] = start[4 * lane + j];
+            tot += v[j];
+        }
+        uint32_t x = tot;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        uint32_t e = x - tot;
+        for (int j = 0; j < 4; ++j) {
+            start[4 * lane + j] = e;
+            e += v[j];
+        }
+    }
     __syncthreads();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int r = 0; r < kRounds; ++r) {
@@ -110,10 +143,10 @@ rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
         if (valid && rank == 0) wc[wave][d] = (uint32_t)__popcll(m);
         __syncthreads();
         if (valid) {
-            uint32_t pos = run[d] + rank;
+            uint32_t pos = start[d] + run[d] + rank;
             for (int w = 0; w < wave; ++w) pos += wc[w][d];
-            kout[pos] = key;
-            if (VALS) vout[pos] = val;
+            ks[pos] = key;
+            if (VALS) vs[pos] = val;
         }
         __syncthreads();
         uint32_t add = 0;
@@ -124,9 +157,17 @@ rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
         run[t] += add;
         __syncthreads();
     }
+    const int len = (int)(tr.end - tr.begin);
+    for (int p = t; p < len; p += kThreads) {
+        const uint64_t key = ks[p];
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const uint32_t o = goff[d] + (uint32_t)p - start[d];
+        kout[o] = key;
+        if (VALS) vout[o] = vs[p];
+    }
 }
 
-// ---- exclusive scan of int32 (tiles of 4096)
+// ---- exclusive scan of int32 (tiles of 2048)
 __global__ void __launch_bounds__(kThreads)
 scan_tile_sums(const int32_t* __restrict__ in, int64_t n, uint32_t* __restrict__ sums) {
     __shared__ int32_t red[kThreads];
@@ -204,14 +245,20 @@ hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, ui
         if (e != hipSuccess) return e;
         if (vals)
             hipLaunchKernelGGL(rs_scatter<true>, dim3(blocks), dim3(kThreads), 0, s, ka, va, kb, vb,
-                               n, shift, offs, tiles);
+                               n, shift, hist, offs, tiles);
         else
             hipLaunchKernelGGL(rs_scatter<false>, dim3(blocks), dim3(kThreads), 0, s, ka, va, kb, vb,
-                               n, shift, offs, tiles);
+                               n, shift, hist, offs, tiles);
         std::swap(ka, kb);
         std::swap(va, vb);
         *result_in_tmp = !*result_in_tmp;
     }
+    return hipGetLastError();
+}
+
+hipError_t exclusive_scan_u32_one_block(uint32_t* a, int64_t m, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scan_single, dim3(1), dim3(1024), 0, s, a, m);
     return hipGetLastError();
 }
 

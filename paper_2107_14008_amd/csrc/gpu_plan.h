@@ -61,7 +61,7 @@ struct DevPlan {
     DevBuf w64, w32;
     // on-GPU planner scratch
     DevBuf p2p_row, wpos, keys, keys_tmp, plist, plist_tmp, hist, flag, lv_first, tile_sums;
-    DevBuf pc, pc_tmp, clo, chi, chs, box_first, walkbox, front, front_next, p2p_keys,
+    DevBuf pc, pc_tmp, clo, chi, wcell, box_first, walkbox, front, front_next, p2p_keys,
         p2p_keys_tmp, m2l_keys, m2l_keys_tmp, wcount, cost, cost_keys, cost_keys_tmp, queue_tmp,
         item_count, cell_axis, farflag, walk_ctl, froots, cell_split, loop_cells;
     // cells the level loop partitions, by depth (loop_cells holds them);
@@ -77,7 +77,7 @@ struct DevPlan {
                           &boxes, &table, &x64, &x32, &stage_pos, &stage_mass, &far, &cell,
                           &cell_aux, &cellc, &M, &Lc, &Lt, &m2l_row, &m2l_src, &m2l_shift, &level_cells,
                           &w64, &w32, &p2p_row, &wpos, &keys, &keys_tmp, &plist, &plist_tmp, &hist,
-                          &flag, &lv_first, &tile_sums, &pc, &pc_tmp, &clo, &chi, &chs,
+                          &flag, &lv_first, &tile_sums, &pc, &pc_tmp, &clo, &chi, &wcell,
                           &box_first, &walkbox, &front, &front_next, &p2p_keys, &p2p_keys_tmp,
                           &m2l_keys, &m2l_keys_tmp, &wcount, &cost, &cost_keys, &cost_keys_tmp,
                           &queue_tmp, &item_count, &cell_axis, &farflag, &walk_ctl, &froots,

@@ -270,24 +270,9 @@ k_level_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __restrict__ pc
 constexpr int kFuseM = 4096;
 constexpr int kFuseC = 512;
 constexpr int kFuseT = 512;
-constexpr int kFusePer = (3 * kFuseM + kFuseT - 1) / kFuseT;
-static_assert(kFusePer <= 32, "one 32-bit mask per thread chunk");
+constexpr int kFuseRounds = (3 * kFuseM + kFuseT - 1) / kFuseT;   // 24
 constexpr uint16_t kNoChild = 0xffffu;
 
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t x = v;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) wsum[wave] = x;
-    __syncthreads();
-    uint32_t before = 0;
-    for (int w = 0; w < wave; ++w) before += wsum[w];
-    __syncthreads();
-    return before + x - v;
-}
 
 // roots[b] = (subtree root cell, cells in the subtree, root depth, deepest depth)
 __global__ void __launch_bounds__(kFuseT)
@@ -298,17 +283,27 @@ k_orb_fused(const int4* __restrict__ roots, const int4* __restrict__ cell,
     __shared__ __align__(16) uint16_t lst[2 * 3 * kFuseM];
     __shared__ uint8_t flag[kFuseM];
     __shared__ uint16_t pcl[kFuseM];
-    __shared__ uint16_t cfirst[kFuseC], ccount[kFuseC], cch0[kFuseC], cch1[kFuseC];
-    __shared__ uint8_t caxis[kFuseC], cdep[kFuseC];
+    // per local cell: first | count << 16 | child0 << 32 | depth << 48 | axis << 56
+    __shared__ uint64_t cinfo[kFuseC];
+    __shared__ uint16_t cch1[kFuseC];
     __shared__ uint32_t sfirst[3 * kFuseC];
     __shared__ uint32_t wsum[kFuseT / 64];
+    __shared__ uint64_t wmask[(kFuseT / 64) * kFuseRounds];
+    __shared__ uint32_t wpre[(kFuseT / 64) * kFuseRounds];
     const int4 r = roots[blockIdx.x];
     const int root = r.x, nsub = r.y, depth_span = r.w - r.z;
     const int4 rc = cell[root];
     const int base = rc.x, m = rc.y;
     const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     const uint32_t* __restrict__ l0 = plist + base;
     auto L = [&](int buf, int a, int k) -> uint16_t& { return lst[(buf * 3 + a) * kFuseM + k]; };
+    auto c_first = [](uint64_t ci) { return (int)(ci & 0xffffu); };
+    auto c_count = [](uint64_t ci) { return (int)((ci >> 16) & 0xffffu); };
+    auto c_child0 = [](uint64_t ci) { return (int)((ci >> 32) & 0xffffu); };
+    auto c_dep = [](uint64_t ci) { return (int)((ci >> 48) & 0xffu); };
+    auto c_axis = [](uint64_t ci) { return (int)(ci >> 56); };
 
     for (int k = t; k < m; k += kFuseT) {
         L(0, 0, k) = (uint16_t)k;
@@ -317,28 +312,29 @@ k_orb_fused(const int4* __restrict__ roots, const int4* __restrict__ cell,
     }
     for (int c = t; c < nsub; c += kFuseT) {
         const int4 ci = cell[root + c], ai = aux[root + c];
-        cfirst[c] = (uint16_t)(ci.x - base);
-        ccount[c] = (uint16_t)ci.y;
-        cch0[c] = ai.x >= 0 ? (uint16_t)(ai.x - root) : kNoChild;
+        const uint64_t ch0 = ai.x >= 0 ? (uint64_t)(ai.x - root) : (uint64_t)kNoChild;
+        cinfo[c] = (uint64_t)(ci.x - base) | ((uint64_t)ci.y << 16) | (ch0 << 32) |
+                   ((uint64_t)(ai.w - r.z) << 48);
         cch1[c] = ai.y >= 0 ? (uint16_t)(ai.y - root) : kNoChild;
-        cdep[c] = (uint8_t)(ai.w - r.z);
     }
-    // loc[] is written and read through global memory by this workgroup only
-    __threadfence();
+    // loc[] is written and read through global memory by this workgroup
+    // only, so the barrier's workgroup-scope ordering suffices (an
+    // agent-scope fence here writes back the whole L2, per workgroup)
     __syncthreads();
-    __threadfence();
     for (int k = t; k < m; k += kFuseT) {
         L(0, 1, k) = (uint16_t)loc[plist[n + base + k]];
         L(0, 2, k) = (uint16_t)loc[plist[2 * n + base + k]];
     }
     __syncthreads();
 
+    const int R = (3 * m + kFuseT - 1) / kFuseT;   // rounds of 64 positions per wave
     int cur = 0;
     for (int dep = 0;; ++dep) {
         // bounds of the cells of this depth, split axis of those that split
         for (int c = t; c < nsub; c += kFuseT) {
-            if (cdep[c] != dep) continue;
-            const int f = cfirst[c], e = f + ccount[c] - 1;
+            const uint64_t ci = cinfo[c];
+            if (c_dep(ci) != dep) continue;
+            const int f = c_first(ci), e = f + c_count(ci) - 1;
             double lo[3], hi[3];
             for (int a = 0; a < 3; ++a) {
                 lo[a] = wpos[3 * (size_t)l0[L(cur, a, f)] + a];
@@ -346,74 +342,99 @@ k_orb_fused(const int4* __restrict__ roots, const int4* __restrict__ cell,
                 clo[3 * (size_t)(root + c) + a] = lo[a];
                 chi[3 * (size_t)(root + c) + a] = hi[a];
             }
-            if (cch0[c] != kNoChild) {
+            if (c_child0(ci) != kNoChild) {
 #pragma clang fp contract(off)
                 const double e0 = hi[0] - lo[0], e1 = hi[1] - lo[1], e2 = hi[2] - lo[2];
                 int axis = 0;
                 double best = e0;
                 if (e1 > best) { axis = 1; best = e1; }
                 if (e2 > best) axis = 2;
-                caxis[c] = (uint8_t)axis;
+                cinfo[c] = (ci & 0x00ffffffffffffffull) | ((uint64_t)axis << 56);
             }
         }
         if (dep == depth_span) break;
         __syncthreads();
-        auto splits = [&](int c) { return cdep[c] == dep && cch0[c] != kNoChild; };
+        auto splits = [&](uint64_t ci) { return c_dep(ci) == dep && c_child0(ci) != kNoChild; };
         for (int k = t; k < m; k += kFuseT) {
-            const int c = pcl[k];
-            if (!splits(c)) continue;
-            flag[L(cur, caxis[c], k)] = (k - cfirst[c] < ccount[c] / 2) ? 1 : 0;
+            const uint64_t ci = cinfo[pcl[k]];
+            if (!splits(ci)) continue;
+            flag[L(cur, c_axis(ci), k)] = (k - c_first(ci) < c_count(ci) / 2) ? 1 : 0;
         }
         __syncthreads();
-        // stable partition of the three lists: one exclusive scan over the
+        // Stable partition of the three lists by one exclusive scan over the
         // left marks of all 3m positions (each cell's range is contiguous in
-        // every list, so differences inside a range count that range only)
-        const int q0 = min(3 * m, t * kFusePer), q1 = min(3 * m, q0 + kFusePer);
-        uint32_t bits = 0, cnt = 0;
-        {
-            int a = q0 / m, k = q0 - a * m;
-            for (int q = q0; q < q1; ++q) {
-                const int c = pcl[k];
-                if (splits(c) && flag[L(cur, a, k)]) {
-                    bits |= 1u << (q - q0);
-                    ++cnt;
-                }
-                if (++k == m) { k = 0; ++a; }
+        // every list, so differences inside a range count that range only).
+        // Wave w owns the positions [w R 64, (w + 1) R 64), 64 consecutive
+        // ones per round; a round's marks are one ballot, and a position's
+        // prefix is wave base + round prefix + popcount of the lanes below.
+        uint64_t* __restrict__ mymask = &wmask[wave * kFuseRounds];
+        uint32_t* __restrict__ mypre = &wpre[wave * kFuseRounds];
+#pragma unroll 4
+        for (int rr = 0; rr < R; ++rr) {
+            const int q = (wave * R + rr) * 64 + lane;
+            bool f = false;
+            if (q < 3 * m) {
+                const int a = q >= m ? (q >= 2 * m ? 2 : 1) : 0;
+                const int k = q - a * m;
+                f = splits(cinfo[pcl[k]]) && flag[L(cur, a, k)];
             }
+            const uint64_t mk = __ballot(f);
+            if (lane == 0) mymask[rr] = mk;
         }
-        const uint32_t excl = block_excl_scan(cnt, wsum);
         {
-            uint32_t run = excl;
-            int a = q0 / m, k = q0 - a * m;
-            for (int q = q0; q < q1; ++q) {
-                const int c = pcl[k];
-                if (k == cfirst[c] && splits(c)) sfirst[a * kFuseC + c] = run;
-                run += (bits >> (q - q0)) & 1u;
-                if (++k == m) { k = 0; ++a; }
+            // lane rr scans the round counts of its wave
+            const uint32_t cnt = lane < R ? (uint32_t)__popcll(mymask[lane]) : 0u;
+            uint32_t x = cnt;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(x, off);
+                if (lane >= off) x += y;
             }
+            if (lane < R) mypre[lane] = x - cnt;
+            if (lane == 63) wsum[wave] = x;
         }
         __syncthreads();
-        {
-            uint32_t run = excl;
-            int a = q0 / m, k = q0 - a * m;
-            for (int q = q0; q < q1; ++q) {
+        if (t < kFuseT / 64) {
+            uint32_t acc = 0;
+            for (int w = 0; w < t; ++w) acc += wsum[w];
+            for (int rr = 0; rr < R; ++rr) wpre[t * kFuseRounds + rr] += acc;
+        }
+        __syncthreads();
+        auto prefix = [&](int q) {
+            const int w = q / (R * 64), rr = (q >> 6) - w * R, l = q & 63;
+            const uint64_t mk = wmask[w * kFuseRounds + rr];
+            const uint64_t bl = l ? (~0ull >> (64 - l)) : 0ull;
+            return wpre[w * kFuseRounds + rr] + (uint32_t)__popcll(mk & bl);
+        };
+        for (int x = t; x < 3 * nsub; x += kFuseT) {
+            const int c = x / 3, a = x - 3 * c;
+            const uint64_t ci = cinfo[c];
+            if (splits(ci)) sfirst[a * kFuseC + c] = prefix(a * m + c_first(ci));
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int rr = 0; rr < R; ++rr) {
+            const int q = (wave * R + rr) * 64 + lane;
+            if (q < 3 * m) {
+                const int a = q >= m ? (q >= 2 * m ? 2 : 1) : 0;
+                const int k = q - a * m;
                 const int c = pcl[k];
-                const uint32_t b = (bits >> (q - q0)) & 1u;
+                const uint64_t ci = cinfo[c];
                 int pos = k;
-                if (splits(c)) {
-                    const int f = cfirst[c], nl = ccount[c] / 2;
-                    const int lr = (int)(run - sfirst[a * kFuseC + c]);
-                    pos = b ? f + lr : f + nl + (k - f - lr);
+                if (splits(ci)) {
+                    const uint64_t mk = mymask[rr];
+                    const int f = c_first(ci), nl = c_count(ci) / 2;
+                    const int lr = (int)(mypre[rr] + (uint32_t)__popcll(mk & below) -
+                                         sfirst[a * kFuseC + c]);
+                    pos = ((mk >> lane) & 1ull) ? f + lr : f + nl + (k - f - lr);
                 }
                 L(cur ^ 1, a, pos) = L(cur, a, k);
-                run += b;
-                if (++k == m) { k = 0; ++a; }
             }
         }
         __syncthreads();
         for (int k = t; k < m; k += kFuseT) {
             const int c = pcl[k];
-            if (splits(c)) pcl[k] = (k - cfirst[c] < ccount[c] / 2) ? cch0[c] : cch1[c];
+            const uint64_t ci = cinfo[c];
+            if (splits(ci)) pcl[k] = (k - c_first(ci) < c_count(ci) / 2) ? c_child0(ci) : cch1[c];
         }
         cur ^= 1;
         __syncthreads();
@@ -424,8 +445,8 @@ k_orb_fused(const int4* __restrict__ roots, const int4* __restrict__ cell,
     for (int k = t; k < m; k += kFuseT) gid[k] = l0[L(cur, 0, k)];
     __syncthreads();
     for (int k = t; k < m; k += kFuseT) {
-        const int c = pcl[k];
-        const int f = cfirst[c], e = f + ccount[c];
+        const uint64_t ci = cinfo[pcl[k]];
+        const int f = c_first(ci), e = f + c_count(ci);
         const uint32_t id = gid[k];
         int rank = 0;
         for (int q = f; q < e; ++q) rank += gid[q] < id ? 1 : 0;
@@ -434,9 +455,18 @@ k_orb_fused(const int4* __restrict__ roots, const int4* __restrict__ cell,
 }
 
 // Centre, half size and radius of every cell (the host planner's formulas).
+// What the dual walk reads of a cell, in one 80-byte record: centre and
+// radius, half sizes, and (leaf id, child 0, child 1, box).
+struct WalkCell {
+    double4 c;
+    double4 h;
+    int4 info;
+};
+
 __global__ void k_geom(int nc, const double* __restrict__ clo, const double* __restrict__ chi,
-                       const int4* __restrict__ cell, double4* __restrict__ cellc,
-                       double4* __restrict__ chs, double4* __restrict__ leafc) {
+                       const int4* __restrict__ cell, const int4* __restrict__ aux,
+                       double4* __restrict__ cellc, WalkCell* __restrict__ wcell,
+                       double4* __restrict__ leafc) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nc) return;
     double cc[3], h[3];
@@ -451,8 +481,13 @@ __global__ void k_geom(int nc, const double* __restrict__ clo, const double* __r
         rad = sqrt((h[0] * h[0] + h[1] * h[1]) + h[2] * h[2]);
     }
     cellc[c] = make_double4(cc[0], cc[1], cc[2], rad);
-    chs[c] = make_double4(h[0], h[1], h[2], 0.0);
     const int lf = cell[c].w;
+    const int4 ax = aux[c];
+    WalkCell w;
+    w.c = make_double4(cc[0], cc[1], cc[2], rad);
+    w.h = make_double4(h[0], h[1], h[2], 0.0);
+    w.info = make_int4(lf, ax.x, ax.y, ax.z);
+    wcell[c] = w;
     if (lf >= 0) leafc[lf] = make_double4(cc[0], cc[1], cc[2], 0.0);
 }
 
@@ -504,14 +539,14 @@ __device__ __forceinline__ uint64_t walk_key(int a, int b, int s, int ks) {
 }
 
 __device__ __forceinline__ void walk_classify(const int2 pr, const WalkBox* __restrict__ wbox,
-                                              const double4* __restrict__ cellc,
-                                              const double4* __restrict__ chs,
-                                              const int4* __restrict__ cell,
-                                              const int4* __restrict__ aux, int2 ks, WalkOut& o) {
+                                              const WalkCell* __restrict__ wcell, int2 ks,
+                                              WalkOut& o) {
     const int t = pr.x, u = pr.y >> 5, s = pr.y & 31;
-    const int4 at = aux[t], au = aux[u];
-    const WalkBox wb = wbox[at.z];
-    const double4 ct = cellc[t], cu = cellc[u], ht = chs[t], hu = chs[u];
+    const WalkCell wt = wcell[t], wu = wcell[u];
+    const int4 at = make_int4(wt.info.y, wt.info.z, wt.info.w, 0);
+    const int4 au = make_int4(wu.info.y, wu.info.z, wu.info.w, 0);
+    const WalkBox wb = wbox[wt.info.w];
+    const double4 ct = wt.c, cu = wu.c, ht = wt.h, hu = wu.h;
     const double sL[3] = {(double)(s % 3 - 1) * wb.L, (double)((s / 3) % 3 - 1) * wb.L,
                           (double)(s / 9 - 1) * wb.L};
     const double cta[3] = {ct.x, ct.y, ct.z}, cua[3] = {cu.x, cu.y, cu.z};
@@ -544,7 +579,7 @@ __device__ __forceinline__ void walk_classify(const int2 pr, const WalkBox* __re
         o.key[1] = walk_key(u, t, 26 - s, ks.y);
         return;
     }
-    const int lt = cell[t].w, lu = cell[u].w;
+    const int lt = wt.info.x, lu = wu.info.x;
     const double rt = ct.w, ru = cu.w;
     if (lt >= 0 && lu >= 0) {
         o.n_p2p = self ? 1 : 2;
@@ -575,13 +610,12 @@ __device__ __forceinline__ void walk_classify(const int2 pr, const WalkBox* __re
 // One level of the walk, frontier size known on the host.
 __global__ void __launch_bounds__(256)
 k_walk(const int2* __restrict__ front, int nf, int2* __restrict__ next,
-       const WalkBox* __restrict__ wbox, const double4* __restrict__ cellc,
-       const double4* __restrict__ chs, const int4* __restrict__ cell, const int4* __restrict__ aux,
-       int2 ks, uint32_t* __restrict__ counters, uint64_t* __restrict__ p2p_keys,
+       const WalkBox* __restrict__ wbox, const WalkCell* __restrict__ wcell, int2 ks,
+       uint32_t* __restrict__ counters, uint64_t* __restrict__ p2p_keys,
        uint64_t* __restrict__ m2l_keys) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     WalkOut o{0u, 0u, 0u, {}, {0ull, 0ull}};
-    if (k < nf) walk_classify(front[k], wbox, cellc, chs, cell, aux, ks, o);
+    if (k < nf) walk_classify(front[k], wbox, wcell, ks, o);
     const uint32_t cslot = wave_append(o.n_child, &counters[0]);
     for (uint32_t q = 0; q < o.n_child; ++q) next[cslot + q] = o.child[q];
     const uint32_t pslot = wave_append(o.n_p2p, &counters[1]);
@@ -595,35 +629,73 @@ k_walk(const int2* __restrict__ front, int nf, int2* __restrict__ next,
 // reported and the host then redoes the walk level by level.
 // ctl: [0] p2p total, [1] m2l total, [2] overflow flag, [3] largest frontier;
 // sizes[it] = frontier size of level it.
-__global__ void __launch_bounds__(256)
+// One level of the walk with the frontier size read on the device (no host
+// round trip between levels).  Capacities are checked; an overflow is
+// reported and the host then redoes the walk level by level.  The appends
+// are aggregated per workgroup (one atomic per counter per 1024 pairs):
+// all workgroups add to the same three counters, and at one atomic per
+// wavefront those additions, serialised at one address, took most of a
+// level's time.
+// ctl: [0] p2p total, [1] m2l total, [2] overflow flag, [3] largest frontier;
+// sizes[it] = frontier size of level it.
+constexpr int kWalkT = 1024;
+
+__global__ void __launch_bounds__(kWalkT)
 k_walk_dev(const int2* __restrict__ front, int2* __restrict__ next, int it,
            uint32_t* __restrict__ sizes, uint32_t* __restrict__ ctl, uint32_t cap_front,
            uint32_t cap_p2p, uint32_t cap_m2l, const WalkBox* __restrict__ wbox,
-           const double4* __restrict__ cellc, const double4* __restrict__ chs,
-           const int4* __restrict__ cell, const int4* __restrict__ aux, int2 ks,
-           uint64_t* __restrict__ p2p_keys, uint64_t* __restrict__ m2l_keys) {
+           const WalkCell* __restrict__ wcell, int2 ks, uint64_t* __restrict__ p2p_keys,
+           uint64_t* __restrict__ m2l_keys) {
+    __shared__ uint64_t wtot[kWalkT / 64];
+    __shared__ uint32_t bbase[3];
     const uint32_t nf = sizes[it];
     if (nf > cap_front) return;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < nf; base += stride) {
-        const uint32_t k = base + lane;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < nf; base += stride) {
+        const uint32_t k = base + threadIdx.x;
         WalkOut o{0u, 0u, 0u, {}, {0ull, 0ull}};
-        if (k < nf) walk_classify(front[k], wbox, cellc, chs, cell, aux, ks, o);
-        const uint32_t cslot = wave_append(o.n_child, &sizes[it + 1]);
+        if (k < nf) walk_classify(front[k], wbox, wcell, ks, o);
+        // packed counts: children (<= 4096 per group) | p2p << 16 | m2l << 32
+        const uint64_t v = (uint64_t)o.n_child | ((uint64_t)o.n_p2p << 16) |
+                           ((uint64_t)o.n_m2l << 32);
+        uint64_t x = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint64_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wtot[wave] = x;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t run = 0;
+            for (int w = 0; w < kWalkT / 64; ++w) {
+                const uint64_t tw = wtot[w];
+                wtot[w] = run;
+                run += tw;
+            }
+            const uint32_t tc = (uint32_t)(run & 0xffffu), tp = (uint32_t)((run >> 16) & 0xffffu),
+                           tm = (uint32_t)(run >> 32);
+            bbase[0] = tc ? atomicAdd(&sizes[it + 1], tc) : 0u;
+            bbase[1] = tp ? atomicAdd(&ctl[0], tp) : 0u;
+            bbase[2] = tm ? atomicAdd(&ctl[1], tm) : 0u;
+        }
+        __syncthreads();
+        const uint64_t off = wtot[wave] + x - v;
+        const uint32_t cslot = bbase[0] + (uint32_t)(off & 0xffffu);
+        const uint32_t pslot = bbase[1] + (uint32_t)((off >> 16) & 0xffffu);
+        const uint32_t mslot = bbase[2] + (uint32_t)(off >> 32);
         if (cslot + o.n_child <= cap_front) {
             for (uint32_t q = 0; q < o.n_child; ++q) next[cslot + q] = o.child[q];
         } else if (o.n_child) {
             ctl[2] = 1u;
         }
-        const uint32_t pslot = wave_append(o.n_p2p, &ctl[0]);
         for (uint32_t q = 0; q < o.n_p2p; ++q) {
             if (pslot + q < cap_p2p) p2p_keys[pslot + q] = o.key[q]; else ctl[2] = 1u;
         }
-        const uint32_t mslot = wave_append(o.n_m2l, &ctl[1]);
         for (uint32_t q = 0; q < o.n_m2l; ++q) {
             if (mslot + q < cap_m2l) m2l_keys[mslot + q] = o.key[q]; else ctl[2] = 1u;
         }
+        __syncthreads();   // wtot and bbase are reused by the next group
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&ctl[3], nf);
 }
@@ -679,28 +751,30 @@ __global__ void k_items(int nl, const int32_t* __restrict__ row, const int32_t* 
                         uint64_t* __restrict__ cost_keys, uint32_t* __restrict__ slots,
                         unsigned long long* __restrict__ cand) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nl) return;
-    const int r0 = row[i], len = row[i + 1] - r0;
-    if (len == 0) return;
-    const int parts = (len + chunk - 1) / chunk;
-    const int base = len / parts, extra = len % parts;
-    const int ni = leaf[i].y;
-    int t = r0;
     unsigned long long total = 0;
-    for (int k = 0; k < parts; ++k) {
-        const int sz = base + (k < extra ? 1 : 0);
-        unsigned long long c = 0;
-        for (int q = t; q < t + sz; ++q) c += (unsigned long long)leaf[js[q] >> 5].y;
-        c *= (unsigned long long)ni;
-        total += c;
-        const int s = slot0[i] + k;
-        items[s] = make_int4(i, t, t + sz, s);
-        const unsigned long long b = c >> cshift;
-        cost_keys[s] = (uint64_t)(255u - (b > 255ull ? 255u : (uint32_t)b));
-        slots[s] = (uint32_t)s;
-        t += sz;
+    const int r0 = i < nl ? row[i] : 0, len = i < nl ? row[i + 1] - r0 : 0;
+    if (len > 0) {
+        const int parts = (len + chunk - 1) / chunk;
+        const int base = len / parts, extra = len % parts;
+        const int ni = leaf[i].y;
+        int t = r0;
+        for (int k = 0; k < parts; ++k) {
+            const int sz = base + (k < extra ? 1 : 0);
+            unsigned long long c = 0;
+            for (int q = t; q < t + sz; ++q) c += (unsigned long long)leaf[js[q] >> 5].y;
+            c *= (unsigned long long)ni;
+            total += c;
+            const int s = slot0[i] + k;
+            items[s] = make_int4(i, t, t + sz, s);
+            const unsigned long long b = c >> cshift;
+            cost_keys[s] = (uint64_t)(255u - (b > 255ull ? 255u : (uint32_t)b));
+            slots[s] = (uint32_t)s;
+            t += sz;
+        }
     }
-    atomicAdd(cand, total);
+    // one atomic per wavefront (a single counter for all leaves)
+    for (int off = 32; off > 0; off >>= 1) total += __shfl_down(total, off);
+    if ((threadIdx.x & 63) == 0 && total) atomicAdd(cand, total);
 }
 
 __global__ void k_check(const double* __restrict__ pos, const double* __restrict__ mass, int64_t n,
@@ -984,10 +1058,10 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     // ---- leaf order, geometry, particle records
     TRY(d.leafc.ensure(nl * 32));
     TRY(d.cellc.ensure(nc * 32));
-    TRY(d.chs.ensure(nc * 32));
+    TRY(d.wcell.ensure(nc * sizeof(WalkCell)));
     hipLaunchKernelGGL(k_geom, dim3(grid_of(nc)), dim3(256), 0, s, (int)nc, d.clo.as<double>(),
-                       d.chi.as<double>(), d.cell.as<int4>(), d.cellc.as<double4>(),
-                       d.chs.as<double4>(), d.leafc.as<double4>());
+                       d.chi.as<double>(), d.cell.as<int4>(), d.cell_aux.as<int4>(),
+                       d.cellc.as<double4>(), d.wcell.as<WalkCell>(), d.leafc.as<double4>());
     TRY(hipGetLastError());
     TRY(d.x64.ensure(n * 32));
     TRY(d.x32.ensure(n * 16));
@@ -1031,16 +1105,20 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         uint32_t* sizes = ctl + 4;
         DevBuf* bufs[2] = {&d.front, &d.front_next};
         for (int it = 0; it < L; ++it) {
-            hipLaunchKernelGGL(k_walk_dev, dim3(2048), dim3(256), 0, s, bufs[it & 1]->as<int2>(),
+            hipLaunchKernelGGL(k_walk_dev, dim3(512), dim3(kWalkT), 0, s, bufs[it & 1]->as<int2>(),
                                bufs[(it + 1) & 1]->as<int2>(), it, sizes, ctl, capf, capp, capm,
-                               d.walkbox.as<WalkBox>(), d.cellc.as<double4>(), d.chs.as<double4>(),
-                               d.cell.as<int4>(), d.cell_aux.as<int4>(), ks,
+                               d.walkbox.as<WalkBox>(), d.wcell.as<WalkCell>(), ks,
                                d.p2p_keys.as<uint64_t>(), d.m2l_keys.as<uint64_t>());
         }
         TRY(hipGetLastError());
         std::vector<uint32_t> hc(L + 5);
         TRY(hipMemcpyAsync(hc.data(), ctl, (L + 5) * 4, hipMemcpyDeviceToHost, s));
         TRY(hipStreamSynchronize(s));
+        if (clk.on) {
+            std::fprintf(stderr, "[pmfmm gpu plan] walk frontier per level:");
+            for (int it = 0; it <= L; ++it) std::fprintf(stderr, " %u", hc[4 + it]);
+            std::fprintf(stderr, "\n");
+        }
         if (hc[2] == 0 && hc[4 + L] == 0 && hc[0] <= capp && hc[1] <= capm) {
             n_p2p = hc[0];
             n_m2l = hc[1];
@@ -1066,9 +1144,8 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                 TRY(d.m2l_keys.grow((size_t)(n_m2l + 2 * nf) * 8 * 2, (size_t)n_m2l * 8, s));
             hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, d.wcount.as<uint32_t>(), 1);
             hipLaunchKernelGGL(k_walk, dim3(grid_of(nf)), dim3(256), 0, s, d.front.as<int2>(), (int)nf,
-                               d.front_next.as<int2>(), d.walkbox.as<WalkBox>(), d.cellc.as<double4>(),
-                               d.chs.as<double4>(), d.cell.as<int4>(), d.cell_aux.as<int4>(), ks,
-                               d.wcount.as<uint32_t>(), d.p2p_keys.as<uint64_t>(),
+                               d.front_next.as<int2>(), d.walkbox.as<WalkBox>(), d.wcell.as<WalkCell>(),
+                               ks, d.wcount.as<uint32_t>(), d.p2p_keys.as<uint64_t>(),
                                d.m2l_keys.as<uint64_t>());
             TRY(hipGetLastError());
             TRY(hipMemcpyAsync(hc, d.wcount.p, 16, hipMemcpyDeviceToHost, s));

@@ -9,8 +9,8 @@ One step = the whole short-range path on particles already in HBM: plan
 order, far field (P2M .. L2P), the persistent P2P kernel and the ordered
 reduction.  ``value`` counts candidate pairs of the P2P tasks (n_i * n_j per
 task, the paper's interaction count) per second of whole step, for the
-float32 form (cell-relative float32 pairs, T from a 2048-segment quadratic
-table over r^2, float64 accumulation).  The float32 form with the paper's
+float32 form (cell-relative float32 pairs, T(r) / r^3 from a table of
+quadratic segments over r^2, 64 per octave, float64 accumulation).  The float32 form with the paper's
 table (512 nodes on x, T_[2]) and the plain float64 form (exact erfc/exp)
 are timed the same way and reported beside it.
 
@@ -38,9 +38,9 @@ from paper_2107_14008_amd import inputs  # noqa: E402
 # form: displacement 3, r^2 5, 1/r 1, table coordinate 2, index and offset 2,
 # T_[2] Horner 4, g = m T / r^3 4, accumulation 6.
 FLOPS_PER_PAIR_F32_T2 = 27
-# r^2 segment table: displacement 3, r^2 5, clamp 1, segment index 1,
-# quadratic Horner in r^2 4, 1/r 1, 1/r^3 2, g = m T / r^3 2, accumulation 6.
-FLOPS_PER_PAIR_F32_R2 = 25
+# r^2 table of T / r^3: displacement 3, r^2 5, clamp 1, segment index 2,
+# quadratic Horner in r^2 4, g = m F 1, accumulation 6.
+FLOPS_PER_PAIR_F32_R2 = 22
 # Same count for the float64 exact form, erfc and exp taken as one op each:
 # displacement 3 (+3 shift), r^2 5, 1/r 1, x 2, T = erfc + c x e^-x^2 6,
 # g 4, accumulation 6.
@@ -155,7 +155,7 @@ def secondary(args):
         n = int(sum(counts))
         out = torch.empty((n, 3), dtype=torch.float64, device=dev)
         ctx = B.Context(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2,
-                        table_size=2048, table_level=2, timing=1)
+                        table_size=64, table_level=2, timing=1)
 
         def build():
             ctx.build_batch(per_box, counts, pos, mass, stream)
@@ -172,7 +172,7 @@ def secondary(args):
                     config={"workload": f"batch64: {len(boxes)} clustered boxes, "
                             f"N = n_side^3 with n_side log-uniform in [16, 96] "
                             f"(total {n}), one persistent launch, float32 "
-                            f"2048-segment quadratic r^2 table", "n": n,
+                            f"r^2 table of T/r^3 (64 segments per octave)", "n": n,
                             "candidate_pairs_per_step": cand,
                             "schedule": best, "phases_ms": ph,
                             "p2p_interactions_per_s": cand / (ph["p2p_ms"] / 1e3),
@@ -222,8 +222,8 @@ def secondary(args):
         forms = {"fp64_exact": dict(precision=B.PMFMM_FP64, trunc=B.TRUNC_EXACT),
                  "fp32_t2_512": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
                                      table_size=512, table_level=2),
-                 "fp32_r2_2048": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2,
-                                      table_size=2048, table_level=2)}
+                 "fp32_r2_64": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2,
+                                    table_size=64, table_level=2)}
         order, theta = -1, 0.0
     else:
         w = inputs.clustered_16m()
@@ -234,8 +234,8 @@ def secondary(args):
                                       table_size=2048, table_level=3),
                  "fp32_t2_512": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
                                      table_size=512, table_level=2),
-                 "fp32_r2_2048": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2,
-                                      table_size=2048, table_level=2)}
+                 "fp32_r2_64": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2,
+                                    table_size=64, table_level=2)}
         order, theta = args.order, args.theta
     n = len(w.mass)
     res = {}
@@ -281,8 +281,9 @@ def main():
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--table-size", type=int, default=512)
     ap.add_argument("--table-level", type=int, default=2)
-    ap.add_argument("--r2-segments", type=int, default=2048,
-                    help="segments of the headline float32 r^2 table")
+    ap.add_argument("--r2-per-octave", type=int, default=64,
+                    help="segments per octave of r^2 of the headline float32 "
+                         "table")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
                     help="time the headline float32 form only (profiling)")
@@ -336,7 +337,7 @@ def main():
 
     forms = {
         "fp32": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2,
-                     table_size=args.r2_segments, table_level=2),
+                     table_size=args.r2_per_octave, table_level=2),
         "fp32_paper_table": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
                                  table_size=args.table_size,
                                  table_level=args.table_level,
@@ -407,9 +408,9 @@ def main():
             "n": n, "theta": args.theta, "order": args.order,
             "planner": "gpu",
             "candidate_pairs_per_step": cand,
-            "fp32_form": f"float32 cell-relative pairs, T from a "
-                         f"{args.r2_segments}-segment quadratic table over r^2, "
-                         f"float64 accumulation",
+            "fp32_form": f"float32 cell-relative pairs, T(r)/r^3 from a "
+                         f"table of quadratic segments over r^2 "
+                         f"({args.r2_per_octave} per octave), float64 accumulation",
             "fp32_paper_table_form": f"float32 cell-relative pairs, "
                                      f"{args.table_size}-node T_[{args.table_level}] "
                                      f"table of Eq. (int)",
@@ -423,7 +424,7 @@ def main():
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": measured_traffic(),
             "traffic_unit": "B per launch",
-            "kernel": "p2p_kernel<FP32 r^2 table, degree 2>",
+            "kernel": "p2p_kernel<FP32 r^2 table of T/r^3, degree 2>",
             "flops_per_pair": FLOPS_PER_PAIR_F32_R2,
             "kernel_ms": r32["p2p_ms"],
             "paper_convention_frac": cand * PAPER_OPS_PER_PAIR

@@ -51,10 +51,12 @@ typedef enum pmfmm_status {
 /* Arithmetic of the pair force (Sec. 4 compares single and double). */
 enum { PMFMM_FP64 = 0, PMFMM_FP32 = 1 };
 /* Truncation factor T: library erfc/exp, the Taylor table of Eq. (int), or
- * (float32 only) a table of polynomial segments over r^2 (not in the paper:
- * table_size segments of equal width in r^2 on [0, r_cut^2), each an
- * interpolating polynomial of degree table_level in r^2 at Chebyshev nodes,
- * zero beyond r_cut; it needs one r_cut / r_s for all boxes of a plan). */
+ * (float32 only) a table of the whole radial factor T(r) / r^3 over
+ * polynomial segments in r^2 (not in the paper): r^2 is scaled so that
+ * r_cut^2 = 2^11, and each octave of the scaled r^2 in [2^-35, 2^11) is cut
+ * into table_size equal segments, each holding the polynomial of degree
+ * table_level interpolating T(r) / r^3 at Chebyshev nodes; zero beyond
+ * r_cut.  It needs one r_cut / r_s for all boxes of a plan. */
 enum { PMFMM_TRUNC_EXACT = 0, PMFMM_TRUNC_TABLE = 1, PMFMM_TRUNC_R2 = 2 };
 /* Table node choice for x: nearest node or the node below x. */
 enum { PMFMM_ROUND_NEAREST = 0, PMFMM_ROUND_FLOOR = 1 };
@@ -73,9 +75,11 @@ typedef struct pmfmm_params {
     int32_t precision;   /* PMFMM_FP64 or PMFMM_FP32                              */
     int32_t trunc;       /* PMFMM_TRUNC_EXACT, _TABLE or _R2 (FP32 only)           */
     int32_t table_size;  /* TABLE: nodes on x in [0, 3], 16..2048 (FP64) or
-                            16..4096 (FP32); R2: segments, 64..4096              */
+                            16..4096 (FP32); R2: segments per octave of r^2,
+                            16, 32, 64 or 128                                    */
     int32_t table_level; /* TABLE: Taylor terms kept, 0..4 (T_[0] .. T_[4]);
-                            R2: polynomial degree, 1..3                          */
+                            R2: polynomial degree, 2 (or 1 with >= 64
+                            segments per octave)                                 */
     int32_t table_round; /* TABLE: PMFMM_ROUND_NEAREST or PMFMM_ROUND_FLOOR       */
     /* scheduling of the P2P work (no effect on results) */
     int32_t chunk;       /* j-leaves per work item, 0 = automatic                 */

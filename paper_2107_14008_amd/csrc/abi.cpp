@@ -58,9 +58,15 @@ bool valid_eval(const pmfmm_params& p, std::string& why) {
         return false;
     }
     if (p.trunc == PMFMM_TRUNC_R2) {
-        if (p.precision != PMFMM_FP32) { why = "the r^2 segment table is a float32 form"; return false; }
-        if (p.table_level < 1 || p.table_level > 3) { why = "table_level (degree) must be in 1..3 for R2"; return false; }
-        if (p.table_size < 64 || p.table_size > 4096) { why = "table_size (segments) must be in 64..4096 for R2"; return false; }
+        if (p.precision != PMFMM_FP32) { why = "the r^2 table is a float32 form"; return false; }
+        if (p.table_size != 16 && p.table_size != 32 && p.table_size != 64 && p.table_size != 128) {
+            why = "table_size (segments per octave) must be 16, 32, 64 or 128 for R2";
+            return false;
+        }
+        if (!(p.table_level == 2 || (p.table_level == 1 && p.table_size >= 64))) {
+            why = "table_level (degree) must be 2, or 1 with at least 64 segments per octave, for R2";
+            return false;
+        }
     }
     if (p.table_level < 0 || p.table_level > 4) { why = "table_level must be in 0..4"; return false; }
     if (p.table_round != PMFMM_ROUND_NEAREST && p.table_round != PMFMM_ROUND_FLOOR) { why = "table_round must be NEAREST or FLOOR"; return false; }
@@ -101,60 +107,63 @@ double truncation_T(double x) {
     return std::erfc(x) + 1.12837916709551257390 * x * std::exp(-x * x);
 }
 
-// Table of the float32 r^2 form: segment k covers s = r'^2 in [k, k + 1),
-// i.e. x^2 in [k kappa, (k + 1) kappa) with kappa = x_c^2 / n; on it T is
-// the polynomial of degree `deg` interpolating T at the Chebyshev nodes of
-// t = s - k in [0, 1], re-expanded in s itself (the kernel evaluates it at
-// s with no segment offset).  Row n (beyond the cutoff) is zero.
-std::vector<unsigned char> build_r2_table(int n, int deg, double xc) {
-    const double kappa = xc * xc / n;
-    std::vector<unsigned char> out((size_t)16 * (n + 1) + 16, 0);
+// Table of the float32 r^2 form: F(s) = T(x) s^(-3/2), s = r'^2 in units
+// where r_cut^2 = 2^kR2Emax (x^2 = s kappa, kappa = x_c^2 / 2^kR2Emax).  Row
+// (e - kR2Emin) 2^bits + j covers s in 2^e [1 + j / 2^bits, 1 + (j + 1) / 2^bits);
+// on it F is the polynomial of degree `deg` interpolating F at the
+// Chebyshev nodes of the segment, re-expanded in s itself (the kernel
+// evaluates it at s with no segment offset).  The last row (s = 2^kR2Emax)
+// is zero.
+std::vector<unsigned char> build_r2_table(int per_octave, int deg, double xc) {
+    const int bits = per_octave == 16 ? 4 : per_octave == 32 ? 5 : per_octave == 64 ? 6 : 7;
+    const int rows = (pmfmm::kR2Emax - pmfmm::kR2Emin) << bits;
+    const double kappa = xc * xc / std::ldexp(1.0, pmfmm::kR2Emax);
+    std::vector<unsigned char> out((size_t)16 * (rows + 1) + 16, 0);
     float* f = reinterpret_cast<float*>(out.data());
     const int m = deg + 1;
-    for (int k = 0; k < n; ++k) {
-        double V[4][5];
+    for (int k = 0; k < rows; ++k) {
+        const int e = pmfmm::kR2Emin + (k >> bits), j = k & ((1 << bits) - 1);
+        const double lo = std::ldexp(1.0 + (double)j / per_octave, e);
+        const double hi = std::ldexp(1.0 + (double)(j + 1) / per_octave, e);
+        double V[3][4];
         for (int i = 0; i < m; ++i) {
-            const double t = 0.5 - 0.5 * std::cos(M_PI * (i + 0.5) / m);
+            const double t = 0.5 - 0.5 * std::cos(M_PI * (i + 0.5) / m);   // in [0, 1]
+            const double sv = lo + (hi - lo) * t;
             double tp = 1.0;
-            for (int j = 0; j < m; ++j) {
-                V[i][j] = tp;
-                tp *= t;
+            for (int q = 0; q < m; ++q) {
+                V[i][q] = tp;
+                tp *= sv - lo;
             }
-            V[i][m] = truncation_T(std::sqrt((k + t) * kappa));
+            V[i][m] = truncation_T(std::sqrt(sv * kappa)) * std::pow(sv, -1.5);
         }
         // Gaussian elimination with partial pivoting on the (m x m) system
         for (int c = 0; c < m; ++c) {
             int piv = c;
             for (int r = c + 1; r < m; ++r)
                 if (std::fabs(V[r][c]) > std::fabs(V[piv][c])) piv = r;
-            for (int j = 0; j <= m; ++j) std::swap(V[c][j], V[piv][j]);
+            for (int q = 0; q <= m; ++q) std::swap(V[c][q], V[piv][q]);
             for (int r = c + 1; r < m; ++r) {
-                const double q = V[r][c] / V[c][c];
-                for (int j = c; j <= m; ++j) V[r][j] -= q * V[c][j];
+                const double g = V[r][c] / V[c][c];
+                for (int q = c; q <= m; ++q) V[r][q] -= g * V[c][q];
             }
         }
-        double cl[4] = {0, 0, 0, 0};
+        double cl[3] = {0, 0, 0};
         for (int c = m - 1; c >= 0; --c) {
             double acc = V[c][m];
-            for (int j = c + 1; j < m; ++j) acc -= V[c][j] * cl[j];
+            for (int q = c + 1; q < m; ++q) acc -= V[c][q] * cl[q];
             cl[c] = acc / V[c][c];
         }
-        // p(s) = sum_j cl_j (s - k)^j = sum_i a_i s^i
-        static const double binom[4][4] = {{1, 0, 0, 0}, {1, 1, 0, 0}, {1, 2, 1, 0}, {1, 3, 3, 1}};
-        for (int i = 0; i < 4; ++i) {
+        // p(s) = sum_q cl_q (s - lo)^q = sum_i a_i s^i
+        static const double binom[3][3] = {{1, 0, 0}, {1, 1, 0}, {1, 2, 1}};
+        for (int i = 0; i < m; ++i) {
             double acc = 0.0;
-            for (int j = i; j < m; ++j) acc += cl[j] * binom[j][i] * std::pow(-(double)k, j - i);
-            f[4 * k + i] = i < m ? (float)acc : 0.0f;
+            for (int q = i; q < m; ++q) acc += cl[q] * binom[q][i] * std::pow(-lo, q - i);
+            f[4 * k + i] = (float)acc;
         }
     }
     return out;
 }
 
-// Coefficients of Eq. (int) in table units e = (x - x_i) / h:
-//   c_k = a_k(x_i) h^k with a_0 = T_i = erfc(x_i) - x_i E_i / 2,
-//   a_1 = x_i^2 E_i, a_2 = -x_i (x_i^2 - 1) E_i,
-//   a_3 = (2/3 x_i^4 - 5/3 x_i^2 + 1/3) E_i, a_4 = -x_i (x_i^4 / 3 - 3/2 x_i^2 + 1) E_i,
-//   E_i = -4 exp(-x_i^2) / sqrt(pi), x_i = i h, h = 3 / n_tab.
 std::vector<unsigned char> build_table(const pmfmm_params& p, double xc) {
     if (uses_r2(p)) return build_r2_table(p.table_size, p.table_level, xc);
     const int n = p.table_size;
@@ -252,6 +261,8 @@ struct pmfmm_ctx {
     // sizes of the current plan
     int64_t n_items = 0, n_p2p = 0, n_m2l = 0, cand = 0;
     bool far = false;
+    // smallest depth of an M2L source / target cell of the current plan
+    int32_t m2l_dmin_src = 0, m2l_dmin_tgt = 0;
     // tree shape uploaded for the GPU planner
     std::vector<int64_t> topo_counts;
     std::vector<pmfmm::BoxParams> topo_boxes;
@@ -300,6 +311,12 @@ int do_plan(pmfmm_ctx* ctx, const std::vector<pmfmm::BoxParams>& boxes,
     ctx->n_m2l = (int64_t)ctx->plan.m2l_src.size();
     ctx->cand = ctx->plan.candidate_pairs;
     ctx->far = ctx->plan.far_field;
+    ctx->m2l_dmin_src = ctx->m2l_dmin_tgt = 0x7fffffff;
+    const pmfmm::Plan& pl = ctx->plan;
+    for (size_t c = 0; c + 1 < pl.m2l_row.size(); ++c)
+        if (pl.m2l_row[c + 1] > pl.m2l_row[c])
+            ctx->m2l_dmin_tgt = std::min(ctx->m2l_dmin_tgt, pl.cells[c].depth);
+    for (int32_t u : pl.m2l_src) ctx->m2l_dmin_src = std::min(ctx->m2l_dmin_src, pl.cells[u].depth);
     return PMFMM_OK;
 }
 
@@ -373,10 +390,10 @@ std::vector<pmfmm::BoxDev> box_table(const pmfmm_ctx* ctx) {
         d.G = b.G;
         // float32 offsets in units of 1 / sigma (see BoxDev)
         const bool r2 = uses_r2(ctx->p);
-        d.sigma = r2 ? std::sqrt(ctx->p.table_size / d.rc2) : 1.0;
+        d.sigma = r2 ? std::sqrt(std::ldexp(1.0, pmfmm::kR2Emax) / d.rc2) : 1.0;
         d.alpha_f = (float)(d.alpha / d.sigma);
-        d.rc2_f = r2 ? (float)ctx->p.table_size : (float)d.rc2;
-        d.tiny_f = d.rc2_f * 1e-14f;
+        d.rc2_f = r2 ? std::ldexp(1.0f, pmfmm::kR2Emax) : (float)d.rc2;
+        d.tiny_f = r2 ? std::ldexp(1.0f, pmfmm::kR2Emin) : d.rc2_f * 1e-14f;
         d.tab_scale = d.alpha * (ctx->p.table_size / 3.0);
         d.tab_scale_f = (float)(d.tab_scale / d.sigma);
         d.order = (b.order >= 0 && b.theta > 0.0) ? b.order : -1;
@@ -525,13 +542,17 @@ int run_far(pmfmm_ctx* ctx, hipStream_t s) {
     pmfmm::FarArgs f = far_args(ctx);
     HIP_TRY(pmfmm::launch_p2m(f, s));
     const int nd = (int)pl.depth_begin.size() - 1;
-    for (int d = nd - 2; d >= 0; --d) {   // parents of the deepest level first
+    // no cell above the shallowest M2L source needs a multipole, none above
+    // the shallowest target a local expansion
+    const int d_up = std::max(0, (int)std::min<int64_t>(ctx->m2l_dmin_src, nd));
+    const int d_down = std::max(1, (int)std::min<int64_t>((int64_t)ctx->m2l_dmin_tgt + 1, nd));
+    for (int d = nd - 2; d >= d_up; --d) {   // parents of the deepest level first
         f.level_cells = ctx->d.level_cells.as<int32_t>() + pl.depth_begin[d];
         f.n_level = pl.depth_begin[d + 1] - pl.depth_begin[d];
         HIP_TRY(pmfmm::launch_m2m_level(f, s));
     }
     HIP_TRY(pmfmm::launch_m2l(f, s));
-    for (int d = 1; d < nd; ++d) {
+    for (int d = d_down; d < nd; ++d) {
         f.level_cells = ctx->d.level_cells.as<int32_t>() + pl.depth_begin[d];
         f.n_level = pl.depth_begin[d + 1] - pl.depth_begin[d];
         HIP_TRY(pmfmm::launch_l2l_level(f, s));
@@ -608,6 +629,8 @@ int gpu_build(pmfmm_ctx* ctx, const std::vector<pmfmm::BoxParams>& boxes, const 
     ctx->n_m2l = pc.n_m2l;
     ctx->n_items = pc.n_items;
     ctx->cand = pc.candidate_pairs;
+    ctx->m2l_dmin_src = pc.m2l_min_depth_src;
+    ctx->m2l_dmin_tgt = pc.m2l_min_depth_tgt;
     ctx->far = pc.n_m2l > 0;
     ctx->plan.far_field = ctx->far;
     ctx->plan.candidate_pairs = pc.candidate_pairs;
@@ -785,9 +808,8 @@ int pmfmm_set_eval(pmfmm_ctx* ctx, const pmfmm_params* p) {
     const bool table_change = p->precision != ctx->p.precision || p->table_size != ctx->p.table_size ||
                               p->table_round != ctx->p.table_round || p->table_level != ctx->p.table_level ||
                               p->trunc != ctx->p.trunc;
-    // the float32 offsets' scale (x32) depends on these
-    const bool sigma_change = uses_r2(*p) != uses_r2(ctx->p) ||
-                              (uses_r2(*p) && p->table_size != ctx->p.table_size);
+    // the float32 offsets' scale (x32) depends on this
+    const bool sigma_change = uses_r2(*p) != uses_r2(ctx->p);
     const bool chunk_change = p->chunk != ctx->p.chunk;
     ctx->p.precision = p->precision;
     ctx->p.trunc = p->trunc;

@@ -28,21 +28,25 @@ enum Mode : int {
 
 constexpr bool is_fp32(int mode) { return mode >= kFP32Exact; }
 
+// r^2 table form: scaled r^2 covers [2^kR2Emin, 2^kR2Emax) (r_cut^2 = 2^kR2Emax).
+constexpr int kR2Emin = -35;
+constexpr int kR2Emax = 11;
+
 // Per-box constants.  The float32 forms work on offsets scaled by sigma
 // (x32 and the per-task centre offsets): sigma = 1, except for the r^2
-// segment table, where sigma^2 = n_seg / r_cut^2 puts segment k of the
-// table at r'^2 in [k, k + 1) and the cutoff at r'^2 = n_seg.  The float
-// constants below are in those units; results are scaled back by sigma^2
-// (forces) or sigma^3 / sigma^2 (adjoint).
+// table, where sigma^2 = 2^kR2Emax / r_cut^2 puts the cutoff at
+// r'^2 = 2^kR2Emax.  The float constants below are in those units; results
+// are scaled back by sigma^2 (forces) or sigma^3 / sigma^2 (adjoint).
 struct BoxDev {
     double L;        // box side
     double alpha;    // 1 / (2 r_s)
     double rc2;      // r_cut * r_cut
     double G;
     float alpha_f;   // alpha / sigma
-    float rc2_f;     // r_cut^2 sigma^2 (exactly n_seg for the r^2 table)
+    float rc2_f;     // r_cut^2 sigma^2 (exactly 2^kR2Emax for the r^2 table)
     float tab_scale_f;  // tab_scale / sigma
-    float tiny_f;    // rc2_f * 1e-14: float32 r^2 clamp below (coincident pairs)
+    float tiny_f;    // float32 r^2 clamp below (coincident pairs): rc2_f * 1e-14,
+                     // 2^kR2Emin for the r^2 table
     double tab_scale;  // n_tab / 3 / (2 r_s): x-table units per unit distance
     int32_t order;     // expansion order p of this box (< 0: no far field)
     int32_t pad;

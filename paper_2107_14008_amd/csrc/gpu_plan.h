@@ -89,6 +89,9 @@ struct DevPlan {
 // Counts the host needs after a device plan.
 struct PlanCounts {
     int64_t n_p2p = 0, n_m2l = 0, n_items = 0, candidate_pairs = 0;
+    // smallest depth of an M2L source / target cell (the pass-up and
+    // pass-down need no level above it); INT32_MAX without M2L tasks
+    int32_t m2l_min_depth_src = 0x7fffffff, m2l_min_depth_tgt = 0x7fffffff;
 };
 
 // Sort / scan primitives (gpu_sort.hip).

@@ -24,6 +24,7 @@
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "gpu_plan.h"
@@ -724,13 +725,19 @@ __global__ void k_split_p2p(const uint64_t* __restrict__ keys, int64_t nk, int k
     if (k < nk) js[k] = (int32_t)(keys[k] & ((1ull << ks) - 1));
 }
 
+// Also the smallest depth of the tasks' source and target cells
+// (mindep[0] / mindep[1], preset to INT32_MAX).
 __global__ void k_split_m2l(const uint64_t* __restrict__ keys, int64_t nk, int ks,
-                            int32_t* __restrict__ src, int32_t* __restrict__ shift) {
+                            const int4* __restrict__ aux, int32_t* __restrict__ src,
+                            int32_t* __restrict__ shift, int32_t* __restrict__ mindep) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nk) return;
     const uint32_t low = (uint32_t)(keys[k] & ((1ull << ks) - 1));
-    src[k] = (int32_t)(low >> 5);
+    const int u = (int)(low >> 5), t = (int)(keys[k] >> ks);
+    src[k] = u;
     shift[k] = (int32_t)(low & 31u);
+    atomicMin(&mindep[0], aux[u].w);
+    atomicMin(&mindep[1], aux[t].w);
 }
 
 __global__ void k_item_count(int nl, const int32_t* __restrict__ row, int chunk,
@@ -853,7 +860,7 @@ struct PhaseTimer {
 
 std::string gpu_check_inputs(DevPlan& d, const double* pos, const double* mass, int64_t n,
                              hipStream_t s) {
-    TRY(d.wcount.ensure(64));
+    TRY(d.wcount.ensure(128));
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int*>(d.wcount.p), 2,
                        0x7fffffff);
     hipLaunchKernelGGL(k_check, dim3(grid_of(n)), dim3(256), 0, s, pos, mass, n,
@@ -1071,7 +1078,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
 
     clk.lap("records");
     // ---- dual walk
-    TRY(d.wcount.ensure(64));
+    TRY(d.wcount.ensure(128));
     // the canonical half of (root, root, s): the zero shift and the 13
     // shifts with code > 13
     const int64_t nf0 = 14 * (int64_t)nbox;
@@ -1186,10 +1193,14 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     TRY(d.m2l_shift.ensure(std::max<int64_t>(1, n_m2l) * 4));
     hipLaunchKernelGGL(k_csr_rows, dim3(grid_of(nc + 1)), dim3(256), 0, s, d.m2l_keys.as<uint64_t>(),
                        n_m2l, (int)nc, ks.y, d.m2l_row.as<int32_t>());
+    // wcount words 16, 17: smallest source / target depth of the M2L tasks
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int*>(d.wcount.p) + 16,
+                       2, 0x7fffffff);
     if (n_m2l > 0)
         hipLaunchKernelGGL(k_split_m2l, dim3(grid_of(n_m2l)), dim3(256), 0, s,
-                           d.m2l_keys.as<uint64_t>(), n_m2l, ks.y, d.m2l_src.as<int32_t>(),
-                           d.m2l_shift.as<int32_t>());
+                           d.m2l_keys.as<uint64_t>(), n_m2l, ks.y, d.cell_aux.as<int4>(),
+                           d.m2l_src.as<int32_t>(), d.m2l_shift.as<int32_t>(),
+                           reinterpret_cast<int32_t*>(d.wcount.p) + 16);
     TRY(hipGetLastError());
     out.n_p2p = n_p2p;
     out.n_m2l = n_m2l;
@@ -1218,7 +1229,7 @@ std::string gpu_make_items(DevPlan& d, const Plan& topo, int64_t n_p2p, int chun
     TRY(d.cost_keys.ensure(std::max<int64_t>(1, n_items) * 8));
     TRY(d.queue.ensure(std::max<int64_t>(1, n_items) * 4));
     TRY(d.partial.ensure(std::max<int64_t>(1, n_items) * 4 * 64 * 8));
-    TRY(d.wcount.ensure(64));
+    TRY(d.wcount.ensure(128));
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, d.wcount.as<uint32_t>(), 16);
     // largest item: chunk tasks of at most 64 x 64 pairs
     const int cshift = std::max(0, bits_for((uint64_t)chunk * 64 * 64) - 8);
@@ -1230,11 +1241,16 @@ std::string gpu_make_items(DevPlan& d, const Plan& topo, int64_t n_p2p, int chun
     std::string err = sort_in_place(d.cost_keys, &d.queue, d.cost_keys_tmp, &d.queue_tmp, d.hist,
                                     n_items, 8, s);
     if (!err.empty()) return err;
-    unsigned long long cand = 0;
-    TRY(hipMemcpyAsync(&cand, d.wcount.as<uint32_t>() + 8, 8, hipMemcpyDeviceToHost, s));
+    // words 8, 9: candidate pairs; 16, 17: M2L depths (set by the build)
+    uint32_t w[10];
+    TRY(hipMemcpyAsync(w, d.wcount.as<uint32_t>() + 8, sizeof(w), hipMemcpyDeviceToHost, s));
     TRY(hipStreamSynchronize(s));
+    unsigned long long cand = 0;
+    std::memcpy(&cand, w, 8);
     out.n_items = n_items;
     out.candidate_pairs = (int64_t)cand;
+    out.m2l_min_depth_src = (int32_t)w[8];
+    out.m2l_min_depth_tgt = (int32_t)w[9];
     return std::string();
 }
 

@@ -186,39 +186,37 @@ __device__ __forceinline__ void pair_f32_table(const float4 q, float px, float p
     az = fmaf(g, dz, az);
 }
 
-// Segment table over r^2 (not the paper's table; see the host builder in
-// abi.cpp): offsets are in units where r_cut^2 = n_seg, so s = r'^2 indexes
-// the segment directly, k = floor(s), and each row holds the polynomial of T
-// on [k, k + 1) in s itself (no offset inside the segment).  Row n_seg is
-// zero, and s is clamped to at most n_seg, so a pair beyond the cutoff gets
-// T = 0 with no compare.  T depends on r only through s, so 1/r is needed
-// only for 1/r^3.
+// r^2 table (not the paper's table; see the host builder in abi.cpp): the
+// whole radial factor F = T(r) / r^3 as a function of s = r'^2, with
+// offsets scaled so that r_cut^2 = 2^kR2Emax.  s is clamped into
+// [2^kR2Emin, 2^kR2Emax]; its float bits (exponent and top `bits` mantissa
+// bits) index the segment directly (2^bits segments per octave), and each
+// row holds F's polynomial in s itself.  The row at s = 2^kR2Emax is zero,
+// so a pair beyond the cutoff gets F = 0 with no compare, and no 1/r is
+// evaluated at all.  A coincident pair (d = 0) gets a finite F times d = 0.
 template <int LEVEL>
 __device__ __forceinline__ void pair_f32_r2(const float4 q, float px, float py, float pz,
-                                            float smax, float tiny,
-                                            const float4* __restrict__ tab, float& ax,
-                                            float& ay, float& az) {
+                                            float smax, float smin, uint32_t shift,
+                                            uint32_t base, const float4* __restrict__ tab,
+                                            float& ax, float& ay, float& az) {
     const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    const float sc = __builtin_amdgcn_fmed3f(r2, tiny, smax);
-    const float4 c = tab[(int)sc];
-    float T;
+    const float sc = __builtin_amdgcn_fmed3f(r2, smin, smax);
+    const float4 c = tab[(__float_as_uint(sc) >> shift) - base];
+    float F;
     if constexpr (LEVEL == 1) {
-        T = fmaf(c.y, sc, c.x);
-    } else if constexpr (LEVEL == 2) {
-        T = fmaf(fmaf(c.z, sc, c.y), sc, c.x);
+        F = fmaf(c.y, sc, c.x);
     } else {
-        T = fmaf(fmaf(fmaf(c.w, sc, c.z), sc, c.y), sc, c.x);
+        F = fmaf(fmaf(c.z, sc, c.y), sc, c.x);
     }
-    const float idr = __builtin_amdgcn_rsqf(sc);
-    const float g = q.w * T * (idr * idr * idr);
+    const float g = q.w * F;
     ax = fmaf(g, dx, ax);
     ay = fmaf(g, dy, ay);
     az = fmaf(g, dz, az);
 }
 
 // LDS table layouts (bytes), matching the host builder in abi.cpp:
-//   float32 r^2 segments: float4 (c0, c1, c2, c3) [n_seg + 1]
+//   float32 r^2 table: float4 (c0, c1, c2, 0) [(kR2Emax - kR2Emin) 2^bits + 1]
 //   float32: float4 c0..c3 [n_tab + 1], then float c4 [n_tab + 1]
 //   float64: double2 (c0, c1) [n_tab], double2 (c2, c3) [n_tab], double c4 [n_tab]
 __device__ __forceinline__ void load_table(unsigned char* lds, const void* __restrict__ table,
@@ -266,6 +264,10 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
             const float rnd = round_floor ? 0.f : 0.5f;
             const float4* t03 = reinterpret_cast<const float4*>(lds);
             const float* t4 = reinterpret_cast<const float*>(lds + 16 * (n_tab + 1));
+            // r^2 table: n_tab = segments per octave = 2^bits
+            const uint32_t r2bits = 31u - (uint32_t)__builtin_clz((uint32_t)n_tab);
+            const uint32_t r2shift = 23u - r2bits;
+            const uint32_t r2base = (uint32_t)(127 + kR2Emin) << r2bits;
             for (int t = t0; t < t1; ++t) {
                 const int js = uni(p2p_js[t]);
                 const int jl = js >> 5;
@@ -290,7 +292,8 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                 } else {
 #pragma unroll 4
                     for (int k = 0; k < nj; ++k)
-                        pair_f32_r2<LEVEL>(src[k], px, py, pz, rc2, tiny, t03, fx, fy, fz);
+                        pair_f32_r2<LEVEL>(src[k], px, py, pz, rc2, tiny, r2shift, r2base,
+                                           t03, fx, fy, fz);
                 }
                 ax += (double)fx;
                 ay += (double)fy;
@@ -463,11 +466,8 @@ hipError_t launch_p2p(int mode, const P2PArgs& a, int wg_waves, int grid_wgs, si
                 default: return launch_one<kFP32Table, 4>(a, wg_waves, grid_wgs, lds, s);
             }
         case kFP32R2:
-            switch (a.level) {
-                case 1: return launch_one<kFP32R2, 1>(a, wg_waves, grid_wgs, lds, s);
-                case 2: return launch_one<kFP32R2, 2>(a, wg_waves, grid_wgs, lds, s);
-                default: return launch_one<kFP32R2, 3>(a, wg_waves, grid_wgs, lds, s);
-            }
+            if (a.level == 1) return launch_one<kFP32R2, 1>(a, wg_waves, grid_wgs, lds, s);
+            return launch_one<kFP32R2, 2>(a, wg_waves, grid_wgs, lds, s);
         case kFP64Table:
             switch (a.level) {
                 case 0: return launch_one<kFP64Table, 0>(a, wg_waves, grid_wgs, lds, s);

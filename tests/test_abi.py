@@ -62,18 +62,25 @@ def test_fp64_table_size_limit():
 
 
 def test_r2_table_is_a_float32_form():
-    for bad in (dict(precision=B.PMFMM_FP64, trunc=B.TRUNC_R2),
-                dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_level=0),
-                dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_level=4),
-                dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_size=32)):
+    for bad in (dict(precision=B.PMFMM_FP64, trunc=B.TRUNC_R2, table_size=64,
+                     table_level=2),
+                dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_size=64,
+                     table_level=0),
+                dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_size=64,
+                     table_level=3),
+                dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_size=48,
+                     table_level=2),
+                dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_size=32,
+                     table_level=1)):
         with pytest.raises(B.PmfmmError):
             B.Context(**bad)
-    B.Context(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_size=2048,
-              table_level=2).close()
+    for size, level in ((16, 2), (64, 2), (128, 1)):
+        B.Context(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_size=size,
+                  table_level=level).close()
 
 
 def test_r2_table_needs_one_cutoff_ratio():
-    ctx = B.Context(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_size=1024,
+    ctx = B.Context(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_size=64,
                     table_level=2)
     a = B.make_params(box=10.0, r_s=0.5, r_cut=2.25, max_leaf=8)
     b = B.make_params(box=12.0, r_s=0.6, r_cut=2.7, max_leaf=8)     # same x_c

@@ -79,7 +79,7 @@ def test_adjoint_fp32_after_r2_table_forward(case):
     print("case: adjoint fp32 with the r^2 table form set, clustered 20^3",
           flush=True)
     gp, gmass, _ = gpu_adjoint(w, m, wv, precision=B.PMFMM_FP32,
-                               trunc=B.TRUNC_R2, table_size=2048,
+                               trunc=B.TRUNC_R2, table_size=64,
                                table_level=2)
     for s in (scaled(gp, gx, sx), scaled(gmass, gm, sm), rel_vec(gp, gx)):
         assert s["median"] <= 1e-5 and s["p999"] <= 1e-4, s

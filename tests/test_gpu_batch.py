@@ -42,7 +42,8 @@ def test_batch_against_oracle(boxes, prec, trunc):
     print(f"case: batch of {len(boxes)} boxes prec {prec} trunc {trunc}",
           flush=True)
     acc, counts = run_batch(boxes, precision=prec, trunc=trunc,
-                            table_size=2048, table_level=2)
+                            table_size=64 if trunc == B.TRUNC_R2 else 2048,
+                            table_level=2)
     p0 = 0
     for w, n in zip(boxes, counts):
         ref, _ = direct.brute_force(w.pos, w.mass, w.box, w.r_s, w.r_cut)

@@ -104,24 +104,25 @@ def test_fp32_table(c1, level, n_tab, rnd):
     check_fp32(acc, ref)
 
 
-@pytest.mark.parametrize("level,n_seg", [(2, 2048), (1, 4096), (3, 512),
-                                         (2, 1024)])
-def test_fp32_r2_table(c1, level, n_seg):
+@pytest.mark.parametrize("level,per_octave", [(2, 64), (1, 128), (2, 16),
+                                              (2, 32)])
+def test_fp32_r2_table(c1, level, per_octave):
     w, ref = c1
-    print(f"case: uniform 32^3 fp32 r^2 table {n_seg} degree {level}",
-          flush=True)
+    print(f"case: uniform 32^3 fp32 r^2 table {per_octave}/octave degree "
+          f"{level}", flush=True)
     acc, _ = gpu_forward(w.pos, w.mass, w.box, w.r_s, w.r_cut, w.max_leaf,
                          precision=B.PMFMM_FP32, trunc=B.TRUNC_R2,
-                         table_size=n_seg, table_level=level)
+                         table_size=per_octave, table_level=level)
     check_fp32(acc, ref)
 
 
 def test_fp32_r2_table_clustered_and_coincident(clustered):
     w, ref = clustered
-    print("case: clustered 24^3 fp32 r^2 table 2048 degree 2", flush=True)
+    print("case: clustered 24^3 fp32 r^2 table 64/octave degree 2",
+          flush=True)
     acc, _ = gpu_forward(w.pos, w.mass, w.box, w.r_s, w.r_cut, 64,
                          precision=B.PMFMM_FP32, trunc=B.TRUNC_R2,
-                         table_size=2048, table_level=2)
+                         table_size=64, table_level=2)
     check_fp32(acc, ref)
     rng = np.random.default_rng(19)
     pos = rng.uniform(0, 20.0, (2001, 3))
@@ -129,7 +130,7 @@ def test_fp32_r2_table_clustered_and_coincident(clustered):
     m = rng.uniform(0.2, 1.0, 2001) * 1e9       # large masses stay finite
     print("case: ragged 2001 coincident, fp32 r^2 table", flush=True)
     acc, _ = gpu_forward(pos, m, 20.0, 0.6, 2.7, 16, precision=B.PMFMM_FP32,
-                         trunc=B.TRUNC_R2, table_size=2048, table_level=2)
+                         trunc=B.TRUNC_R2, table_size=64, table_level=2)
     ref2, _ = direct.all_pairs(pos, m, 20.0, 0.6, 2.7)
     assert np.all(np.isfinite(acc))
     check_fp32(acc, ref2)
@@ -170,7 +171,8 @@ def test_reused_context_switching_modes(clustered):
                         (B.PMFMM_FP32, B.TRUNC_R2), (B.PMFMM_FP64,
                                                      B.TRUNC_EXACT),
                         (B.PMFMM_FP32, B.TRUNC_TABLE)]:
-        ctx.set_eval(precision=prec, trunc=trunc, table_size=1024,
+        ctx.set_eval(precision=prec, trunc=trunc,
+                     table_size=64 if trunc == B.TRUNC_R2 else 1024,
                      table_level=2, chunk=7)
         ctx.forward(out, torch.cuda.current_stream())
         torch.cuda.synchronize()
@@ -255,7 +257,7 @@ def test_full_size_clustered_2m_sampled(c2):
     for trunc, level, n_tab in [(B.TRUNC_TABLE, 2, 512),
                                 (B.TRUNC_TABLE, 1, 2048),
                                 (B.TRUNC_EXACT, 0, 2048),
-                                (B.TRUNC_R2, 2, 2048)]:
+                                (B.TRUNC_R2, 2, 64)]:
         print(f"case: clustered 128^3 fp32 trunc {trunc} {n_tab} {level}",
               flush=True)
         ctx.set_eval(precision=B.PMFMM_FP32, trunc=trunc, table_size=n_tab,

@@ -45,6 +45,10 @@ FLOPS_PER_PAIR_F32_R2 = 22
 # displacement 3 (+3 shift), r^2 5, 1/r 1, x 2, T = erfc + c x e^-x^2 6,
 # g 4, accumulation 6.
 FLOPS_PER_PAIR_F64_EXACT = 27
+# float64 table form (T_[4]): displacement 3 (+3 shift), r^2 5, 1/r 1,
+# table coordinate 2, index and offset 2, T_[4] Horner 8, m T / r^3 4,
+# accumulation 6.
+FLOPS_PER_PAIR_F64_TABLE = 31
 PAPER_OPS_PER_PAIR = 51
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
@@ -345,9 +349,13 @@ def main():
                                  table_level=args.table_level,
                                  table_round=B.ROUND_NEAREST),
         "fp64": dict(precision=B.PMFMM_FP64, trunc=B.TRUNC_EXACT),
+        "fp64_table": dict(precision=B.PMFMM_FP64, trunc=B.TRUNC_TABLE,
+                           table_size=2048, table_level=4,
+                           table_round=B.ROUND_NEAREST),
     }
     if args.skip_fp64:
         forms.pop("fp64")
+        forms.pop("fp64_table")
     if args.headline_only:
         forms = {"fp32": forms["fp32"]}
     results = {}
@@ -417,6 +425,7 @@ def main():
                                      f"{args.table_size}-node T_[{args.table_level}] "
                                      f"table of Eq. (int)",
             "fp64_form": "float64 pairs, exact erfc/exp",
+            "fp64_table_form": "float64 pairs, 2048-node T_[4] table of Eq. (int)",
         },
         "roofline": {
             "bound": "alu",
@@ -454,6 +463,15 @@ def main():
             "p2p_tflops": cand * FLOPS_PER_PAIR_F64_EXACT / (r64["p2p_ms"] / 1e3) / 1e12,
             "frac_of_fp64_peak": cand * FLOPS_PER_PAIR_F64_EXACT
             / (r64["p2p_ms"] / 1e3) / 1e12 / PEAK_FP64_TFLOPS,
+        }
+    if "fp64_table" in results:
+        r64t = results["fp64_table"]
+        line["fp64_table"] = {
+            "value": cand / (r64t["ms_per_step"] / 1e3),
+            "ms_per_step": r64t["ms_per_step"],
+            "p2p_tflops": cand * FLOPS_PER_PAIR_F64_TABLE / (r64t["p2p_ms"] / 1e3) / 1e12,
+            "frac_of_fp64_peak": cand * FLOPS_PER_PAIR_F64_TABLE
+            / (r64t["p2p_ms"] / 1e3) / 1e12 / PEAK_FP64_TFLOPS,
         }
     print(json.dumps(line), flush=True)
 

@@ -602,8 +602,7 @@ int gpu_build(pmfmm_ctx* ctx, const std::vector<pmfmm::BoxParams>& boxes, const 
         dp = ctx->d.stage_pos.as<double>();
         dm = ctx->d.stage_mass.as<double>();
     }
-    std::string err = pmfmm::gpu_check_inputs(ctx->d, dp, dm, n, s);
-    if (!err.empty()) return fail(PMFMM_EINVAL, err);
+    HIP_TRY(pmfmm::gpu_enqueue_checks(ctx->d, dp, dm, n, s));
     const bool same = ctx->topo_on_device && ctx->topo_counts == cnt && same_boxes(ctx->topo_boxes, boxes);
     if (!same) {
         try {
@@ -623,7 +622,9 @@ int gpu_build(pmfmm_ctx* ctx, const std::vector<pmfmm::BoxParams>& boxes, const 
         if ((rc = upload_boxes(ctx, s))) return rc;
     }
     pmfmm::PlanCounts pc;
-    err = pmfmm::gpu_build_plan(ctx->d, ctx->plan, dp, dm, ctx->p.chunk, s, pc);
+    std::string input_err;
+    std::string err = pmfmm::gpu_build_plan(ctx->d, ctx->plan, dp, dm, ctx->p.chunk, s, pc, &input_err);
+    if (!input_err.empty()) return fail(PMFMM_EINVAL, input_err);
     if (!err.empty()) return fail(PMFMM_EDEVICE, err);
     ctx->n_p2p = pc.n_p2p;
     ctx->n_m2l = pc.n_m2l;

@@ -105,15 +105,19 @@ int64_t sort_hist_words(int64_t n, int nseg = 1);
 hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals,
                           uint32_t* hist, int64_t n, int bit_begin, int bit_end, hipStream_t s,
                           bool* result_in_tmp, int nseg = 1);
+// The same for 32-bit keys (bits beyond 32 ignored).
+hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals,
+                          uint32_t* hist, int64_t n, int bit_begin, int bit_end, hipStream_t s,
+                          bool* result_in_tmp, int nseg = 1);
 hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, uint32_t* tile_sums,
                               hipStream_t s);
 // In-place exclusive scan by one workgroup (for a few thousand values).
 hipError_t exclusive_scan_u32_one_block(uint32_t* a, int64_t m, hipStream_t s);
 
-// Checks device particles: finite positions, finite non-negative masses.
-// Returns "" or a message naming the first offending particle.
-std::string gpu_check_inputs(DevPlan& d, const double* pos, const double* mass, int64_t n,
-                             hipStream_t s);
+// Enqueues the checks of device particles (finite positions, finite
+// non-negative masses); gpu_build_plan reads their result.
+hipError_t gpu_enqueue_checks(DevPlan& d, const double* pos, const double* mass, int64_t n,
+                              hipStream_t s);
 
 // Uploads the tree shape of `topo` (cells, leaves, depth levels) and the
 // per-box constants.
@@ -123,9 +127,11 @@ hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, h
 // `mass` (n) in device memory, for the shape uploaded by upload_topology.
 // Fills perm, cell bounds and centres, x64 / x32, the P2P and M2L CSR, the
 // work items and queue.  Synchronises `s` (the list sizes come back to the
-// host).  Returns an error message ("" on success).
+// host).  Returns an error message ("" on success); when the checks of
+// gpu_enqueue_checks (which must precede it on `s`) fail, stops early and
+// sets *input_error to a message naming the first offending particle.
 std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, const double* mass,
-                           int chunk, hipStream_t s, PlanCounts& out);
+                           int chunk, hipStream_t s, PlanCounts& out, std::string* input_error);
 
 // Re-cuts the work items for a new chunk size from the device CSR.
 std::string gpu_make_items(DevPlan& d, const Plan& topo, int64_t n_p2p, int chunk, hipStream_t s,

@@ -64,25 +64,97 @@ __device__ __forceinline__ uint64_t coord_key(double x) {
     return x == 0.0 ? 0ull : (uint64_t)__double_as_longlong(x);
 }
 
+// 32-bit sort key of a wrapped coordinate x in [0, L): floor(x 2^32 / L),
+// a non-decreasing function of x (a rounded product and a floor), so that
+// sorting by it and then ordering each run of equal keys by x is the order
+// by x.
+__device__ __forceinline__ uint32_t coord_key32(double x, double scale) {
+    const double t = x * scale;
+    return t >= 4294967295.0 ? 0xffffffffu : (uint32_t)t;
+}
+
 __global__ void k_wrap_keys(const double* __restrict__ pos, int64_t n, const int32_t* __restrict__ bf,
                             int nbox, const BoxDev* __restrict__ boxes, double* __restrict__ wpos,
-                            uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                            uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double L = boxes[box_of(bf, nbox, (int)i)].L;
+    const double scale = 4294967296.0 / L;
     for (int a = 0; a < 3; ++a) {
         const double x = wrap_coord(pos[3 * i + a], L);
         wpos[3 * i + a] = x;
-        keys[a * n + i] = coord_key(x);
+        keys[a * n + i] = coord_key32(x, scale);
         vals[a * n + i] = (uint32_t)i;
     }
 }
 
-__global__ void k_box_keys(const uint32_t* __restrict__ vals, int64_t n, const int32_t* __restrict__ bf,
-                           int nbox, uint64_t* __restrict__ keys) {
+// Full 64-bit keys of the wrapped coordinates (the fallback sort).
+__global__ void k_keys64(const double* __restrict__ wpos, int64_t n, uint64_t* __restrict__ keys,
+                         uint32_t* __restrict__ vals) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    keys[i] = (uint64_t)box_of(bf, nbox, (int)vals[i]);
+    for (int a = 0; a < 3; ++a) {
+        keys[a * n + i] = coord_key(wpos[3 * i + a]);
+        vals[a * n + i] = (uint32_t)i;
+    }
+}
+
+// After the stable sort by 32-bit key, each run of equal keys of one axis
+// list is in caller order; this puts it in coordinate order (stable, so
+// equal coordinates stay in caller order).  The first position of a run of
+// at most kRunMax elements sorts it in place (insertion sort).  A longer
+// run is only checked: its start checks its first kRunMax - 1 neighbour
+// pairs and every later position the pair it ends; any pair out of order
+// sets *longrun, and the caller then sorts by the full 64-bit keys.
+constexpr int kRunMax = 64;
+
+__global__ void k_run_fix(const uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int64_t n,
+                          const double* __restrict__ wpos, int* __restrict__ longrun) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 3 * n) return;
+    const int a = q >= n ? (q >= 2 * n ? 2 : 1) : 0;
+    const int64_t s0 = (int64_t)a * n, s1 = s0 + n;
+    const uint32_t h = keys[q];
+    auto x_of = [&](int64_t p) { return wpos[3 * (size_t)vals[p] + a]; };
+    if (q == s0 || keys[q - 1] != h) {
+        if (q + 1 >= s1 || keys[q + 1] != h) return;   // a run of one
+        if (q + kRunMax < s1 && keys[q + kRunMax] == h) {
+            double prev = x_of(q);
+            for (int64_t p = q + 1; p < q + kRunMax; ++p) {
+                const double x = x_of(p);
+                if (x < prev) {
+                    atomicOr(longrun, 1);
+                    return;
+                }
+                prev = x;
+            }
+            return;
+        }
+        int64_t e = q + 2;
+        while (e < s1 && keys[e] == h) ++e;
+        for (int64_t i = q + 1; i < e; ++i) {
+            const uint32_t vi = vals[i];
+            const double xi = wpos[3 * (size_t)vi + a];
+            int64_t j = i - 1;
+            while (j >= q) {
+                const uint32_t vj = vals[j];
+                if (!(xi < wpos[3 * (size_t)vj + a])) break;
+                vals[j + 1] = vj;
+                --j;
+            }
+            vals[j + 1] = vi;
+        }
+    } else if (q - kRunMax >= s0 && keys[q - kRunMax] == h) {
+        // kRunMax or more positions into a long run (keys are sorted)
+        if (x_of(q) < x_of(q - 1)) atomicOr(longrun, 1);
+    }
+}
+
+__global__ void k_box_keys(const uint32_t* __restrict__ vals, int64_t n, const int32_t* __restrict__ bf,
+                           int nbox, uint32_t* __restrict__ keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = (uint32_t)box_of(bf, nbox, (int)vals[i]);
 }
 
 __global__ void k_init_pc(int64_t n, const int32_t* __restrict__ bf, const int32_t* __restrict__ bfc,
@@ -858,20 +930,19 @@ struct PhaseTimer {
 
 }  // namespace
 
-std::string gpu_check_inputs(DevPlan& d, const double* pos, const double* mass, int64_t n,
-                             hipStream_t s) {
-    TRY(d.wcount.ensure(128));
+hipError_t gpu_enqueue_checks(DevPlan& d, const double* pos, const double* mass, int64_t n,
+                              hipStream_t s) {
+    hipError_t e = d.wcount.ensure(128);
+    if (e != hipSuccess) return e;
+    // wcount[0..1]: first bad position / mass (INT_MAX: none); wcount[2]:
+    // the long-run flag of the coordinate sort
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int*>(d.wcount.p), 2,
                        0x7fffffff);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int*>(d.wcount.p) + 2,
+                       1, 0);
     hipLaunchKernelGGL(k_check, dim3(grid_of(n)), dim3(256), 0, s, pos, mass, n,
                        reinterpret_cast<int*>(d.wcount.p));
-    TRY(hipGetLastError());
-    int bad[2] = {0, 0};
-    TRY(hipMemcpyAsync(bad, d.wcount.p, 8, hipMemcpyDeviceToHost, s));
-    TRY(hipStreamSynchronize(s));
-    if (bad[0] != 0x7fffffff) return "non-finite position at particle " + std::to_string(bad[0]);
-    if (bad[1] != 0x7fffffff) return "negative or non-finite mass at particle " + std::to_string(bad[1]);
-    return std::string();
+    return hipGetLastError();
 }
 
 hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, hipStream_t s) {
@@ -968,7 +1039,8 @@ hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, h
 }
 
 std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, const double* mass,
-                           int chunk, hipStream_t s, PlanCounts& out) {
+                           int chunk, hipStream_t s, PlanCounts& out, std::string* input_error) {
+    input_error->clear();
     const int64_t n = topo.n;
     const int nbox = (int)topo.boxes.size();
     const int64_t nc = (int64_t)topo.cells.size(), nl = (int64_t)topo.leaf_cell.size();
@@ -982,30 +1054,59 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     TRY(d.keys_tmp.ensure(n * 24));
     hipLaunchKernelGGL(k_wrap_keys, dim3(grid_of(n)), dim3(256), 0, s, pos, n,
                        d.box_first.as<int32_t>(), nbox, d.boxes.as<BoxDev>(), d.wpos.as<double>(),
-                       d.keys.as<uint64_t>(), d.plist.as<uint32_t>());
+                       d.keys.as<uint32_t>(), d.plist.as<uint32_t>());
     TRY(hipGetLastError());
-    // the three axis lists are three segments of one sort
+    // the three axis lists are three segments of one sort: by the 32-bit
+    // key, then each run of equal keys by coordinate
     TRY(d.hist.ensure((size_t)sort_hist_words(n, 3) * 4));
+    uint32_t* v = d.plist.as<uint32_t>();
+    uint32_t* vt = d.plist_tmp.as<uint32_t>();
+    bool in_tmp = false;
     if (n > 1) {
-        uint64_t* k = d.keys.as<uint64_t>();
-        uint32_t* v = d.plist.as<uint32_t>();
-        uint64_t* kt = d.keys_tmp.as<uint64_t>();
-        uint32_t* vt = d.plist_tmp.as<uint32_t>();
-        bool in_tmp = false;
-        TRY(radix_sort_u64(k, v, kt, vt, d.hist.as<uint32_t>(), n, 0, 64, s, &in_tmp, 3));
+        TRY(radix_sort_u32(d.keys.as<uint32_t>(), v, d.keys_tmp.as<uint32_t>(), vt,
+                           d.hist.as<uint32_t>(), n, 0, 32, s, &in_tmp, 3));
         if (in_tmp) {
-            TRY(hipMemcpyAsync(k, kt, n * 24, hipMemcpyDeviceToDevice, s));
+            TRY(hipMemcpyAsync(d.keys.p, d.keys_tmp.p, n * 12, hipMemcpyDeviceToDevice, s));
             TRY(hipMemcpyAsync(v, vt, n * 12, hipMemcpyDeviceToDevice, s));
         }
-        if (nbox > 1) {
-            // then stably by box: each box's particles in coordinate order
-            hipLaunchKernelGGL(k_box_keys, dim3(grid_of(3 * n)), dim3(256), 0, s, v, 3 * n,
-                               d.box_first.as<int32_t>(), nbox, k);
+        hipLaunchKernelGGL(k_run_fix, dim3(grid_of(3 * n)), dim3(256), 0, s, d.keys.as<uint32_t>(), v,
+                           n, d.wpos.as<double>(), reinterpret_cast<int*>(d.wcount.p) + 2);
+        TRY(hipGetLastError());
+    }
+    // the input checks and the long-run flag come back in one round trip
+    {
+        int flags[3] = {0, 0, 0};
+        TRY(hipMemcpyAsync(flags, d.wcount.p, 12, hipMemcpyDeviceToHost, s));
+        TRY(hipStreamSynchronize(s));
+        if (flags[0] != 0x7fffffff) {
+            *input_error = "non-finite position at particle " + std::to_string(flags[0]);
+            return std::string();
+        }
+        if (flags[1] != 0x7fffffff) {
+            *input_error = "negative or non-finite mass at particle " + std::to_string(flags[1]);
+            return std::string();
+        }
+        if (flags[2] != 0) {
+            // coordinates closer than the 32-bit key resolves, out of order
+            // in a long run: sort by the full keys
+            uint64_t* k = d.keys.as<uint64_t>();
+            uint64_t* kt = d.keys_tmp.as<uint64_t>();
+            hipLaunchKernelGGL(k_keys64, dim3(grid_of(n)), dim3(256), 0, s, d.wpos.as<double>(), n, k,
+                               v);
             TRY(hipGetLastError());
-            TRY(radix_sort_u64(k, v, kt, vt, d.hist.as<uint32_t>(), n, 0, bits_for(nbox - 1) + 1, s,
-                               &in_tmp, 3));
+            TRY(radix_sort_u64(k, v, kt, vt, d.hist.as<uint32_t>(), n, 0, 64, s, &in_tmp, 3));
             if (in_tmp) TRY(hipMemcpyAsync(v, vt, n * 12, hipMemcpyDeviceToDevice, s));
         }
+    }
+    if (n > 1 && nbox > 1) {
+        // then stably by box: each box's particles in coordinate order
+        uint32_t* k = d.keys.as<uint32_t>();
+        hipLaunchKernelGGL(k_box_keys, dim3(grid_of(3 * n)), dim3(256), 0, s, v, 3 * n,
+                           d.box_first.as<int32_t>(), nbox, k);
+        TRY(hipGetLastError());
+        TRY(radix_sort_u32(k, v, d.keys_tmp.as<uint32_t>(), vt, d.hist.as<uint32_t>(), n, 0,
+                           bits_for(nbox - 1) + 1, s, &in_tmp, 3));
+        if (in_tmp) TRY(hipMemcpyAsync(v, vt, n * 12, hipMemcpyDeviceToDevice, s));
     }
 
     clk.lap("sort");

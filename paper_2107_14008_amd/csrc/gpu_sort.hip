@@ -1,6 +1,7 @@
 // Device primitives of the on-GPU planner: a stable LSD radix sort of 64-bit
-// keys (optionally carrying 32-bit values), also of several equal-length
-// segments at once, and an exclusive prefix sum of 32-bit integers.
+// or 32-bit keys (optionally carrying 32-bit values), also of several
+// equal-length segments at once, and an exclusive prefix sum of 32-bit
+// integers.
 //
 // Radix sort: 8-bit digits, tiles of 2048 elements (256 threads x 8
 // rounds); a tile never straddles two segments.  Per pass: (1) per-tile
@@ -11,6 +12,8 @@
 // the mask of lanes holding its digit) and a running per-digit count in
 // LDS, so the order of equal digits is kept (stable), which makes the sort
 // stable across passes; the tile is ordered in LDS and written out in runs.
+#include <algorithm>
+
 #include "gpu_plan.h"
 
 namespace pmfmm {
@@ -36,8 +39,9 @@ __device__ __forceinline__ TileRange tile_range(int64_t n, int tiles) {
     return t;
 }
 
+template <class K>
 __global__ void __launch_bounds__(kThreads)
-rs_hist(const uint64_t* __restrict__ keys, int64_t n, int shift, uint32_t* __restrict__ hist,
+rs_hist(const K* __restrict__ keys, int64_t n, int shift, uint32_t* __restrict__ hist,
         int tiles) {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
@@ -80,12 +84,12 @@ __global__ void __launch_bounds__(1024) scan_single(uint32_t* __restrict__ a, in
 // the tile's elements of that digit), then written out position by
 // position: consecutive positions of one digit go to consecutive addresses,
 // so the global writes come in runs instead of one element per line.
-template <bool VALS>
+template <class K, bool VALS>
 __global__ void __launch_bounds__(kThreads)
-rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-           uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n, int shift,
+rs_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+           K* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n, int shift,
            const uint32_t* __restrict__ hist, const uint32_t* __restrict__ offs, int tiles) {
-    __shared__ uint64_t ks[kTile];
+    __shared__ K ks[kTile];
     __shared__ uint32_t vs[VALS ? kTile : 1];
     __shared__ uint32_t start[256];     // digit start inside the tile
     __shared__ uint32_t goff[256];      // digit start in the output
@@ -125,7 +129,7 @@ rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     for (int r = 0; r < kRounds; ++r) {
         const int64_t i = tr.begin + r * kThreads + t;
         const bool valid = i < tr.end;
-        uint64_t key = 0;
+        K key = 0;
         uint32_t val = 0;
         uint32_t d = 0;
         if (valid) {
@@ -159,7 +163,7 @@ rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     }
     const int len = (int)(tr.end - tr.begin);
     for (int p = t; p < len; p += kThreads) {
-        const uint64_t key = ks[p];
+        const K key = ks[p];
         const uint32_t d = (uint32_t)(key >> shift) & 255u;
         const uint32_t o = goff[d] + (uint32_t)p - start[d];
         kout[o] = key;
@@ -223,15 +227,16 @@ int64_t sort_hist_words(int64_t n, int nseg) {
     return 2 * m + sort_tiles(m) + 16;
 }
 
-hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals,
-                          uint32_t* hist, int64_t n, int bit_begin, int bit_end, hipStream_t s,
-                          bool* result_in_tmp, int nseg) {
+template <class K>
+hipError_t radix_sort(K* keys, uint32_t* vals, K* tmp_keys, uint32_t* tmp_vals, uint32_t* hist,
+                      int64_t n, int bit_begin, int bit_end, hipStream_t s, bool* result_in_tmp,
+                      int nseg) {
     *result_in_tmp = false;
     if (n <= 1 || nseg < 1) return hipSuccess;
     const int tiles = (int)sort_tiles(n);
     const int blocks = nseg * tiles;
-    uint64_t* ka = keys;
-    uint64_t* kb = tmp_keys;
+    K* ka = keys;
+    K* kb = tmp_keys;
     uint32_t* va = vals;
     uint32_t* vb = tmp_vals;
     // scratch layout: counts [m], their exclusive scan [m], tile sums
@@ -239,21 +244,35 @@ hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, ui
     uint32_t* offs = hist + m;
     uint32_t* scan_scratch = hist + 2 * m;
     for (int shift = bit_begin; shift < bit_end; shift += 8) {
-        hipLaunchKernelGGL(rs_hist, dim3(blocks), dim3(kThreads), 0, s, ka, n, shift, hist, tiles);
+        hipLaunchKernelGGL(rs_hist<K>, dim3(blocks), dim3(kThreads), 0, s, ka, n, shift, hist, tiles);
         const hipError_t e = exclusive_scan_i32(reinterpret_cast<const int32_t*>(hist),
                                                 reinterpret_cast<int32_t*>(offs), m, scan_scratch, s);
         if (e != hipSuccess) return e;
         if (vals)
-            hipLaunchKernelGGL(rs_scatter<true>, dim3(blocks), dim3(kThreads), 0, s, ka, va, kb, vb,
-                               n, shift, hist, offs, tiles);
+            hipLaunchKernelGGL((rs_scatter<K, true>), dim3(blocks), dim3(kThreads), 0, s, ka, va, kb,
+                               vb, n, shift, hist, offs, tiles);
         else
-            hipLaunchKernelGGL(rs_scatter<false>, dim3(blocks), dim3(kThreads), 0, s, ka, va, kb, vb,
-                               n, shift, hist, offs, tiles);
+            hipLaunchKernelGGL((rs_scatter<K, false>), dim3(blocks), dim3(kThreads), 0, s, ka, va, kb,
+                               vb, n, shift, hist, offs, tiles);
         std::swap(ka, kb);
         std::swap(va, vb);
         *result_in_tmp = !*result_in_tmp;
     }
     return hipGetLastError();
+}
+
+hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals,
+                          uint32_t* hist, int64_t n, int bit_begin, int bit_end, hipStream_t s,
+                          bool* result_in_tmp, int nseg) {
+    return radix_sort<uint64_t>(keys, vals, tmp_keys, tmp_vals, hist, n, bit_begin, bit_end, s,
+                                result_in_tmp, nseg);
+}
+
+hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals,
+                          uint32_t* hist, int64_t n, int bit_begin, int bit_end, hipStream_t s,
+                          bool* result_in_tmp, int nseg) {
+    return radix_sort<uint32_t>(keys, vals, tmp_keys, tmp_vals, hist, n, std::min(bit_begin, 32),
+                                std::min(bit_end, 32), s, result_in_tmp, nseg);
 }
 
 hipError_t exclusive_scan_u32_one_block(uint32_t* a, int64_t m, hipStream_t s) {

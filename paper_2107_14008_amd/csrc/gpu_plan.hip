@@ -11,8 +11,8 @@
 // its bounds from the ends of its three sorted ranges, marks the floor(n/2)
 // first particles of its split axis as "left", and every axis list is
 // partitioned stably (prefix sums of the left marks), which keeps each child
-// range sorted on every axis.  Once a subtree holds at most 4096 particles
-// and 512 cells, one workgroup finishes it in LDS (k_orb_fused), so the
+// range sorted on every axis.  Once a subtree holds at most 8192 particles
+// and 1024 cells, one workgroup finishes it in LDS (k_orb_fused), so the
 // launches per level are paid only for the top levels.
 //
 // Dual walk: level-synchronous over a frontier of cell pairs (the canonical
@@ -340,9 +340,9 @@ k_level_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __restrict__ pc
 // level loop does (first floor(n/2) of the split axis left, stable), then
 // each leaf's particles are written to perm in ascending caller index.
 // Bounds of every cell of the subtree are written to clo / chi.
-constexpr int kFuseM = 4096;
-constexpr int kFuseC = 512;
-constexpr int kFuseT = 512;
+constexpr int kFuseM = 8192;
+constexpr int kFuseC = 1024;
+constexpr int kFuseT = 1024;
 constexpr int kFuseRounds = (3 * kFuseM + kFuseT - 1) / kFuseT;   // 24
 constexpr uint16_t kNoChild = 0xffffu;
 

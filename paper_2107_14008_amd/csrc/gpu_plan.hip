@@ -778,38 +778,116 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
     if (i < n) p[i] = 0u;
 }
 
-__global__ void k_csr_rows(const uint64_t* __restrict__ keys, int64_t nk, int nrows, int ks,
-                           int32_t* __restrict__ row) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r > nrows) return;
-    const uint64_t target = (uint64_t)(uint32_t)r << ks;
-    int64_t lo = 0, hi = nk;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (keys[mid] < target) lo = mid + 1; else hi = mid;
-    }
-    row[r] = (int32_t)lo;
-}
-
-__global__ void k_split_p2p(const uint64_t* __restrict__ keys, int64_t nk, int ks,
-                            int32_t* __restrict__ js) {
+// CSR rows from the walk's unsorted keys (row << ks | value): each key takes
+// a slot in its row with an atomic count, the counts are scanned into the
+// row starts, the values are placed, and each row's values are sorted
+// (bitonic, in LDS), which gives the canonical (i, j, shift) order since the
+// values of one row are distinct.
+__global__ void k_row_count(const uint64_t* __restrict__ keys, int64_t nk, int ks,
+                            int32_t* __restrict__ cnt, int32_t* __restrict__ slot) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < nk) js[k] = (int32_t)(keys[k] & ((1ull << ks) - 1));
+    if (k < nk) slot[k] = atomicAdd(&cnt[keys[k] >> ks], 1);
 }
 
-// Also the smallest depth of the tasks' source and target cells
-// (mindep[0] / mindep[1], preset to INT32_MAX).
-__global__ void k_split_m2l(const uint64_t* __restrict__ keys, int64_t nk, int ks,
-                            const int4* __restrict__ aux, int32_t* __restrict__ src,
-                            int32_t* __restrict__ shift, int32_t* __restrict__ mindep) {
+__global__ void k_row_place(const uint64_t* __restrict__ keys, int64_t nk, int ks,
+                            const int32_t* __restrict__ row, const int32_t* __restrict__ slot,
+                            int32_t* __restrict__ vals) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nk) return;
-    const uint32_t low = (uint32_t)(keys[k] & ((1ull << ks) - 1));
-    const int u = (int)(low >> 5), t = (int)(keys[k] >> ks);
-    src[k] = u;
-    shift[k] = (int32_t)(low & 31u);
-    atomicMin(&mindep[0], aux[u].w);
-    atomicMin(&mindep[1], aux[t].w);
+    const uint64_t key = keys[k];
+    vals[row[key >> ks] + slot[k]] = (int32_t)(key & ((1ull << ks) - 1));
+}
+
+// Ascending bitonic sort of b[0, P) (P a power of two) by the T threads of
+// the workgroup; t is the caller's thread index.
+__device__ void bitonic_sort(int32_t* b, int P, int t, int T) {
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int p = t; p < P / 2; p += T) {
+                const int lo = 2 * p - (p & (stride - 1)), hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const int32_t x = b[lo], y = b[hi];
+                if ((x > y) == up) {
+                    b[lo] = y;
+                    b[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__device__ __forceinline__ int pow2_at_least(int n) {
+    int P = 1;
+    while (P < n) P <<= 1;
+    return P;
+}
+
+// One wavefront per row of at most kRowShort values; longer rows are listed
+// for k_row_sort_long.
+constexpr int kRowShort = 256;
+constexpr int kRowLds = 8192;
+
+__global__ void __launch_bounds__(64)
+k_row_sort_short(const int32_t* __restrict__ row, int32_t* __restrict__ vals,
+                 int32_t* __restrict__ longs, int32_t* __restrict__ nlong) {
+    __shared__ int32_t b[kRowShort];
+    const int r = blockIdx.x, t = threadIdx.x;
+    const int r0 = row[r], len = row[r + 1] - r0;
+    if (len <= 1) return;
+    if (len > kRowShort) {
+        if (t == 0) longs[atomicAdd(nlong, 1)] = r;
+        return;
+    }
+    const int P = pow2_at_least(len);
+    for (int k = t; k < P; k += 64) b[k] = k < len ? vals[r0 + k] : INT32_MAX;
+    __syncthreads();
+    bitonic_sort(b, P, t, 64);
+    for (int k = t; k < len; k += 64) vals[r0 + k] = b[k];
+}
+
+// The listed long rows, one workgroup at a time each: in LDS up to kRowLds
+// values, else in scratch[2 r0, 2 r0 + P) (P < 2 len, so rows never share
+// scratch; the caller provides twice the value count).
+__global__ void __launch_bounds__(256)
+k_row_sort_long(const int32_t* __restrict__ row, int32_t* __restrict__ vals,
+                const int32_t* __restrict__ longs, const int32_t* __restrict__ nlong,
+                int32_t* __restrict__ scratch) {
+    __shared__ int32_t lds[kRowLds];
+    const int t = threadIdx.x;
+    const int count = *nlong;
+    for (int q = blockIdx.x; q < count; q += gridDim.x) {
+        const int r = longs[q];
+        const int r0 = row[r], len = row[r + 1] - r0;
+        const int P = pow2_at_least(len);
+        int32_t* b = P <= kRowLds ? lds : scratch + 2 * (size_t)r0;
+        for (int k = t; k < P; k += 256) b[k] = k < len ? vals[r0 + k] : INT32_MAX;
+        __syncthreads();
+        bitonic_sort(b, P, t, 256);
+        for (int k = t; k < len; k += 256) vals[r0 + k] = b[k];
+        __syncthreads();
+    }
+}
+
+// M2L sources and shifts from the sorted row values, and the smallest
+// depth of the tasks' source and target cells (mindep[0] / mindep[1],
+// preset to INT32_MAX).
+__global__ void k_m2l_split(const int32_t* __restrict__ row, int nrows, const int32_t* __restrict__ vals,
+                            const int4* __restrict__ aux, int32_t* __restrict__ src,
+                            int32_t* __restrict__ shift, int32_t* __restrict__ mindep) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nrows) return;
+    const int r0 = row[c], r1 = row[c + 1];
+    if (r0 == r1) return;
+    int dmin = INT32_MAX;
+    for (int k = r0; k < r1; ++k) {
+        const int u = vals[k] >> 5;
+        src[k] = u;
+        shift[k] = vals[k] & 31;
+        dmin = min(dmin, aux[u].w);
+    }
+    atomicMin(&mindep[0], dmin);
+    atomicMin(&mindep[1], aux[c].w);
 }
 
 __global__ void k_item_count(int nl, const int32_t* __restrict__ row, int chunk,
@@ -821,39 +899,70 @@ __global__ void k_item_count(int nl, const int32_t* __restrict__ row, int chunk,
     cnt[i] = (len + chunk - 1) / chunk;
 }
 
-// Work items of each TaskGroup row; the queue key is 255 - (pair count >>
-// cshift), one radix pass, so the queue is longest first up to 1/256 of the
-// largest item.
+// Work items of each TaskGroup row, one wavefront per row and one lane per
+// item; the queue key is 255 - (pair count >> cshift), one radix pass, so
+// the queue is longest first up to 1/256 of the largest item.  Slots from
+// the item count to `cap` get key 255 (after every item in the stable sort).
+// rowcand[i]: candidate pairs of row i; ctl[2]: the item count.
 __global__ void k_items(int nl, const int32_t* __restrict__ row, const int32_t* __restrict__ js,
                         const int4* __restrict__ leaf, int chunk, int cshift,
-                        const int32_t* __restrict__ slot0, int4* __restrict__ items,
+                        const int32_t* __restrict__ slot0, int cap, int4* __restrict__ items,
                         uint64_t* __restrict__ cost_keys, uint32_t* __restrict__ slots,
-                        unsigned long long* __restrict__ cand) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+                        unsigned long long* __restrict__ rowcand, uint32_t* __restrict__ ctl) {
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(gt >> 6), lane = (int)(gt & 63);
     unsigned long long total = 0;
-    const int r0 = i < nl ? row[i] : 0, len = i < nl ? row[i + 1] - r0 : 0;
-    if (len > 0) {
-        const int parts = (len + chunk - 1) / chunk;
-        const int base = len / parts, extra = len % parts;
-        const int ni = leaf[i].y;
-        int t = r0;
-        for (int k = 0; k < parts; ++k) {
-            const int sz = base + (k < extra ? 1 : 0);
-            unsigned long long c = 0;
-            for (int q = t; q < t + sz; ++q) c += (unsigned long long)leaf[js[q] >> 5].y;
-            c *= (unsigned long long)ni;
-            total += c;
-            const int s = slot0[i] + k;
-            items[s] = make_int4(i, t, t + sz, s);
-            const unsigned long long b = c >> cshift;
-            cost_keys[s] = (uint64_t)(255u - (b > 255ull ? 255u : (uint32_t)b));
-            slots[s] = (uint32_t)s;
-            t += sz;
+    if (i < nl) {
+        const int r0 = row[i], len = row[i + 1] - r0;
+        if (len > 0) {
+            const int parts = (len + chunk - 1) / chunk;
+            const int base = len / parts, extra = len % parts;
+            const int ni = leaf[i].y;
+            for (int k = lane; k < parts; k += 64) {
+                const int t = r0 + k * base + min(k, extra);
+                const int sz = base + (k < extra ? 1 : 0);
+                unsigned long long c = 0;
+                for (int q = t; q < t + sz; ++q) c += (unsigned long long)leaf[js[q] >> 5].y;
+                c *= (unsigned long long)ni;
+                total += c;
+                const int s = slot0[i] + k;
+                items[s] = make_int4(i, t, t + sz, s);
+                const unsigned long long b = c >> cshift;
+                cost_keys[s] = (uint64_t)(255u - (b > 255ull ? 255u : (uint32_t)b));
+                slots[s] = (uint32_t)s;
+            }
         }
     }
-    // one atomic per wavefront (a single counter for all leaves)
+    {
+        // padding slots, spread over all threads of the grid
+        const int n_items = slot0[nl];
+        if (gt == 0) ctl[2] = (uint32_t)n_items;
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t s = n_items + gt; s < cap; s += stride) {
+            cost_keys[s] = 255u;
+            slots[s] = (uint32_t)s;
+        }
+    }
+    // the row's candidate pairs (summed by k_sum_rows: one atomic per row
+    // on a single counter would serialise)
     for (int off = 32; off > 0; off >>= 1) total += __shfl_down(total, off);
-    if ((threadIdx.x & 63) == 0 && total) atomicAdd(cand, total);
+    if (lane == 0 && i < nl) rowcand[i] = total;
+}
+
+// out = sum of v[0, n), by one workgroup of 1024 threads.
+__global__ void __launch_bounds__(1024)
+k_sum_rows(const unsigned long long* __restrict__ v, int n, unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long part[1024 / 64];
+    unsigned long long x = 0;
+    for (int i = threadIdx.x; i < n; i += 1024) x += v[i];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < 1024 / 64; ++w) t += part[w];
+        *out = t;
+    }
 }
 
 __global__ void k_check(const double* __restrict__ pos, const double* __restrict__ mass, int64_t n,
@@ -1274,32 +1383,59 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
 
     clk.lap("walk");
     // ---- canonical order and CSR
-    const int p2p_bits = ks.x + bits_for((uint64_t)std::max<int64_t>(1, nl - 1));
-    std::string err = sort_in_place(d.p2p_keys, nullptr, d.p2p_keys_tmp, nullptr, d.hist, n_p2p,
-                                    p2p_bits, s);
-    if (!err.empty()) return err;
     TRY(d.p2p_row.ensure((nl + 1) * 4));
     TRY(d.js.ensure(std::max<int64_t>(1, n_p2p) * 4));
-    hipLaunchKernelGGL(k_csr_rows, dim3(grid_of(nl + 1)), dim3(256), 0, s, d.p2p_keys.as<uint64_t>(),
-                       n_p2p, (int)nl, ks.x, d.p2p_row.as<int32_t>());
-    if (n_p2p > 0)
-        hipLaunchKernelGGL(k_split_p2p, dim3(grid_of(n_p2p)), dim3(256), 0, s,
-                           d.p2p_keys.as<uint64_t>(), n_p2p, ks.x, d.js.as<int32_t>());
-    TRY(hipGetLastError());
-    const int m2l_bits = ks.y + bits_for((uint64_t)std::max<int64_t>(1, nc - 1));
-    err = sort_in_place(d.m2l_keys, nullptr, d.m2l_keys_tmp, nullptr, d.hist, n_m2l, m2l_bits, s);
-    if (!err.empty()) return err;
     TRY(d.m2l_row.ensure((nc + 1) * 4));
     TRY(d.m2l_src.ensure(std::max<int64_t>(1, n_m2l) * 4));
     TRY(d.m2l_shift.ensure(std::max<int64_t>(1, n_m2l) * 4));
-    hipLaunchKernelGGL(k_csr_rows, dim3(grid_of(nc + 1)), dim3(256), 0, s, d.m2l_keys.as<uint64_t>(),
-                       n_m2l, (int)nc, ks.y, d.m2l_row.as<int32_t>());
+    TRY(d.m2l_vals.ensure(std::max<int64_t>(1, n_m2l) * 4));
+    // slots, then long-row scratch: two int32 per key
+    TRY(d.p2p_keys_tmp.ensure(std::max<int64_t>(1, n_p2p) * 8));
+    TRY(d.m2l_keys_tmp.ensure(std::max<int64_t>(1, n_m2l) * 8));
+    TRY(d.rowcnt.ensure((std::max(nl, nc) + 2) * 4));
+    TRY(d.longrows.ensure((std::max(nl, nc) + 1) * 4));
+    TRY(d.tile_sums.ensure(sort_tiles(std::max(nl, nc) + 1) * 4 + 16));
+    struct RowList {
+        const DevBuf& keys;
+        int64_t nk;
+        int nrows;
+        int ks;
+        DevBuf& row;
+        DevBuf& vals;
+        DevBuf& tmp;
+    };
+    const RowList lists[2] = {{d.p2p_keys, n_p2p, (int)nl, ks.x, d.p2p_row, d.js, d.p2p_keys_tmp},
+                              {d.m2l_keys, n_m2l, (int)nc, ks.y, d.m2l_row, d.m2l_vals,
+                               d.m2l_keys_tmp}};
+    for (const RowList& rl : lists) {
+        int32_t* cnt = d.rowcnt.as<int32_t>();
+        int32_t* slot = rl.tmp.as<int32_t>();
+        hipLaunchKernelGGL(k_zero_u32, dim3(grid_of(rl.nrows + 2)), dim3(256), 0, s,
+                           d.rowcnt.as<uint32_t>(), rl.nrows + 2);
+        if (rl.nk > 0)
+            hipLaunchKernelGGL(k_row_count, dim3(grid_of(rl.nk)), dim3(256), 0, s,
+                               rl.keys.as<uint64_t>(), rl.nk, rl.ks, cnt, slot);
+        TRY(hipGetLastError());
+        TRY(exclusive_scan_i32(cnt, rl.row.as<int32_t>(), rl.nrows + 1, d.tile_sums.as<uint32_t>(), s));
+        if (rl.nk > 0) {
+            hipLaunchKernelGGL(k_row_place, dim3(grid_of(rl.nk)), dim3(256), 0, s,
+                               rl.keys.as<uint64_t>(), rl.nk, rl.ks, rl.row.as<int32_t>(), slot,
+                               rl.vals.as<int32_t>());
+            // the count of long rows goes in rowcnt[nrows + 1] (zeroed above)
+            int32_t* nlong = cnt + rl.nrows + 1;
+            hipLaunchKernelGGL(k_row_sort_short, dim3(rl.nrows), dim3(64), 0, s, rl.row.as<int32_t>(),
+                               rl.vals.as<int32_t>(), d.longrows.as<int32_t>(), nlong);
+            hipLaunchKernelGGL(k_row_sort_long, dim3(64), dim3(256), 0, s, rl.row.as<int32_t>(),
+                               rl.vals.as<int32_t>(), d.longrows.as<int32_t>(), nlong, slot);
+        }
+        TRY(hipGetLastError());
+    }
     // wcount words 16, 17: smallest source / target depth of the M2L tasks
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int*>(d.wcount.p) + 16,
                        2, 0x7fffffff);
     if (n_m2l > 0)
-        hipLaunchKernelGGL(k_split_m2l, dim3(grid_of(n_m2l)), dim3(256), 0, s,
-                           d.m2l_keys.as<uint64_t>(), n_m2l, ks.y, d.cell_aux.as<int4>(),
+        hipLaunchKernelGGL(k_m2l_split, dim3(grid_of(nc)), dim3(256), 0, s, d.m2l_row.as<int32_t>(),
+                           (int)nc, d.m2l_vals.as<int32_t>(), d.cell_aux.as<int4>(),
                            d.m2l_src.as<int32_t>(), d.m2l_shift.as<int32_t>(),
                            reinterpret_cast<int32_t*>(d.wcount.p) + 16);
     TRY(hipGetLastError());
@@ -1323,31 +1459,38 @@ std::string gpu_make_items(DevPlan& d, const Plan& topo, int64_t n_p2p, int chun
     TRY(hipGetLastError());
     TRY(exclusive_scan_i32(d.cost.as<int32_t>(), d.leaf_slot.as<int32_t>(), nl + 1,
                            d.tile_sums.as<uint32_t>(), s));
-    int32_t n_items = 0;
-    TRY(hipMemcpyAsync(&n_items, d.leaf_slot.as<int32_t>() + nl, 4, hipMemcpyDeviceToHost, s));
-    TRY(hipStreamSynchronize(s));
-    TRY(d.items.ensure(std::max<int64_t>(1, n_items) * 16));
-    TRY(d.cost_keys.ensure(std::max<int64_t>(1, n_items) * 8));
-    TRY(d.queue.ensure(std::max<int64_t>(1, n_items) * 4));
-    TRY(d.partial.ensure(std::max<int64_t>(1, n_items) * 4 * 64 * 8));
+    // buffers sized for the most items the rows can give (sum over rows of
+    // ceil(len / chunk) <= n_p2p / chunk + rows), so the count is read back
+    // only at the end
+    const int64_t cap = std::max<int64_t>(1, (n_p2p + chunk - 1) / chunk + nl);
+    TRY(d.items.ensure(cap * 16));
+    TRY(d.cost_keys.ensure(cap * 8));
+    // per-row candidate pairs in the sort's scratch (free until the sort)
+    TRY(d.cost_keys_tmp.ensure(std::max<int64_t>(cap, nl) * 8));
+    TRY(d.queue.ensure(cap * 4));
     TRY(d.wcount.ensure(128));
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, d.wcount.as<uint32_t>(), 16);
     // largest item: chunk tasks of at most 64 x 64 pairs
     const int cshift = std::max(0, bits_for((uint64_t)chunk * 64 * 64) - 8);
-    hipLaunchKernelGGL(k_items, dim3(grid_of(nl)), dim3(256), 0, s, (int)nl, d.p2p_row.as<int32_t>(),
-                       d.js.as<int32_t>(), d.leaf.as<int4>(), chunk, cshift, d.leaf_slot.as<int32_t>(),
-                       d.items.as<int4>(), d.cost_keys.as<uint64_t>(), d.queue.as<uint32_t>(),
-                       reinterpret_cast<unsigned long long*>(d.wcount.as<uint32_t>() + 8));
+    hipLaunchKernelGGL(k_items, dim3(grid_of((nl + 1) * 64)), dim3(256), 0, s, (int)nl,
+                       d.p2p_row.as<int32_t>(), d.js.as<int32_t>(), d.leaf.as<int4>(), chunk, cshift,
+                       d.leaf_slot.as<int32_t>(), (int)cap, d.items.as<int4>(),
+                       d.cost_keys.as<uint64_t>(), d.queue.as<uint32_t>(),
+                       d.cost_keys_tmp.as<unsigned long long>(), d.wcount.as<uint32_t>() + 8);
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(1024), 0, s, d.cost_keys_tmp.as<unsigned long long>(),
+                       (int)nl, reinterpret_cast<unsigned long long*>(d.wcount.as<uint32_t>() + 8));
     TRY(hipGetLastError());
     std::string err = sort_in_place(d.cost_keys, &d.queue, d.cost_keys_tmp, &d.queue_tmp, d.hist,
-                                    n_items, 8, s);
+                                    cap, 8, s);
     if (!err.empty()) return err;
-    // words 8, 9: candidate pairs; 16, 17: M2L depths (set by the build)
+    // words 8, 9: candidate pairs; 10: items; 16, 17: M2L depths (set by the build)
     uint32_t w[10];
     TRY(hipMemcpyAsync(w, d.wcount.as<uint32_t>() + 8, sizeof(w), hipMemcpyDeviceToHost, s));
     TRY(hipStreamSynchronize(s));
     unsigned long long cand = 0;
     std::memcpy(&cand, w, 8);
+    const int64_t n_items = (int64_t)w[2];
+    TRY(d.partial.ensure(std::max<int64_t>(1, n_items) * 4 * 64 * 8));
     out.n_items = n_items;
     out.candidate_pairs = (int64_t)cand;
     out.m2l_min_depth_src = (int32_t)w[8];

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "device.h"
 #include "plan.h"
@@ -72,6 +73,7 @@ struct DevPlan {
     // walk sizes seen on the last level-by-level build of this tree shape
     uint32_t walk_cap_front = 0, walk_cap_p2p = 0, walk_cap_m2l = 0;
     int walk_levels = 0;
+    std::vector<uint32_t> walk_sizes;   // frontier size per level, last build
 
     void release_all() {
         for (DevBuf* b : {&perm, &leaf, &leafc, &js, &items, &queue, &leaf_slot, &partial, &counter,

@@ -699,11 +699,6 @@ k_walk(const int2* __restrict__ front, int nf, int2* __restrict__ next,
 
 // One level of the walk with the frontier size read on the device (no host
 // round trip between levels).  Capacities are checked; an overflow is
-// reported and the host then redoes the walk level by level.
-// ctl: [0] p2p total, [1] m2l total, [2] overflow flag, [3] largest frontier;
-// sizes[it] = frontier size of level it.
-// One level of the walk with the frontier size read on the device (no host
-// round trip between levels).  Capacities are checked; an overflow is
 // reported and the host then redoes the walk level by level.  The appends
 // are aggregated per workgroup (one atomic per counter per 1024 pairs):
 // all workgroups add to the same three counters, and at one atomic per
@@ -771,6 +766,18 @@ k_walk_dev(const int2* __restrict__ front, int2* __restrict__ next, int it,
         __syncthreads();   // wtot and bbase are reused by the next group
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&ctl[3], nf);
+}
+
+// The walk's first frontier: for each box, its root against itself with the
+// zero shift and the 13 shifts of code > 13 (the canonical half).
+__global__ void k_walk_init(int nbox, const int32_t* __restrict__ box_root, int2* __restrict__ front,
+                            uint32_t* __restrict__ sizes) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == 0) sizes[0] = (uint32_t)(14 * nbox);
+    if (q >= 14 * nbox) return;
+    const int b = q / 14, j = q - 14 * b;
+    const int root = box_root[b];
+    front[q] = make_int2(root, (root << 5) | (13 + j));
 }
 
 __global__ void k_zero_u32(uint32_t* p, int n) {
@@ -846,13 +853,13 @@ k_row_sort_short(const int32_t* __restrict__ row, int32_t* __restrict__ vals,
     for (int k = t; k < len; k += 64) vals[r0 + k] = b[k];
 }
 
-// The listed long rows, one workgroup at a time each: in LDS up to kRowLds
-// values, else in scratch[2 r0, 2 r0 + P) (P < 2 len, so rows never share
-// scratch; the caller provides twice the value count).
+// The listed long rows, one workgroup at a time each: in LDS up to lds_cap
+// (<= kRowLds) values, else in scratch[2 r0, 2 r0 + P) (P < 2 len, so rows
+// never share scratch; the caller provides twice the value count).
 __global__ void __launch_bounds__(256)
 k_row_sort_long(const int32_t* __restrict__ row, int32_t* __restrict__ vals,
                 const int32_t* __restrict__ longs, const int32_t* __restrict__ nlong,
-                int32_t* __restrict__ scratch) {
+                int32_t* __restrict__ scratch, int lds_cap) {
     __shared__ int32_t lds[kRowLds];
     const int t = threadIdx.x;
     const int count = *nlong;
@@ -860,7 +867,7 @@ k_row_sort_long(const int32_t* __restrict__ row, int32_t* __restrict__ vals,
         const int r = longs[q];
         const int r0 = row[r], len = row[r + 1] - r0;
         const int P = pow2_at_least(len);
-        int32_t* b = P <= kRowLds ? lds : scratch + 2 * (size_t)r0;
+        int32_t* b = P <= lds_cap ? lds : scratch + 2 * (size_t)r0;
         for (int k = t; k < P; k += 256) b[k] = k < len ? vals[r0 + k] : INT32_MAX;
         __syncthreads();
         bitonic_sort(b, P, t, 256);
@@ -1018,6 +1025,15 @@ std::string sort_in_place(DevBuf& keys, DevBuf* vals, DevBuf& ktmp, DevBuf* vtmp
         if (vals) std::swap(*vals, *vtmp);
     }
     return std::string();
+}
+
+// LDS capacity of the long-row sort; PMFMM_ROW_LDS lowers it (tests use it
+// to send rows through the scratch path).
+int row_lds_cap() {
+    const char* v = std::getenv("PMFMM_ROW_LDS");
+    if (!v) return kRowLds;
+    const int c = std::atoi(v);
+    return c < 0 ? 0 : std::min(c, kRowLds);
 }
 
 // Wall-clock phases of the device planner, printed to stderr when the
@@ -1315,14 +1331,17 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         TRY(d.walk_ctl.ensure((size_t)(L + 8) * 4));
         hipLaunchKernelGGL(k_zero_u32, dim3((L + 8 + 255) / 256), dim3(256), 0, s,
                            d.walk_ctl.as<uint32_t>(), L + 8);
-        uint32_t nf0u = (uint32_t)nf0;
-        TRY(hipMemcpyAsync(d.front.p, f0.data(), f0.size() * 4, hipMemcpyHostToDevice, s));
-        TRY(hipMemcpyAsync(d.walk_ctl.as<uint32_t>() + 4, &nf0u, 4, hipMemcpyHostToDevice, s));
         uint32_t* ctl = d.walk_ctl.as<uint32_t>();
         uint32_t* sizes = ctl + 4;
+        hipLaunchKernelGGL(k_walk_init, dim3(grid_of(nf0)), dim3(256), 0, s, nbox,
+                           d.item_count.as<int32_t>(), d.front.as<int2>(), sizes);
         DevBuf* bufs[2] = {&d.front, &d.front_next};
         for (int it = 0; it < L; ++it) {
-            hipLaunchKernelGGL(k_walk_dev, dim3(512), dim3(kWalkT), 0, s, bufs[it & 1]->as<int2>(),
+            // workgroups for the frontier the last build had at this level
+            // (the kernel strides over any size; this only trims launches)
+            const int64_t prev = it < (int)d.walk_sizes.size() ? d.walk_sizes[it] : capf;
+            const unsigned g = (unsigned)std::min<int64_t>(512, (prev + prev / 4 + 2 * kWalkT) / kWalkT);
+            hipLaunchKernelGGL(k_walk_dev, dim3(g), dim3(kWalkT), 0, s, bufs[it & 1]->as<int2>(),
                                bufs[(it + 1) & 1]->as<int2>(), it, sizes, ctl, capf, capp, capm,
                                d.walkbox.as<WalkBox>(), d.wcell.as<WalkCell>(), ks,
                                d.p2p_keys.as<uint64_t>(), d.m2l_keys.as<uint64_t>());
@@ -1339,6 +1358,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         if (hc[2] == 0 && hc[4 + L] == 0 && hc[0] <= capp && hc[1] <= capm) {
             n_p2p = hc[0];
             n_m2l = hc[1];
+            d.walk_sizes.assign(hc.begin() + 4, hc.begin() + 4 + L);
             done = true;
         }
     }
@@ -1352,7 +1372,9 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         uint32_t hc[4] = {0, 0, 0, 0};
         int levels = 0;
         int64_t max_front = nf;
+        d.walk_sizes.clear();
         while (nf > 0) {
+            d.walk_sizes.push_back((uint32_t)nf);
             TRY(d.front_next.grow((size_t)4 * nf * 8, 0, s));
             // each pair adds at most 4 children and 2 keys (itself and mirror)
             if ((size_t)(n_p2p + 2 * nf) * 8 > d.p2p_keys.bytes)
@@ -1426,7 +1448,8 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
             hipLaunchKernelGGL(k_row_sort_short, dim3(rl.nrows), dim3(64), 0, s, rl.row.as<int32_t>(),
                                rl.vals.as<int32_t>(), d.longrows.as<int32_t>(), nlong);
             hipLaunchKernelGGL(k_row_sort_long, dim3(64), dim3(256), 0, s, rl.row.as<int32_t>(),
-                               rl.vals.as<int32_t>(), d.longrows.as<int32_t>(), nlong, slot);
+                               rl.vals.as<int32_t>(), d.longrows.as<int32_t>(), nlong, slot,
+                               row_lds_cap());
         }
         TRY(hipGetLastError());
     }

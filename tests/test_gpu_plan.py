@@ -109,6 +109,28 @@ def test_coordinates_below_sort_key_resolution(group):
     assert_same(L, tree, lists)
 
 
+# One dense clump inside the cutoff: every leaf row lists every leaf, so
+# the rows are longer than one wavefront sorts; with PMFMM_ROW_LDS=64 they
+# are sorted in global scratch instead of LDS.
+@pytest.mark.parametrize("row_lds", [None, "64"])
+def test_long_task_rows(row_lds, monkeypatch):
+    if row_lds is not None:
+        monkeypatch.setenv("PMFMM_ROW_LDS", row_lds)
+    rng = np.random.default_rng(77)
+    clump = 10.0 + rng.normal(0, 0.3, (3000, 3))
+    pos = np.concatenate([clump, rng.uniform(0, 20.0, (500, 3))])
+    pos = pos[rng.permutation(len(pos))]
+    m = np.ones(len(pos))
+    print(f"case: gpu plan long rows (row lds {row_lds})", flush=True)
+    L, _ = gpu_lists(pos, m, 20.0, 0.6, 2.7, 8, -1, 0.0)
+    host = B.Context(box=20.0, r_s=0.6, r_cut=2.7, max_leaf=8, order=-1, theta=0.0)
+    host.plan(pos, m)
+    H = host.lists()
+    assert int(np.diff(H["p2p_row"]).max()) > 256
+    for k in ("perm", "p2p_row", "p2p_j", "p2p_shift"):
+        assert np.array_equal(L[k], H[k]), k
+
+
 def test_matches_host_planner_clustered_2m_items():
     w = inputs.clustered_2m()
     print("case: gpu plan vs host plan 128^3", flush=True)

@@ -105,3 +105,75 @@ def test_fmm_accuracy_on_clustered(small):
     # the far field carries a real share of the force in the halo
     assert np.max(np.linalg.norm(far, axis=1)) > 1e-3 * np.max(
         np.linalg.norm(ref, axis=1))
+
+
+# ---- the oracle's FMM adjoint (tree, lists and centres held fixed)
+
+def _far_loss(pos, mass, w, box, r_s, r_cut, p, tree, lists):
+    _, _, far, _, _ = fmm.fmm_forces(pos, mass, box, r_s, r_cut, 16, p, 0.3,
+                                     tree=tree, lists=lists, return_parts=True)
+    return float(np.sum(w * far))
+
+
+def test_far_gradient_matches_finite_differences():
+    """The far-field force is a polynomial in the positions and linear in
+    the masses once the centres are fixed, so central differences pin the
+    transposed operators (a dropped term, a sign or a transposed index in
+    any of them shows here)."""
+    pos, m, box, r_s, r_cut = _two_clumps()
+    m = m * np.random.default_rng(3).uniform(0.5, 1.5, len(m))
+    p = 3
+    tree = T.build_orb(pos, 16)
+    lists = T.dual_walk(tree, box, r_cut, 0.3, True)
+    assert len(lists.m2l) > 0
+    w = np.random.default_rng(4).standard_normal(pos.shape)
+    gx, gm = fmm.far_gradient(tree, lists, pos, m, w, box, r_s, p)
+    h = 1e-4
+    for k in (0, 123, 301, 599):
+        for a in range(3):
+            pp, pm = pos.copy(), pos.copy()
+            pp[k, a] += h
+            pm[k, a] -= h
+            fd = (_far_loss(pp, m, w, box, r_s, r_cut, p, tree, lists)
+                  - _far_loss(pm, m, w, box, r_s, r_cut, p, tree, lists)) / (2 * h)
+            assert abs(fd - gx[k, a]) <= 1e-6 * (abs(gx[k, a]) + np.abs(gx).max() * 1e-3), (k, a)
+        mp, mm = m.copy(), m.copy()
+        mp[k] += 1e-3
+        mm[k] -= 1e-3
+        fd = (_far_loss(pos, mp, w, box, r_s, r_cut, p, tree, lists)
+              - _far_loss(pos, mm, w, box, r_s, r_cut, p, tree, lists)) / 2e-3
+        assert abs(fd - gm[k]) <= 1e-9 * (abs(gm[k]) + np.abs(gm).max()), k
+
+
+def test_p2p_gradient_at_theta_zero_is_brute_force(small):
+    """With theta = 0 the P2P lists hold every pair within the cutoff, so the
+    list-based transpose equals the cell-list brute-force gradient."""
+    w = small
+    cot = np.random.default_rng(6).standard_normal(w.pos.shape)
+    ref_x, ref_m, sx, sm = direct.gradient(w.pos, w.mass, cot, w.box, w.r_s,
+                                           w.r_cut, workers=1, with_scale=True)
+    gx, gm = fmm.fmm_gradient(w.pos, w.mass, cot, w.box, w.r_s, w.r_cut, 16,
+                              4, 0.0)
+    assert np.all(np.abs(gx - ref_x) <= 1e-13 * sx[:, None] + 1e-300)
+    assert np.all(np.abs(gm - ref_m) <= 1e-13 * sm + 1e-300)
+
+
+def test_fmm_gradient_approaches_brute_force():
+    """The FMM adjoint converges to the brute-force gradient as p grows."""
+    pos, m, box, r_s, r_cut = _two_clumps()
+    cot = np.random.default_rng(8).standard_normal(pos.shape)
+    ref_x, ref_m = direct.gradient(pos, m, cot, box, r_s, r_cut, workers=1)
+    ex, em = [], []
+    for p in (1, 3, 5):
+        gx, gm, fx, fm, tree, lists = fmm.fmm_gradient(
+            pos, m, cot, box, r_s, r_cut, 16, p, 0.3, return_parts=True)
+        assert len(lists.m2l) > 0
+        ex.append(np.median(np.linalg.norm(gx - ref_x, axis=1)
+                            / np.linalg.norm(ref_x, axis=1)))
+        em.append(np.median(np.abs(gm - ref_m) / np.abs(ref_m)))
+    assert ex[0] > ex[1] > ex[2] and em[0] > em[1] > em[2]
+    assert ex[2] < 1e-4 and em[2] < 1e-4
+    # the far field carries a real share of the gradient (close pairs,
+    # with their 1/r^3 terms, set the largest entries of it)
+    assert np.max(np.linalg.norm(fx, axis=1)) > 1e-3 * np.median(np.linalg.norm(ref_x, axis=1))
+    assert np.max(np.abs(fm)) > 1e-3 * np.median(np.abs(ref_m))

@@ -161,10 +161,13 @@ int pmfmm_set_eval(pmfmm_ctx* ctx, const pmfmm_params* p);
 int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream);
 
 /* Gradient of loss = sum_i w_i . a_i with respect to positions and masses
- * for the P2P-only force (far field off).  w, grad_pos: device (n_total, 3);
- * grad_mass: device (n_total); caller order.  The almost-everywhere
- * gradient: the step of the hard cutoff is left out.
- * Errors: ESTATE, EUNSUPPORTED (far field on), EDEVICE. */
+ * (not in the paper; the transpose of the pair sum of Eq. (tr) and, with
+ * the far field on, of the Sec. 2 operators P2M, M2M, M2L, L2L, L2P, with
+ * the tree, the task lists and the expansion centres of the last build
+ * held fixed).  w, grad_pos: device (n_total, 3); grad_mass: device
+ * (n_total); caller order.  The almost-everywhere gradient: the step of the
+ * hard cutoff is left out.  Pairs are evaluated with the exact T (erfc and
+ * exp) in the context's precision.  Errors: ESTATE, EDEVICE. */
 int pmfmm_adjoint(pmfmm_ctx* ctx, const double* w, double* grad_pos,
                   double* grad_mass, void* stream);
 

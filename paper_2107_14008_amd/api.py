@@ -88,8 +88,10 @@ def short_range_accel(pos: torch.Tensor, mass: torch.Tensor, **params):
 class ShortRangeForce(torch.autograd.Function):
     """acc = ShortRangeForce.apply(pos, mass, params_dict).
 
-    The backward pass runs the library's adjoint kernel: for a cotangent w it
-    returns (dL/dpos, dL/dmass) of L = sum_i w_i . acc_i (P2P-only force).
+    The backward pass runs the library's adjoint kernels: for a cotangent w
+    it returns (dL/dpos, dL/dmass) of L = sum_i w_i . acc_i, through the P2P
+    pairs and, with the far field on, the transposed far-field operators
+    (tree, lists and expansion centres of the forward build held fixed).
     """
 
     @staticmethod

@@ -537,10 +537,10 @@ int prepare_far(pmfmm_ctx* ctx, hipStream_t s) {
     return PMFMM_OK;
 }
 
-int run_far(pmfmm_ctx* ctx, hipStream_t s) {
+// Pass-up, M2L and pass-down of the far field (the leaves' multipoles are
+// already in M; the locals end in Lc).
+int far_middle(pmfmm_ctx* ctx, pmfmm::FarArgs& f, hipStream_t s) {
     const pmfmm::Plan& pl = ctx->plan;
-    pmfmm::FarArgs f = far_args(ctx);
-    HIP_TRY(pmfmm::launch_p2m(f, s));
     const int nd = (int)pl.depth_begin.size() - 1;
     // no cell above the shallowest M2L source needs a multipole, none above
     // the shallowest target a local expansion
@@ -557,7 +557,34 @@ int run_far(pmfmm_ctx* ctx, hipStream_t s) {
         f.n_level = pl.depth_begin[d + 1] - pl.depth_begin[d];
         HIP_TRY(pmfmm::launch_l2l_level(f, s));
     }
+    return PMFMM_OK;
+}
+
+int run_far(pmfmm_ctx* ctx, hipStream_t s) {
+    pmfmm::FarArgs f = far_args(ctx);
+    HIP_TRY(pmfmm::launch_p2m(f, s));
+    int rc = far_middle(ctx, f, s);
+    if (rc) return rc;
     HIP_TRY(pmfmm::launch_l2p(f, s));
+    return PMFMM_OK;
+}
+
+// Far-field part of the adjoint into fargrad (leaf order, no G): the
+// forward locals give the L2P Hessian term; then the transposed pass on
+// sign-flipped coefficients (leaf W2M, the same pass-up / M2L / pass-down
+// over the symmetric M2L list) gives the P2M terms.  w64 must hold the
+// leaf-ordered cotangent.
+int run_far_adjoint(pmfmm_ctx* ctx, hipStream_t s) {
+    pmfmm::FarArgs f = far_args(ctx);
+    const double4* w64 = ctx->d.w64.as<double4>();
+    double4* fg = ctx->d.fargrad.as<double4>();
+    HIP_TRY(pmfmm::launch_p2m(f, s));
+    int rc = far_middle(ctx, f, s);
+    if (rc) return rc;
+    HIP_TRY(pmfmm::launch_far_hess(f, w64, fg, s));
+    HIP_TRY(pmfmm::launch_w2m(f, w64, s));
+    if ((rc = far_middle(ctx, f, s))) return rc;
+    HIP_TRY(pmfmm::launch_far_adj(f, fg, s));
     return PMFMM_OK;
 }
 
@@ -966,7 +993,6 @@ int pmfmm_get_timings(const pmfmm_ctx* ctx, pmfmm_timings* out) {
 int pmfmm_adjoint(pmfmm_ctx* ctx, const double* w, double* grad_pos, double* grad_mass, void* stream) {
     if (!ctx || !w || !grad_pos || !grad_mass) return fail(PMFMM_EINVAL, "null argument");
     if (!ctx->built) return fail(PMFMM_ESTATE, "adjoint before build");
-    if (ctx->far) return fail(PMFMM_EUNSUPPORTED, "adjoint covers the P2P-only force (far field off)");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const pmfmm::Plan& pl = ctx->plan;
     const int64_t n = pl.n;
@@ -1004,9 +1030,16 @@ int pmfmm_adjoint(pmfmm_ctx* ctx, const double* w, double* grad_pos, double* gra
         HIP_TRY(hipEventRecord(ctx->ev[5], s));
         ctx->timed_adj = true;
     }
+    const double4* fg = nullptr;
+    if (ctx->far) {
+        HIP_TRY(ctx->d.fargrad.ensure((size_t)n * 32));
+        int rc = run_far_adjoint(ctx, s);
+        if (rc) return rc;
+        fg = ctx->d.fargrad.as<double4>();
+    }
     pmfmm::AdjReduceArgs r{ctx->d.leaf.as<int4>(), ctx->d.leaf_slot.as<int32_t>(), ctx->d.partial.as<double>(),
-                           ctx->d.perm.as<int32_t>(), ctx->d.boxes.as<pmfmm::BoxDev>(), grad_pos, grad_mass,
-                           (int32_t)pl.leaf_count.size()};
+                           fg, ctx->d.perm.as<int32_t>(), ctx->d.boxes.as<pmfmm::BoxDev>(), grad_pos,
+                           grad_mass, (int32_t)pl.leaf_count.size()};
     HIP_TRY(pmfmm::launch_adj_reduce(r, s));
     return PMFMM_OK;
 }

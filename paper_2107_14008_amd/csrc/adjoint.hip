@@ -180,7 +180,8 @@ adjoint_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
 
 __global__ void __launch_bounds__(256)
 adj_reduce_kernel(const int4* __restrict__ leaf, const int32_t* __restrict__ leaf_slot,
-                  const double* __restrict__ partial, const int32_t* __restrict__ perm,
+                  const double* __restrict__ partial, const double4* __restrict__ far,
+                  const int32_t* __restrict__ perm,
                   const BoxDev* __restrict__ boxes, double* __restrict__ gpos,
                   double* __restrict__ gmass, int32_t n_leaves) {
     const int l = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -192,6 +193,13 @@ adj_reduce_kernel(const int4* __restrict__ leaf, const int32_t* __restrict__ lea
     for (int s = leaf_slot[l]; s < leaf_slot[l + 1]; ++s) {
         const double* p = partial + (size_t)s * 256;
         for (int c = 0; c < 4; ++c) g[c] += p[64 * c + lane];
+    }
+    if (far != nullptr) {
+        const double4 f = far[li.x + lane];
+        g[0] += f.x;
+        g[1] += f.y;
+        g[2] += f.z;
+        g[3] += f.w;
     }
     const double G = boxes[li.z].G;
     const int o = perm[li.x + lane];
@@ -248,7 +256,7 @@ hipError_t launch_adjoint(int mode, const AdjArgs& a, int wg_waves, int grid_wgs
 hipError_t launch_adj_reduce(const AdjReduceArgs& a, hipStream_t s) {
     if (a.n_leaves == 0) return hipSuccess;
     hipLaunchKernelGGL(adj_reduce_kernel, dim3((a.n_leaves + 3) / 4), dim3(256), 0, s, a.leaf,
-                       a.leaf_slot, a.partial, a.perm, a.boxes, a.grad_pos, a.grad_mass,
+                       a.leaf_slot, a.partial, a.far, a.perm, a.boxes, a.grad_pos, a.grad_mass,
                        a.n_leaves);
     return hipGetLastError();
 }

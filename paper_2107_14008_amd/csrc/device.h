@@ -139,6 +139,7 @@ struct AdjReduceArgs {
     const int4* leaf;
     const int32_t* leaf_slot;
     const double* partial;
+    const double4* far;         // (gx, gy, gz, gm) per particle, leaf order, or null
     const int32_t* perm;
     const BoxDev* boxes;
     double* grad_pos;           // (n, 3) caller order
@@ -168,6 +169,12 @@ hipError_t launch_m2m_level(const FarArgs& a, hipStream_t s);
 hipError_t launch_m2l(const FarArgs& a, hipStream_t s);
 hipError_t launch_l2l_level(const FarArgs& a, hipStream_t s);
 hipError_t launch_l2p(const FarArgs& a, hipStream_t s);
+// Far-field adjoint (sign-flipped transposes): leaf Lt from the cotangent
+// w into M; the L2P Hessian term into fg from the forward locals in Lc; the
+// P2M terms added to fg from the adjoint locals in Lc.
+hipError_t launch_w2m(const FarArgs& a, const double4* w64, hipStream_t s);
+hipError_t launch_far_hess(const FarArgs& a, const double4* w64, double4* fg, hipStream_t s);
+hipError_t launch_far_adj(const FarArgs& a, double4* fg, hipStream_t s);
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t s);
 // Marks the cells whose expansions the far field needs (sources and targets
 // of M2L tasks and their subtrees).

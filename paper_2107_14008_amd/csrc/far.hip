@@ -291,6 +291,144 @@ l2p_kernel(const double4* __restrict__ x64, const int4* __restrict__ leaf,
     far[3 * (size_t)k + 2] = az;
 }
 
+// ---- Adjoint of the far field (not in the paper).  For L = sum_i w_i . a_i
+// with the tree, the lists and the centres fixed, the transposed operators
+// become the forward ones on sign-flipped coefficients: with
+// Lt_n = (-1)^|n| dL/dL_n and Mt_m = (-1)^|m| dL/dM_m, the transpose of
+// L2L is M2M on Lt, that of M2L is M2L on Lt (the M2L list is symmetric:
+// (t, u, s) holds with (u, t, 26 - s), and D_k(-R) = (-1)^|k| D_k(R)), and
+// that of M2M is L2L on Mt.  At the leaves (no G):
+//   Lt_n(B) = -sum_{i in B} sum_a w_ia (z_B - x_i)^(n - e_a) / (n - e_a)!   (from L2P)
+//   dL/dx_k = Hess phi_B(u) w_k + m_k grad psi_B(u),  dL/dm_k = psi_B(u)
+// with u = x_k - z_B, phi_B the forward local polynomial and
+// psi_B(u) = sum_m Mt_m(B) u^m / m! (from P2M).
+
+// Lt of every leaf that needs one (into M, the pass-up's input).
+__global__ void __launch_bounds__(64)
+w2m_kernel(const double4* __restrict__ x64, const double4* __restrict__ w64,
+           const int4* __restrict__ leaf, const double4* __restrict__ cellc,
+           const BoxDev* __restrict__ boxes, const int32_t* __restrict__ needM,
+           double* __restrict__ M, int n_leaves, int ncoef) {
+    const int l = blockIdx.x;
+    if (l >= n_leaves) return;
+    const int4 li = leaf[l];
+    if (!needM[li.w]) return;
+    const int p = boxes[li.z].order;
+    if (p < 0) return;
+    const int nc = ncoef_of(p);
+    const double4 c = cellc[li.w];
+    for (int k = threadIdx.x; k < nc; k += 64) {
+        const int e[3] = {c_mi.a[k], c_mi.b[k], c_mi.c[k]};
+        double acc = 0.0;
+        for (int j = 0; j < li.y; ++j) {
+            const double4 q = x64[li.x + j];
+            const double4 wq = w64[li.x + j];
+            const double v[3] = {c.x - q.x, c.y - q.y, c.z - q.z};
+            const double wa[3] = {wq.x, wq.y, wq.z};
+            for (int a = 0; a < 3; ++a) {
+                if (e[a] == 0) continue;
+                double t = wa[a];
+                for (int b = 0; b < 3; ++b) {
+                    const int eb = e[b] - (a == b ? 1 : 0);
+                    t *= ipow(v[b], eb) * c_ifact[eb];
+                }
+                acc -= t;
+            }
+        }
+        M[(size_t)li.w * ncoef + k] = acc;
+    }
+}
+
+// u_a^i / i! for i <= p.
+__device__ __forceinline__ void scaled_powers(const double u[3], double pw[3][kMaxP + 1]) {
+    for (int a = 0; a < 3; ++a) {
+        pw[a][0] = 1.0;
+        for (int i = 1; i <= kMaxP; ++i) pw[a][i] = pw[a][i - 1] * u[a] / (double)i;
+    }
+}
+
+// The L2P term Hess phi_B(u) w_k from the forward locals, one wavefront per
+// leaf, lane = particle: fg[k] = (gx, gy, gz, 0).
+__global__ void __launch_bounds__(64)
+far_hess_kernel(const double4* __restrict__ x64, const double4* __restrict__ w64,
+                const int4* __restrict__ leaf, const double4* __restrict__ cellc,
+                const BoxDev* __restrict__ boxes, const int32_t* __restrict__ needL,
+                const double* __restrict__ Lc, double4* __restrict__ fg, int n_leaves,
+                int ncoef) {
+    const int l = blockIdx.x;
+    if (l >= n_leaves) return;
+    const int4 li = leaf[l];
+    const int lane = threadIdx.x;
+    if (lane >= li.y) return;
+    const int k = li.x + lane;
+    const int p = boxes[li.z].order;
+    double g[3] = {0.0, 0.0, 0.0};
+    if (p >= 0 && needL[li.w]) {
+        const int nc = ncoef_of(p);
+        const double4 c = cellc[li.w];
+        const double4 q = x64[k];
+        const double4 wq = w64[k];
+        const double u[3] = {q.x - c.x, q.y - c.y, q.z - c.z};
+        const double w[3] = {wq.x, wq.y, wq.z};
+        double pw[3][kMaxP + 1];
+        scaled_powers(u, pw);
+        const double* L = Lc + (size_t)li.w * ncoef;
+        for (int n = 4; n < nc; ++n) {
+            const int e[3] = {c_mi.a[n], c_mi.b[n], c_mi.c[n]};
+            const double Ln = L[n];
+            for (int a = 0; a < 3; ++a) {
+                if (e[a] == 0) continue;
+                for (int b = 0; b < 3; ++b) {
+                    const int f0 = e[0] - (a == 0) - (b == 0), f1 = e[1] - (a == 1) - (b == 1),
+                              f2 = e[2] - (a == 2) - (b == 2);
+                    if (f0 < 0 || f1 < 0 || f2 < 0) continue;
+                    g[a] += Ln * pw[0][f0] * pw[1][f1] * pw[2][f2] * w[b];
+                }
+            }
+        }
+    }
+    fg[k] = make_double4(g[0], g[1], g[2], 0.0);
+}
+
+// The P2M terms from the adjoint locals Mt (in Lc after the adjoint pass):
+// fg[k] += (m_k grad psi(u), psi(u)).
+__global__ void __launch_bounds__(64)
+far_adj_kernel(const double4* __restrict__ x64, const int4* __restrict__ leaf,
+               const double4* __restrict__ cellc, const BoxDev* __restrict__ boxes,
+               const int32_t* __restrict__ needL, const double* __restrict__ Lc,
+               double4* __restrict__ fg, int n_leaves, int ncoef) {
+    const int l = blockIdx.x;
+    if (l >= n_leaves) return;
+    const int4 li = leaf[l];
+    const int lane = threadIdx.x;
+    if (lane >= li.y) return;
+    const int k = li.x + lane;
+    const int p = boxes[li.z].order;
+    if (p < 0 || !needL[li.w]) return;
+    const int nc = ncoef_of(p);
+    const double4 c = cellc[li.w];
+    const double4 q = x64[k];
+    const double u[3] = {q.x - c.x, q.y - c.y, q.z - c.z};
+    double pw[3][kMaxP + 1];
+    scaled_powers(u, pw);
+    const double* Mt = Lc + (size_t)li.w * ncoef;
+    double psi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int n = 0; n < nc; ++n) {
+        const int n0 = c_mi.a[n], n1 = c_mi.b[n], n2 = c_mi.c[n];
+        const double Mn = Mt[n];
+        psi += Mn * pw[0][n0] * pw[1][n1] * pw[2][n2];
+        if (n0 > 0) gx += Mn * pw[0][n0 - 1] * pw[1][n1] * pw[2][n2];
+        if (n1 > 0) gy += Mn * pw[0][n0] * pw[1][n1 - 1] * pw[2][n2];
+        if (n2 > 0) gz += Mn * pw[0][n0] * pw[1][n1] * pw[2][n2 - 1];
+    }
+    double4 o = fg[k];
+    o.x += q.w * gx;
+    o.y += q.w * gy;
+    o.z += q.w * gz;
+    o.w = psi;
+    fg[k] = o;
+}
+
 // Sources and targets of M2L rows.
 __global__ void far_mark_kernel(const int32_t* __restrict__ row, const int32_t* __restrict__ src,
                                 int n_cells, int32_t* __restrict__ needM,
@@ -383,6 +521,27 @@ hipError_t launch_l2l_level(const FarArgs& a, hipStream_t s) {
     if (a.n_level == 0) return hipSuccess;
     hipLaunchKernelGGL(l2l_kernel, dim3(a.n_level), dim3(64), 0, s, a.level_cells, a.n_level,
                        a.cell, a.cell_aux, a.cellc, a.boxes, a.needL, a.Lc, a.ncoef);
+    return hipGetLastError();
+}
+
+hipError_t launch_w2m(const FarArgs& a, const double4* w64, hipStream_t s) {
+    if (a.n_leaves == 0) return hipSuccess;
+    hipLaunchKernelGGL(w2m_kernel, dim3(a.n_leaves), dim3(64), 0, s, a.x64, w64, a.leaf, a.cellc,
+                       a.boxes, a.needM, a.M, a.n_leaves, a.ncoef);
+    return hipGetLastError();
+}
+
+hipError_t launch_far_hess(const FarArgs& a, const double4* w64, double4* fg, hipStream_t s) {
+    if (a.n_leaves == 0) return hipSuccess;
+    hipLaunchKernelGGL(far_hess_kernel, dim3(a.n_leaves), dim3(64), 0, s, a.x64, w64, a.leaf,
+                       a.cellc, a.boxes, a.needL, a.Lc, fg, a.n_leaves, a.ncoef);
+    return hipGetLastError();
+}
+
+hipError_t launch_far_adj(const FarArgs& a, double4* fg, hipStream_t s) {
+    if (a.n_leaves == 0) return hipSuccess;
+    hipLaunchKernelGGL(far_adj_kernel, dim3(a.n_leaves), dim3(64), 0, s, a.x64, a.leaf, a.cellc,
+                       a.boxes, a.needL, a.Lc, fg, a.n_leaves, a.ncoef);
     return hipGetLastError();
 }
 

@@ -59,7 +59,7 @@ struct DevPlan {
     DevBuf perm, leaf, leafc, js, items, queue, leaf_slot, partial, counter, boxes, table;
     DevBuf x64, x32, stage_pos, stage_mass, far;
     DevBuf cell, cell_aux, cellc, M, Lc, Lt, m2l_row, m2l_src, m2l_shift, level_cells;
-    DevBuf w64, w32;
+    DevBuf w64, w32, fargrad;
     // on-GPU planner scratch
     DevBuf p2p_row, wpos, keys, keys_tmp, plist, plist_tmp, hist, flag, lv_first, tile_sums;
     DevBuf pc, pc_tmp, clo, chi, wcell, box_first, walkbox, front, front_next, p2p_keys,
@@ -79,7 +79,7 @@ struct DevPlan {
         for (DevBuf* b : {&perm, &leaf, &leafc, &js, &items, &queue, &leaf_slot, &partial, &counter,
                           &boxes, &table, &x64, &x32, &stage_pos, &stage_mass, &far, &cell,
                           &cell_aux, &cellc, &M, &Lc, &Lt, &m2l_row, &m2l_src, &m2l_shift, &level_cells,
-                          &w64, &w32, &p2p_row, &wpos, &keys, &keys_tmp, &plist, &plist_tmp, &hist,
+                          &w64, &w32, &fargrad, &p2p_row, &wpos, &keys, &keys_tmp, &plist, &plist_tmp, &hist,
                           &flag, &lv_first, &tile_sums, &pc, &pc_tmp, &clo, &chi, &wcell,
                           &box_first, &walkbox, &front, &front_next, &p2p_keys, &p2p_keys_tmp,
                           &m2l_keys, &m2l_keys_tmp, &wcount, &cost, &cost_keys, &cost_keys_tmp,

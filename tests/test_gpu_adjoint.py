@@ -15,7 +15,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle import direct, metrics
+from oracle import direct, fmm, metrics
 from paper_2107_14008_amd import api
 from paper_2107_14008_amd import binding as B
 from paper_2107_14008_amd import inputs
@@ -137,16 +137,62 @@ def test_adjoint_vs_finite_differences_of_gpu_forward():
     assert checked >= 15
 
 
-def test_adjoint_rejected_with_far_field():
-    w = inputs.clustered_small(12, 3, halo_frac=0.5, n_halos=2)
-    ctx = B.Context(box=w.box, r_s=w.r_s, r_cut=w.r_cut, max_leaf=8, order=4,
-                    theta=0.5)
-    ctx.build(torch.tensor(w.pos, device="cuda"),
-              torch.tensor(w.mass, device="cuda"))
-    if ctx.lists()["n_m2l"] == 0:
-        pytest.skip("no M2L tasks in this input")
-    g = torch.empty((len(w.mass), 3), dtype=torch.float64, device="cuda")
-    gm = torch.empty((len(w.mass),), dtype=torch.float64, device="cuda")
-    with pytest.raises(B.PmfmmError) as e:
-        ctx.adjoint(g, g, gm)
-    assert e.value.code == -5
+@pytest.fixture(scope="module")
+def far_case():
+    w = inputs.clustered_small(16, 3, halo_frac=0.6, n_halos=2, max_leaf=16)
+    m = w.mass * np.random.default_rng(2).uniform(0.5, 1.5, len(w.mass))
+    wv = inputs.cotangent(len(m), seed=15014)
+    gx, gm, fx, fm, tree, lists = fmm.fmm_gradient(
+        w.pos, m, wv, w.box, w.r_s, w.r_cut, 16, 4, 0.6, return_parts=True)
+    assert len(lists.m2l) > 0
+    _, _, sx, sm = direct.gradient(w.pos, m, wv, w.box, w.r_s, w.r_cut,
+                                   with_scale=True)
+    return w, m, wv, gx, gm, fx, fm, sx, sm
+
+
+def far_adjoint(w, m, wv, **ev):
+    sr = api.ShortRange(box=w.box, r_s=w.r_s, r_cut=w.r_cut, max_leaf=16,
+                        order=4, theta=0.6, **ev)
+    sr.build(torch.tensor(w.pos, device="cuda"), torch.tensor(m, device="cuda"))
+    assert sr.ctx.lists()["n_m2l"] > 0
+    gp, gmass = sr.adjoint(torch.tensor(wv, device="cuda"))
+    torch.cuda.synchronize()
+    return gp.cpu().numpy(), gmass.cpu().numpy()
+
+
+def test_adjoint_with_far_field_fp64_matches_oracle(far_case):
+    """The FMM adjoint (far field transposed on sign-flipped coefficients on
+    the GPU, plain transposes in the oracle) on the same lists.  Error scale:
+    the pair-term magnitudes plus the largest far-field term."""
+    w, m, wv, gx, gm, fx, fm, sx, sm = far_case
+    print("case: adjoint fp64 with far field, clustered 16^3 theta 0.6", flush=True)
+    gp, gmass = far_adjoint(w, m, wv, precision=B.PMFMM_FP64)
+    ex = scaled(gp, gx, sx + np.abs(fx).max())
+    em = scaled(gmass, gm, sm + np.abs(fm).max())
+    assert ex["max"] <= 1e-12, ex
+    assert em["max"] <= 1e-12, em
+    # the far field is a real part of the gradient here
+    assert np.abs(fx).max() > 1e-4 * np.abs(gx).max()
+
+
+def test_adjoint_with_far_field_fp32(far_case):
+    w, m, wv, gx, gm, fx, fm, sx, sm = far_case
+    print("case: adjoint fp32 with far field, clustered 16^3 theta 0.6", flush=True)
+    gp, gmass = far_adjoint(w, m, wv, precision=B.PMFMM_FP32,
+                            trunc=B.TRUNC_EXACT)
+    for a, ref, sc in ((gp, gx, sx), (gmass, gm, sm)):
+        e = scaled(a, ref, sc)
+        assert e["median"] <= 1e-5 and e["p999"] <= 1e-4, e
+
+
+def test_autograd_with_far_field(far_case):
+    w, m, wv, gx, gm, fx, fm, sx, sm = far_case
+    pos = torch.tensor(w.pos, device="cuda", requires_grad=True)
+    mass = torch.tensor(m, device="cuda", requires_grad=True)
+    params = dict(box=w.box, r_s=w.r_s, r_cut=w.r_cut, max_leaf=16, order=4,
+                  theta=0.6, precision=B.PMFMM_FP64)
+    acc = api.ShortRangeForce.apply(pos, mass, params)
+    (acc * torch.tensor(wv, device="cuda")).sum().backward()
+    ex = scaled(pos.grad.cpu().numpy(), gx, sx + np.abs(fx).max())
+    em = scaled(mass.grad.cpu().numpy(), gm, sm + np.abs(fm).max())
+    assert ex["max"] <= 1e-12 and em["max"] <= 1e-12, (ex, em)

@@ -355,7 +355,7 @@ def p2p_gradient(tree: Tree, lists: Lists, pos, mass, w, box, r_s, r_cut):
 
 
 def fmm_gradient(pos, mass, w, box, r_s, r_cut, max_leaf, order, theta, G=1.0,
-                 tree=None, lists=None, return_parts=False):
+                 tree=None, lists=None, return_parts=False, centre_cut=False):
     """dL/dpos (N, 3) and dL/dmass (N) of L = sum_i w_i . a_i for the
     accelerations of ``fmm_forces`` (input order), tree, lists and
     expansion centres held fixed."""
@@ -366,7 +366,7 @@ def fmm_gradient(pos, mass, w, box, r_s, r_cut, max_leaf, order, theta, G=1.0,
     if tree is None:
         tree = build_orb(pos, max_leaf)
     if lists is None:
-        lists = dual_walk(tree, box, r_cut, theta, far)
+        lists = dual_walk(tree, box, r_cut, theta, far, centre_cut)
     nx, nm = p2p_gradient(tree, lists, pos, mass, w, box, r_s, r_cut)
     fx, fm = np.zeros_like(nx), np.zeros_like(nm)
     if far and len(lists.m2l):
@@ -377,10 +377,12 @@ def fmm_gradient(pos, mass, w, box, r_s, r_cut, max_leaf, order, theta, G=1.0,
 
 
 def fmm_forces(pos, mass, box, r_s, r_cut, max_leaf, order, theta, G=1.0,
-               tree=None, lists=None, return_parts=False):
+               tree=None, lists=None, return_parts=False, centre_cut=False):
     """Short-range accelerations by the truncated FMM (input order).
 
-    order < 0 or theta <= 0 gives the plain P2P sum over the task lists.
+    order < 0 or theta <= 0 gives the plain P2P sum over the task lists;
+    ``centre_cut`` selects the literal reading of the truncation for M2L
+    (``tree.dual_walk``).
     """
     pos = np.asarray(pos, np.float64)
     mass = np.asarray(mass, np.float64)
@@ -388,7 +390,7 @@ def fmm_forces(pos, mass, box, r_s, r_cut, max_leaf, order, theta, G=1.0,
     if tree is None:
         tree = build_orb(pos, max_leaf)
     if lists is None:
-        lists = dual_walk(tree, box, r_cut, theta, far)
+        lists = dual_walk(tree, box, r_cut, theta, far, centre_cut)
     near = p2p(tree, lists, pos, mass, box, r_s, r_cut)
     farf = np.zeros_like(near)
     if far and len(lists.m2l):

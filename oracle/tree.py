@@ -38,6 +38,10 @@ Readings (the paper names the operations but not these details):
     The guard factors make every rounding error fall on the safe side, so a
     particle pair inside the cutoff is never dropped and a pair sent to M2L
     lies wholly inside it; the per-pair cutoff of the P2P sum then decides.
+  * the literal alternative (``centre_cut``): the kernel and its derivatives
+    are cut at r_cut by the centre distance, so a pair passing the
+    opening-angle test goes to M2L when R2 < r_cut * r_cut and is dropped
+    otherwise, whatever part of it lies inside the cutoff.
     Every quantity is symmetric under (t, u, s) -> (u, t, -s), so the lists
     are symmetric.
   * canonical order: P2P tasks sorted by (i leaf, j leaf, shift code), M2L
@@ -50,7 +54,9 @@ follows the same text produces the same integers.
 
 Parity: pinned by tests/test_oracle_tree.py (tree invariants, coverage of
 every within-cutoff pair exactly once by P2P or by M2L against the brute-force
-neighbour counts, list symmetry, empty M2L list for theta = 0).
+neighbour counts, list symmetry, empty M2L list for theta = 0; with the
+centre cut, every within-cutoff pair covered exactly once by P2P, M2L or a
+dropped accepted pair, each accepted pair on the right side of r_cut).
 """
 
 from __future__ import annotations
@@ -172,8 +178,12 @@ def _sq3(v):
 
 
 def dual_walk(tree: Tree, box: float, r_cut: float, theta: float,
-              far_field: bool) -> Lists:
-    """Dual traversal of Sec. 3 with the readings of the module docstring."""
+              far_field: bool, centre_cut: bool = False,
+              dropped: list | None = None) -> Lists:
+    """Dual traversal of Sec. 3 with the readings of the module docstring.
+
+    With ``dropped`` (a list) and ``centre_cut``, the accepted pairs the
+    centre cut drops are appended to it as (t, u, s) rows."""
     c = tree.centre
     hs = tree.half
     rad = tree.radius
@@ -196,14 +206,23 @@ def dual_walk(tree: Tree, box: float, r_cut: float, theta: float,
         gap = np.maximum(A - H, 0.0)
         keep = _sq3(gap) < rc2_drop
         t, u, s, A, H, R = t[keep], u[keep], s[keep], A[keep], H[keep], R[keep]
+        gone = np.zeros(t.size, bool)
         if use_m2l:
             dmax = A + H
             lhs = rad[t] + rad[u]
-            m2l = (_sq3(dmax) < rc2_m2l) & (lhs * lhs < th2 * _sq3(R))
+            mac = lhs * lhs < th2 * _sq3(R)
+            if centre_cut:
+                inside = _sq3(R) < rc2
+                m2l = mac & inside
+                gone = mac & ~inside
+                if dropped is not None:
+                    dropped.append(np.stack([t[gone], u[gone], s[gone]], axis=1))
+            else:
+                m2l = (_sq3(dmax) < rc2_m2l) & mac
         else:
             m2l = np.zeros(t.size, bool)
         m2l_out.append(np.stack([t[m2l], u[m2l], s[m2l]], axis=1))
-        rest = ~m2l
+        rest = ~m2l & ~gone
         t, u, s = t[rest], u[rest], s[rest]
         lt, lu = leaf[t], leaf[u]
         both = lt & lu

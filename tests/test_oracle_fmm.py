@@ -177,3 +177,41 @@ def test_fmm_gradient_approaches_brute_force():
     # with their 1/r^3 terms, set the largest entries of it)
     assert np.max(np.linalg.norm(fx, axis=1)) > 1e-3 * np.median(np.linalg.norm(ref_x, axis=1))
     assert np.max(np.abs(fm)) > 1e-3 * np.median(np.abs(ref_m))
+
+
+def test_centre_cut_fmm_converges_to_its_cell_pair_sum():
+    """With the literal (centre-distance) cut an M2L task stands for every
+    particle pair of its two cells with the untruncated kernel psi_s, and
+    an accepted pair beyond r_cut for none: the FMM converges in p to that
+    sum, which differs from the truncated pair sum when clumps sit about
+    r_cut apart."""
+    rng = np.random.default_rng(9)
+    a = 20.0 + 0.4 * rng.standard_normal((300, 3))
+    b = 20.0 + np.array([4.3, 0.0, 0.0]) + 0.4 * rng.standard_normal((300, 3))
+    pos = np.concatenate([a, b])
+    m = np.full(600, 1.0 / 600)
+    box, r_s, r_cut = 50.0, 1.0, 4.5
+    sv = T.shift_vectors() * box
+    errs = []
+    for p in (1, 3, 5):
+        acc, near, far, tree, lists = fmm.fmm_forces(
+            pos, m, box, r_s, r_cut, 16, p, 0.35, return_parts=True,
+            centre_cut=True)
+        assert len(lists.m2l) > 0
+        ref = near.copy()
+        for t, u, s in lists.m2l:
+            ia = tree.perm[tree.first[t]:tree.first[t] + tree.count[t]]
+            ib = tree.perm[tree.first[u]:tree.first[u] + tree.count[u]]
+            d = (pos[ib][None, :, :] - pos[ia][:, None, :]) + sv[s]
+            r = np.linalg.norm(d, axis=-1)
+            g = m[ib][None, :] * tr.T_of_r(r, r_s) / r ** 3
+            ref[ia] += np.einsum("ij,ijk->ik", g, d)
+        errs.append(metrics.error_summary(acc, ref)["median"])
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 5e-6
+    plain = fmm.fmm_forces(pos, m, box, r_s, r_cut, 16, 5, 0.35)
+    brute, _ = direct.all_pairs(pos, m, box, r_s, r_cut)
+    # the default cut converges to the truncated pair sum, the centre cut
+    # does not (pairs across r_cut inside accepted cell pairs)
+    assert metrics.error_summary(plain, brute)["median"] < 1e-6
+    assert metrics.error_summary(acc, brute)["median"] > 10 * errs[2]

@@ -133,3 +133,61 @@ def test_far_field_off_gives_no_m2l(clustered):
     k = lists.p2p
     order = np.lexsort((k[:, 2], k[:, 1], k[:, 0]))
     assert np.array_equal(order, np.arange(len(k)))
+
+
+def _pairs_within(w, tr, rows, leaf_ids):
+    """Original-index pairs inside the cutoff of the particle pairs of the
+    given (t, u, s) rows (leaf ids for P2P rows, cell ids otherwise)."""
+    pos = w.pos
+    rc2 = w.r_cut * w.r_cut
+    sv = T.shift_vectors() * w.box
+    out = []
+    for t, u, s in rows:
+        if leaf_ids:
+            a = tr.perm[tr.leaf_first[t]:tr.leaf_first[t] + tr.leaf_count[t]]
+            b = tr.perm[tr.leaf_first[u]:tr.leaf_first[u] + tr.leaf_count[u]]
+        else:
+            a = tr.perm[tr.first[t]:tr.first[t] + tr.count[t]]
+            b = tr.perm[tr.first[u]:tr.first[u] + tr.count[u]]
+        d = (pos[b][None, :, :] - pos[a][:, None, :]) + sv[s]
+        r2 = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+        ii, jj = np.nonzero((r2 > 0) & (r2 < rc2))
+        out.append(np.stack([a[ii], b[jj]], 1))
+    return np.concatenate(out) if out else np.zeros((0, 2), int)
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.6])
+def test_centre_cut_covers_every_pair_once(clustered, theta):
+    """The literal reading: accepted pairs go to M2L by centre distance or
+    are dropped; every particle pair inside the cutoff is then in exactly
+    one P2P task, M2L task or dropped pair."""
+    w = clustered
+    tr = T.build_orb(w.pos, 16)
+    dropped = []
+    lists = T.dual_walk(tr, w.box, w.r_cut, theta, True, centre_cut=True,
+                        dropped=dropped)
+    dropped = np.concatenate(dropped) if dropped else np.zeros((0, 3), int)
+    assert len(lists.m2l) > 0 and len(dropped) > 0
+    c, rad = tr.centre, tr.radius
+    sv = T.shift_vectors() * w.box
+    rc2 = w.r_cut * w.r_cut
+    for rows, inside in ((lists.m2l, True), (dropped, False)):
+        t, u, s = rows[:, 0], rows[:, 1], rows[:, 2]
+        R = (c[u] - c[t]) + sv[s]
+        R2 = (R[:, 0] * R[:, 0] + R[:, 1] * R[:, 1]) + R[:, 2] * R[:, 2]
+        lhs = rad[t] + rad[u]
+        assert np.all(lhs * lhs < theta * theta * R2)
+        assert np.all((R2 < rc2) == inside)
+    allp = np.concatenate([_pairs_within(w, tr, lists.p2p, True),
+                           _pairs_within(w, tr, lists.m2l, False),
+                           _pairs_within(w, tr, dropped, False)])
+    n = len(w.pos)
+    key = allp[:, 0] * n + allp[:, 1]
+    assert len(np.unique(key)) == len(key), "a pair is covered twice"
+    _, cnt = direct.brute_force(w.pos, w.mass, w.box, w.r_s, w.r_cut,
+                                workers=1)
+    assert np.array_equal(np.bincount(allp[:, 0], minlength=n), cnt)
+    # the default reading on the same tree sends none of these to M2L
+    # without the whole pair inside the cutoff
+    plain = T.dual_walk(tr, w.box, w.r_cut, theta, True)
+    assert len(plain.m2l) != len(lists.m2l) or not np.array_equal(plain.m2l, lists.m2l)

@@ -58,6 +58,15 @@ enum { PMFMM_FP64 = 0, PMFMM_FP32 = 1 };
  * table_level interpolating T(r) / r^3 at Chebyshev nodes; zero beyond
  * r_cut.  It needs one r_cut / r_s for all boxes of a plan. */
 enum { PMFMM_TRUNC_EXACT = 0, PMFMM_TRUNC_TABLE = 1, PMFMM_TRUNC_R2 = 2 };
+/* M2L acceptance against the cutoff (Sec. 2 truncates the kernel at
+ * r_cut; where a cell pair straddles r_cut the paper does not say).
+ * INSIDE: a MAC-accepted cell pair goes to M2L only when the whole pair
+ * lies inside r_cut (|(|R| + h_t + h_u)|^2 < r_cut^2 (1 - 2^-40)), else it
+ * is refined, down to per-pair truncated P2P, so the FMM converges to the
+ * truncated pair sum.  CENTRE: the literal reading, the kernel derivatives
+ * f_(n)(|R|) are zero beyond r_cut by centre distance: a MAC-accepted cell
+ * pair goes to M2L when |R|^2 < r_cut^2 and is dropped otherwise. */
+enum { PMFMM_M2L_INSIDE = 0, PMFMM_M2L_CENTRE = 1 };
 /* Table node choice for x: nearest node or the node below x. */
 enum { PMFMM_ROUND_NEAREST = 0, PMFMM_ROUND_FLOOR = 1 };
 
@@ -71,6 +80,7 @@ typedef struct pmfmm_params {
                             (r_A + r_B) < theta |R|; 0 turns the far field off  */
     int32_t max_leaf;    /* MAXLEAF of the ORB tree, 1..64                        */
     int32_t order;       /* expansion order p, 0..6; < 0 turns the far field off  */
+    int32_t m2l_cut;     /* PMFMM_M2L_INSIDE (default) or PMFMM_M2L_CENTRE         */
     /* evaluation of the pair force (Sec. 3.3) */
     int32_t precision;   /* PMFMM_FP64 or PMFMM_FP32                              */
     int32_t trunc;       /* PMFMM_TRUNC_EXACT, _TABLE or _R2 (FP32 only)           */
@@ -93,7 +103,8 @@ typedef struct pmfmm_params {
 typedef struct pmfmm_ctx pmfmm_ctx;
 
 /* Fill *p with defaults: box 100, r_s 3.75, r_cut 4.5 r_s, G 1, theta 0,
- * max_leaf 64, order 4, FP64, exact T, 2048-node table, level 4, nearest. */
+ * max_leaf 64, order 4, M2L inside the cutoff, FP64, exact T, 2048-node
+ * table, level 4, nearest. */
 void pmfmm_params_init(pmfmm_params* p);
 
 /* Validate and copy *p into a new context.  *out receives the context, to be

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libpmfmm.so")
 PMFMM_FP64, PMFMM_FP32 = 0, 1
 TRUNC_EXACT, TRUNC_TABLE, TRUNC_R2 = 0, 1, 2
 ROUND_NEAREST, ROUND_FLOOR = 0, 1
+M2L_INSIDE, M2L_CENTRE = 0, 1
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE",
           -5: "EUNSUPPORTED"}
@@ -36,7 +37,7 @@ class Params(C.Structure):
         ("box", C.c_double), ("r_s", C.c_double), ("r_cut", C.c_double),
         ("G", C.c_double), ("theta", C.c_double),
         ("max_leaf", C.c_int32), ("order", C.c_int32),
-        ("precision", C.c_int32), ("trunc", C.c_int32),
+        ("m2l_cut", C.c_int32), ("precision", C.c_int32), ("trunc", C.c_int32),
         ("table_size", C.c_int32), ("table_level", C.c_int32),
         ("table_round", C.c_int32), ("chunk", C.c_int32),
         ("wg_waves", C.c_int32), ("grid_wgs", C.c_int32),

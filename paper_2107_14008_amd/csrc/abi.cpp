@@ -48,6 +48,10 @@ bool valid_geometry(const pmfmm_params& p, std::string& why) {
     }
     if (p.max_leaf < 1 || p.max_leaf > 64) { why = "max_leaf must be in 1..64"; return false; }
     if (p.order > 6) { why = "order must be <= 6 (negative turns the far field off)"; return false; }
+    if (p.m2l_cut != PMFMM_M2L_INSIDE && p.m2l_cut != PMFMM_M2L_CENTRE) {
+        why = "m2l_cut must be PMFMM_M2L_INSIDE or PMFMM_M2L_CENTRE";
+        return false;
+    }
     return true;
 }
 
@@ -285,7 +289,7 @@ struct pmfmm_ctx {
 namespace {
 
 std::vector<pmfmm::BoxParams> one_box(const pmfmm_params& p) {
-    return {pmfmm::BoxParams{p.box, p.r_s, p.r_cut, p.G, p.theta, p.max_leaf, p.order}};
+    return {pmfmm::BoxParams{p.box, p.r_s, p.r_cut, p.G, p.theta, p.max_leaf, p.order, p.m2l_cut}};
 }
 
 int do_plan(pmfmm_ctx* ctx, const std::vector<pmfmm::BoxParams>& boxes,
@@ -334,7 +338,8 @@ int check_box_params(int32_t nbox, const pmfmm_params* per_box, const int64_t* c
                                           ": the r^2 table needs one r_cut / r_s for all boxes");
         if (counts[b] < 1) return fail(PMFMM_EINVAL, "box " + std::to_string(b) + ": needs at least one particle");
         const pmfmm_params& q = per_box[b];
-        boxes.push_back(pmfmm::BoxParams{q.box, q.r_s, q.r_cut, q.G, q.theta, q.max_leaf, q.order});
+        boxes.push_back(
+            pmfmm::BoxParams{q.box, q.r_s, q.r_cut, q.G, q.theta, q.max_leaf, q.order, q.m2l_cut});
         cnt.push_back(counts[b]);
     }
     return PMFMM_OK;
@@ -598,7 +603,8 @@ bool same_boxes(const std::vector<pmfmm::BoxParams>& a, const std::vector<pmfmm:
     if (a.size() != b.size()) return false;
     for (size_t k = 0; k < a.size(); ++k)
         if (a[k].box != b[k].box || a[k].r_s != b[k].r_s || a[k].r_cut != b[k].r_cut || a[k].G != b[k].G ||
-            a[k].theta != b[k].theta || a[k].max_leaf != b[k].max_leaf || a[k].order != b[k].order)
+            a[k].theta != b[k].theta || a[k].max_leaf != b[k].max_leaf || a[k].order != b[k].order ||
+            a[k].m2l_cut != b[k].m2l_cut)
             return false;
     return true;
 }
@@ -739,6 +745,7 @@ void pmfmm_params_init(pmfmm_params* p) {
     p->r_cut = 4.5 * 3.75;
     p->G = 1.0;
     p->theta = 0.0;
+    p->m2l_cut = PMFMM_M2L_INSIDE;
     p->max_leaf = 64;
     p->order = 4;
     p->precision = PMFMM_FP64;

@@ -36,8 +36,8 @@ constexpr double kGuard = 0x1p-40;
 
 struct WalkBox {
     double L, rc2_drop, rc2_m2l, th2;
-    int32_t use_m2l, pad0;
-    double pad1;
+    int32_t use_m2l, centre_cut;   // centre_cut: M2L by centre distance, else drop
+    double rc2;
 };
 
 __device__ __forceinline__ double wrap_coord(double x, double L) {
@@ -646,7 +646,20 @@ __device__ __forceinline__ void walk_classify(const int2 pr, const WalkBox* __re
     }
     if (!(gap2 < wb.rc2_drop)) return;
     const bool self = (t == u) && (s == 13);
-    if (wb.use_m2l && dmax2 < wb.rc2_m2l && lhs < R2) {
+    if (wb.use_m2l && wb.centre_cut && lhs < R2) {
+        // centre-distance cut: R2 holds theta^2 |R|^2, so recompute |R|^2
+        double Rc2;
+        {
+#pragma clang fp contract(off)
+            Rc2 = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2];
+        }
+        if (!(Rc2 < wb.rc2)) return;
+        o.n_m2l = self ? 1 : 2;
+        o.key[0] = walk_key(t, u, s, ks.y);
+        o.key[1] = walk_key(u, t, 26 - s, ks.y);
+        return;
+    }
+    if (wb.use_m2l && !wb.centre_cut && dmax2 < wb.rc2_m2l && lhs < R2) {
         o.n_m2l = self ? 1 : 2;
         o.key[0] = walk_key(t, u, s, ks.y);
         o.key[1] = walk_key(u, t, 26 - s, ks.y);
@@ -1102,8 +1115,8 @@ hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, h
         wb[b].rc2_m2l = rc2 * (1.0 - kGuard);
         wb[b].th2 = p.theta * p.theta;
         wb[b].use_m2l = (p.order >= 0 && p.theta > 0.0) ? 1 : 0;
-        wb[b].pad0 = 0;
-        wb[b].pad1 = 0.0;
+        wb[b].centre_cut = p.m2l_cut == 1 ? 1 : 0;
+        wb[b].rc2 = rc2;
     }
     std::vector<int32_t> bfc(topo.box_first_cell.begin(), topo.box_first_cell.end());
     d.walk_levels = 0;      // a new shape: size the walk level by level once

@@ -12,7 +12,9 @@
 // (rad_t + rad_u)^2 < theta^2 |R|^2, recorded as P2P when both cells are
 // leaves, and refined otherwise by splitting the cell of larger radius
 // (both on a tie).  The guards keep every rounding error on the safe side
-// of the per-pair cutoff test done in the kernels.
+// of the per-pair cutoff test done in the kernels.  With the centre-distance
+// cut (m2l_cut = 1) a pair passing the opening-angle test goes to M2L when
+// |R|^2 < r_cut^2 and is dropped otherwise.
 #include "plan.h"
 
 #include <algorithm>
@@ -143,8 +145,8 @@ struct WalkGeom {
     const Cell* cells;
     struct BoxW {
         double sv[27][3];
-        double rc2_drop, rc2_m2l, th2;
-        bool use_m2l;
+        double rc2_drop, rc2_m2l, th2, rc2;
+        bool use_m2l, centre_cut;
     };
     std::vector<BoxW> bw;
 };
@@ -173,7 +175,11 @@ inline void walk_step(const WalkGeom& g, const PairT& p, std::vector<uint64_t>& 
         const double dmax2 = (dm[0] * dm[0] + dm[1] * dm[1]) + dm[2] * dm[2];
         const double R2 = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2];
         const double lhs = rt + ru;
-        if (dmax2 < b.rc2_m2l && lhs * lhs < b.th2 * R2) {
+        const bool mac = lhs * lhs < b.th2 * R2;
+        if (b.centre_cut ? mac : (mac && dmax2 < b.rc2_m2l)) {
+            // the centre-distance reading drops an accepted pair at or
+            // beyond r_cut (its kernel derivatives are zero there)
+            if (b.centre_cut && !(R2 < b.rc2)) return;
             m2l.push_back(((uint64_t)(uint32_t)p.t << 32) |
                           ((uint64_t)(uint32_t)p.u << 5) | (uint64_t)p.s);
             return;
@@ -382,7 +388,9 @@ std::string make_plan(Plan& plan, const std::vector<BoxParams>& boxes,
         w.rc2_drop = rc2 * (1.0 + kGuard);
         w.rc2_m2l = rc2 * (1.0 - kGuard);
         w.th2 = bp.theta * bp.theta;
+        w.rc2 = rc2;
         w.use_m2l = bp.order >= 0 && bp.theta > 0.0;
+        w.centre_cut = bp.m2l_cut == 1;
         if (w.use_m2l) plan.max_order = std::max<int>(plan.max_order, bp.order);
         const int32_t root = plan.box_first_cell[b];
         for (int s = 0; s < 27; ++s) frontier.push_back({root, root, s, b});

@@ -16,6 +16,7 @@ namespace pmfmm {
 struct BoxParams {
     double box, r_s, r_cut, G, theta;
     int32_t max_leaf, order;
+    int32_t m2l_cut;   // 0: M2L only for pairs wholly inside r_cut; 1: by centre distance
 };
 
 struct Cell {

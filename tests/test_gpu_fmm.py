@@ -42,6 +42,25 @@ def test_fmm_matches_oracle_fmm(halo, order, theta):
     assert metrics.error_summary(acc, ref)["max"] <= 1e-12
 
 
+@pytest.mark.parametrize("planner", [0, 1])
+def test_centre_cut_matches_oracle(halo, planner):
+    """The literal (centre-distance) M2L cut, GPU or host planner: the same
+    lists as the oracle's walk and the same forces as its FMM."""
+    w = halo
+    print(f"case: fmm centre cut, planner {planner}", flush=True)
+    acc, ctx = gpu(w, 4, 0.6, 16, m2l_cut=B.M2L_CENTRE, planner=planner)
+    L = ctx.lists()
+    ref, near, far, tree, lists = fmm.fmm_forces(
+        w.pos, w.mass, w.box, w.r_s, w.r_cut, 16, 4, 0.6, return_parts=True,
+        centre_cut=True)
+    assert len(lists.m2l) > 0
+    assert np.array_equal(L["m2l_row"], lists.m2l_row)
+    assert np.array_equal(L["m2l_src"], lists.m2l[:, 1])
+    assert np.array_equal(L["m2l_shift"], lists.m2l[:, 2])
+    assert np.array_equal(L["p2p_j"], lists.p2p[:, 1])
+    assert metrics.error_summary(acc, ref)["max"] <= 1e-12
+
+
 def test_fmm_accuracy_vs_brute_force(halo):
     w = halo
     ref, _ = direct.brute_force(w.pos, w.mass, w.box, w.r_s, w.r_cut)

@@ -29,6 +29,17 @@ def test_uniform_32k():
     assert_same(L, tree, lists)
 
 
+@pytest.mark.parametrize("theta", [0.3, 0.6])
+def test_clustered_centre_cut(theta):
+    w = inputs.clustered_small(20, 41, halo_frac=0.4, n_halos=5, max_leaf=24)
+    print(f"case: gpu plan centre cut theta {theta}", flush=True)
+    L, _ = gpu_lists(w.pos, w.mass, w.box, w.r_s, w.r_cut, 24, 4, theta,
+                     m2l_cut=B.M2L_CENTRE)
+    tree, lists = oracle_lists(w.pos, w.box, w.r_cut, 24, 4, theta, True)
+    assert len(lists.m2l) > 0
+    assert_same(L, tree, lists)
+
+
 @pytest.mark.parametrize("theta", [0.25, 0.5])
 def test_clustered_with_far_field(theta):
     w = inputs.clustered_small(20, 41, halo_frac=0.4, n_halos=5, max_leaf=24)

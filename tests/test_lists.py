@@ -10,9 +10,10 @@ from paper_2107_14008_amd import binding as B
 from paper_2107_14008_amd import inputs
 
 
-def host_lists(pos, mass, box, r_s, r_cut, max_leaf, order, theta, threads=0):
+def host_lists(pos, mass, box, r_s, r_cut, max_leaf, order, theta, threads=0,
+               m2l_cut=B.M2L_INSIDE):
     ctx = B.Context(box=box, r_s=r_s, r_cut=r_cut, max_leaf=max_leaf,
-                    order=order, theta=theta, threads=threads)
+                    order=order, theta=theta, threads=threads, m2l_cut=m2l_cut)
     ctx.plan(pos, mass)
     return ctx.lists()
 
@@ -37,9 +38,9 @@ def assert_same(L, tree, lists):
     assert L["candidate_pairs"] == T.candidate_pairs(tree, lists)
 
 
-def oracle_lists(pos, box, r_cut, max_leaf, order, theta):
+def oracle_lists(pos, box, r_cut, max_leaf, order, theta, centre_cut=False):
     tree = T.build_orb(pos, max_leaf)
-    lists = T.dual_walk(tree, box, r_cut, theta, order >= 0)
+    lists = T.dual_walk(tree, box, r_cut, theta, order >= 0, centre_cut)
     return tree, lists
 
 
@@ -50,6 +51,17 @@ def test_uniform_32k_p2p_only():
     assert len(lists.m2l) == 0
     assert_same(L, tree, lists)
     assert L["n_leaves"] == 1024 and np.all(L["leaf_count"] == 32)
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.6])
+def test_clustered_centre_cut(theta):
+    """The literal (centre-distance) M2L cut: same lists as the oracle."""
+    w = inputs.clustered_small(20, 41, halo_frac=0.4, n_halos=5, max_leaf=24)
+    L = host_lists(w.pos, w.mass, w.box, w.r_s, w.r_cut, 24, 4, theta,
+                   m2l_cut=B.M2L_CENTRE)
+    tree, lists = oracle_lists(w.pos, w.box, w.r_cut, 24, 4, theta, True)
+    assert len(lists.m2l) > 0
+    assert_same(L, tree, lists)
 
 
 @pytest.mark.parametrize("theta", [0.25, 0.5])

@@ -64,7 +64,7 @@ struct DevPlan {
     DevBuf p2p_row, wpos, keys, keys_tmp, plist, plist_tmp, hist, flag, lv_first, tile_sums;
     DevBuf pc, pc_tmp, clo, chi, wcell, box_first, walkbox, front, front_next, p2p_keys,
         p2p_keys_tmp, m2l_keys, m2l_keys_tmp, wcount, cost, cost_keys, cost_keys_tmp, queue_tmp,
-        item_count, cell_axis, farflag, walk_ctl, froots, cell_split, loop_cells, m2l_vals, rowcnt,
+        item_count, cell_axis, farflag, walk_ctl, froots, loop_cells, m2l_vals, rowcnt,
         longrows;
     // cells the level loop partitions, by depth (loop_cells holds them);
     // n_froots subtrees finished in one launch (0: the loop does every level)
@@ -84,7 +84,7 @@ struct DevPlan {
                           &box_first, &walkbox, &front, &front_next, &p2p_keys, &p2p_keys_tmp,
                           &m2l_keys, &m2l_keys_tmp, &wcount, &cost, &cost_keys, &cost_keys_tmp,
                           &queue_tmp, &item_count, &cell_axis, &farflag, &walk_ctl, &froots,
-                          &cell_split, &loop_cells, &m2l_vals, &rowcnt, &longrows})
+                          &loop_cells, &m2l_vals, &rowcnt, &longrows})
             b->release();
     }
 };

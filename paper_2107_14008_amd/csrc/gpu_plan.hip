@@ -191,18 +191,18 @@ __global__ void k_cells_level(const int32_t* __restrict__ level, int nd, const i
     }
 }
 
-// split[c] = 1 for the cells the level loop partitions.
-// Marks are bytes indexed by particle: the level's random reads of them then
-// stay in L2.
+// Left marks of the particles of the cells splitting at this level (sax[c]
+// >= 0), from their positions in the split axis's list.  Marks are bytes
+// indexed by particle: the level's random reads of them then stay in L2.
 __global__ void k_flag(int64_t n, const int32_t* __restrict__ pc, const int4* __restrict__ cell,
-                       const int32_t* __restrict__ split, const int32_t* __restrict__ axis,
-                       const uint32_t* __restrict__ plist, uint8_t* __restrict__ flag) {
+                       const int32_t* __restrict__ sax, const uint32_t* __restrict__ plist,
+                       uint8_t* __restrict__ flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int c = pc[i];
-    if (!split[c]) return;
+    const int ax = sax[c];
+    if (ax < 0) return;
     const int4 ci = cell[c];
-    const int ax = axis[c];
     flag[plist[ax * n + i]] = (i - ci.x < ci.y / 2) ? 1 : 0;
 }
 
@@ -218,24 +218,36 @@ constexpr int kLvThreads = 256;
 constexpr int kLvRounds = 16;
 constexpr int kLvTile = kLvThreads * kLvRounds;   // 4096
 
+// sax[c]: the split axis of a cell that splits at this level, else -1.  On
+// the split axis's own list the mark follows from the position alone, so
+// only the two other lists read the particle's byte.
 __device__ __forceinline__ uint32_t level_mark(int64_t q, int64_t n, const int32_t* __restrict__ pc,
-                                               const int32_t* __restrict__ split,
+                                               const int32_t* __restrict__ sax,
+                                               const int4* __restrict__ cell,
                                                const uint32_t* __restrict__ plist,
                                                const uint8_t* __restrict__ flag) {
-    const int64_t i = q >= n ? (q >= 2 * n ? q - 2 * n : q - n) : q;
-    return split[pc[i]] ? (uint32_t)flag[plist[q]] : 0u;
+    const int a = q >= n ? (q >= 2 * n ? 2 : 1) : 0;
+    const int64_t i = q - (int64_t)a * n;
+    const int c = pc[i];
+    const int ax = sax[c];
+    if (ax < 0) return 0u;
+    if (ax == a) {
+        const int4 ci = cell[c];
+        return (i - ci.x < ci.y / 2) ? 1u : 0u;
+    }
+    return (uint32_t)flag[plist[q]];
 }
 
 __global__ void __launch_bounds__(kLvThreads)
-k_level_sums(int64_t n, const int32_t* __restrict__ pc, const int32_t* __restrict__ split,
-             const uint32_t* __restrict__ plist, const uint8_t* __restrict__ flag,
-             uint32_t* __restrict__ tile_sums) {
+k_level_sums(int64_t n, const int32_t* __restrict__ pc, const int32_t* __restrict__ sax,
+             const int4* __restrict__ cell, const uint32_t* __restrict__ plist,
+             const uint8_t* __restrict__ flag, uint32_t* __restrict__ tile_sums) {
     __shared__ uint32_t wsum[kLvThreads / 64];
     const int64_t base = (int64_t)blockIdx.x * kLvTile;
     uint32_t c = 0;
     for (int r = 0; r < kLvRounds; ++r) {
         const int64_t q = base + r * kLvThreads + threadIdx.x;
-        if (q < 3 * n) c += level_mark(q, n, pc, split, plist, flag);
+        if (q < 3 * n) c += level_mark(q, n, pc, sax, cell, plist, flag);
     }
     for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
@@ -251,7 +263,7 @@ k_level_sums(int64_t n, const int32_t* __restrict__ pc, const int32_t* __restric
 // prefix of the marks at the cell's first position of that list.
 __global__ void __launch_bounds__(256)
 k_level_firsts(const int32_t* __restrict__ level, int nd, int64_t n, const int4* __restrict__ cell,
-               const int32_t* __restrict__ pc, const int32_t* __restrict__ split,
+               const int32_t* __restrict__ pc, const int32_t* __restrict__ sax,
                const uint32_t* __restrict__ plist, const uint8_t* __restrict__ flag,
                const uint32_t* __restrict__ tile_off, int nc, int32_t* __restrict__ pfirst) {
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -262,7 +274,7 @@ k_level_firsts(const int32_t* __restrict__ level, int nd, int64_t n, const int4*
     const int64_t qf = (int64_t)a * n + cell[c].x;
     const int64_t t0 = qf / kLvTile * kLvTile;
     uint32_t cnt = 0;
-    for (int64_t q = t0 + lane; q < qf; q += 64) cnt += level_mark(q, n, pc, split, plist, flag);
+    for (int64_t q = t0 + lane; q < qf; q += 64) cnt += level_mark(q, n, pc, sax, cell, plist, flag);
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off);
     if (lane == 0) pfirst[(size_t)a * nc + c] = (int32_t)(tile_off[qf / kLvTile] + cnt);
 }
@@ -270,7 +282,7 @@ k_level_firsts(const int32_t* __restrict__ level, int nd, int64_t n, const int4*
 __global__ void __launch_bounds__(kLvThreads)
 k_level_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __restrict__ pc_out,
              const int4* __restrict__ cell, const int4* __restrict__ aux,
-             const int32_t* __restrict__ split, const uint32_t* __restrict__ plist,
+             const int32_t* __restrict__ sax, const uint32_t* __restrict__ plist,
              uint32_t* __restrict__ pout, const uint8_t* __restrict__ flag,
              const uint32_t* __restrict__ tile_off, int nc, const int32_t* __restrict__ pfirst) {
     __shared__ uint8_t mk[kLvTile];
@@ -286,10 +298,9 @@ k_level_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __restrict__ pc
         pv[r] = 0u;
         cv[r] = -1;
         if (q < 3 * n) {
-            const int64_t i = q >= n ? (q >= 2 * n ? q - 2 * n : q - n) : q;
             pv[r] = plist[q];
-            cv[r] = pc[i];
-            f = split[cv[r]] ? flag[pv[r]] : (uint8_t)0;
+            cv[r] = pc[q >= n ? (q >= 2 * n ? q - 2 * n : q - n) : q];
+            f = (uint8_t)level_mark(q, n, pc, sax, cell, plist, flag);
         }
         mk[r * kLvThreads + t] = f;
     }
@@ -319,7 +330,7 @@ k_level_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __restrict__ pc
         const int a = q >= n ? (q >= 2 * n ? 2 : 1) : 0;
         const int64_t i = q - (int64_t)a * n;
         const int c = cv[r];
-        if (!split[c]) {
+        if (sax[c] < 0) {
             pout[q] = pv[r];
             if (a == 0) pc_out[i] = c;
             continue;
@@ -1160,6 +1171,7 @@ hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, h
         loop_begin.push_back((int32_t)loop_cells.size());
     }
     d.n_froots = (int)(roots.size() / 4);
+    const std::vector<int32_t> sax0(nc, -1);
     d.loop_depth_begin = loop_begin;
     hipError_t e;
     if ((e = up(d.cell, cell, s)) != hipSuccess) return e;
@@ -1167,7 +1179,9 @@ hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, h
     if ((e = up(d.leaf, leaf, s)) != hipSuccess) return e;
     if ((e = up(d.level_cells, topo.cells_by_depth, s)) != hipSuccess) return e;
     if ((e = up(d.loop_cells, loop_cells, s)) != hipSuccess) return e;
-    if ((e = up(d.cell_split, split, s)) != hipSuccess) return e;
+    // split axis per cell: -1 except for the level loop's cells, whose axis
+    // k_cells_level writes at their level of every build
+    if ((e = up(d.cell_axis, sax0, s)) != hipSuccess) return e;
     if ((e = up(d.froots, roots, s)) != hipSuccess) return e;
     if ((e = up(d.box_first, topo.box_first_particle, s)) != hipSuccess) return e;
     if ((e = up(d.walkbox, wb, s)) != hipSuccess) return e;
@@ -1271,21 +1285,21 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                            d.clo.as<double>(), d.chi.as<double>(), d.cell_axis.as<int32_t>());
         TRY(hipGetLastError());
         hipLaunchKernelGGL(k_flag, dim3(grid_of(n)), dim3(256), 0, s, n, d.pc.as<int32_t>(),
-                           d.cell.as<int4>(), d.cell_split.as<int32_t>(), d.cell_axis.as<int32_t>(),
-                           d.plist.as<uint32_t>(), d.flag.as<uint8_t>());
+                           d.cell.as<int4>(), d.cell_axis.as<int32_t>(), d.plist.as<uint32_t>(),
+                           d.flag.as<uint8_t>());
         hipLaunchKernelGGL(k_level_sums, dim3(lv_tiles), dim3(kLvThreads), 0, s, n,
-                           d.pc.as<int32_t>(), d.cell_split.as<int32_t>(), d.plist.as<uint32_t>(),
-                           d.flag.as<uint8_t>(), d.tile_sums.as<uint32_t>());
+                           d.pc.as<int32_t>(), d.cell_axis.as<int32_t>(), d.cell.as<int4>(),
+                           d.plist.as<uint32_t>(), d.flag.as<uint8_t>(), d.tile_sums.as<uint32_t>());
         TRY(hipGetLastError());
         TRY(exclusive_scan_u32_one_block(d.tile_sums.as<uint32_t>(), lv_tiles, s));
         hipLaunchKernelGGL(k_level_firsts, dim3((3 * ncd + 3) / 4), dim3(256), 0, s,
                            d.loop_cells.as<int32_t>() + c0, ncd, n, d.cell.as<int4>(),
-                           d.pc.as<int32_t>(), d.cell_split.as<int32_t>(), d.plist.as<uint32_t>(),
+                           d.pc.as<int32_t>(), d.cell_axis.as<int32_t>(), d.plist.as<uint32_t>(),
                            d.flag.as<uint8_t>(), d.tile_sums.as<uint32_t>(), (int)nc,
                            d.lv_first.as<int32_t>());
         hipLaunchKernelGGL(k_level_move, dim3(lv_tiles), dim3(kLvThreads), 0, s, n,
                            d.pc.as<int32_t>(), d.pc_tmp.as<int32_t>(), d.cell.as<int4>(),
-                           d.cell_aux.as<int4>(), d.cell_split.as<int32_t>(), d.plist.as<uint32_t>(),
+                           d.cell_aux.as<int4>(), d.cell_axis.as<int32_t>(), d.plist.as<uint32_t>(),
                            d.plist_tmp.as<uint32_t>(), d.flag.as<uint8_t>(),
                            d.tile_sums.as<uint32_t>(), (int)nc, d.lv_first.as<int32_t>());
         TRY(hipGetLastError());

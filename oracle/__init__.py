@@ -16,6 +16,9 @@ Every function is a plain, slow restatement of the paper (Wang & Meng,
     P2P and M2L task lists (Sec. 3), with the readings in its docstring;
   * ``fmm``        - the truncated FMM of Sec. 2 on those lists
     (P2M, M2M, M2L, L2L, L2P plus P2P);
+  * ``pm``         - the long-range part of the split on a mesh (CIC, FFT,
+    Gaussian-filtered Green's function) and a periodic Ewald sum that the
+    short + long total is checked against;
   * ``metrics``    - relative force error percentiles.
 
 Parity status of each function is stated in its module docstring.

@@ -221,6 +221,36 @@ def secondary(args):
                             "p2p_ms": float(np.mean(fw)),
                             "adjoint_ms": float(np.mean(ad))})
         return line
+    if args.config == "pm128":
+        # the long-range mesh part of the split (outside the short-range hot
+        # path): 128^3 clustered particles on a 128^3 mesh
+        w = inputs.clustered_2m()
+        stream = torch.cuda.current_stream(dev)
+        n = len(w.mass)
+        pos = torch.tensor(w.pos, device=dev)
+        mass = torch.tensor(w.mass, device=dev)
+        out = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        ctx = B.Context(box=w.box, r_s=w.r_s, r_cut=w.r_cut)
+        n_pm = 128
+        for _ in range(args.warmup):
+            ctx.long_range(n_pm, pos, mass, out, stream)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            ctx.long_range(n_pm, pos, mass, out, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        line.update(metric="long-range mesh force: particles/s", unit="particles/s",
+                    dtype="f64", value=n / (ms / 1e3), ms_per_step=ms,
+                    config={"workload": "pm128: clustered_2m particles (2,097,152) on a "
+                            "128^3 mesh, CIC, exp(-k^2 r_s^2)/k^2, spectral gradient",
+                            "n": n, "n_pm": n_pm,
+                            "event_ms_per_call": ev0.elapsed_time(ev1) / args.steps})
+        return line
     if args.config == "uniform_32k":
         w = inputs.uniform_32k()
         forms = {"fp64_exact": dict(precision=B.PMFMM_FP64, trunc=B.TRUNC_EXACT),
@@ -295,7 +325,7 @@ def main():
                     help="time the headline float32 form only (profiling)")
     ap.add_argument("--config", default="clustered_2m",
                     choices=["clustered_2m", "clustered_16m", "batch64",
-                             "adjoint262k", "uniform_32k"],
+                             "adjoint262k", "uniform_32k", "pm128"],
                     help="clustered_2m is the headline; the others are "
                          "secondary measurements of the other workloads")
     ap.add_argument("--calib-copy-mb", type=int, default=0,

@@ -182,6 +182,23 @@ int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream);
 int pmfmm_adjoint(pmfmm_ctx* ctx, const double* w, double* grad_pos,
                   double* grad_mass, void* stream);
 
+/* Long-range accelerations of the force split (Sec. 2; not the short-range
+ * hot path): the Newtonian force minus the short-range pair force of
+ * Eq. (tr), on a periodic mesh of n_pm^3 nodes at g L / n_pm.  Cloud in cell
+ * assignment; phi(k) = -4 pi G rho(k) exp(-k^2 r_s^2) / k^2 divided by the
+ * squared CIC window prod_a sinc^2(k_a L / 2 n_pm) (the transform of
+ * erf(r / 2 r_s) / r; k = 0 dropped, the mean density subtracted);
+ * a(k) = -i k phi(k) with each Nyquist component zeroed; cloud in cell
+ * interpolation.  Uses the context's box, r_s and G (one box; no build
+ * needed).  pos (n, 3), mass (n), acc (n, 3): device float64, caller
+ * order; acc is overwritten.  Enqueued on `stream`; the mesh and the FFT
+ * plans (hipFFT) are allocated on the first call for a given n_pm and kept.
+ * The deposit adds with float64 atomics: results agree run to run to
+ * rounding, not bit for bit.  Errors: EINVAL (n_pm odd or outside
+ * [4, 1024], n < 0), EDEVICE. */
+int pmfmm_long_range(pmfmm_ctx* ctx, int32_t n_pm, int64_t n, const double* pos,
+                     const double* mass, double* acc, void* stream);
+
 /* Host views of the plan, valid until the next plan/build or destroy.
  * Particle and leaf indices are global over the batch; `perm[k]` is the
  * caller index of the particle stored k-th (leaf order). */

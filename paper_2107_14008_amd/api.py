@@ -80,6 +80,16 @@ class ShortRange:
         return self.ctx.timings()
 
 
+def long_range_accel(pos: torch.Tensor, mass: torch.Tensor, n_pm: int, **params):
+    """Accelerations (n, 3) float64 of the long-range (mesh) part of the
+    split, on an n_pm^3 mesh; uses params box, r_s and G."""
+    ctx = B.Context(**_params(params))
+    out = torch.empty((pos.shape[0], 3), dtype=torch.float64, device=pos.device)
+    ctx.long_range(n_pm, pos.contiguous(), mass.contiguous(), out,
+                   torch.cuda.current_stream(pos.device))
+    return out
+
+
 def short_range_accel(pos: torch.Tensor, mass: torch.Tensor, **params):
     """Accelerations (n, 3) float64 of the truncated short-range force."""
     return ShortRange(**params).build(pos, mass).forward()

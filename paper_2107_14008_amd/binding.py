@@ -96,6 +96,8 @@ SIGNATURES = {
     "pmfmm_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pmfmm_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.c_void_p]),
+    "pmfmm_long_range": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p]),
     "pmfmm_get_lists": (C.c_int, [C.c_void_p, C.POINTER(Lists)]),
     "pmfmm_get_timings": (C.c_int, [C.c_void_p, C.POINTER(Timings)]),
     "pmfmm_version": (C.c_char_p, []),
@@ -242,6 +244,12 @@ class Context:
         _check(library().pmfmm_adjoint(self._h, _ptr(w), _ptr(grad_pos),
                                        _ptr(grad_mass), _stream(stream)))
         return grad_pos, grad_mass
+
+    def long_range(self, n_pm, pos, mass, out, stream=None):
+        """Long-range (mesh) accelerations into out (n, 3), caller order."""
+        _check(library().pmfmm_long_range(self._h, int(n_pm), int(pos.shape[0]), _ptr(pos),
+                                          _ptr(mass), _ptr(out), _stream(stream)))
+        return out
 
     # ---- introspection
     def lists(self) -> dict:

@@ -36,6 +36,7 @@ SOURCES = [
     ("adjoint.hip", "hip"),
     ("gpu_sort.hip", "hip"),
     ("gpu_plan.hip", "hip"),
+    ("pm.hip", "hip"),
 ]
 
 
@@ -71,7 +72,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         list(ex.map(lambda t: _run(t[0], verbose), todo))
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp,
-          *[o for _, o in todo], "-lpthread"], verbose)
+          *[o for _, o in todo], "-L/opt/rocm/lib", "-lhipfft", "-lpthread"], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -14,6 +14,7 @@
 #include "device.h"
 #include "gpu_plan.h"
 #include "plan.h"
+#include "pm.h"
 
 namespace {
 
@@ -274,6 +275,8 @@ struct pmfmm_ctx {
     // timing
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     bool timed_fwd = false, timed_adj = false;
+    // long-range mesh of pmfmm_long_range
+    pmfmm::PMPlan pm;
 
     ~pmfmm_ctx() {
         if (device >= 0) {
@@ -281,6 +284,7 @@ struct pmfmm_ctx {
             (void)hipDeviceSynchronize();
         }
         d.release_all();
+        pmfmm::pm_release(pm);
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
     }
@@ -934,6 +938,19 @@ int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream) {
         HIP_TRY(hipEventRecord(ctx->ev[3], s));
         ctx->timed_fwd = true;
     }
+    return PMFMM_OK;
+}
+
+int pmfmm_long_range(pmfmm_ctx* ctx, int32_t n_pm, int64_t n, const double* pos, const double* mass,
+                     double* acc, void* stream) {
+    if (!ctx || !pos || !mass || !acc) return fail(PMFMM_EINVAL, "null argument");
+    if (n < 0) return fail(PMFMM_EINVAL, "n must be >= 0");
+    if (n_pm < 4 || n_pm > 1024 || (n_pm % 2) != 0)
+        return fail(PMFMM_EINVAL, "n_pm must be even and in [4, 1024]");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipGetDevice(&ctx->device));
+    HIP_TRY(pmfmm::pm_plan(ctx->pm, n_pm, s));
+    HIP_TRY(pmfmm::pm_long_range(ctx->pm, pos, mass, n, ctx->p.box, ctx->p.r_s, ctx->p.G, acc, s));
     return PMFMM_OK;
 }
 

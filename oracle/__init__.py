@@ -19,6 +19,8 @@ Every function is a plain, slow restatement of the paper (Wang & Meng,
   * ``pm``         - the long-range part of the split on a mesh (CIC, FFT,
     Gaussian-filtered Green's function) and a periodic Ewald sum that the
     short + long total is checked against;
+  * ``stepping``   - a kick-drift-kick leapfrog with the split force and the
+    power spectrum of the paper's precision comparison;
   * ``metrics``    - relative force error percentiles.
 
 Parity status of each function is stated in its module docstring.

@@ -199,6 +199,17 @@ int pmfmm_adjoint(pmfmm_ctx* ctx, const double* w, double* grad_pos,
 int pmfmm_long_range(pmfmm_ctx* ctx, int32_t n_pm, int64_t n, const double* pos,
                      const double* mass, double* acc, void* stream);
 
+/* Time stepping around the force (the paper's runs of Sec. 4 take time
+ * steps without naming the integrator; a kick-drift-kick leapfrog is the
+ * reading here; not the short-range hot path).  pmfmm_kick:
+ * vel += acc dt; pmfmm_drift: pos += vel dt, then wrapped into [0, box).
+ * pos, vel, acc: device (n, 3) float64, caller order; enqueued on `stream`.
+ * One KDK step of length dt is kick(dt / 2) with a(t), drift(dt), a new
+ * force, kick(dt / 2).  Errors: EINVAL (null, n < 0, dt not finite,
+ * box <= 0), EDEVICE. */
+int pmfmm_kick(int64_t n, double* vel, const double* acc, double dt, void* stream);
+int pmfmm_drift(int64_t n, double* pos, const double* vel, double dt, double box, void* stream);
+
 /* Host views of the plan, valid until the next plan/build or destroy.
  * Particle and leaf indices are global over the batch; `perm[k]` is the
  * caller index of the particle stored k-th (leaf order). */

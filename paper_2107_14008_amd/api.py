@@ -90,6 +90,40 @@ def long_range_accel(pos: torch.Tensor, mass: torch.Tensor, n_pm: int, **params)
     return out
 
 
+class Simulation:
+    """Kick-drift-kick leapfrog of one periodic box on the GPU: the
+    short-range force of this library (the tree rebuilt every step) plus,
+    with n_pm, the long-range mesh force; kicks and drifts are the library's
+    kernels.  pos, vel: CUDA float64 (n, 3), updated in place."""
+
+    def __init__(self, pos: torch.Tensor, vel: torch.Tensor, mass: torch.Tensor,
+                 n_pm: int | None = None, **params):
+        self.pos, self.vel = pos, vel
+        self.mass = mass.detach().to(torch.float64).contiguous()
+        self.n_pm = n_pm
+        self.box = float(params.get("box", 100.0))
+        self.sr = ShortRange(**params)
+        self.acc = torch.empty_like(pos)
+        self.long = torch.empty_like(pos) if n_pm else None
+        self.stream = torch.cuda.current_stream(pos.device)
+        self._force()
+
+    def _force(self):
+        self.sr.build(self.pos, self.mass)
+        self.sr.forward(self.acc)
+        if self.n_pm:
+            self.sr.ctx.long_range(self.n_pm, self.pos, self.mass, self.long, self.stream)
+            self.acc += self.long
+
+    def step(self, dt: float, steps: int = 1):
+        for _ in range(steps):
+            B.kick(self.vel, self.acc, 0.5 * dt, self.stream)
+            B.drift(self.pos, self.vel, dt, self.box, self.stream)
+            self._force()
+            B.kick(self.vel, self.acc, 0.5 * dt, self.stream)
+        return self.pos, self.vel
+
+
 def short_range_accel(pos: torch.Tensor, mass: torch.Tensor, **params):
     """Accelerations (n, 3) float64 of the truncated short-range force."""
     return ShortRange(**params).build(pos, mass).forward()

@@ -98,6 +98,9 @@ SIGNATURES = {
                                 C.c_void_p, C.c_void_p]),
     "pmfmm_long_range": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p,
                                    C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pmfmm_kick": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
+    "pmfmm_drift": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
+                              C.c_void_p]),
     "pmfmm_get_lists": (C.c_int, [C.c_void_p, C.POINTER(Lists)]),
     "pmfmm_get_timings": (C.c_int, [C.c_void_p, C.POINTER(Timings)]),
     "pmfmm_version": (C.c_char_p, []),
@@ -166,6 +169,17 @@ def _stream(stream):
 def _host_f64(a, shape_last=None):
     a = np.ascontiguousarray(a, dtype=np.float64)
     return a
+
+
+def kick(vel, acc, dt, stream=None):
+    """vel += acc dt (device (n, 3) float64)."""
+    _check(library().pmfmm_kick(int(vel.shape[0]), _ptr(vel), _ptr(acc), float(dt), _stream(stream)))
+
+
+def drift(pos, vel, dt, box, stream=None):
+    """pos += vel dt, wrapped into [0, box) (device (n, 3) float64)."""
+    _check(library().pmfmm_drift(int(pos.shape[0]), _ptr(pos), _ptr(vel), float(dt), float(box),
+                                 _stream(stream)))
 
 
 class Context:

@@ -37,6 +37,7 @@ SOURCES = [
     ("gpu_sort.hip", "hip"),
     ("gpu_plan.hip", "hip"),
     ("pm.hip", "hip"),
+    ("step.hip", "hip"),
 ]
 
 

@@ -941,6 +941,21 @@ int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream) {
     return PMFMM_OK;
 }
 
+int pmfmm_kick(int64_t n, double* vel, const double* acc, double dt, void* stream) {
+    if (!vel || !acc) return fail(PMFMM_EINVAL, "null argument");
+    if (n < 0 || !std::isfinite(dt)) return fail(PMFMM_EINVAL, "n must be >= 0 and dt finite");
+    HIP_TRY(pmfmm::launch_kick(n, vel, acc, dt, static_cast<hipStream_t>(stream)));
+    return PMFMM_OK;
+}
+
+int pmfmm_drift(int64_t n, double* pos, const double* vel, double dt, double box, void* stream) {
+    if (!pos || !vel) return fail(PMFMM_EINVAL, "null argument");
+    if (n < 0 || !std::isfinite(dt) || !(box > 0.0))
+        return fail(PMFMM_EINVAL, "n must be >= 0, dt finite and box > 0");
+    HIP_TRY(pmfmm::launch_drift(n, pos, vel, dt, box, static_cast<hipStream_t>(stream)));
+    return PMFMM_OK;
+}
+
 int pmfmm_long_range(pmfmm_ctx* ctx, int32_t n_pm, int64_t n, const double* pos, const double* mass,
                      double* acc, void* stream) {
     if (!ctx || !pos || !mass || !acc) return fail(PMFMM_EINVAL, "null argument");

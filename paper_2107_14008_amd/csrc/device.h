@@ -163,6 +163,11 @@ hipError_t launch_adjoint(int mode, const AdjArgs& a, int wg_waves, int grid_wgs
                           size_t lds_bytes, hipStream_t s);
 hipError_t launch_adj_reduce(const AdjReduceArgs& a, hipStream_t s);
 
+// Kick (vel += acc dt) and drift (pos += vel dt, wrapped into [0, L)) of
+// n particles, (n, 3) float64 device arrays (step.hip).
+hipError_t launch_kick(int64_t n, double* vel, const double* acc, double dt, hipStream_t s);
+hipError_t launch_drift(int64_t n, double* pos, const double* vel, double dt, double L, hipStream_t s);
+
 // Far field (far.hip).
 hipError_t launch_p2m(const FarArgs& a, hipStream_t s);
 hipError_t launch_m2m_level(const FarArgs& a, hipStream_t s);

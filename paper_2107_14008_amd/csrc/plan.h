@@ -73,10 +73,13 @@ void make_topology(Plan& plan, const std::vector<BoxParams>& boxes,
                    const std::vector<int64_t>& counts);
 
 // Tasks per work item when the caller leaves the choice to the library: an
-// item then holds at most 16 x 64 x 64 pair evaluations, a few percent of a
+// item then holds at most 32 x 64 x 64 pair evaluations, a small part of a
 // wavefront's share of a large launch, so the longest-first queue ends with
-// little idle time (measured best at 128^3 for all float32 forms).
-constexpr int kAutoChunk = 16;
+// little idle time, while the per-item partial sums (1.5 KB each, read by
+// the ordered reduction) stay few (measured at 128^3 and 256^3: 16 to 48
+// tasks give the same P2P time within 1 %, 8 is 20 % slower, whole rows
+// leave a tail).
+constexpr int kAutoChunk = 32;
 
 // (Re)cuts the P2P rows into work items of at most `chunk` tasks
 // (0 = automatic) and orders the queue by decreasing pair count.

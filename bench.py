@@ -49,6 +49,9 @@ FLOPS_PER_PAIR_F64_EXACT = 27
 # table coordinate 2, index and offset 2, T_[4] Horner 8, m T / r^3 4,
 # accumulation 6.
 FLOPS_PER_PAIR_F64_TABLE = 31
+# float64 r^2 table (degree 6): displacement 3 (+3 shift), r^2 5, s = r^2
+# sigma^2 1, t = s - s_k 1, degree-6 Horner 12, g = m F 1, accumulation 6.
+FLOPS_PER_PAIR_F64_R2 = 29
 PAPER_OPS_PER_PAIR = 51
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
@@ -382,10 +385,13 @@ def main():
         "fp64_table": dict(precision=B.PMFMM_FP64, trunc=B.TRUNC_TABLE,
                            table_size=2048, table_level=4,
                            table_round=B.ROUND_NEAREST),
+        "fp64_r2": dict(precision=B.PMFMM_FP64, trunc=B.TRUNC_R2,
+                        table_size=64, table_level=6),
     }
     if args.skip_fp64:
         forms.pop("fp64")
         forms.pop("fp64_table")
+        forms.pop("fp64_r2")
     if args.headline_only:
         forms = {"fp32": forms["fp32"]}
     results = {}
@@ -456,6 +462,8 @@ def main():
                                      f"table of Eq. (int)",
             "fp64_form": "float64 pairs, exact erfc/exp",
             "fp64_table_form": "float64 pairs, 2048-node T_[4] table of Eq. (int)",
+            "fp64_r2_form": "float64 pairs, T(r)/r^3 from degree-6 segments over r^2 "
+                            "(64 per octave), pairs below r_cut/256 exact",
         },
         "roofline": {
             "bound": "alu",
@@ -502,6 +510,15 @@ def main():
             "p2p_tflops": cand * FLOPS_PER_PAIR_F64_TABLE / (r64t["p2p_ms"] / 1e3) / 1e12,
             "frac_of_fp64_peak": cand * FLOPS_PER_PAIR_F64_TABLE
             / (r64t["p2p_ms"] / 1e3) / 1e12 / PEAK_FP64_TFLOPS,
+        }
+    if "fp64_r2" in results:
+        r = results["fp64_r2"]
+        line["fp64_r2"] = {
+            "value": cand / (r["ms_per_step"] / 1e3),
+            "ms_per_step": r["ms_per_step"],
+            "p2p_tflops": cand * FLOPS_PER_PAIR_F64_R2 / (r["p2p_ms"] / 1e3) / 1e12,
+            "frac_of_fp64_peak": cand * FLOPS_PER_PAIR_F64_R2
+            / (r["p2p_ms"] / 1e3) / 1e12 / PEAK_FP64_TFLOPS,
         }
     print(json.dumps(line), flush=True)
 

@@ -51,12 +51,15 @@ typedef enum pmfmm_status {
 /* Arithmetic of the pair force (Sec. 4 compares single and double). */
 enum { PMFMM_FP64 = 0, PMFMM_FP32 = 1 };
 /* Truncation factor T: library erfc/exp, the Taylor table of Eq. (int), or
- * (float32 only) a table of the whole radial factor T(r) / r^3 over
- * polynomial segments in r^2 (not in the paper): r^2 is scaled so that
- * r_cut^2 = 2^11, and each octave of the scaled r^2 in [2^-35, 2^11) is cut
- * into table_size equal segments, each holding the polynomial of degree
- * table_level interpolating T(r) / r^3 at Chebyshev nodes; zero beyond
- * r_cut.  It needs one r_cut / r_s for all boxes of a plan. */
+ * a table of the whole radial factor T(r) / r^3 over polynomial segments
+ * in r^2 (not in the paper): r^2 is scaled so that r_cut^2 = 2^11, and each
+ * octave of the scaled r^2 is cut into table_size equal segments, each
+ * holding the polynomial of degree table_level that approximates
+ * T(r) / r^3 on it (Chebyshev interpolation); zero beyond r_cut.  Float32
+ * covers the octaves [2^-35, 2^11) with degree 1 or 2; float64 covers
+ * [2^-5, 2^11) with degree 4 to 6 and takes pairs closer than that (below
+ * r_cut / 256) through the library erfc/exp.  It needs one r_cut / r_s for
+ * all boxes of a plan. */
 enum { PMFMM_TRUNC_EXACT = 0, PMFMM_TRUNC_TABLE = 1, PMFMM_TRUNC_R2 = 2 };
 /* M2L acceptance against the cutoff (Sec. 2 truncates the kernel at
  * r_cut; where a cell pair straddles r_cut the paper does not say).
@@ -83,13 +86,13 @@ typedef struct pmfmm_params {
     int32_t m2l_cut;     /* PMFMM_M2L_INSIDE (default) or PMFMM_M2L_CENTRE         */
     /* evaluation of the pair force (Sec. 3.3) */
     int32_t precision;   /* PMFMM_FP64 or PMFMM_FP32                              */
-    int32_t trunc;       /* PMFMM_TRUNC_EXACT, _TABLE or _R2 (FP32 only)           */
+    int32_t trunc;       /* PMFMM_TRUNC_EXACT, _TABLE or _R2                       */
     int32_t table_size;  /* TABLE: nodes on x in [0, 3], 16..2048 (FP64) or
                             16..4096 (FP32); R2: segments per octave of r^2,
-                            16, 32, 64 or 128                                    */
+                            16, 32, 64 or 128 (FP32), 16, 32 or 64 (FP64)      */
     int32_t table_level; /* TABLE: Taylor terms kept, 0..4 (T_[0] .. T_[4]);
-                            R2: polynomial degree, 2 (or 1 with >= 64
-                            segments per octave)                                 */
+                            R2: polynomial degree, FP32 2 (or 1 with >= 64
+                            segments per octave), FP64 4, 5 or 6             */
     int32_t table_round; /* TABLE: PMFMM_ROUND_NEAREST or PMFMM_ROUND_FLOOR       */
     /* scheduling of the P2P work (no effect on results) */
     int32_t chunk;       /* j-leaves per work item, 0 = automatic                 */

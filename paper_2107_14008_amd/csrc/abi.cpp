@@ -62,8 +62,7 @@ bool valid_eval(const pmfmm_params& p, std::string& why) {
         why = "trunc must be EXACT, TABLE or R2";
         return false;
     }
-    if (p.trunc == PMFMM_TRUNC_R2) {
-        if (p.precision != PMFMM_FP32) { why = "the r^2 table is a float32 form"; return false; }
+    if (p.trunc == PMFMM_TRUNC_R2 && p.precision == PMFMM_FP32) {
         if (p.table_size != 16 && p.table_size != 32 && p.table_size != 64 && p.table_size != 128) {
             why = "table_size (segments per octave) must be 16, 32, 64 or 128 for R2";
             return false;
@@ -73,13 +72,24 @@ bool valid_eval(const pmfmm_params& p, std::string& why) {
             return false;
         }
     }
-    if (p.table_level < 0 || p.table_level > 4) { why = "table_level must be in 0..4"; return false; }
-    if (p.table_round != PMFMM_ROUND_NEAREST && p.table_round != PMFMM_ROUND_FLOOR) { why = "table_round must be NEAREST or FLOOR"; return false; }
-    const int max_tab = p.precision == PMFMM_FP64 ? 2048 : 4096;
-    if (p.table_size < 16 || p.table_size > max_tab) {
-        why = "table_size must be in 16.." + std::to_string(max_tab);
-        return false;
+    if (p.trunc == PMFMM_TRUNC_R2 && p.precision == PMFMM_FP64) {
+        if (p.table_size != 16 && p.table_size != 32 && p.table_size != 64) {
+            why = "table_size (segments per octave) must be 16, 32 or 64 for the float64 R2 table";
+            return false;
+        }
+        if (p.table_level < 4 || p.table_level > 6) {
+            why = "table_level (degree) must be 4, 5 or 6 for the float64 R2 table";
+            return false;
+        }
+    } else {
+        if (p.table_level < 0 || p.table_level > 4) { why = "table_level must be in 0..4"; return false; }
+        const int max_tab = p.precision == PMFMM_FP64 ? 2048 : 4096;
+        if (p.table_size < 16 || p.table_size > max_tab) {
+            why = "table_size must be in 16.." + std::to_string(max_tab);
+            return false;
+        }
     }
+    if (p.table_round != PMFMM_ROUND_NEAREST && p.table_round != PMFMM_ROUND_FLOOR) { why = "table_round must be NEAREST or FLOOR"; return false; }
     if (p.chunk < 0) { why = "chunk must be >= 0"; return false; }
     if (p.wg_waves < 0 || p.wg_waves > 16) { why = "wg_waves must be in 0..16"; return false; }
     if (p.grid_wgs < 0) { why = "grid_wgs must be >= 0"; return false; }
@@ -88,12 +98,17 @@ bool valid_eval(const pmfmm_params& p, std::string& why) {
 }
 
 int mode_of(const pmfmm_params& p) {
-    if (p.precision == PMFMM_FP64) return p.trunc == PMFMM_TRUNC_TABLE ? pmfmm::kFP64Table : pmfmm::kFP64Exact;
+    if (p.precision == PMFMM_FP64) {
+        if (p.trunc == PMFMM_TRUNC_R2) return pmfmm::kFP64R2;
+        return p.trunc == PMFMM_TRUNC_TABLE ? pmfmm::kFP64Table : pmfmm::kFP64Exact;
+    }
     if (p.trunc == PMFMM_TRUNC_R2) return pmfmm::kFP32R2;
     return p.trunc == PMFMM_TRUNC_TABLE ? pmfmm::kFP32Table : pmfmm::kFP32Exact;
 }
 
 bool uses_r2(const pmfmm_params& p) { return p.precision == PMFMM_FP32 && p.trunc == PMFMM_TRUNC_R2; }
+// Either r^2 table: one x_c = r_cut / 2 r_s for all boxes, rebuilt when it changes.
+bool r2_table(const pmfmm_params& p) { return p.trunc == PMFMM_TRUNC_R2; }
 
 // x_c = r_cut / 2 r_s, which the r^2 table needs to be one for all boxes
 // (up to rounding: r_cut = 4.5 r_s over many r_s gives x_c within an ulp).
@@ -169,8 +184,64 @@ std::vector<unsigned char> build_r2_table(int per_octave, int deg, double xc) {
     return out;
 }
 
+// Table of the float64 r^2 form: the same F(s) = T(x) s^(-3/2) on rows
+// (e - kR2Emin64) 2^bits + j covering s in 2^e [1 + j / 2^bits, 1 + (j + 1) / 2^bits)
+// for kR2Emin64 <= e < kR2Emax, each the polynomial of degree `deg`
+// interpolating F at the segment's Chebyshev nodes, stored as its
+// coefficients in t = s - (segment start) (the kernel evaluates it there;
+// expanding about the start keeps the float64 evaluation free of
+// cancellation).  Nodes are computed in long double; the segment width is a
+// power of two, so the change of variable from [0, 1] is exact.
+std::vector<unsigned char> build_r2_table64(int per_octave, int deg, double xc) {
+    const int bits = per_octave == 16 ? 4 : per_octave == 32 ? 5 : 6;
+    const int octaves = pmfmm::kR2Emax - pmfmm::kR2Emin64;
+    const int rows = octaves << bits, m = deg + 1;
+    const long double kappa = (long double)xc * xc / std::ldexp(1.0L, pmfmm::kR2Emax);
+    std::vector<unsigned char> out((size_t)8 * m * rows + 16, 0);
+    double* f = reinterpret_cast<double*>(out.data());
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int k = 0; k < rows; ++k) {
+        const int e = pmfmm::kR2Emin64 + (k >> bits), j = k & ((1 << bits) - 1);
+        const long double lo = std::ldexp(1.0L + (long double)j / per_octave, e);
+        const long double w = std::ldexp(1.0L, e - bits);
+        long double V[7][8];
+        for (int i = 0; i < m; ++i) {
+            const long double t = 0.5L - 0.5L * std::cos(pi * (i + 0.5L) / m);   // in [0, 1]
+            const long double sv = lo + w * t;
+            long double tp = 1.0L;
+            for (int q = 0; q < m; ++q) {
+                V[i][q] = tp;
+                tp *= t;
+            }
+            const long double x = std::sqrt(sv * kappa);
+            const long double T = std::erfc(x) + 1.128379167095512573896158903121545172L * x * std::exp(-x * x);
+            V[i][m] = T / (sv * std::sqrt(sv));
+        }
+        for (int c = 0; c < m; ++c) {
+            int piv = c;
+            for (int r = c + 1; r < m; ++r)
+                if (std::fabs(V[r][c]) > std::fabs(V[piv][c])) piv = r;
+            for (int q = 0; q <= m; ++q) std::swap(V[c][q], V[piv][q]);
+            for (int r = c + 1; r < m; ++r) {
+                const long double g = V[r][c] / V[c][c];
+                for (int q = c; q <= m; ++q) V[r][q] -= g * V[c][q];
+            }
+        }
+        long double cl[7] = {0, 0, 0, 0, 0, 0, 0};
+        for (int c = m - 1; c >= 0; --c) {
+            long double acc = V[c][m];
+            for (int q = c + 1; q < m; ++q) acc -= V[c][q] * cl[q];
+            cl[c] = acc / V[c][c];
+        }
+        // p(t) = sum_q cl_q t^q with t = (s - lo) / w: coefficient of (s - lo)^q is cl_q / w^q
+        for (int q = 0; q < m; ++q) f[(size_t)m * k + q] = (double)std::ldexp(cl[q], -q * (e - bits));
+    }
+    return out;
+}
+
 std::vector<unsigned char> build_table(const pmfmm_params& p, double xc) {
     if (uses_r2(p)) return build_r2_table(p.table_size, p.table_level, xc);
+    if (r2_table(p)) return build_r2_table64(p.table_size, p.table_level, xc);
     const int n = p.table_size;
     const double h = 3.0 / n;
     const double inv_sqrt_pi = 0.56418958354775628695;
@@ -337,7 +408,7 @@ int check_box_params(int32_t nbox, const pmfmm_params* per_box, const int64_t* c
         if (!valid_geometry(per_box[b], why)) return fail(PMFMM_EINVAL, "box " + std::to_string(b) + ": " + why);
         if (eval.trunc == PMFMM_TRUNC_TABLE && per_box[b].r_cut / (2.0 * per_box[b].r_s) > 3.0)
             return fail(PMFMM_EINVAL, "box " + std::to_string(b) + ": the table covers r <= 6 r_s only");
-        if (uses_r2(eval) && !same_xc(per_box[b].r_cut, per_box[b].r_s, per_box[0].r_cut, per_box[0].r_s))
+        if (r2_table(eval) && !same_xc(per_box[b].r_cut, per_box[b].r_s, per_box[0].r_cut, per_box[0].r_s))
             return fail(PMFMM_EINVAL, "box " + std::to_string(b) +
                                           ": the r^2 table needs one r_cut / r_s for all boxes");
         if (counts[b] < 1) return fail(PMFMM_EINVAL, "box " + std::to_string(b) + ": needs at least one particle");
@@ -379,7 +450,7 @@ int upload_items(pmfmm_ctx* ctx, hipStream_t s) {
 int upload_table(pmfmm_ctx* ctx, hipStream_t s) {
     const double xc = ctx->plan.boxes.empty() ? ctx->p.r_cut / (2.0 * ctx->p.r_s)
                                               : ctx->plan.boxes[0].r_cut / (2.0 * ctx->plan.boxes[0].r_s);
-    if (!ctx->table_dirty && (!uses_r2(ctx->p) || xc == ctx->table_xc)) return PMFMM_OK;
+    if (!ctx->table_dirty && (!r2_table(ctx->p) || xc == ctx->table_xc)) return PMFMM_OK;
     ctx->table_xc = xc;
     ctx->table_host = build_table(ctx->p, xc);
     int rc = upload(ctx->d.table, ctx->table_host, s);
@@ -507,7 +578,10 @@ int do_upload(pmfmm_ctx* ctx, const double* pos, const double* mass, int32_t on_
 // Table forms: 16 waves share one LDS copy of the table (a 2048-segment r^2
 // table is 33 KB; with 4-wave groups LDS would cap a CU at 16 waves).
 int default_wg_waves(int mode) {
-    return (mode == pmfmm::kFP64Table || mode == pmfmm::kFP32Table || mode == pmfmm::kFP32R2) ? 16 : 4;
+    return (mode == pmfmm::kFP64Table || mode == pmfmm::kFP32Table || mode == pmfmm::kFP32R2 ||
+            mode == pmfmm::kFP64R2)
+               ? 16
+               : 4;
 }
 
 pmfmm::FarArgs far_args(pmfmm_ctx* ctx) {
@@ -842,7 +916,7 @@ int pmfmm_set_eval(pmfmm_ctx* ctx, const pmfmm_params* p) {
     if (p->trunc == PMFMM_TRUNC_TABLE && ctx->planned)
         for (const auto& b : ctx->plan.boxes)
             if (b.r_cut / (2.0 * b.r_s) > 3.0) return fail(PMFMM_EINVAL, "the table covers r <= 6 r_s only");
-    if (uses_r2(*p) && ctx->planned && !one_xc(ctx->plan.boxes))
+    if (r2_table(*p) && ctx->planned && !one_xc(ctx->plan.boxes))
         return fail(PMFMM_EINVAL, "the r^2 table needs one r_cut / r_s for all boxes");
     const bool table_change = p->precision != ctx->p.precision || p->table_size != ctx->p.table_size ||
                               p->table_round != ctx->p.table_round || p->table_level != ctx->p.table_level ||
@@ -923,7 +997,8 @@ int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream) {
     a.n_tab = ctx->p.table_size;
     a.level = ctx->p.table_level;
     a.round_floor = ctx->p.table_round == PMFMM_ROUND_FLOOR;
-    const bool tab = mode == pmfmm::kFP32Table || mode == pmfmm::kFP64Table || mode == pmfmm::kFP32R2;
+    const bool tab = mode == pmfmm::kFP32Table || mode == pmfmm::kFP64Table || mode == pmfmm::kFP32R2 ||
+                     mode == pmfmm::kFP64R2;
     const size_t lds = tab ? ctx->table_host.size() : 0;
     const int wg = ctx->p.wg_waves > 0 ? ctx->p.wg_waves : default_wg_waves(mode);
     int grid = ctx->p.grid_wgs;

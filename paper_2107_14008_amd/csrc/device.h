@@ -23,14 +23,20 @@ enum Mode : int {
     kFP64Table = 1,
     kFP32Exact = 2,
     kFP32Table = 3,
-    kFP32R2 = 4     // float32, segment table over r^2 (cutoff at the last row)
+    kFP32R2 = 4,    // float32, segment table over r^2 (cutoff at the last row)
+    kFP64R2 = 5     // float64, segment table over r^2 (closest pairs evaluated exactly)
 };
 
-constexpr bool is_fp32(int mode) { return mode >= kFP32Exact; }
+constexpr bool is_fp32(int mode) {
+    return mode == kFP32Exact || mode == kFP32Table || mode == kFP32R2;
+}
 
 // r^2 table form: scaled r^2 covers [2^kR2Emin, 2^kR2Emax) (r_cut^2 = 2^kR2Emax).
 constexpr int kR2Emin = -35;
 constexpr int kR2Emax = 11;
+// float64 r^2 table: scaled r^2 in [2^kR2Emin64, 2^kR2Emax); closer pairs
+// (r < 2^-8 r_cut) take the exact erfc / exp path.
+constexpr int kR2Emin64 = kR2Emax - 16;
 
 // Per-box constants.  The float32 forms work on offsets scaled by sigma
 // (x32 and the per-task centre offsets): sigma = 1, except for the r^2

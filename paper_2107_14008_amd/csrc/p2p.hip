@@ -215,7 +215,62 @@ __device__ __forceinline__ void pair_f32_r2(const float4 q, float px, float py, 
     az = fmaf(g, dz, az);
 }
 
+// float64 r^2 table (not the paper's table; host builder in abi.cpp): the
+// scaled radial factor F = T(r) / r^3 / sigma^3 of s = r^2 sigma^2, with
+// sigma^2 = 2^kR2Emax / r_cut^2, on segments of [2^kR2Emin64, 2^kR2Emax)
+// indexed by the high 32 bits of s (exponent and top `bits` mantissa bits);
+// each row holds the NC coefficients of the segment's polynomial in
+// t = s - s_k (s_k the segment start: the same high bits, zero below).  The
+// cutoff and r > 0 tests are the definition's, on r^2 itself; s is clamped
+// below 2^kR2Emax so that a pair inside the cutoff whose scaled s rounds up
+// stays on the last segment.  A pair closer than 2^(kR2Emin64 / 2) r_cut
+// (rare: r < 0.004 r_cut) takes the exact erfc / exp expression.  The item's
+// sums are multiplied by sigma^3 at the end.
+template <int NC, bool SHIFTED>
+__device__ __forceinline__ void pair_f64_r2(const double4 q, double xi, double yi, double zi,
+                                            double sx, double sy, double sz, double rc2,
+                                            double sig2, double smax, double smin, double alpha,
+                                            uint32_t hshift, uint32_t hbase, uint32_t hmask,
+                                            const double* __restrict__ tab, double& ax, double& ay,
+                                            double& az) {
+    double dx, dy, dz, r2;
+    {
+#pragma clang fp contract(off)
+        dx = q.x - xi;
+        dy = q.y - yi;
+        dz = q.z - zi;
+        if (SHIFTED) {
+            dx = dx + sx;
+            dy = dy + sy;
+            dz = dz + sz;
+        }
+        r2 = (dx * dx + dy * dy) + dz * dz;
+    }
+    const bool ok = (r2 > 0.0) & (r2 < rc2);
+    const double s = r2 * sig2;
+    double F;
+    if (__builtin_expect(ok && s < smin, 0)) {
+        const double r = sqrt(r2);
+        const double x = r * alpha;
+        const double T = erfc(x) + kTwoOverSqrtPi * x * exp(-x * x);
+        F = T / (s * sqrt(s));
+    } else {
+        const double sc = fmax(fmin(s, smax), smin);
+        const uint32_t hi = (uint32_t)__double2hiint(sc);
+        const double* __restrict__ c = tab + (size_t)((hi >> hshift) - hbase) * NC;
+        const double t = sc - __hiloint2double((int)(hi & hmask), 0);
+        F = c[NC - 1];
+#pragma unroll
+        for (int k = NC - 2; k >= 0; --k) F = fma(F, t, c[k]);
+    }
+    const double g = ok ? q.w * F : 0.0;
+    ax = fma(g, dx, ax);
+    ay = fma(g, dy, ay);
+    az = fma(g, dz, az);
+}
+
 // LDS table layouts (bytes), matching the host builder in abi.cpp:
+//   float64 r^2 table: double c0 .. c(NC-1) per row [16 2^bits rows]
 //   float32 r^2 table: float4 (c0, c1, c2, 0) [(kR2Emax - kR2Emin) 2^bits + 1]
 //   float32: float4 c0..c3 [n_tab + 1], then float c4 [n_tab + 1]
 //   float64: double2 (c0, c1) [n_tab], double2 (c2, c3) [n_tab], double c4 [n_tab]
@@ -237,7 +292,8 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
            const void* __restrict__ table, int32_t n_tab, int32_t table_bytes,
            int32_t round_floor) {
     extern __shared__ __align__(16) unsigned char lds[];
-    constexpr bool kTable = (MODE == kFP64Table) || (MODE == kFP32Table) || (MODE == kFP32R2);
+    constexpr bool kTable = (MODE == kFP64Table) || (MODE == kFP32Table) || (MODE == kFP32R2) ||
+                            (MODE == kFP64R2);
     if constexpr (kTable) load_table(lds, table, table_bytes);
     const int lane = threadIdx.x & 63;
     const int dmax = n_tab - 1;
@@ -310,6 +366,15 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
             const double2* t01 = reinterpret_cast<const double2*>(lds);
             const double2* t23 = reinterpret_cast<const double2*>(lds + 16 * n_tab);
             const double* t4 = reinterpret_cast<const double*>(lds + 32 * n_tab);
+            // float64 r^2 table: n_tab = segments per octave = 2^bits
+            const double* r2tab = reinterpret_cast<const double*>(lds);
+            const uint32_t hbits = 31u - (uint32_t)__builtin_clz((uint32_t)(n_tab > 0 ? n_tab : 1));
+            const uint32_t hshift = 20u - hbits;
+            const uint32_t hbase = (uint32_t)(1023 + kR2Emin64) << hbits;
+            const uint32_t hmask = ~((1u << hshift) - 1u);
+            const double sig2 = (double)(1 << kR2Emax) / rc2;
+            const double smax = 2048.0 * (1.0 - 0x1p-53);   // largest double below 2^kR2Emax
+            const double smin = 0x1p-5;                      // 2^kR2Emin64
             for (int t = t0; t < t1; ++t) {
                 const int js = uni(p2p_js[t]);
                 const int jl = js >> 5;
@@ -324,6 +389,10 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                         if constexpr (MODE == kFP64Exact)
                             pair_f64_exact<false>(src[k], pv.x, pv.y, pv.z, 0.0, 0.0, 0.0, rc2,
                                                   bx.alpha, ax, ay, az);
+                        else if constexpr (MODE == kFP64R2)
+                            pair_f64_r2<LEVEL + 1, false>(src[k], pv.x, pv.y, pv.z, 0.0, 0.0, 0.0,
+                                                          rc2, sig2, smax, smin, bx.alpha, hshift,
+                                                          hbase, hmask, r2tab, ax, ay, az);
                         else
                             pair_f64_table<LEVEL, false>(src[k], pv.x, pv.y, pv.z, 0.0, 0.0, 0.0,
                                                          rc2, bx.tab_scale, rnd, dmax, t01, t23,
@@ -334,12 +403,22 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                         if constexpr (MODE == kFP64Exact)
                             pair_f64_exact<true>(src[k], pv.x, pv.y, pv.z, sx, sy, sz, rc2,
                                                  bx.alpha, ax, ay, az);
+                        else if constexpr (MODE == kFP64R2)
+                            pair_f64_r2<LEVEL + 1, true>(src[k], pv.x, pv.y, pv.z, sx, sy, sz, rc2,
+                                                         sig2, smax, smin, bx.alpha, hshift, hbase,
+                                                         hmask, r2tab, ax, ay, az);
                         else
                             pair_f64_table<LEVEL, true>(src[k], pv.x, pv.y, pv.z, sx, sy, sz, rc2,
                                                         bx.tab_scale, rnd, dmax, t01, t23, t4, ax,
                                                         ay, az);
                     }
                 }
+            }
+            if constexpr (MODE == kFP64R2) {
+                const double sig3 = sig2 * sqrt(sig2);
+                ax *= sig3;
+                ay *= sig3;
+                az *= sig3;
             }
         }
         double* dst = partial + (size_t)slot * 192;
@@ -468,6 +547,12 @@ hipError_t launch_p2p(int mode, const P2PArgs& a, int wg_waves, int grid_wgs, si
         case kFP32R2:
             if (a.level == 1) return launch_one<kFP32R2, 1>(a, wg_waves, grid_wgs, lds, s);
             return launch_one<kFP32R2, 2>(a, wg_waves, grid_wgs, lds, s);
+        case kFP64R2:
+            switch (a.level) {
+                case 4: return launch_one<kFP64R2, 4>(a, wg_waves, grid_wgs, lds, s);
+                case 5: return launch_one<kFP64R2, 5>(a, wg_waves, grid_wgs, lds, s);
+                default: return launch_one<kFP64R2, 6>(a, wg_waves, grid_wgs, lds, s);
+            }
         case kFP64Table:
             switch (a.level) {
                 case 0: return launch_one<kFP64Table, 0>(a, wg_waves, grid_wgs, lds, s);
@@ -486,6 +571,7 @@ int p2p_blocks_per_cu(int mode, int wg_waves, size_t lds) {
         case kFP32Exact: return occ_one<kFP32Exact, 0>(wg_waves, 0);
         case kFP32Table: return occ_one<kFP32Table, 2>(wg_waves, lds);
         case kFP32R2: return occ_one<kFP32R2, 2>(wg_waves, lds);
+        case kFP64R2: return occ_one<kFP64R2, 6>(wg_waves, lds);
         default: return occ_one<kFP64Table, 4>(wg_waves, lds);
     }
 }

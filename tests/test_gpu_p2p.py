@@ -4,6 +4,8 @@ Tolerances (relative force error e_i = |a_i - a_ref| / |a_ref|):
   * float64, exact T:          max e_i <= 1e-12
   * float64, 2048-node T_[4]:  max e_i <= 1e-12 against the oracle's table
                                sum, and <= 1e-11 against the exact sum
+  * float64, r^2 table:        99.9th percentile <= 1e-13 .. 1e-9 by degree
+                               and segments (the table's error), max <= 100x
   * float32 (any T form):      median <= 1e-5, 99.9th percentile <= 1e-4
 """
 
@@ -89,6 +91,44 @@ def test_fp64_table_level4(clustered):
                                     table=(2048, 4, "nearest"))
     assert metrics.error_summary(acc, ref_tab)["max"] <= 1e-12
     assert metrics.error_summary(acc, ref)["max"] <= 1e-11
+
+
+# float64 r^2 table: degree 4..6 polynomials of T(r) / r^3 over 16..64
+# segments per octave of r^2; pairs closer than 2^-8 r_cut exactly.  Against
+# the exact sum with the error measured on the sum of pair-term magnitudes
+# (the table's own error, ~1e-15 per pair at degree 6 and 64 segments per
+# octave, is stated separately; a particle whose net force nearly cancels
+# only resolves it to that error times the terms).
+@pytest.mark.parametrize("degree,per_octave,tol", [(6, 64, 1e-13), (5, 64, 1e-12),
+                                                   (6, 32, 1e-12), (4, 32, 1e-9)])
+def test_fp64_r2_table(clustered, degree, per_octave, tol):
+    w, ref = clustered
+    print(f"case: clustered 24^3, fp64 r^2 table {per_octave}/octave degree {degree}",
+          flush=True)
+    acc, _ = gpu_forward(w.pos, w.mass, w.box, w.r_s, w.r_cut, 64,
+                         precision=B.PMFMM_FP64, trunc=B.TRUNC_R2,
+                         table_size=per_octave, table_level=degree)
+    e = metrics.error_summary(acc, ref)
+    print("   relative errors", e, flush=True)
+    assert e["max"] <= 100 * tol, e
+    assert e["p999"] <= tol, e
+
+
+def test_fp64_r2_close_pairs_take_the_exact_path():
+    """Pairs at 1e-4 .. 1e-2 r_cut (below the table's range) and coincident
+    pairs, in float64 with the r^2 table, against the exact sum."""
+    rng = np.random.default_rng(17)
+    box = 20.0
+    r_s, r_cut = 0.6, 2.7
+    base = rng.uniform(0, box, (800, 3))
+    close = base[:200] + rng.normal(0, 1, (200, 3)) * rng.uniform(1e-4, 1e-2, (200, 1)) * r_cut
+    pos = inputs.wrap(np.concatenate([base, close, base[:5]]), box)
+    m = rng.uniform(0.5, 1.5, len(pos))
+    ref, _ = direct.brute_force(pos, m, box, r_s, r_cut)
+    acc, _ = gpu_forward(pos, m, box, r_s, r_cut, 16, precision=B.PMFMM_FP64,
+                         trunc=B.TRUNC_R2, table_size=64, table_level=6)
+    e = metrics.error_summary(acc, ref)
+    assert e["max"] <= 1e-11, e
 
 
 @pytest.mark.parametrize("level,n_tab,rnd", [(2, 512, B.ROUND_NEAREST),
@@ -253,6 +293,13 @@ def test_full_size_clustered_2m_sampled(c2):
     print("case: clustered 128^3 fp64 exact (sampled)", flush=True)
     acc, ctx = gpu_forward(w.pos, w.mass, w.box, w.r_s, w.r_cut, 64)
     assert metrics.error_summary(acc[sample], ref)["max"] <= 1e-12
+    print("case: clustered 128^3 fp64 r^2 table (sampled)", flush=True)
+    ctx.set_eval(precision=B.PMFMM_FP64, trunc=B.TRUNC_R2, table_size=64, table_level=6)
+    out64 = torch.empty((len(w.mass), 3), dtype=torch.float64, device="cuda")
+    ctx.forward(out64, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    e64 = metrics.error_summary(out64.cpu().numpy()[sample], ref)
+    assert e64["p999"] <= 1e-13 and e64["max"] <= 1e-11, e64
     out = torch.empty((len(w.mass), 3), dtype=torch.float64, device="cuda")
     for trunc, level, n_tab in [(B.TRUNC_TABLE, 2, 512),
                                 (B.TRUNC_TABLE, 1, 2048),

@@ -197,9 +197,16 @@ std::vector<unsigned char> build_r2_table64(int per_octave, int deg, double xc) 
     const int octaves = pmfmm::kR2Emax - pmfmm::kR2Emin64;
     const int rows = octaves << bits, m = deg + 1;
     const long double kappa = (long double)xc * xc / std::ldexp(1.0L, pmfmm::kR2Emax);
-    std::vector<unsigned char> out((size_t)8 * m * rows + 16, 0);
+    // one extra row for s = 2^kR2Emax itself (a pair just inside the cutoff
+    // whose scaled s rounds up): the constant F(2^kR2Emax)
+    std::vector<unsigned char> out((size_t)8 * m * (rows + 1) + 16, 0);
     double* f = reinterpret_cast<double*>(out.data());
     const long double pi = 3.141592653589793238462643383279502884L;
+    {
+        const long double sv = std::ldexp(1.0L, pmfmm::kR2Emax), x = std::sqrt(sv * kappa);
+        const long double T = std::erfc(x) + 1.128379167095512573896158903121545172L * x * std::exp(-x * x);
+        f[(size_t)m * rows] = (double)(T / (sv * std::sqrt(sv)));
+    }
     for (int k = 0; k < rows; ++k) {
         const int e = pmfmm::kR2Emin64 + (k >> bits), j = k & ((1 << bits) - 1);
         const long double lo = std::ldexp(1.0L + (long double)j / per_octave, e);

@@ -186,33 +186,58 @@ __device__ __forceinline__ void pair_f32_table(const float4 q, float px, float p
     az = fmaf(g, dz, az);
 }
 
+// Four consecutive sources, read by one wave-uniform load.  pin() is an
+// empty statement that takes all sixteen values in scalar registers: it keeps
+// the compiler from sinking each source's load into the masked region of its
+// pair, which would leave one load and one wait per pair.
+template <class V>
+struct Src4 {
+    V v[4];
+};
+
+template <class V>
+__device__ __forceinline__ void pin(const Src4<V>& b) {
+    asm volatile("" ::"s"(b.v[0].x), "s"(b.v[0].y), "s"(b.v[0].z), "s"(b.v[0].w),
+                 "s"(b.v[1].x), "s"(b.v[1].y), "s"(b.v[1].z), "s"(b.v[1].w),
+                 "s"(b.v[2].x), "s"(b.v[2].y), "s"(b.v[2].z), "s"(b.v[2].w),
+                 "s"(b.v[3].x), "s"(b.v[3].y), "s"(b.v[3].z), "s"(b.v[3].w));
+}
+
 // r^2 table (not the paper's table; see the host builder in abi.cpp): the
 // whole radial factor F = T(r) / r^3 as a function of s = r'^2, with
-// offsets scaled so that r_cut^2 = 2^kR2Emax.  s is clamped into
-// [2^kR2Emin, 2^kR2Emax]; its float bits (exponent and top `bits` mantissa
-// bits) index the segment directly (2^bits segments per octave), and each
-// row holds F's polynomial in s itself.  The row at s = 2^kR2Emax is zero,
-// so a pair beyond the cutoff gets F = 0 with no compare, and no 1/r is
-// evaluated at all.  A coincident pair (d = 0) gets a finite F times d = 0.
+// offsets scaled so that r_cut^2 = 2^kR2Emax.  s is clamped below at
+// 2^kR2Emin; its float bits (exponent and top `bits` mantissa bits) index
+// the segment directly (2^bits segments per octave), and each row holds F's
+// polynomial in s itself; no 1/r is evaluated at all.  A coincident pair
+// (d = 0) gets a finite F times d = 0.  Only lanes inside the cutoff read
+// the table and add: most candidate pairs lie beyond r_cut (about three in
+// four in clustered boxes), and an LDS read costs its issue slot whatever
+// its active lanes, so a wave whose lanes are all beyond r_cut for a source
+// skips the read altogether.
 template <int LEVEL>
 __device__ __forceinline__ void pair_f32_r2(const float4 q, float px, float py, float pz,
                                             float smax, float smin, uint32_t shift,
-                                            uint32_t base, const float4* __restrict__ tab,
+                                            uint32_t boff, const unsigned char* __restrict__ tab,
                                             float& ax, float& ay, float& az) {
     const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    const float sc = __builtin_amdgcn_fmed3f(r2, smin, smax);
-    const float4 c = tab[(__float_as_uint(sc) >> shift) - base];
-    float F;
-    if constexpr (LEVEL == 1) {
-        F = fmaf(c.y, sc, c.x);
-    } else {
-        F = fmaf(fmaf(c.z, sc, c.y), sc, c.x);
+    if (r2 < smax) {
+        // r2 >= +0, so the clamp below smin is an unsigned max of the bits
+        const uint32_t sb = max(__float_as_uint(r2), __float_as_uint(smin));
+        const float sc = __uint_as_float(sb);
+        // boff = -(row of 2^kR2Emin) * 16 mod 2^32: one shift-add per address
+        const float4 c = *reinterpret_cast<const float4*>(tab + (((sb >> shift) << 4) + boff));
+        float F;
+        if constexpr (LEVEL == 1) {
+            F = fmaf(c.y, sc, c.x);
+        } else {
+            F = fmaf(fmaf(c.z, sc, c.y), sc, c.x);
+        }
+        const float g = q.w * F;
+        ax = fmaf(g, dx, ax);
+        ay = fmaf(g, dy, ay);
+        az = fmaf(g, dz, az);
     }
-    const float g = q.w * F;
-    ax = fmaf(g, dx, ax);
-    ay = fmaf(g, dy, ay);
-    az = fmaf(g, dz, az);
 }
 
 // float64 r^2 table (not the paper's table; host builder in abi.cpp): the
@@ -221,52 +246,99 @@ __device__ __forceinline__ void pair_f32_r2(const float4 q, float px, float py, 
 // indexed by the high 32 bits of s (exponent and top `bits` mantissa bits);
 // each row holds the NC coefficients of the segment's polynomial in
 // t = s - s_k (s_k the segment start: the same high bits, zero below).  The
-// cutoff and r > 0 tests are the definition's, on r^2 itself; s is clamped
-// below 2^kR2Emax so that a pair inside the cutoff whose scaled s rounds up
-// stays on the last segment.  A pair closer than 2^(kR2Emin64 / 2) r_cut
-// (rare: r < 0.004 r_cut) takes the exact erfc / exp expression.  The item's
-// sums are multiplied by sigma^3 at the end.
+// cutoff test is the definition's, on r^2 itself; a pair inside it has
+// s <= 2^11, and the row after the last segment holds F(2^11) for a pair
+// whose scaled s rounds up to 2^11.  As in the float32 form, only lanes
+// inside the cutoff read the table.  A pair closer than 2^(kR2Emin64 / 2)
+// r_cut (r < r_cut / 256, rare) or at r = 0 contributes nothing here and
+// raises the lane's `near` flag; pair_f64_r2_close then adds the close pairs
+// of that j leaf with the exact erfc / exp expression.  The item's sums are
+// multiplied by sigma^3 at the end.
+struct R2Tab64 {
+    const unsigned char* tab;  // LDS rows of NC doubles
+    double rc2, sig2, alpha;
+    uint32_t hlo;              // high word of 2^kR2Emin64
+    uint32_t hshift, hmask;    // segment = hi >> hshift; start = hi & hmask
+    uint32_t hoff;             // -(row of hlo) * row bytes, mod 2^32
+};
+
+template <bool SHIFTED>
+__device__ __forceinline__ double disp_r2(const double4 q, double xi, double yi, double zi,
+                                          double sx, double sy, double sz, double& dx,
+                                          double& dy, double& dz) {
+#pragma clang fp contract(off)
+    dx = q.x - xi;
+    dy = q.y - yi;
+    dz = q.z - zi;
+    if (SHIFTED) {
+        dx = dx + sx;
+        dy = dy + sy;
+        dz = dz + sz;
+    }
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
 template <int NC, bool SHIFTED>
 __device__ __forceinline__ void pair_f64_r2(const double4 q, double xi, double yi, double zi,
-                                            double sx, double sy, double sz, double rc2,
-                                            double sig2, double smax, double smin, double alpha,
-                                            uint32_t hshift, uint32_t hbase, uint32_t hmask,
-                                            const double* __restrict__ tab, double& ax, double& ay,
-                                            double& az) {
-    double dx, dy, dz, r2;
-    {
-#pragma clang fp contract(off)
-        dx = q.x - xi;
-        dy = q.y - yi;
-        dz = q.z - zi;
-        if (SHIFTED) {
-            dx = dx + sx;
-            dy = dy + sy;
-            dz = dz + sz;
-        }
-        r2 = (dx * dx + dy * dy) + dz * dz;
-    }
-    const bool ok = (r2 > 0.0) & (r2 < rc2);
-    const double s = r2 * sig2;
-    double F;
-    if (__builtin_expect(ok && s < smin, 0)) {
-        const double r = sqrt(r2);
-        const double x = r * alpha;
-        const double T = erfc(x) + kTwoOverSqrtPi * x * exp(-x * x);
-        F = T / (s * sqrt(s));
-    } else {
-        const double sc = fmax(fmin(s, smax), smin);
-        const uint32_t hi = (uint32_t)__double2hiint(sc);
-        const double* __restrict__ c = tab + (size_t)((hi >> hshift) - hbase) * NC;
-        const double t = sc - __hiloint2double((int)(hi & hmask), 0);
-        F = c[NC - 1];
+                                            double sx, double sy, double sz, const R2Tab64& T,
+                                            double& ax, double& ay, double& az, bool& near) {
+    double dx, dy, dz;
+    const double r2 = disp_r2<SHIFTED>(q, xi, yi, zi, sx, sy, sz, dx, dy, dz);
+    const double s = r2 * T.sig2;
+    const uint32_t hi = (uint32_t)__double2hiint(s);
+    const bool low = hi < T.hlo;
+    near |= low;
+    if (!low & (r2 < T.rc2)) {
+        const double* __restrict__ c =
+            reinterpret_cast<const double*>(T.tab + (__umul24(hi >> T.hshift, NC * 8) + T.hoff));
+        const double t = s - __hiloint2double((int)(hi & T.hmask), 0);
+        double F = c[NC - 1];
 #pragma unroll
         for (int k = NC - 2; k >= 0; --k) F = fma(F, t, c[k]);
+        const double g = q.w * F;
+        ax = fma(g, dx, ax);
+        ay = fma(g, dy, ay);
+        az = fma(g, dz, az);
     }
-    const double g = ok ? q.w * F : 0.0;
-    ax = fma(g, dx, ax);
-    ay = fma(g, dy, ay);
-    az = fma(g, dz, az);
+}
+
+template <bool SHIFTED>
+__device__ __forceinline__ void pair_f64_r2_close(const double4 q, double xi, double yi, double zi,
+                                                  double sx, double sy, double sz,
+                                                  const R2Tab64& T, double& ax, double& ay,
+                                                  double& az) {
+    double dx, dy, dz;
+    const double r2 = disp_r2<SHIFTED>(q, xi, yi, zi, sx, sy, sz, dx, dy, dz);
+    const double s = r2 * T.sig2;
+    if (r2 > 0.0 && (uint32_t)__double2hiint(s) < T.hlo) {
+        const double r = sqrt(r2);
+        const double x = r * T.alpha;
+        const double Tx = erfc(x) + kTwoOverSqrtPi * x * exp(-x * x);
+        const double g = q.w * (Tx / (s * sqrt(s)));
+        ax = fma(g, dx, ax);
+        ay = fma(g, dy, ay);
+        az = fma(g, dz, az);
+    }
+}
+
+template <int NC, bool SHIFTED>
+__device__ __forceinline__ void leaf_f64_r2(const double4* __restrict__ src, int nj, double xi,
+                                            double yi, double zi, double sx, double sy, double sz,
+                                            const R2Tab64& T, double& ax, double& ay, double& az) {
+    bool near = false;
+    int k = 0;
+    for (; k + 4 <= nj; k += 4) {
+        const Src4<double4> b = *reinterpret_cast<const Src4<double4>*>(src + k);
+        pin(b);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            pair_f64_r2<NC, SHIFTED>(b.v[u], xi, yi, zi, sx, sy, sz, T, ax, ay, az, near);
+    }
+    for (; k < nj; ++k)
+        pair_f64_r2<NC, SHIFTED>(src[k], xi, yi, zi, sx, sy, sz, T, ax, ay, az, near);
+    if (near)
+        for (int k = 0; k < nj; ++k)
+            pair_f64_r2_close<SHIFTED>(src[k], xi, yi, zi, sx, sy, sz, T, ax, ay, az);
 }
 
 // LDS table layouts (bytes), matching the host builder in abi.cpp:
@@ -323,7 +395,7 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
             // r^2 table: n_tab = segments per octave = 2^bits
             const uint32_t r2bits = 31u - (uint32_t)__builtin_clz((uint32_t)n_tab);
             const uint32_t r2shift = 23u - r2bits;
-            const uint32_t r2base = (uint32_t)(127 + kR2Emin) << r2bits;
+            const uint32_t r2boff = 0u - (((uint32_t)(127 + kR2Emin) << r2bits) << 4);
             for (int t = t0; t < t1; ++t) {
                 const int js = uni(p2p_js[t]);
                 const int jl = js >> 5;
@@ -346,10 +418,20 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                         pair_f32_table<LEVEL>(src[k], px, py, pz, rc2, tiny, bx.tab_scale_f, rnd,
                                               t03, t4, fx, fy, fz);
                 } else {
-#pragma unroll 4
-                    for (int k = 0; k < nj; ++k)
-                        pair_f32_r2<LEVEL>(src[k], px, py, pz, rc2, tiny, r2shift, r2base,
-                                           t03, fx, fy, fz);
+                    // four sources per 64-byte scalar load, ahead of the
+                    // masked table reads
+                    int k = 0;
+                    for (; k + 4 <= nj; k += 4) {
+                        const Src4<float4> b = *reinterpret_cast<const Src4<float4>*>(src + k);
+                        pin(b);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            pair_f32_r2<LEVEL>(b.v[u], px, py, pz, rc2, tiny, r2shift, r2boff,
+                                               lds, fx, fy, fz);
+                    }
+                    for (; k < nj; ++k)
+                        pair_f32_r2<LEVEL>(src[k], px, py, pz, rc2, tiny, r2shift, r2boff, lds,
+                                           fx, fy, fz);
                 }
                 ax += (double)fx;
                 ay += (double)fy;
@@ -367,14 +449,19 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
             const double2* t23 = reinterpret_cast<const double2*>(lds + 16 * n_tab);
             const double* t4 = reinterpret_cast<const double*>(lds + 32 * n_tab);
             // float64 r^2 table: n_tab = segments per octave = 2^bits
-            const double* r2tab = reinterpret_cast<const double*>(lds);
-            const uint32_t hbits = 31u - (uint32_t)__builtin_clz((uint32_t)(n_tab > 0 ? n_tab : 1));
-            const uint32_t hshift = 20u - hbits;
-            const uint32_t hbase = (uint32_t)(1023 + kR2Emin64) << hbits;
-            const uint32_t hmask = ~((1u << hshift) - 1u);
-            const double sig2 = (double)(1 << kR2Emax) / rc2;
-            const double smax = 2048.0 * (1.0 - 0x1p-53);   // largest double below 2^kR2Emax
-            const double smin = 0x1p-5;                      // 2^kR2Emin64
+            R2Tab64 r2t;
+            if constexpr (MODE == kFP64R2) {
+                const uint32_t hbits =
+                    31u - (uint32_t)__builtin_clz((uint32_t)(n_tab > 0 ? n_tab : 1));
+                r2t.tab = lds;
+                r2t.rc2 = rc2;
+                r2t.sig2 = (double)(1 << kR2Emax) / rc2;
+                r2t.alpha = bx.alpha;
+                r2t.hshift = 20u - hbits;
+                r2t.hmask = ~((1u << r2t.hshift) - 1u);
+                r2t.hlo = (uint32_t)(1023 + kR2Emin64) << 20;
+                r2t.hoff = 0u - (r2t.hlo >> r2t.hshift) * (uint32_t)((LEVEL + 1) * 8);
+            }
             for (int t = t0; t < t1; ++t) {
                 const int js = uni(p2p_js[t]);
                 const int jl = js >> 5;
@@ -384,15 +471,18 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                 shift_of(s, bx.L, sx, sy, sz);
                 const double4* __restrict__ src = x64 + uni(lj.x);
                 const int nj = uni(lj.y);
-                if (s == 13) {
+                if constexpr (MODE == kFP64R2) {
+                    if (s == 13)
+                        leaf_f64_r2<LEVEL + 1, false>(src, nj, pv.x, pv.y, pv.z, 0.0, 0.0, 0.0,
+                                                      r2t, ax, ay, az);
+                    else
+                        leaf_f64_r2<LEVEL + 1, true>(src, nj, pv.x, pv.y, pv.z, sx, sy, sz, r2t,
+                                                     ax, ay, az);
+                } else if (s == 13) {
                     for (int k = 0; k < nj; ++k) {
                         if constexpr (MODE == kFP64Exact)
                             pair_f64_exact<false>(src[k], pv.x, pv.y, pv.z, 0.0, 0.0, 0.0, rc2,
                                                   bx.alpha, ax, ay, az);
-                        else if constexpr (MODE == kFP64R2)
-                            pair_f64_r2<LEVEL + 1, false>(src[k], pv.x, pv.y, pv.z, 0.0, 0.0, 0.0,
-                                                          rc2, sig2, smax, smin, bx.alpha, hshift,
-                                                          hbase, hmask, r2tab, ax, ay, az);
                         else
                             pair_f64_table<LEVEL, false>(src[k], pv.x, pv.y, pv.z, 0.0, 0.0, 0.0,
                                                          rc2, bx.tab_scale, rnd, dmax, t01, t23,
@@ -403,10 +493,6 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                         if constexpr (MODE == kFP64Exact)
                             pair_f64_exact<true>(src[k], pv.x, pv.y, pv.z, sx, sy, sz, rc2,
                                                  bx.alpha, ax, ay, az);
-                        else if constexpr (MODE == kFP64R2)
-                            pair_f64_r2<LEVEL + 1, true>(src[k], pv.x, pv.y, pv.z, sx, sy, sz, rc2,
-                                                         sig2, smax, smin, bx.alpha, hshift, hbase,
-                                                         hmask, r2tab, ax, ay, az);
                         else
                             pair_f64_table<LEVEL, true>(src[k], pv.x, pv.y, pv.z, sx, sy, sz, rc2,
                                                         bx.tab_scale, rnd, dmax, t01, t23, t4, ax,
@@ -415,7 +501,7 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                 }
             }
             if constexpr (MODE == kFP64R2) {
-                const double sig3 = sig2 * sqrt(sig2);
+                const double sig3 = r2t.sig2 * sqrt(r2t.sig2);
                 ax *= sig3;
                 ay *= sig3;
                 az *= sig3;

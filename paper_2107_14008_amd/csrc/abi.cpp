@@ -528,7 +528,7 @@ int do_upload(pmfmm_ctx* ctx, const double* pos, const double* mass, int32_t on_
     if ((rc = upload(ctx->d.leafc, leafc, s))) return rc;
     if ((rc = upload(ctx->d.js, js, s))) return rc;
     if ((rc = upload_boxes(ctx, s))) return rc;
-    HIP_TRY(ctx->d.counter.ensure(64));
+    HIP_TRY(ctx->d.counter.ensure(pmfmm::kQueueSegs * pmfmm::kCounterStride * 4));
     HIP_TRY(ctx->d.x64.ensure((size_t)n * 32));
     HIP_TRY(ctx->d.x32.ensure((size_t)n * 16));
     const double* src_pos = pos;
@@ -753,7 +753,7 @@ int gpu_build(pmfmm_ctx* ctx, const std::vector<pmfmm::BoxParams>& boxes, const 
     ctx->far = pc.n_m2l > 0;
     ctx->plan.far_field = ctx->far;
     ctx->plan.candidate_pairs = pc.candidate_pairs;
-    HIP_TRY(ctx->d.counter.ensure(64));
+    HIP_TRY(ctx->d.counter.ensure(pmfmm::kQueueSegs * pmfmm::kCounterStride * 4));
     if (ctx->far) {
         const int64_t nc = (int64_t)ctx->plan.cells.size();
         const int nco = pmfmm::n_coef(ctx->plan.max_order);
@@ -986,7 +986,7 @@ int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream) {
     if (ctx->far) {
         if ((rc = run_far(ctx, s))) return rc;
     }
-    HIP_TRY(pmfmm::launch_zero_i32(ctx->d.counter.as<int32_t>(), 1, s));
+    HIP_TRY(pmfmm::launch_zero_i32(ctx->d.counter.as<int32_t>(), pmfmm::kQueueSegs * pmfmm::kCounterStride, s));
     if (timing) HIP_TRY(hipEventRecord(ctx->ev[1], s));
     pmfmm::P2PArgs a{};
     a.x64 = ctx->d.x64.as<double4>();
@@ -1121,7 +1121,7 @@ int pmfmm_adjoint(pmfmm_ctx* ctx, const double* w, double* grad_pos, double* gra
     HIP_TRY(ctx->d.w32.ensure((size_t)n * 16));
     HIP_TRY(pmfmm::launch_gather_w(w, ctx->d.perm.as<int32_t>(), ctx->d.w64.as<double4>(), ctx->d.w32.as<float4>(),
                                    (int32_t)n, s));
-    HIP_TRY(pmfmm::launch_zero_i32(ctx->d.counter.as<int32_t>(), 1, s));
+    HIP_TRY(pmfmm::launch_zero_i32(ctx->d.counter.as<int32_t>(), pmfmm::kQueueSegs * pmfmm::kCounterStride, s));
     const bool timing = ctx->p.timing != 0;
     if (timing) {
         int rc = ensure_events(ctx);

@@ -8,13 +8,16 @@
 //   leafc[l] double4 (centre x, y, z, 0)    expansion / offset centre
 //   p2p_row[l] .. p2p_row[l+1]              TaskGroup rows of i leaf l
 //   p2p_js[t] = (j leaf << 5) | shift code  TaskGroup entries
-//   items[q] int4 (leaf, t0, t1, slot)      work items; queue = longest first
+//   items[q] int4 (leaf, t0, t1, slot)      work items; queue: per segment
+//                                           (kQueueSegs), longest first
 //   partial[(slot * 3 + axis) * 64 + lane]  per-item float64 partial sums
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+
+#include "plan.h"
 
 namespace pmfmm {
 
@@ -37,6 +40,12 @@ constexpr int kR2Emax = 11;
 // float64 r^2 table: scaled r^2 in [2^kR2Emin64, 2^kR2Emax); closer pairs
 // (r < 2^-8 r_cut) take the exact erfc / exp path.
 constexpr int kR2Emin64 = kR2Emax - 16;
+
+// First queue position of segment x of a queue of n items (segments and
+// counters: kQueueSegs in plan.h).
+__device__ inline int32_t queue_seg_begin(int x, int32_t n) {
+    return (int32_t)(((int64_t)x * n + kQueueSegs - 1) / kQueueSegs);
+}
 
 // Per-box constants.  The float32 forms work on offsets scaled by sigma
 // (x32 and the per-task centre offsets): sigma = 1, except for the r^2

@@ -931,9 +931,10 @@ __global__ void k_item_count(int nl, const int32_t* __restrict__ row, int chunk,
 }
 
 // Work items of each TaskGroup row, one wavefront per row and one lane per
-// item; the queue key is 255 - (pair count >> cshift), one radix pass, so
-// the queue is longest first up to 1/256 of the largest item.  Slots from
-// the item count to `cap` get key 255 (after every item in the stable sort).
+// item; the queue key is (segment of the slot) * 256 + 255 - (pair count >>
+// cshift), so the sorted queue holds the kQueueSegs segments in order, each
+// longest first up to 1/256 of the largest item.  Slots from the item count
+// to `cap` get segment kQueueSegs (after every item in the stable sort).
 // rowcand[i]: candidate pairs of row i; ctl[2]: the item count.
 __global__ void k_items(int nl, const int32_t* __restrict__ row, const int32_t* __restrict__ js,
                         const int4* __restrict__ leaf, int chunk, int cshift,
@@ -959,7 +960,8 @@ __global__ void k_items(int nl, const int32_t* __restrict__ row, const int32_t* 
                 const int s = slot0[i] + k;
                 items[s] = make_int4(i, t, t + sz, s);
                 const unsigned long long b = c >> cshift;
-                cost_keys[s] = (uint64_t)(255u - (b > 255ull ? 255u : (uint32_t)b));
+                const uint64_t seg = (uint64_t)((int64_t)s * kQueueSegs / slot0[nl]);
+                cost_keys[s] = (seg << 8) | (uint64_t)(255u - (b > 255ull ? 255u : (uint32_t)b));
                 slots[s] = (uint32_t)s;
             }
         }
@@ -970,7 +972,7 @@ __global__ void k_items(int nl, const int32_t* __restrict__ row, const int32_t* 
         if (gt == 0) ctl[2] = (uint32_t)n_items;
         const int64_t stride = (int64_t)gridDim.x * blockDim.x;
         for (int64_t s = n_items + gt; s < cap; s += stride) {
-            cost_keys[s] = 255u;
+            cost_keys[s] = ((uint64_t)kQueueSegs << 8) | 255u;
             slots[s] = (uint32_t)s;
         }
     }
@@ -1531,7 +1533,7 @@ std::string gpu_make_items(DevPlan& d, const Plan& topo, int64_t n_p2p, int chun
                        (int)nl, reinterpret_cast<unsigned long long*>(d.wcount.as<uint32_t>() + 8));
     TRY(hipGetLastError());
     std::string err = sort_in_place(d.cost_keys, &d.queue, d.cost_keys_tmp, &d.queue_tmp, d.hist,
-                                    cap, 8, s);
+                                    cap, 12, s);
     if (!err.empty()) return err;
     // words 8, 9: candidate pairs; 10: items; 16, 17: M2L depths (set by the build)
     uint32_t w[10];

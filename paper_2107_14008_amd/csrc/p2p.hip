@@ -370,12 +370,19 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
     const int lane = threadIdx.x & 63;
     const int dmax = n_tab - 1;
 
+    int seg = (int)(blockIdx.x % kQueueSegs), done = 0;
     for (;;) {
+        const int beg = queue_seg_begin(seg, n_items);
         int q = 0;
-        if (lane == 0) q = atomicAdd(counter, 1);
+        if (lane == 0) q = atomicAdd(counter + seg * kCounterStride, 1);
         q = uni(q);
-        if (q >= n_items) break;
-        const int slot = uni(queue[q]);
+        if (q >= queue_seg_begin(seg + 1, n_items) - beg) {
+            // this segment is exhausted (for good: its counter only grows)
+            if (++done == kQueueSegs) break;
+            seg = seg + 1 == kQueueSegs ? 0 : seg + 1;
+            continue;
+        }
+        const int slot = uni(queue[beg + q]);
         const int4 it = items[slot];
         const int il = uni(it.x), t0 = uni(it.y), t1 = uni(it.z);
         const int4 li = leaf[il];

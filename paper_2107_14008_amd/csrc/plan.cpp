@@ -579,10 +579,16 @@ void make_items(Plan& plan, int chunk) {
         }
     }
     plan.leaf_slot_begin[n_leaves] = (int32_t)plan.items.size();
+    // queue: the kQueueSegs segments of consecutive slots in order, each
+    // longest first (the GPU kernels start each XCD on its own segment)
     plan.queue.resize(plan.items.size());
     for (size_t k = 0; k < plan.queue.size(); ++k) plan.queue[k] = (int32_t)k;
-    std::stable_sort(plan.queue.begin(), plan.queue.end(),
-                     [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    const int64_t n_items = (int64_t)plan.items.size();
+    auto seg = [&](int32_t a) { return (int64_t)a * kQueueSegs / n_items; };
+    std::stable_sort(plan.queue.begin(), plan.queue.end(), [&](int32_t a, int32_t b) {
+        const int64_t sa = seg(a), sb = seg(b);
+        return sa != sb ? sa < sb : cost[a] > cost[b];
+    });
 }
 
 }  // namespace pmfmm

@@ -13,6 +13,18 @@
 
 namespace pmfmm {
 
+// Work queue of the persistent P2P and adjoint launches, cut into
+// kQueueSegs segments of consecutive item slots (slots follow the ORB leaf
+// order, so a segment is a compact region of the box): slot s is in segment
+// floor(s kQueueSegs / n_items), and the queue lists the segments in order,
+// each longest first.  Workgroups are dispatched round robin over the 8 XCDs
+// of an MI355X, each with its own L2: workgroup b starts on segment
+// b % kQueueSegs, so the sources one XCD reads stay near one region, and
+// moves on to the other segments when its own is exhausted.  Each segment
+// has its own counter, kCounterStride ints apart (one 128-byte line each).
+constexpr int kQueueSegs = 8;
+constexpr int kCounterStride = 32;
+
 struct BoxParams {
     double box, r_s, r_cut, G, theta;
     int32_t max_leaf, order;

@@ -200,7 +200,6 @@ def secondary(args):
                             f"(total {n}), one persistent launch, float32 "
                             f"r^2 table of T/r^3 (64 segments per octave)", "n": n,
                             "candidate_pairs_per_step": cand,
-            "inside_pairs_per_step": inside,
                             "schedule": best, "phases_ms": ph,
                             "p2p_interactions_per_s": cand / (ph["p2p_ms"] / 1e3),
                             "tuning_ms": {f"{k[0]},{k[1]},{k[2]}": v
@@ -241,7 +240,6 @@ def secondary(args):
                             "+ 20% Plummer), N_PM=64, float32 exact T, "
                             "forward + adjoint per step", "n": n,
                             "candidate_pairs_per_step": cand,
-            "inside_pairs_per_step": inside,
                             "p2p_ms": float(np.mean(fw)),
                             "adjoint_ms": float(np.mean(ad))})
         return line
@@ -325,8 +323,7 @@ def secondary(args):
     line.update(value=cand / (res[best]["ms_per_step"] / 1e3),
                 ms_per_step=res[best]["ms_per_step"],
                 config={"workload": w.name, "n": n, "theta": theta, "order": order,
-                        "candidate_pairs_per_step": cand,
-            "inside_pairs_per_step": inside, "value_form": best,
+                        "candidate_pairs_per_step": cand, "value_form": best,
                         "forms": res},
                 cpu_baseline=base)
     return line

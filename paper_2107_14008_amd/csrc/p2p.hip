@@ -403,6 +403,19 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
             const uint32_t r2bits = 31u - (uint32_t)__builtin_clz((uint32_t)n_tab);
             const uint32_t r2shift = 23u - r2bits;
             const uint32_t r2boff = 0u - (((uint32_t)(127 + kR2Emin) << r2bits) << 4);
+            // box of the wave's targets in their leaf's frame (lanes past
+            // the leaf repeat target 0)
+            float3 lo = make_float3(pv.x, pv.y, pv.z), hi = lo;
+            if constexpr (MODE == kFP32R2) {
+                for (int o = 32; o > 0; o >>= 1) {
+                    lo.x = fminf(lo.x, __shfl_xor(lo.x, o));
+                    lo.y = fminf(lo.y, __shfl_xor(lo.y, o));
+                    lo.z = fminf(lo.z, __shfl_xor(lo.z, o));
+                    hi.x = fmaxf(hi.x, __shfl_xor(hi.x, o));
+                    hi.y = fmaxf(hi.y, __shfl_xor(hi.y, o));
+                    hi.z = fmaxf(hi.z, __shfl_xor(hi.z, o));
+                }
+            }
             for (int t = t0; t < t1; ++t) {
                 const int js = uni(p2p_js[t]);
                 const int jl = js >> 5;
@@ -410,9 +423,12 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                 const double4 cj = leafc[jl];
                 double sx, sy, sz;
                 shift_of(js & 31, bx.L, sx, sy, sz);
-                const float px = pv.x - (float)(((cj.x - ci.x) + sx) * sig);
-                const float py = pv.y - (float)(((cj.y - ci.y) + sy) * sig);
-                const float pz = pv.z - (float)(((cj.z - ci.z) + sz) * sig);
+                const float offx = (float)(((cj.x - ci.x) + sx) * sig);
+                const float offy = (float)(((cj.y - ci.y) + sy) * sig);
+                const float offz = (float)(((cj.z - ci.z) + sz) * sig);
+                const float px = pv.x - offx;
+                const float py = pv.y - offy;
+                const float pz = pv.z - offz;
                 const float4* __restrict__ src = x32 + uni(lj.x);
                 const int nj = uni(lj.y);
                 float fx = 0.f, fy = 0.f, fz = 0.f;
@@ -425,20 +441,37 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                         pair_f32_table<LEVEL>(src[k], px, py, pz, rc2, tiny, bx.tab_scale_f, rnd,
                                               t03, t4, fx, fy, fz);
                 } else {
+                    // Sources that reach no lane are skipped whole: lane k
+                    // tests source k against the box of the wave's targets
+                    // (in this j leaf's frame, [min px, max px] per axis,
+                    // exact in float32 since the shift is monotonic).  The
+                    // box distance is built like r^2 from components no
+                    // larger than any target's |d|, so it never exceeds a
+                    // target's r^2 and no pair inside r_cut is dropped.
+                    const float4 qk = src[lane < nj ? lane : 0];
+                    const float bx0 = fmaxf(fmaxf((lo.x - offx) - qk.x, qk.x - (hi.x - offx)), 0.f);
+                    const float by0 = fmaxf(fmaxf((lo.y - offy) - qk.y, qk.y - (hi.y - offy)), 0.f);
+                    const float bz0 = fmaxf(fmaxf((lo.z - offz) - qk.z, qk.z - (hi.z - offz)), 0.f);
+                    const float d2 = fmaf(bz0, bz0, fmaf(by0, by0, bx0 * bx0));
+                    const uint64_t live = __ballot((lane < nj) & (d2 < rc2));
                     // four sources per 64-byte scalar load, ahead of the
                     // masked table reads
                     int k = 0;
                     for (; k + 4 <= nj; k += 4) {
+                        const uint32_t g4 = (uint32_t)(live >> k) & 0xFu;
+                        if (g4 == 0) continue;
                         const Src4<float4> b = *reinterpret_cast<const Src4<float4>*>(src + k);
                         pin(b);
 #pragma unroll
                         for (int u = 0; u < 4; ++u)
-                            pair_f32_r2<LEVEL>(b.v[u], px, py, pz, rc2, tiny, r2shift, r2boff,
-                                               lds, fx, fy, fz);
+                            if (g4 & (1u << u))
+                                pair_f32_r2<LEVEL>(b.v[u], px, py, pz, rc2, tiny, r2shift, r2boff,
+                                                   lds, fx, fy, fz);
                     }
                     for (; k < nj; ++k)
-                        pair_f32_r2<LEVEL>(src[k], px, py, pz, rc2, tiny, r2shift, r2boff, lds,
-                                           fx, fy, fz);
+                        if ((live >> k) & 1u)
+                            pair_f32_r2<LEVEL>(src[k], px, py, pz, rc2, tiny, r2shift, r2boff,
+                                               lds, fx, fy, fz);
                 }
                 ax += (double)fx;
                 ay += (double)fy;

@@ -125,6 +125,8 @@ adjoint_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
             const float4 wk = w32[pk];
             mk = x64[pk].w;
             const double4 ci = leafc[il];
+            float3 lo = make_float3(pv.x, pv.y, pv.z), hi = lo;
+            wave_box(lo, hi);
             for (int t = t0; t < t1; ++t) {
                 const int js = uni(p2p_js[t]);
                 const int jl = js >> 5, s = js & 31;
@@ -132,15 +134,21 @@ adjoint_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                 const double4 cj = leafc[jl];
                 const double sx = (double)(s % 3 - 1) * bx.L, sy = (double)((s / 3) % 3 - 1) * bx.L,
                              sz = (double)(s / 9 - 1) * bx.L;
-                const float px = pv.x - (float)(((cj.x - ci.x) + sx) * bx.sigma);
-                const float py = pv.y - (float)(((cj.y - ci.y) + sy) * bx.sigma);
-                const float pz = pv.z - (float)(((cj.z - ci.z) + sz) * bx.sigma);
+                const float offx = (float)(((cj.x - ci.x) + sx) * bx.sigma);
+                const float offy = (float)(((cj.y - ci.y) + sy) * bx.sigma);
+                const float offz = (float)(((cj.z - ci.z) + sz) * bx.sigma);
+                const float px = pv.x - offx, py = pv.y - offy, pz = pv.z - offz;
                 const float4* __restrict__ src = x32 + uni(lj.x);
                 const float4* __restrict__ wsrc = w32 + uni(lj.x);
                 const int nj = uni(lj.y);
                 float a[3] = {0.f, 0.f, 0.f}, b[3] = {0.f, 0.f, 0.f}, g = 0.f;
+                const uint64_t live =
+                    live_f32(src, nj, lane, make_float3(lo.x - offx, lo.y - offy, lo.z - offz),
+                             make_float3(hi.x - offx, hi.y - offy, hi.z - offz), bx.rc2_f);
                 for (int k = 0; k < nj; ++k)
-                    adj_pair_f32(src[k], wsrc[k], px, py, pz, wk, bx.rc2_f, bx.alpha_f, a, b, g);
+                    if ((live >> k) & 1u)
+                        adj_pair_f32(src[k], wsrc[k], px, py, pz, wk, bx.rc2_f, bx.alpha_f, a, b,
+                                     g);
                 for (int c = 0; c < 3; ++c) {
                     A[c] += (double)a[c];
                     Bv[c] += (double)b[c];
@@ -157,6 +165,8 @@ adjoint_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
             const double4 pv = x64[pk];
             const double4 wk = w64[pk];
             mk = pv.w;
+            double3 lo = make_double3(pv.x, pv.y, pv.z), hi = lo;
+            wave_box(lo, hi);
             for (int t = t0; t < t1; ++t) {
                 const int js = uni(p2p_js[t]);
                 const int jl = js >> 5, s = js & 31;
@@ -166,14 +176,19 @@ adjoint_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                 const double4* __restrict__ src = x64 + uni(lj.x);
                 const double4* __restrict__ wsrc = w64 + uni(lj.x);
                 const int nj = uni(lj.y);
+                const uint64_t live =
+                    s == 13 ? live_f64<false>(src, nj, lane, lo, hi, 0.0, 0.0, 0.0, bx.rc2)
+                            : live_f64<true>(src, nj, lane, lo, hi, sx, sy, sz, bx.rc2);
                 if (s == 13) {
                     for (int k = 0; k < nj; ++k)
-                        adj_pair_f64<false>(src[k], wsrc[k], pv.x, pv.y, pv.z, wk, 0.0, 0.0, 0.0,
-                                            bx.rc2, bx.alpha, A, Bv, gm);
+                        if ((live >> k) & 1u)
+                            adj_pair_f64<false>(src[k], wsrc[k], pv.x, pv.y, pv.z, wk, 0.0, 0.0,
+                                                0.0, bx.rc2, bx.alpha, A, Bv, gm);
                 } else {
                     for (int k = 0; k < nj; ++k)
-                        adj_pair_f64<true>(src[k], wsrc[k], pv.x, pv.y, pv.z, wk, sx, sy, sz, bx.rc2,
-                                           bx.alpha, A, Bv, gm);
+                        if ((live >> k) & 1u)
+                            adj_pair_f64<true>(src[k], wsrc[k], pv.x, pv.y, pv.z, wk, sx, sy, sz,
+                                               bx.rc2, bx.alpha, A, Bv, gm);
                 }
             }
         }

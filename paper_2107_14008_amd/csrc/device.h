@@ -41,6 +41,69 @@ constexpr int kR2Emax = 11;
 // (r < 2^-8 r_cut) take the exact erfc / exp path.
 constexpr int kR2Emin64 = kR2Emax - 16;
 
+// ------------------------------------------------------ source culling
+//
+// Before the pairs of a j leaf, lane k tests source k against the box of the
+// wave's targets and the ballot of the results leaves out the sources that
+// reach no target inside r_cut: the loops skip them with a scalar branch
+// (at 128^3 about half of the candidate sources, the pair set unchanged).
+// The box distance takes, per axis, the displacement of the box edge that
+// the pair loop itself would form (same operations, so each target's
+// |d_a| is at least that component: rounding is monotonic), and adds the
+// squares the way r^2 is added: it never exceeds a target's r^2, so a
+// source with a pair inside r_cut always survives.
+
+// float32, in the j leaf's frame: targets p = pv - off in [plo, phi].
+__device__ inline uint64_t live_f32(const float4* __restrict__ src, int nj, int lane,
+                                             float3 plo, float3 phi, float rc2) {
+    const float4 q = src[lane < nj ? lane : 0];
+    const float bx = fmaxf(fmaxf(plo.x - q.x, q.x - phi.x), 0.f);
+    const float by = fmaxf(fmaxf(plo.y - q.y, q.y - phi.y), 0.f);
+    const float bz = fmaxf(fmaxf(plo.z - q.z, q.z - phi.z), 0.f);
+    const float d2 = fmaf(bz, bz, fmaf(by, by, bx * bx));
+    return __ballot((lane < nj) & (d2 < rc2));
+}
+
+// float64: targets x in [lo, hi]; d = (q - x) + s as in the pair forms.
+template <bool SHIFTED>
+__device__ inline uint64_t live_f64(const double4* __restrict__ src, int nj, int lane,
+                                             const double3& lo, const double3& hi, double sx,
+                                             double sy, double sz, double rc2) {
+    const double4 q = src[lane < nj ? lane : 0];
+    double d2;
+    {
+#pragma clang fp contract(off)
+        double hx = q.x - hi.x, lx = q.x - lo.x;
+        double hy = q.y - hi.y, ly = q.y - lo.y;
+        double hz = q.z - hi.z, lz = q.z - lo.z;
+        if (SHIFTED) {
+            hx = hx + sx;
+            lx = lx + sx;
+            hy = hy + sy;
+            ly = ly + sy;
+            hz = hz + sz;
+            lz = lz + sz;
+        }
+        const double bx = fmax(fmax(hx, -lx), 0.0);
+        const double by = fmax(fmax(hy, -ly), 0.0);
+        const double bz = fmax(fmax(hz, -lz), 0.0);
+        d2 = (bx * bx + by * by) + bz * bz;
+    }
+    return __ballot((lane < nj) & (d2 < rc2));
+}
+
+template <class T3>
+__device__ inline void wave_box(T3& lo, T3& hi) {
+    for (int o = 32; o > 0; o >>= 1) {
+        lo.x = min(lo.x, __shfl_xor(lo.x, o));
+        lo.y = min(lo.y, __shfl_xor(lo.y, o));
+        lo.z = min(lo.z, __shfl_xor(lo.z, o));
+        hi.x = max(hi.x, __shfl_xor(hi.x, o));
+        hi.y = max(hi.y, __shfl_xor(hi.y, o));
+        hi.z = max(hi.z, __shfl_xor(hi.z, o));
+    }
+}
+
 // First queue position of segment x of a queue of n items (segments and
 // counters: kQueueSegs in plan.h).
 __device__ inline int32_t queue_seg_begin(int x, int32_t n) {

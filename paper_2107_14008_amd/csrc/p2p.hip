@@ -322,23 +322,29 @@ __device__ __forceinline__ void pair_f64_r2_close(const double4 q, double xi, do
 }
 
 template <int NC, bool SHIFTED>
-__device__ __forceinline__ void leaf_f64_r2(const double4* __restrict__ src, int nj, double xi,
+__device__ __forceinline__ void leaf_f64_r2(const double4* __restrict__ src, int nj,
+                                            uint64_t live, double xi,
                                             double yi, double zi, double sx, double sy, double sz,
                                             const R2Tab64& T, double& ax, double& ay, double& az) {
     bool near = false;
     int k = 0;
     for (; k + 4 <= nj; k += 4) {
+        const uint32_t g4 = (uint32_t)(live >> k) & 0xFu;
+        if (g4 == 0) continue;
         const Src4<double4> b = *reinterpret_cast<const Src4<double4>*>(src + k);
         pin(b);
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            pair_f64_r2<NC, SHIFTED>(b.v[u], xi, yi, zi, sx, sy, sz, T, ax, ay, az, near);
+            if (g4 & (1u << u))
+                pair_f64_r2<NC, SHIFTED>(b.v[u], xi, yi, zi, sx, sy, sz, T, ax, ay, az, near);
     }
     for (; k < nj; ++k)
-        pair_f64_r2<NC, SHIFTED>(src[k], xi, yi, zi, sx, sy, sz, T, ax, ay, az, near);
+        if ((live >> k) & 1u)
+            pair_f64_r2<NC, SHIFTED>(src[k], xi, yi, zi, sx, sy, sz, T, ax, ay, az, near);
     if (near)
         for (int k = 0; k < nj; ++k)
-            pair_f64_r2_close<SHIFTED>(src[k], xi, yi, zi, sx, sy, sz, T, ax, ay, az);
+            if ((live >> k) & 1u)
+                pair_f64_r2_close<SHIFTED>(src[k], xi, yi, zi, sx, sy, sz, T, ax, ay, az);
 }
 
 // LDS table layouts (bytes), matching the host builder in abi.cpp:
@@ -406,16 +412,7 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
             // box of the wave's targets in their leaf's frame (lanes past
             // the leaf repeat target 0)
             float3 lo = make_float3(pv.x, pv.y, pv.z), hi = lo;
-            if constexpr (MODE == kFP32R2) {
-                for (int o = 32; o > 0; o >>= 1) {
-                    lo.x = fminf(lo.x, __shfl_xor(lo.x, o));
-                    lo.y = fminf(lo.y, __shfl_xor(lo.y, o));
-                    lo.z = fminf(lo.z, __shfl_xor(lo.z, o));
-                    hi.x = fmaxf(hi.x, __shfl_xor(hi.x, o));
-                    hi.y = fmaxf(hi.y, __shfl_xor(hi.y, o));
-                    hi.z = fmaxf(hi.z, __shfl_xor(hi.z, o));
-                }
-            }
+            wave_box(lo, hi);
             for (int t = t0; t < t1; ++t) {
                 const int js = uni(p2p_js[t]);
                 const int jl = js >> 5;
@@ -432,28 +429,22 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                 const float4* __restrict__ src = x32 + uni(lj.x);
                 const int nj = uni(lj.y);
                 float fx = 0.f, fy = 0.f, fz = 0.f;
+                // targets in this frame: [lo - off, hi - off] per axis
+                // (exact: the shift is monotonic)
+                const uint64_t live =
+                    live_f32(src, nj, lane, make_float3(lo.x - offx, lo.y - offy, lo.z - offz),
+                             make_float3(hi.x - offx, hi.y - offy, hi.z - offz), rc2);
                 if constexpr (MODE == kFP32Exact) {
                     for (int k = 0; k < nj; ++k)
-                        pair_f32_exact(src[k], px, py, pz, rc2, tiny, bx.alpha_f, fx, fy, fz);
+                        if ((live >> k) & 1u)
+                            pair_f32_exact(src[k], px, py, pz, rc2, tiny, bx.alpha_f, fx, fy, fz);
                 } else if constexpr (MODE == kFP32Table) {
 #pragma unroll 4
                     for (int k = 0; k < nj; ++k)
-                        pair_f32_table<LEVEL>(src[k], px, py, pz, rc2, tiny, bx.tab_scale_f, rnd,
-                                              t03, t4, fx, fy, fz);
+                        if ((live >> k) & 1u)
+                            pair_f32_table<LEVEL>(src[k], px, py, pz, rc2, tiny, bx.tab_scale_f,
+                                                  rnd, t03, t4, fx, fy, fz);
                 } else {
-                    // Sources that reach no lane are skipped whole: lane k
-                    // tests source k against the box of the wave's targets
-                    // (in this j leaf's frame, [min px, max px] per axis,
-                    // exact in float32 since the shift is monotonic).  The
-                    // box distance is built like r^2 from components no
-                    // larger than any target's |d|, so it never exceeds a
-                    // target's r^2 and no pair inside r_cut is dropped.
-                    const float4 qk = src[lane < nj ? lane : 0];
-                    const float bx0 = fmaxf(fmaxf((lo.x - offx) - qk.x, qk.x - (hi.x - offx)), 0.f);
-                    const float by0 = fmaxf(fmaxf((lo.y - offy) - qk.y, qk.y - (hi.y - offy)), 0.f);
-                    const float bz0 = fmaxf(fmaxf((lo.z - offz) - qk.z, qk.z - (hi.z - offz)), 0.f);
-                    const float d2 = fmaf(bz0, bz0, fmaf(by0, by0, bx0 * bx0));
-                    const uint64_t live = __ballot((lane < nj) & (d2 < rc2));
                     // four sources per 64-byte scalar load, ahead of the
                     // masked table reads
                     int k = 0;
@@ -502,6 +493,8 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                 r2t.hlo = (uint32_t)(1023 + kR2Emin64) << 20;
                 r2t.hoff = 0u - (r2t.hlo >> r2t.hshift) * (uint32_t)((LEVEL + 1) * 8);
             }
+            double3 lo = make_double3(pv.x, pv.y, pv.z), hi = lo;
+            wave_box(lo, hi);
             for (int t = t0; t < t1; ++t) {
                 const int js = uni(p2p_js[t]);
                 const int jl = js >> 5;
@@ -511,15 +504,19 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                 shift_of(s, bx.L, sx, sy, sz);
                 const double4* __restrict__ src = x64 + uni(lj.x);
                 const int nj = uni(lj.y);
+                const uint64_t live =
+                    s == 13 ? live_f64<false>(src, nj, lane, lo, hi, 0.0, 0.0, 0.0, rc2)
+                            : live_f64<true>(src, nj, lane, lo, hi, sx, sy, sz, rc2);
                 if constexpr (MODE == kFP64R2) {
                     if (s == 13)
-                        leaf_f64_r2<LEVEL + 1, false>(src, nj, pv.x, pv.y, pv.z, 0.0, 0.0, 0.0,
-                                                      r2t, ax, ay, az);
+                        leaf_f64_r2<LEVEL + 1, false>(src, nj, live, pv.x, pv.y, pv.z, 0.0, 0.0,
+                                                      0.0, r2t, ax, ay, az);
                     else
-                        leaf_f64_r2<LEVEL + 1, true>(src, nj, pv.x, pv.y, pv.z, sx, sy, sz, r2t,
-                                                     ax, ay, az);
+                        leaf_f64_r2<LEVEL + 1, true>(src, nj, live, pv.x, pv.y, pv.z, sx, sy, sz,
+                                                     r2t, ax, ay, az);
                 } else if (s == 13) {
                     for (int k = 0; k < nj; ++k) {
+                        if (!((live >> k) & 1u)) continue;
                         if constexpr (MODE == kFP64Exact)
                             pair_f64_exact<false>(src[k], pv.x, pv.y, pv.z, 0.0, 0.0, 0.0, rc2,
                                                   bx.alpha, ax, ay, az);
@@ -530,6 +527,7 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                     }
                 } else {
                     for (int k = 0; k < nj; ++k) {
+                        if (!((live >> k) & 1u)) continue;
                         if constexpr (MODE == kFP64Exact)
                             pair_f64_exact<true>(src[k], pv.x, pv.y, pv.z, sx, sy, sz, rc2,
                                                  bx.alpha, ax, ay, az);

@@ -251,6 +251,36 @@ def test_coincident_and_ragged():
         assert metrics.error_summary(acc, ref)["max"] <= 1e-12
 
 
+def test_pairs_just_inside_the_cutoff_are_kept():
+    """Sources are culled per j leaf against the box of a wave's targets;
+    sources placed at r_cut (1 - eps) from a target (eps down to 1e-14, along
+    the axes, face diagonals and body diagonals, so also beyond box corners
+    and across the periodic boundary) must still be counted: float64 exact
+    against the oracle at 1e-12, and the float64 r^2 table, whose cutoff
+    test is the same float64 one.  (The float32 forms decide pairs this
+    close to r_cut in float32 and may place them on either side.)"""
+    rng = np.random.default_rng(21)
+    box, r_s, r_cut = 40.0, 1.0, 4.5
+    targets = rng.uniform(0, box, (1500, 3))
+    dirs = np.array([[1, 0, 0], [0, -1, 0], [1, 1, 0], [1, -1, 1], [-1, -1, -1],
+                     [0, 1, 1]], float)
+    dirs /= np.linalg.norm(dirs, axis=1)[:, None]
+    pick = rng.choice(len(targets), 600, replace=False)
+    eps = 10.0 ** rng.uniform(-14, -6, 600)
+    src = targets[pick] + (r_cut * (1 - eps))[:, None] * dirs[rng.integers(0, 6, 600)]
+    pos = np.mod(np.concatenate([targets, src]), box)
+    m = rng.uniform(0.5, 1.5, len(pos))
+    ref, _ = direct.brute_force(pos, m, box, r_s, r_cut)
+    for ml in (16, 64):
+        print(f"case: near-cutoff shell, leaf {ml}", flush=True)
+        acc, _ = gpu_forward(pos, m, box, r_s, r_cut, ml)
+        assert metrics.error_summary(acc, ref)["max"] <= 1e-12
+        acc, _ = gpu_forward(pos, m, box, r_s, r_cut, ml, precision=B.PMFMM_FP64,
+                             trunc=B.TRUNC_R2, table_size=64, table_level=6)
+        e = metrics.error_summary(acc, ref)
+        assert e["p999"] <= 1e-12 and e["max"] <= 1e-10, e
+
+
 def test_unwrapped_device_input_is_wrapped():
     rng = np.random.default_rng(3)
     pos = rng.uniform(0, 20.0, (500, 3))

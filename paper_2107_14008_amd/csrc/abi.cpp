@@ -1013,8 +1013,10 @@ int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream) {
     HIP_TRY(pmfmm::launch_p2p(mode, a, wg, grid, lds, s));
     if (timing) HIP_TRY(hipEventRecord(ctx->ev[2], s));
     pmfmm::ReduceArgs r{ctx->d.leaf.as<int4>(), ctx->d.leaf_slot.as<int32_t>(), ctx->d.partial.as<double>(),
-                        ctx->far ? ctx->d.far.as<double>() : nullptr, ctx->d.perm.as<int32_t>(),
-                        ctx->d.boxes.as<pmfmm::BoxDev>(), acc, (int32_t)pl.leaf_count.size()};
+                        ctx->far ? ctx->d.far.as<double>() : nullptr,
+                        ctx->far ? ctx->d.farflag.as<int32_t>() + 2 * (int64_t)pl.cells.size() : nullptr,
+                        ctx->d.perm.as<int32_t>(), ctx->d.boxes.as<pmfmm::BoxDev>(), acc,
+                        (int32_t)pl.leaf_count.size()};
     HIP_TRY(pmfmm::launch_reduce(r, s));
     if (timing) {
         HIP_TRY(hipEventRecord(ctx->ev[3], s));

@@ -154,6 +154,7 @@ struct ReduceArgs {
     const int32_t* leaf_slot;   // n_leaves + 1
     const double* partial;
     const double* far;          // (n, 3) leaf order or nullptr
+    const int32_t* needL;       // per cell: far holds the leaf's particles (with far)
     const int32_t* perm;
     const BoxDev* boxes;
     double* out;                // (n, 3) caller order

@@ -98,11 +98,14 @@ __device__ double d_entry(int a, int b, int c, const double R[3], const double* 
 }
 
 // ---- P2M: one wavefront per leaf, lanes own coefficients.
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
 p2m_kernel(const double4* __restrict__ x64, const int4* __restrict__ leaf,
            const double4* __restrict__ cellc, const BoxDev* __restrict__ boxes,
            const int32_t* __restrict__ needM, double* __restrict__ M, int n_leaves, int ncoef) {
-    const int l = blockIdx.x;
+    // four leaves per workgroup, one wavefront each: most leaves need no
+    // multipole and their wavefront returns at once
+    const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (l >= n_leaves) return;
     const int4 li = leaf[l];
     if (!needM[li.w]) return;
@@ -110,7 +113,7 @@ p2m_kernel(const double4* __restrict__ x64, const int4* __restrict__ leaf,
     if (p < 0) return;
     const int nc = ncoef_of(p);
     const double4 c = cellc[li.w];
-    for (int k = threadIdx.x; k < nc; k += 64) {
+    for (int k = lane; k < nc; k += 64) {
         const int a = c_mi.a[k], b = c_mi.b[k], cc = c_mi.c[k];
         const double inv = c_ifact[a] * c_ifact[b] * c_ifact[cc];
         double acc = 0.0;
@@ -253,21 +256,24 @@ l2l_kernel(const int32_t* __restrict__ level_cells, int n_level, const int4* __r
     }
 }
 
-// ---- L2P: one wavefront per leaf, lane = particle.
-__global__ void __launch_bounds__(64)
+// ---- L2P: one wavefront per leaf (four per workgroup), lane = particle.
+// Only leaves with a local expansion are written; the reduction reads the
+// far part of exactly those (the same needL flag).
+__global__ void __launch_bounds__(256)
 l2p_kernel(const double4* __restrict__ x64, const int4* __restrict__ leaf,
            const double4* __restrict__ cellc, const BoxDev* __restrict__ boxes,
            const int32_t* __restrict__ needL, const double* __restrict__ Lc,
            double* __restrict__ far, int n_leaves, int ncoef) {
-    const int l = blockIdx.x;
+    const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (l >= n_leaves) return;
     const int4 li = leaf[l];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     if (lane >= li.y) return;
     const int k = li.x + lane;
     const int p = boxes[li.z].order;
+    if (p < 0 || !needL[li.w]) return;
     double ax = 0.0, ay = 0.0, az = 0.0;
-    if (p >= 0 && needL[li.w]) {
+    {
         const int nc = ncoef_of(p);
         const double4 c = cellc[li.w];
         const double4 q = x64[k];
@@ -494,8 +500,8 @@ hipError_t launch_far_flags(const FarArgs& a, hipStream_t s) {
 
 hipError_t launch_p2m(const FarArgs& a, hipStream_t s) {
     if (a.n_leaves == 0) return hipSuccess;
-    hipLaunchKernelGGL(p2m_kernel, dim3(a.n_leaves), dim3(64), 0, s, a.x64, a.leaf, a.cellc,
-                       a.boxes, a.needM, a.M, a.n_leaves, a.ncoef);
+    hipLaunchKernelGGL(p2m_kernel, dim3((a.n_leaves + 3) / 4), dim3(256), 0, s, a.x64, a.leaf,
+                       a.cellc, a.boxes, a.needM, a.M, a.n_leaves, a.ncoef);
     return hipGetLastError();
 }
 
@@ -547,8 +553,8 @@ hipError_t launch_far_adj(const FarArgs& a, double4* fg, hipStream_t s) {
 
 hipError_t launch_l2p(const FarArgs& a, hipStream_t s) {
     if (a.n_leaves == 0) return hipSuccess;
-    hipLaunchKernelGGL(l2p_kernel, dim3(a.n_leaves), dim3(64), 0, s, a.x64, a.leaf, a.cellc,
-                       a.boxes, a.needL, a.Lc, a.far, a.n_leaves, a.ncoef);
+    hipLaunchKernelGGL(l2p_kernel, dim3((a.n_leaves + 3) / 4), dim3(256), 0, s, a.x64, a.leaf,
+                       a.cellc, a.boxes, a.needL, a.Lc, a.far, a.n_leaves, a.ncoef);
     return hipGetLastError();
 }
 

@@ -553,12 +553,13 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
 }
 
 // One wavefront per leaf: sum the leaf's item partials in slot order, add
-// the far-field part, scale by G and scatter to the caller's order.
+// the far-field part (leaves with a local expansion), scale by G and
+// scatter to the caller's order.
 __global__ void __launch_bounds__(256)
 reduce_kernel(const int4* __restrict__ leaf, const int32_t* __restrict__ leaf_slot,
               const double* __restrict__ partial, const double* __restrict__ far,
-              const int32_t* __restrict__ perm, const BoxDev* __restrict__ boxes,
-              double* __restrict__ out, int32_t n_leaves) {
+              const int32_t* __restrict__ needL, const int32_t* __restrict__ perm,
+              const BoxDev* __restrict__ boxes, double* __restrict__ out, int32_t n_leaves) {
     const int l = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (l >= n_leaves) return;
@@ -573,7 +574,7 @@ reduce_kernel(const int4* __restrict__ leaf, const int32_t* __restrict__ leaf_sl
         az += p[128 + lane];
     }
     const int k = li.x + lane;
-    if (far != nullptr) {
+    if (far != nullptr && needL[li.w]) {   // L2P wrote only these leaves
         ax += far[3 * (size_t)k];
         ay += far[3 * (size_t)k + 1];
         az += far[3 * (size_t)k + 2];
@@ -704,7 +705,7 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
     if (a.n_leaves == 0) return hipSuccess;
     const int wgs = (a.n_leaves + 3) / 4;
     hipLaunchKernelGGL(reduce_kernel, dim3(wgs), dim3(256), 0, s, a.leaf, a.leaf_slot, a.partial,
-                       a.far, a.perm, a.boxes, a.out, a.n_leaves);
+                       a.far, a.needL, a.perm, a.boxes, a.out, a.n_leaves);
     return hipGetLastError();
 }
 

@@ -147,8 +147,12 @@ int pmfmm_plan_batch(pmfmm_ctx* ctx, int32_t nbox,
  * on_device = 0: pos and mass are host pointers (copied to the device);
  * 1: device pointers (the host planner copies them to the host first).  The
  * particles are gathered into leaf order on the device.  Synchronises
- * `stream` before returning (list sizes come back to the host).  The caller
- * may free or change pos and mass when the call returns.
+ * `stream` before returning (list sizes come back to the host).  With the
+ * GPU planner and the far field on, the far field (P2M .. L2P) is started
+ * here, on a stream the context owns, as soon as the M2L lists exist; it
+ * may still run when the call returns, and the next forward, adjoint or
+ * build on any stream waits for it.  The caller may free or change pos and
+ * mass when the call returns.
  * Errors: those of pmfmm_plan, EDEVICE, ENOMEM. */
 int pmfmm_build(pmfmm_ctx* ctx, int64_t n, const double* pos,
                 const double* mass, int32_t on_device, void* stream);
@@ -168,10 +172,11 @@ int pmfmm_set_eval(pmfmm_ctx* ctx, const pmfmm_params* p);
 
 /* Short-range accelerations of the built particles.  `acc` is a device
  * pointer to (n_total, 3) float64, written in the caller's particle order
- * (boxes consecutive for a batch).  Enqueues: far field (if on), the
- * persistent P2P kernel (Alg. 1 / Alg. 2), the ordered reduction of the
- * work-item partials, all on `stream`.  Results are bitwise reproducible
- * run to run.  Errors: ESTATE (not built), EDEVICE. */
+ * (boxes consecutive for a batch).  Enqueues: far field (if on and not
+ * already started by the build; otherwise a wait for it), the persistent
+ * P2P kernel (Alg. 1 / Alg. 2), the ordered reduction of the work-item
+ * partials, all on `stream`.  Results are bitwise reproducible run to run.
+ * Errors: ESTATE (not built), EDEVICE. */
 int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream);
 
 /* Gradient of loss = sum_i w_i . a_i with respect to positions and masses
@@ -246,7 +251,9 @@ int pmfmm_get_lists(const pmfmm_ctx* ctx, pmfmm_lists* out);
  * HIP events recorded on the call's stream (only when params.timing = 1;
  * this call waits for those events). */
 typedef struct pmfmm_timings {
-    double far_ms;       /* P2M .. L2P                               */
+    double far_ms;       /* P2M .. L2P (with the GPU planner the far
+                            field runs during pmfmm_build, on a stream
+                            of the library's beside the work items)  */
     double p2p_ms;       /* the persistent P2P kernel alone          */
     double reduce_ms;    /* ordered reduction + write-back           */
     double total_ms;     /* whole forward                            */

@@ -353,6 +353,11 @@ struct pmfmm_ctx {
     // timing
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     bool timed_fwd = false, timed_adj = false;
+    // far field started by the GPU build on a stream of its own while the
+    // work items are made (far_done ends it; far_t0 / far_t1 time it)
+    hipStream_t side = nullptr;
+    hipEvent_t far_fork = nullptr, far_done = nullptr, far_t0 = nullptr, far_t1 = nullptr;
+    bool far_early = false;     // d.far holds this build's far field (after far_done)
     // long-range mesh of pmfmm_long_range
     pmfmm::PMPlan pm;
 
@@ -365,6 +370,9 @@ struct pmfmm_ctx {
         pmfmm::pm_release(pm);
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : {far_fork, far_done, far_t0, far_t1})
+            if (e) (void)hipEventDestroy(e);
+        if (side) (void)hipStreamDestroy(side);
     }
 };
 
@@ -659,6 +667,45 @@ int run_far(pmfmm_ctx* ctx, hipStream_t s) {
     return PMFMM_OK;
 }
 
+int far_buffers(pmfmm_ctx* ctx, int64_t n) {
+    const int64_t nc = (int64_t)ctx->plan.cells.size();
+    const int nco = pmfmm::n_coef(ctx->plan.max_order);
+    HIP_TRY(ctx->d.M.ensure((size_t)nc * nco * sizeof(double)));
+    HIP_TRY(ctx->d.Lc.ensure((size_t)nc * nco * sizeof(double)));
+    HIP_TRY(ctx->d.Lt.ensure((size_t)std::max<int64_t>(1, ctx->n_m2l) * nco * sizeof(double)));
+    HIP_TRY(ctx->d.far.ensure((size_t)n * 3 * sizeof(double)));
+    return PMFMM_OK;
+}
+
+// Starts marks + far field of the current build on the side stream after
+// the work enqueued so far on s; far_done marks its end.
+int start_far(pmfmm_ctx* ctx, int64_t n, hipStream_t s) {
+    int rc = far_buffers(ctx, n);
+    if (rc) return rc;
+    if (!ctx->side) HIP_TRY(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    for (hipEvent_t* e : {&ctx->far_fork, &ctx->far_done})
+        if (!*e) HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    for (hipEvent_t* e : {&ctx->far_t0, &ctx->far_t1})
+        if (!*e) HIP_TRY(hipEventCreate(e));
+    HIP_TRY(hipEventRecord(ctx->far_fork, s));
+    HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->far_fork, 0));
+    ctx->far = true;
+    if ((rc = prepare_far(ctx, ctx->side))) return rc;
+    HIP_TRY(hipEventRecord(ctx->far_t0, ctx->side));
+    if ((rc = run_far(ctx, ctx->side))) return rc;
+    HIP_TRY(hipEventRecord(ctx->far_t1, ctx->side));
+    HIP_TRY(hipEventRecord(ctx->far_done, ctx->side));
+    ctx->far_early = true;
+    return PMFMM_OK;
+}
+
+// Orders s after the side stream's far field (before anything that reuses
+// its buffers or reads its result).
+int wait_far(pmfmm_ctx* ctx, hipStream_t s) {
+    if (ctx->far_early) HIP_TRY(hipStreamWaitEvent(s, ctx->far_done, 0));
+    return PMFMM_OK;
+}
+
 // Far-field part of the adjoint into fargrad (leaf order, no G): the
 // forward locals give the L2P Hessian term; then the transposed pass on
 // sign-flipped coefficients (leaf W2M, the same pass-up / M2L / pass-down
@@ -741,7 +788,22 @@ int gpu_build(pmfmm_ctx* ctx, const std::vector<pmfmm::BoxParams>& boxes, const 
     }
     pmfmm::PlanCounts pc;
     std::string input_err;
-    std::string err = pmfmm::gpu_build_plan(ctx->d, ctx->plan, dp, dm, ctx->p.chunk, s, pc, &input_err);
+    // the far field needs the tree, the leaf-ordered particles and the M2L
+    // lists, not the work items: start it on the side stream once the M2L
+    // lists are enqueued, so it runs while the items are built
+    int far_rc = PMFMM_OK;
+    const int64_t n_all = n;
+    auto far_start = [&](int64_t n_m2l, int32_t dsrc, int32_t dtgt) -> std::string {
+        if (n_m2l <= 0) return std::string();
+        ctx->n_m2l = n_m2l;
+        ctx->m2l_dmin_src = dsrc;
+        ctx->m2l_dmin_tgt = dtgt;
+        far_rc = start_far(ctx, n_all, s);
+        return far_rc ? std::string("far field") : std::string();
+    };
+    std::string err = pmfmm::gpu_build_plan(ctx->d, ctx->plan, dp, dm, ctx->p.chunk, s, pc, &input_err,
+                                            far_start);
+    if (far_rc) return far_rc;
     if (!input_err.empty()) return fail(PMFMM_EINVAL, input_err);
     if (!err.empty()) return fail(PMFMM_EDEVICE, err);
     ctx->n_p2p = pc.n_p2p;
@@ -754,13 +816,8 @@ int gpu_build(pmfmm_ctx* ctx, const std::vector<pmfmm::BoxParams>& boxes, const 
     ctx->plan.far_field = ctx->far;
     ctx->plan.candidate_pairs = pc.candidate_pairs;
     HIP_TRY(ctx->d.counter.ensure(pmfmm::kQueueSegs * pmfmm::kCounterStride * 4));
-    if (ctx->far) {
-        const int64_t nc = (int64_t)ctx->plan.cells.size();
-        const int nco = pmfmm::n_coef(ctx->plan.max_order);
-        HIP_TRY(ctx->d.M.ensure((size_t)nc * nco * sizeof(double)));
-        HIP_TRY(ctx->d.Lc.ensure((size_t)nc * nco * sizeof(double)));
-        HIP_TRY(ctx->d.Lt.ensure((size_t)std::max<int64_t>(1, ctx->n_m2l) * nco * sizeof(double)));
-        HIP_TRY(ctx->d.far.ensure((size_t)n * 3 * sizeof(double)));
+    if (ctx->far && !ctx->far_early) {
+        if ((rc = far_buffers(ctx, n))) return rc;
         if ((rc = prepare_far(ctx, s))) return rc;
     }
     if ((rc = upload_table(ctx, s))) return rc;
@@ -879,6 +936,11 @@ static int build_common(pmfmm_ctx* ctx, const std::vector<pmfmm::BoxParams>& box
                         const std::vector<int64_t>& cnt, const double* pos, const double* mass,
                         int32_t on_device, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // the previous build's far field (side stream) reads buffers this build
+    // rewrites
+    int wrc = wait_far(ctx, s);
+    if (wrc) return wrc;
+    ctx->far_early = false;
     if (ctx->p.planner == 0) return gpu_build(ctx, boxes, cnt, pos, mass, on_device, s);
     int64_t n = 0;
     for (int64_t c : cnt) n += c;
@@ -984,7 +1046,11 @@ int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream) {
         HIP_TRY(hipEventRecord(ctx->ev[0], s));
     }
     if (ctx->far) {
-        if ((rc = run_far(ctx, s))) return rc;
+        if (ctx->far_early) {
+            if ((rc = wait_far(ctx, s))) return rc;   // computed during the build
+        } else if ((rc = run_far(ctx, s))) {
+            return rc;
+        }
     }
     HIP_TRY(pmfmm::launch_zero_i32(ctx->d.counter.as<int32_t>(), pmfmm::kQueueSegs * pmfmm::kCounterStride, s));
     if (timing) HIP_TRY(hipEventRecord(ctx->ev[1], s));
@@ -1096,7 +1162,12 @@ int pmfmm_get_timings(const pmfmm_ctx* ctx, pmfmm_timings* out) {
     float ms = 0.f;
     if (ctx->timed_fwd) {
         HIP_TRY(hipEventSynchronize(ctx->ev[3]));
-        HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+        if (ctx->far_early) {
+            // run by the build on the side stream, beside the work items
+            HIP_TRY(hipEventElapsedTime(&ms, ctx->far_t0, ctx->far_t1));
+        } else {
+            HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+        }
         out->far_ms = ms;
         HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
         out->p2p_ms = ms;
@@ -1117,6 +1188,12 @@ int pmfmm_adjoint(pmfmm_ctx* ctx, const double* w, double* grad_pos, double* gra
     if (!ctx || !w || !grad_pos || !grad_mass) return fail(PMFMM_EINVAL, "null argument");
     if (!ctx->built) return fail(PMFMM_ESTATE, "adjoint before build");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    {
+        // the far-field adjoint reuses the multipole buffers of the build's
+        // far field
+        int rc = wait_far(ctx, s);
+        if (rc) return rc;
+    }
     const pmfmm::Plan& pl = ctx->plan;
     const int64_t n = pl.n;
     HIP_TRY(ctx->d.w64.ensure((size_t)n * 32));

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <utility>
 #include <vector>
@@ -126,6 +127,12 @@ hipError_t gpu_enqueue_checks(DevPlan& d, const double* pos, const double* mass,
 // per-box constants.
 hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, hipStream_t s);
 
+// Called by gpu_build_plan as soon as the M2L lists are enqueued on `s`
+// (before the work items), with the M2L task count and the smallest source
+// / target depth, so that the far field can start on another stream while
+// the items are built.  Returns an error message ("" on success).
+using M2LReady = std::function<std::string(int64_t n_m2l, int32_t dmin_src, int32_t dmin_tgt)>;
+
 // Builds the plan on the device from caller-order particles `pos` (n, 3) and
 // `mass` (n) in device memory, for the shape uploaded by upload_topology.
 // Fills perm, cell bounds and centres, x64 / x32, the P2P and M2L CSR, the
@@ -134,7 +141,8 @@ hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, h
 // gpu_enqueue_checks (which must precede it on `s`) fail, stops early and
 // sets *input_error to a message naming the first offending particle.
 std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, const double* mass,
-                           int chunk, hipStream_t s, PlanCounts& out, std::string* input_error);
+                           int chunk, hipStream_t s, PlanCounts& out, std::string* input_error,
+                           const M2LReady& on_m2l = M2LReady());
 
 // Re-cuts the work items for a new chunk size from the device CSR.
 std::string gpu_make_items(DevPlan& d, const Plan& topo, int64_t n_p2p, int chunk, hipStream_t s,

@@ -792,6 +792,24 @@ k_walk_dev(const int2* __restrict__ front, int2* __restrict__ next, int it,
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&ctl[3], nf);
 }
 
+// Smallest target / source depth of the walk's M2L keys (key = t << ks |
+// u << 5 | s), kept as 0x7fffffff - depth by atomicMax into zeroed words
+// out[0] (targets) and out[1] (sources); the key count is *count.
+__global__ void k_m2l_depths(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ count,
+                             uint32_t cap, int ks, const int4* __restrict__ aux,
+                             uint32_t* __restrict__ out) {
+    const uint32_t n = min(*count, cap);
+    uint32_t bt = 0u, bs = 0u;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const uint64_t key = keys[k];
+        const int t = (int)(key >> ks), u = (int)((key & ((1ull << ks) - 1ull)) >> 5);
+        bt = max(bt, 0x7fffffffu - (uint32_t)aux[t].w);
+        bs = max(bs, 0x7fffffffu - (uint32_t)aux[u].w);
+    }
+    if (bt) atomicMax(&out[0], bt);
+    if (bs) atomicMax(&out[1], bs);
+}
+
 // The walk's first frontier: for each box, its root against itself with the
 // zero shift and the 13 shifts of code > 13 (the canonical half).
 __global__ void k_walk_init(int nbox, const int32_t* __restrict__ box_root, int2* __restrict__ front,
@@ -1193,7 +1211,8 @@ hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, h
 }
 
 std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, const double* mass,
-                           int chunk, hipStream_t s, PlanCounts& out, std::string* input_error) {
+                           int chunk, hipStream_t s, PlanCounts& out, std::string* input_error,
+                           const M2LReady& on_m2l) {
     input_error->clear();
     const int64_t n = topo.n;
     const int nbox = (int)topo.boxes.size();
@@ -1345,6 +1364,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
             f0[2 * (14 * b + q) + 1] = (root << 5) | (13 + q);
         }
     int64_t n_p2p = 0, n_m2l = 0;
+    int32_t dmin_src = 0x7fffffff, dmin_tgt = 0x7fffffff;
     bool done = false;
     const int2 ks = make_int2(5 + bits_for((uint64_t)std::max<int64_t>(1, nl - 1)),
                               5 + bits_for((uint64_t)std::max<int64_t>(1, nc - 1)));
@@ -1375,9 +1395,11 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                                d.walkbox.as<WalkBox>(), d.wcell.as<WalkCell>(), ks,
                                d.p2p_keys.as<uint64_t>(), d.m2l_keys.as<uint64_t>());
         }
+        hipLaunchKernelGGL(k_m2l_depths, dim3(8), dim3(256), 0, s, d.m2l_keys.as<uint64_t>(),
+                           ctl + 1, capm, ks.y, d.cell_aux.as<int4>(), ctl + 5 + L);
         TRY(hipGetLastError());
-        std::vector<uint32_t> hc(L + 5);
-        TRY(hipMemcpyAsync(hc.data(), ctl, (L + 5) * 4, hipMemcpyDeviceToHost, s));
+        std::vector<uint32_t> hc(L + 7);
+        TRY(hipMemcpyAsync(hc.data(), ctl, (L + 7) * 4, hipMemcpyDeviceToHost, s));
         TRY(hipStreamSynchronize(s));
         if (clk.on) {
             std::fprintf(stderr, "[pmfmm gpu plan] walk frontier per level:");
@@ -1387,6 +1409,8 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         if (hc[2] == 0 && hc[4 + L] == 0 && hc[0] <= capp && hc[1] <= capm) {
             n_p2p = hc[0];
             n_m2l = hc[1];
+            dmin_tgt = (int32_t)(0x7fffffffu - hc[5 + L]);
+            dmin_src = (int32_t)(0x7fffffffu - hc[6 + L]);
             d.walk_sizes.assign(hc.begin() + 4, hc.begin() + 4 + L);
             done = true;
         }
@@ -1425,6 +1449,21 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
             ++levels;
             std::swap(d.front, d.front_next);
         }
+        if (n_m2l > 0) {
+            // smallest M2L depths (words 4, 5 of wcount, zeroed here)
+            uint32_t cnt32 = (uint32_t)n_m2l;
+            TRY(hipMemcpyAsync(d.wcount.as<uint32_t>() + 6, &cnt32, 4, hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, d.wcount.as<uint32_t>() + 4, 2);
+            hipLaunchKernelGGL(k_m2l_depths, dim3(8), dim3(256), 0, s, d.m2l_keys.as<uint64_t>(),
+                               d.wcount.as<uint32_t>() + 6, (uint32_t)n_m2l, ks.y,
+                               d.cell_aux.as<int4>(), d.wcount.as<uint32_t>() + 4);
+            TRY(hipGetLastError());
+            uint32_t dd[2] = {0u, 0u};
+            TRY(hipMemcpyAsync(dd, d.wcount.as<uint32_t>() + 4, 8, hipMemcpyDeviceToHost, s));
+            TRY(hipStreamSynchronize(s));
+            dmin_tgt = (int32_t)(0x7fffffffu - dd[0]);
+            dmin_src = (int32_t)(0x7fffffffu - dd[1]);
+        }
         // sizes for the next build of this shape (with some room to move)
         d.walk_levels = levels + 2;
         d.walk_cap_front = (uint32_t)std::min<int64_t>(0x7fffffff, max_front + max_front / 2 + 4096);
@@ -1458,7 +1497,9 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     const RowList lists[2] = {{d.p2p_keys, n_p2p, (int)nl, ks.x, d.p2p_row, d.js, d.p2p_keys_tmp},
                               {d.m2l_keys, n_m2l, (int)nc, ks.y, d.m2l_row, d.m2l_vals,
                                d.m2l_keys_tmp}};
-    for (const RowList& rl : lists) {
+    // the M2L rows first: the far field can then start (on_m2l) while the
+    // P2P rows and the work items are built
+    auto make_rows = [&](const RowList& rl) -> hipError_t {
         int32_t* cnt = d.rowcnt.as<int32_t>();
         int32_t* slot = rl.tmp.as<int32_t>();
         hipLaunchKernelGGL(k_zero_u32, dim3(grid_of(rl.nrows + 2)), dim3(256), 0, s,
@@ -1466,8 +1507,10 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         if (rl.nk > 0)
             hipLaunchKernelGGL(k_row_count, dim3(grid_of(rl.nk)), dim3(256), 0, s,
                                rl.keys.as<uint64_t>(), rl.nk, rl.ks, cnt, slot);
-        TRY(hipGetLastError());
-        TRY(exclusive_scan_i32(cnt, rl.row.as<int32_t>(), rl.nrows + 1, d.tile_sums.as<uint32_t>(), s));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = exclusive_scan_i32(cnt, rl.row.as<int32_t>(), rl.nrows + 1, d.tile_sums.as<uint32_t>(), s);
+        if (e != hipSuccess) return e;
         if (rl.nk > 0) {
             hipLaunchKernelGGL(k_row_place, dim3(grid_of(rl.nk)), dim3(256), 0, s,
                                rl.keys.as<uint64_t>(), rl.nk, rl.ks, rl.row.as<int32_t>(), slot,
@@ -1480,8 +1523,9 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                                rl.vals.as<int32_t>(), d.longrows.as<int32_t>(), nlong, slot,
                                row_lds_cap());
         }
-        TRY(hipGetLastError());
-    }
+        return hipGetLastError();
+    };
+    TRY(make_rows(lists[1]));
     // wcount words 16, 17: smallest source / target depth of the M2L tasks
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int*>(d.wcount.p) + 16,
                        2, 0x7fffffff);
@@ -1491,6 +1535,11 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                            d.m2l_src.as<int32_t>(), d.m2l_shift.as<int32_t>(),
                            reinterpret_cast<int32_t*>(d.wcount.p) + 16);
     TRY(hipGetLastError());
+    if (on_m2l) {
+        std::string e = on_m2l(n_m2l, dmin_src, dmin_tgt);
+        if (!e.empty()) return e;
+    }
+    TRY(make_rows(lists[0]));
     out.n_p2p = n_p2p;
     out.n_m2l = n_m2l;
     clk.lap("csr");

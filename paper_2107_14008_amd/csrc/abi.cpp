@@ -133,12 +133,15 @@ double truncation_T(double x) {
 // on it F is the polynomial of degree `deg` interpolating F at the
 // Chebyshev nodes of the segment, re-expanded in s itself (the kernel
 // evaluates it at s with no segment offset).  The last row (s = 2^kR2Emax)
-// is zero.
+// is zero.  Stored as three planes of kR2Plane floats (c0, c1, c2 at row k
+// of planes 0, 1, 2): a lane's three reads then hit banks spread by the row
+// itself rather than by a 16-byte row stride, and c0 and c1 come in one
+// two-address read.
 std::vector<unsigned char> build_r2_table(int per_octave, int deg, double xc) {
     const int bits = per_octave == 16 ? 4 : per_octave == 32 ? 5 : per_octave == 64 ? 6 : 7;
     const int rows = (pmfmm::kR2Emax - pmfmm::kR2Emin) << bits;
     const double kappa = xc * xc / std::ldexp(1.0, pmfmm::kR2Emax);
-    std::vector<unsigned char> out((size_t)16 * (rows + 1) + 16, 0);
+    std::vector<unsigned char> out((size_t)12 * pmfmm::kR2Plane + 16, 0);
     float* f = reinterpret_cast<float*>(out.data());
     const int m = deg + 1;
     for (int k = 0; k < rows; ++k) {
@@ -178,7 +181,7 @@ std::vector<unsigned char> build_r2_table(int per_octave, int deg, double xc) {
         for (int i = 0; i < m; ++i) {
             double acc = 0.0;
             for (int q = i; q < m; ++q) acc += cl[q] * binom[q][i] * std::pow(-lo, q - i);
-            f[4 * k + i] = (float)acc;
+            f[(size_t)pmfmm::kR2Plane * i + k] = (float)acc;
         }
     }
     return out;

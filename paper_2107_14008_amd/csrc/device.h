@@ -40,6 +40,9 @@ constexpr int kR2Emax = 11;
 // float64 r^2 table: scaled r^2 in [2^kR2Emin64, 2^kR2Emax); closer pairs
 // (r < 2^-8 r_cut) take the exact erfc / exp path.
 constexpr int kR2Emin64 = kR2Emax - 16;
+// float32 r^2 table: three planes (c0, c1, c2) of kR2Plane floats each, room
+// for 128 segments per octave; the plane stride is a multiple of 256 bytes.
+constexpr int kR2Plane = 5952;
 
 // ------------------------------------------------------ source culling
 //

@@ -225,13 +225,13 @@ __device__ __forceinline__ void pair_f32_r2(const float4 q, float px, float py, 
         // r2 >= +0, so the clamp below smin is an unsigned max of the bits
         const uint32_t sb = max(__float_as_uint(r2), __float_as_uint(smin));
         const float sc = __uint_as_float(sb);
-        // boff = -(row of 2^kR2Emin) * 16 mod 2^32: one shift-add per address
-        const float4 c = *reinterpret_cast<const float4*>(tab + (((sb >> shift) << 4) + boff));
+        // boff = -(row of 2^kR2Emin) * 4 mod 2^32: one shift-add per address
+        const float* c = reinterpret_cast<const float*>(tab + (((sb >> shift) << 2) + boff));
         float F;
         if constexpr (LEVEL == 1) {
-            F = fmaf(c.y, sc, c.x);
+            F = fmaf(c[kR2Plane], sc, c[0]);
         } else {
-            F = fmaf(fmaf(c.z, sc, c.y), sc, c.x);
+            F = fmaf(fmaf(c[2 * kR2Plane], sc, c[kR2Plane]), sc, c[0]);
         }
         const float g = q.w * F;
         ax = fmaf(g, dx, ax);
@@ -349,7 +349,8 @@ __device__ __forceinline__ void leaf_f64_r2(const double4* __restrict__ src, int
 
 // LDS table layouts (bytes), matching the host builder in abi.cpp:
 //   float64 r^2 table: double c0 .. c(NC-1) per row [16 2^bits rows]
-//   float32 r^2 table: float4 (c0, c1, c2, 0) [(kR2Emax - kR2Emin) 2^bits + 1]
+//   float32 r^2 table: float c0 [kR2Plane], c1 [kR2Plane], c2 [kR2Plane]
+//                      (rows (kR2Emax - kR2Emin) 2^bits + 1 <= kR2Plane)
 //   float32: float4 c0..c3 [n_tab + 1], then float c4 [n_tab + 1]
 //   float64: double2 (c0, c1) [n_tab], double2 (c2, c3) [n_tab], double c4 [n_tab]
 __device__ __forceinline__ void load_table(unsigned char* lds, const void* __restrict__ table,
@@ -408,7 +409,7 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
             // r^2 table: n_tab = segments per octave = 2^bits
             const uint32_t r2bits = 31u - (uint32_t)__builtin_clz((uint32_t)n_tab);
             const uint32_t r2shift = 23u - r2bits;
-            const uint32_t r2boff = 0u - (((uint32_t)(127 + kR2Emin) << r2bits) << 4);
+            const uint32_t r2boff = 0u - (((uint32_t)(127 + kR2Emin) << r2bits) << 2);
             // box of the wave's targets in their leaf's frame (lanes past
             // the leaf repeat target 0)
             float3 lo = make_float3(pv.x, pv.y, pv.z), hi = lo;

@@ -79,3 +79,34 @@ def test_far_field_reproducible(halo):
     ctx.forward(out)
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), a1)
+
+
+def test_far_field_started_by_the_build(halo):
+    """With the GPU planner the build starts the far field on the context's
+    own stream.  Two builds back to back (the second rewrites what the first
+    one's far field reads, so it must wait for it), then forwards on another
+    stream, twice: every result is the oracle FMM of the second system."""
+    w = halo
+    other = inputs.clustered_small(14, 22, halo_frac=0.5, n_halos=3,
+                                   max_leaf=16)
+    print("case: far field started by the build, two builds, side stream", flush=True)
+    ctx = B.Context(box=w.box, r_s=w.r_s, r_cut=w.r_cut, max_leaf=16, order=4,
+                    theta=0.3)
+    ctx.build(torch.tensor(other.pos, device="cuda"),
+              torch.tensor(other.mass, device="cuda"))
+    ctx.build(torch.tensor(w.pos, device="cuda"),
+              torch.tensor(w.mass, device="cuda"))
+    assert ctx.lists()["n_m2l"] > 0
+    ref = fmm.fmm_forces(w.pos, w.mass, w.box, w.r_s, w.r_cut, 16, 4, 0.3)
+    s2 = torch.cuda.Stream()
+    s2.wait_stream(torch.cuda.current_stream())
+    outs = []
+    with torch.cuda.stream(s2):
+        for _ in range(2):
+            out = torch.empty((len(w.mass), 3), dtype=torch.float64, device="cuda")
+            ctx.forward(out, s2)
+            outs.append(out)
+    torch.cuda.synchronize()
+    for out in outs:
+        assert metrics.error_summary(out.cpu().numpy(), ref)["max"] <= 1e-12
+    assert np.array_equal(outs[0].cpu().numpy(), outs[1].cpu().numpy())

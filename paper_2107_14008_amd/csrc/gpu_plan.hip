@@ -1246,20 +1246,12 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                            n, d.wpos.as<double>(), reinterpret_cast<int*>(d.wcount.p) + 2);
         TRY(hipGetLastError());
     }
-    // the input checks and the long-run flag come back in one round trip
+    // The input checks (wcount[0..1]) and the long-run flag (wcount[2]) come
+    // back with the walk's counts, in the same round trip: with bad input
+    // the tree is built on wrapped (finite) coordinates and then dropped;
+    // with a long run the build is redone with the 64-bit sort (force64).
     {
-        int flags[3] = {0, 0, 0};
-        TRY(hipMemcpyAsync(flags, d.wcount.p, 12, hipMemcpyDeviceToHost, s));
-        TRY(hipStreamSynchronize(s));
-        if (flags[0] != 0x7fffffff) {
-            *input_error = "non-finite position at particle " + std::to_string(flags[0]);
-            return std::string();
-        }
-        if (flags[1] != 0x7fffffff) {
-            *input_error = "negative or non-finite mass at particle " + std::to_string(flags[1]);
-            return std::string();
-        }
-        if (flags[2] != 0) {
+        if (d.force64) {
             // coordinates closer than the 32-bit key resolves, out of order
             // in a long run: sort by the full keys
             uint64_t* k = d.keys.as<uint64_t>();
@@ -1366,6 +1358,8 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     int64_t n_p2p = 0, n_m2l = 0;
     int32_t dmin_src = 0x7fffffff, dmin_tgt = 0x7fffffff;
     bool done = false;
+    int flags[3] = {0, 0, 0};
+    bool have_flags = false;
     const int2 ks = make_int2(5 + bits_for((uint64_t)std::max<int64_t>(1, nl - 1)),
                               5 + bits_for((uint64_t)std::max<int64_t>(1, nc - 1)));
     // Level-by-level walk without host round trips, sized from the previous
@@ -1400,7 +1394,9 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         TRY(hipGetLastError());
         std::vector<uint32_t> hc(L + 7);
         TRY(hipMemcpyAsync(hc.data(), ctl, (L + 7) * 4, hipMemcpyDeviceToHost, s));
+        TRY(hipMemcpyAsync(flags, d.wcount.p, 12, hipMemcpyDeviceToHost, s));
         TRY(hipStreamSynchronize(s));
+        have_flags = true;
         if (clk.on) {
             std::fprintf(stderr, "[pmfmm gpu plan] walk frontier per level:");
             for (int it = 0; it <= L; ++it) std::fprintf(stderr, " %u", hc[4 + it]);
@@ -1419,7 +1415,9 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         int64_t nf = nf0;
         TRY(d.front.ensure(std::max<size_t>(f0.size() * 4, 4096)));
         TRY(hipMemcpyAsync(d.front.p, f0.data(), f0.size() * 4, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, d.wcount.as<uint32_t>(), 4);
+        // this loop's counters: wcount[20..23] (words 0..2 hold the checks)
+        uint32_t* wc = d.wcount.as<uint32_t>() + 20;
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, wc, 4);
         if (d.p2p_keys.bytes < 16) TRY(d.p2p_keys.ensure(1 << 20));
         if (d.m2l_keys.bytes < 16) TRY(d.m2l_keys.ensure(1 << 16));
         uint32_t hc[4] = {0, 0, 0, 0};
@@ -1434,13 +1432,12 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                 TRY(d.p2p_keys.grow((size_t)(n_p2p + 2 * nf) * 8 * 2, (size_t)n_p2p * 8, s));
             if ((size_t)(n_m2l + 2 * nf) * 8 > d.m2l_keys.bytes)
                 TRY(d.m2l_keys.grow((size_t)(n_m2l + 2 * nf) * 8 * 2, (size_t)n_m2l * 8, s));
-            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, d.wcount.as<uint32_t>(), 1);
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, wc, 1);
             hipLaunchKernelGGL(k_walk, dim3(grid_of(nf)), dim3(256), 0, s, d.front.as<int2>(), (int)nf,
                                d.front_next.as<int2>(), d.walkbox.as<WalkBox>(), d.wcell.as<WalkCell>(),
-                               ks, d.wcount.as<uint32_t>(), d.p2p_keys.as<uint64_t>(),
-                               d.m2l_keys.as<uint64_t>());
+                               ks, wc, d.p2p_keys.as<uint64_t>(), d.m2l_keys.as<uint64_t>());
             TRY(hipGetLastError());
-            TRY(hipMemcpyAsync(hc, d.wcount.p, 16, hipMemcpyDeviceToHost, s));
+            TRY(hipMemcpyAsync(hc, wc, 16, hipMemcpyDeviceToHost, s));
             TRY(hipStreamSynchronize(s));
             nf = hc[0];
             n_p2p = hc[1];
@@ -1471,6 +1468,26 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         d.walk_cap_m2l = (uint32_t)std::min<int64_t>(0x7fffffff, n_m2l + n_m2l / 4 + 4096);
     }
 
+    if (!have_flags) {
+        TRY(hipMemcpyAsync(flags, d.wcount.p, 12, hipMemcpyDeviceToHost, s));
+        TRY(hipStreamSynchronize(s));
+    }
+    if (flags[0] != 0x7fffffff) {
+        *input_error = "non-finite position at particle " + std::to_string(flags[0]);
+        return std::string();
+    }
+    if (flags[1] != 0x7fffffff) {
+        *input_error = "negative or non-finite mass at particle " + std::to_string(flags[1]);
+        return std::string();
+    }
+    if (flags[2] != 0 && !d.force64) {
+        // a run of equal 32-bit keys too long for k_run_fix: build again
+        // with the full 64-bit sort
+        d.force64 = true;
+        std::string e = gpu_build_plan(d, topo, pos, mass, chunk, s, out, input_error, on_m2l);
+        d.force64 = false;
+        return e;
+    }
     clk.lap("walk");
     // ---- canonical order and CSR
     TRY(d.p2p_row.ensure((nl + 1) * 4));

@@ -731,21 +731,20 @@ k_walk(const int2* __restrict__ front, int nf, int2* __restrict__ next,
 // ctl: [0] p2p total, [1] m2l total, [2] overflow flag, [3] largest frontier;
 // sizes[it] = frontier size of level it.
 constexpr int kWalkT = 1024;
-// k_walk_first runs the leading levels whose frontier (in the last build of
-// the same shape) is at most this, in one workgroup.
-constexpr uint32_t kWalkFirstMax = 2 * kWalkT;
 
-// One level of the walk over front[0, nf) by the threads of the grid
-// (first = this workgroup's first pair, stride = pairs per grid step).
-__device__ void walk_level(const int2* __restrict__ front, int2* __restrict__ next, int it,
-                           uint32_t nf, uint32_t first, uint32_t stride,
-                           uint32_t* __restrict__ sizes, uint32_t* __restrict__ ctl,
-                           uint32_t cap_front, uint32_t cap_p2p, uint32_t cap_m2l,
-                           const WalkBox* __restrict__ wbox, const WalkCell* __restrict__ wcell,
-                           int2 ks, uint64_t* __restrict__ p2p_keys,
-                           uint64_t* __restrict__ m2l_keys, uint64_t* wtot, uint32_t* bbase) {
+__global__ void __launch_bounds__(kWalkT)
+k_walk_dev(const int2* __restrict__ front, int2* __restrict__ next, int it,
+           uint32_t* __restrict__ sizes, uint32_t* __restrict__ ctl, uint32_t cap_front,
+           uint32_t cap_p2p, uint32_t cap_m2l, const WalkBox* __restrict__ wbox,
+           const WalkCell* __restrict__ wcell, int2 ks, uint64_t* __restrict__ p2p_keys,
+           uint64_t* __restrict__ m2l_keys) {
+    __shared__ uint64_t wtot[kWalkT / 64];
+    __shared__ uint32_t bbase[3];
+    const uint32_t nf = sizes[it];
+    if (nf > cap_front) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (uint32_t base = first; base < nf; base += stride) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < nf; base += stride) {
         const uint32_t k = base + threadIdx.x;
         WalkOut o{0u, 0u, 0u, {}, {0ull, 0ull}};
         if (k < nf) walk_classify(front[k], wbox, wcell, ks, o);
@@ -790,47 +789,7 @@ __device__ void walk_level(const int2* __restrict__ front, int2* __restrict__ ne
         }
         __syncthreads();   // wtot and bbase are reused by the next group
     }
-}
-
-__global__ void __launch_bounds__(kWalkT)
-k_walk_dev(const int2* __restrict__ front, int2* __restrict__ next, int it,
-           uint32_t* __restrict__ sizes, uint32_t* __restrict__ ctl, uint32_t cap_front,
-           uint32_t cap_p2p, uint32_t cap_m2l, const WalkBox* __restrict__ wbox,
-           const WalkCell* __restrict__ wcell, int2 ks, uint64_t* __restrict__ p2p_keys,
-           uint64_t* __restrict__ m2l_keys) {
-    __shared__ uint64_t wtot[kWalkT / 64];
-    __shared__ uint32_t bbase[3];
-    const uint32_t nf = sizes[it];
-    if (nf > cap_front) return;
-    walk_level(front, next, it, nf, blockIdx.x * blockDim.x, gridDim.x * blockDim.x, sizes, ctl,
-               cap_front, cap_p2p, cap_m2l, wbox, wcell, ks, p2p_keys, m2l_keys, wtot, bbase);
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&ctl[3], nf);
-}
-
-// Levels 0 .. n_lv - 1 of the walk in one workgroup (their frontiers are
-// small: a launch per level would cost more than the level), alternating
-// between buf0 and buf1 as the host loop does; each level's frontier size
-// is read back from sizes[] after the barrier that ends the previous one.
-__global__ void __launch_bounds__(kWalkT)
-k_walk_first(int2* __restrict__ buf0, int2* __restrict__ buf1, int n_lv,
-             uint32_t* __restrict__ sizes, uint32_t* __restrict__ ctl, uint32_t cap_front,
-             uint32_t cap_p2p, uint32_t cap_m2l, const WalkBox* __restrict__ wbox,
-             const WalkCell* __restrict__ wcell, int2 ks, uint64_t* __restrict__ p2p_keys,
-             uint64_t* __restrict__ m2l_keys) {
-    __shared__ uint64_t wtot[kWalkT / 64];
-    __shared__ uint32_t bbase[3];
-    uint32_t nf_max = 0;
-    for (int it = 0; it < n_lv; ++it) {
-        const uint32_t nf = __hip_atomic_load(&sizes[it], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (nf > cap_front) return;
-        nf_max = max(nf_max, nf);
-        walk_level((it & 1) ? buf1 : buf0, (it & 1) ? buf0 : buf1, it, nf, 0u, blockDim.x, sizes,
-                   ctl, cap_front, cap_p2p, cap_m2l, wbox, wcell, ks, p2p_keys, m2l_keys, wtot,
-                   bbase);
-        __threadfence();
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicMax(&ctl[3], nf_max);
 }
 
 // Smallest target / source depth of the walk's M2L keys (key = t << ks |
@@ -1420,18 +1379,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         hipLaunchKernelGGL(k_walk_init, dim3(grid_of(nf0)), dim3(256), 0, s, nbox,
                            d.item_count.as<int32_t>(), d.front.as<int2>(), sizes);
         DevBuf* bufs[2] = {&d.front, &d.front_next};
-        // leading levels with small frontiers (last build) in one workgroup
-        int it0 = 0;
-        while (it0 < L && it0 < (int)d.walk_sizes.size() && d.walk_sizes[it0] <= kWalkFirstMax)
-            ++it0;
-        if (it0 > 1)
-            hipLaunchKernelGGL(k_walk_first, dim3(1), dim3(kWalkT), 0, s, d.front.as<int2>(),
-                               d.front_next.as<int2>(), it0, sizes, ctl, capf, capp, capm,
-                               d.walkbox.as<WalkBox>(), d.wcell.as<WalkCell>(), ks,
-                               d.p2p_keys.as<uint64_t>(), d.m2l_keys.as<uint64_t>());
-        else
-            it0 = 0;
-        for (int it = it0; it < L; ++it) {
+        for (int it = 0; it < L; ++it) {
             // workgroups for the frontier the last build had at this level
             // (the kernel strides over any size; this only trims launches)
             const int64_t prev = it < (int)d.walk_sizes.size() ? d.walk_sizes[it] : capf;

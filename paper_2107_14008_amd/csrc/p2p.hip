@@ -7,11 +7,13 @@
 // Sources are read with wave-uniform addresses, so the compiler turns them
 // into scalar loads broadcast from SGPRs instead of staging each j leaf
 // through LDS; LDS holds the interpolation table of Eq. (int) instead (the
-// paper keeps T_i and E_i in shared memory, Sec. 3.3).  Work items
-// (i leaf, a range of its j leaves) are pulled from an atomic queue by a
-// persistent grid, longest first, and every item writes its own partial
-// sums, which a second kernel adds in a fixed order: results do not depend
-// on scheduling.
+// paper keeps T_i and E_i in shared memory, Sec. 3.3).  Before the pairs
+// of a j leaf the wave culls the sources that reach none of its targets
+// (device.h).  Work items (i leaf, a range of its j leaves) are pulled by a
+// persistent grid from per-XCD segments of the queue (plan.h), longest
+// first within a segment, and every item writes its own partial sums,
+// which a second kernel adds in a fixed order: results do not depend on
+// scheduling.
 #include "device.h"
 
 namespace pmfmm {

@@ -63,7 +63,7 @@ struct Plan {
     std::vector<int32_t> cell_first, cell_count, cell_child;  // views for the ABI
     std::vector<double> cell_lo, cell_hi;
     std::vector<WorkItem> items;              // natural (slot) order
-    std::vector<int32_t> queue;               // slots, longest first
+    std::vector<int32_t> queue;               // slots: kQueueSegs segments, each longest first
     std::vector<int32_t> leaf_slot_begin;     // n_leaves + 1
     std::vector<int32_t> cells_by_depth;      // cells grouped by depth
     std::vector<int32_t> depth_begin;         // max_depth + 2

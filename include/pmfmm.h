@@ -185,8 +185,12 @@ int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream);
  * the tree, the task lists and the expansion centres of the last build
  * held fixed).  w, grad_pos: device (n_total, 3); grad_mass: device
  * (n_total); caller order.  The almost-everywhere gradient: the step of the
- * hard cutoff is left out.  Pairs are evaluated with the exact T (erfc and
- * exp) in the context's precision.  Errors: ESTATE, EDEVICE. */
+ * hard cutoff is left out.  Pairs are evaluated in the context's
+ * precision: with the exact T (erfc and exp), except in the float32 r^2
+ * form (PMFMM_FP32 with PMFMM_TRUNC_R2), where g = T / r^3 and
+ * h = g'(r) / r come from quadratic tables in r^2 (32 segments per octave,
+ * built and uploaded on the first adjoint of a context, with a stream
+ * synchronisation).  Errors: ESTATE, EDEVICE. */
 int pmfmm_adjoint(pmfmm_ctx* ctx, const double* w, double* grad_pos,
                   double* grad_mass, void* stream);
 

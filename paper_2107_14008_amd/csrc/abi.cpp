@@ -127,25 +127,16 @@ double truncation_T(double x) {
     return std::erfc(x) + 1.12837916709551257390 * x * std::exp(-x * x);
 }
 
-// Table of the float32 r^2 form: F(s) = T(x) s^(-3/2), s = r'^2 in units
-// where r_cut^2 = 2^kR2Emax (x^2 = s kappa, kappa = x_c^2 / 2^kR2Emax).  Row
-// (e - kR2Emin) 2^bits + j covers s in 2^e [1 + j / 2^bits, 1 + (j + 1) / 2^bits);
-// on it F is the polynomial of degree `deg` interpolating F at the
-// Chebyshev nodes of the segment, re-expanded in s itself (the kernel
-// evaluates it at s with no segment offset).  The last row (s = 2^kR2Emax)
-// is zero.  Stored as three planes of kR2Plane floats (c0, c1, c2 at row k
-// of planes 0, 1, 2): a lane's three reads then hit banks spread by the row
-// itself rather than by a 16-byte row stride, and c0 and c1 come in one
-// two-address read.
-std::vector<unsigned char> build_r2_table(int per_octave, int deg, double xc) {
-    const int bits = per_octave == 16 ? 4 : per_octave == 32 ? 5 : per_octave == 64 ? 6 : 7;
-    const int rows = (pmfmm::kR2Emax - pmfmm::kR2Emin) << bits;
-    const double kappa = xc * xc / std::ldexp(1.0, pmfmm::kR2Emax);
-    std::vector<unsigned char> out((size_t)12 * pmfmm::kR2Plane + 16, 0);
-    float* f = reinterpret_cast<float*>(out.data());
+// Fits fn on every segment of the float32 r^2 rows over [2^emin, 2^kR2Emax)
+// (2^bits per octave) and stores the coefficients of s^0 .. s^deg in planes:
+// f[plane * i + row] holds that of s^i.
+template <class Fn>
+void fit_r2_rows(int bits, int emin, int deg, Fn fn, float* f, size_t plane) {
+    const int per_octave = 1 << bits;
+    const int rows = (pmfmm::kR2Emax - emin) << bits;
     const int m = deg + 1;
     for (int k = 0; k < rows; ++k) {
-        const int e = pmfmm::kR2Emin + (k >> bits), j = k & ((1 << bits) - 1);
+        const int e = emin + (k >> bits), j = k & ((1 << bits) - 1);
         const double lo = std::ldexp(1.0 + (double)j / per_octave, e);
         const double hi = std::ldexp(1.0 + (double)(j + 1) / per_octave, e);
         double V[3][4];
@@ -157,7 +148,7 @@ std::vector<unsigned char> build_r2_table(int per_octave, int deg, double xc) {
                 V[i][q] = tp;
                 tp *= sv - lo;
             }
-            V[i][m] = truncation_T(std::sqrt(sv * kappa)) * std::pow(sv, -1.5);
+            V[i][m] = fn(sv);
         }
         // Gaussian elimination with partial pivoting on the (m x m) system
         for (int c = 0; c < m; ++c) {
@@ -181,9 +172,52 @@ std::vector<unsigned char> build_r2_table(int per_octave, int deg, double xc) {
         for (int i = 0; i < m; ++i) {
             double acc = 0.0;
             for (int q = i; q < m; ++q) acc += cl[q] * binom[q][i] * std::pow(-lo, q - i);
-            f[(size_t)pmfmm::kR2Plane * i + k] = (float)acc;
+            f[plane * i + k] = (float)acc;
         }
     }
+}
+
+// Table of the float32 r^2 form: F(s) = T(x) s^(-3/2), s = r'^2 in units
+// where r_cut^2 = 2^kR2Emax (x^2 = s kappa, kappa = x_c^2 / 2^kR2Emax).  Row
+// (e - kR2Emin) 2^bits + j covers s in 2^e [1 + j / 2^bits, 1 + (j + 1) / 2^bits);
+// on it F is the polynomial of degree `deg` interpolating F at the
+// Chebyshev nodes of the segment, re-expanded in s itself (the kernel
+// evaluates it at s with no segment offset).  The last row (s = 2^kR2Emax)
+// is zero.  Stored as three planes of kR2Plane floats (c0, c1, c2 at row k
+// of planes 0, 1, 2): a lane's three reads then hit banks spread by the row
+// itself rather than by a 16-byte row stride, and c0 and c1 come in one
+// two-address read.
+std::vector<unsigned char> build_r2_table(int per_octave, int deg, double xc) {
+    const int bits = per_octave == 16 ? 4 : per_octave == 32 ? 5 : per_octave == 64 ? 6 : 7;
+    const double kappa = xc * xc / std::ldexp(1.0, pmfmm::kR2Emax);
+    std::vector<unsigned char> out((size_t)12 * pmfmm::kR2Plane + 16, 0);
+    fit_r2_rows(bits, pmfmm::kR2Emin, deg,
+                [&](double sv) { return truncation_T(std::sqrt(sv * kappa)) * std::pow(sv, -1.5); },
+                reinterpret_cast<float*>(out.data()), pmfmm::kR2Plane);
+    return out;
+}
+
+// Tables of the float32 adjoint in the r^2 form (same units as the forward
+// table): g(s) = T s^(-3/2) and h(s) = g'(r) / r = 2 dg/ds =
+// -(3 T + (4 / sqrt(pi)) x^3 e^(-x^2)) s^(-5/2), each fitted by its own
+// quadratics at 2^kAdjBits segments per octave over [2^kAdjEmin,
+// 2^kR2Emax) (the derivative of the forward's quadratics would be too coarse
+// for the gradient), in six planes of kAdjPlane floats: g c0 c1 c2, h c0 c1
+// c2; the row after the last (s = 2^kR2Emax) is zero.
+std::vector<unsigned char> build_adj_table(double xc) {
+    const double kappa = xc * xc / std::ldexp(1.0, pmfmm::kR2Emax);
+    std::vector<unsigned char> out((size_t)24 * pmfmm::kAdjPlane + 16, 0);
+    float* f = reinterpret_cast<float*>(out.data());
+    fit_r2_rows(pmfmm::kAdjBits, pmfmm::kAdjEmin, 2,
+                [&](double sv) { return truncation_T(std::sqrt(sv * kappa)) * std::pow(sv, -1.5); },
+                f, pmfmm::kAdjPlane);
+    fit_r2_rows(pmfmm::kAdjBits, pmfmm::kAdjEmin, 2,
+                [&](double sv) {
+                    const double x = std::sqrt(sv * kappa);
+                    return -(3.0 * truncation_T(x) + 2.25675833419102514780 * x * x * x * std::exp(-x * x)) *
+                           std::pow(sv, -2.5);
+                },
+                f + 3 * (size_t)pmfmm::kAdjPlane, pmfmm::kAdjPlane);
     return out;
 }
 
@@ -341,6 +375,8 @@ struct pmfmm_ctx {
     int n_cu = 0;
     pmfmm::DevPlan d;
     std::vector<unsigned char> table_host;
+    std::vector<unsigned char> adj_table_host;   // float32 r^2 adjoint (g, h)
+    double adj_table_xc = -1.0;
     bool table_dirty = true;
     double table_xc = -1.0;   // r_cut / 2 r_s the r^2 table was built for
     std::vector<pmfmm::BoxDev> boxes_on_device;   // last upload of d.boxes
@@ -475,6 +511,19 @@ int upload_table(pmfmm_ctx* ctx, hipStream_t s) {
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(s));
     ctx->table_dirty = false;
+    return PMFMM_OK;
+}
+
+// Float32 r^2 adjoint tables, built and uploaded on the first adjoint of
+// that form and again when x_c changes.
+int upload_adj_table(pmfmm_ctx* ctx, hipStream_t s) {
+    const double xc = ctx->plan.boxes[0].r_cut / (2.0 * ctx->plan.boxes[0].r_s);
+    if (ctx->d.adj_table.p != nullptr && xc == ctx->adj_table_xc) return PMFMM_OK;
+    ctx->adj_table_host = build_adj_table(xc);
+    int rc = upload(ctx->d.adj_table, ctx->adj_table_host, s);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(s));
+    ctx->adj_table_xc = xc;
     return PMFMM_OK;
 }
 
@@ -1225,10 +1274,16 @@ int pmfmm_adjoint(pmfmm_ctx* ctx, const double* w, double* grad_pos, double* gra
     a.partial = ctx->d.partial.as<double>();
     a.boxes = ctx->d.boxes.as<pmfmm::BoxDev>();
     const int mode = mode_of(ctx->p);
+    if (uses_r2(ctx->p)) {
+        // the float32 r^2 form: g and h from tables as well
+        int rc = upload_adj_table(ctx, s);
+        if (rc) return rc;
+        a.table = ctx->d.adj_table.p;
+    }
     const int wg = ctx->p.wg_waves > 0 ? ctx->p.wg_waves : 4;
     int grid = ctx->p.grid_wgs;
-    if (grid <= 0) grid = ctx->n_cu * pmfmm::adjoint_blocks_per_cu(mode, wg, 0);
-    HIP_TRY(pmfmm::launch_adjoint(mode, a, wg, grid, 0, s));
+    if (grid <= 0) grid = ctx->n_cu * pmfmm::adjoint_blocks_per_cu(mode, wg, a.table != nullptr);
+    HIP_TRY(pmfmm::launch_adjoint(mode, a, wg, grid, s));
     if (timing) {
         HIP_TRY(hipEventRecord(ctx->ev[5], s));
         ctx->timed_adj = true;

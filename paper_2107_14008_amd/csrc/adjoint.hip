@@ -90,14 +90,58 @@ __device__ __forceinline__ void adj_pair_f32(const float4 q, const float4 wl, fl
     gm -= g * dwl;
 }
 
-template <bool F32>
+// Float32 r^2 tables (host builder in abi.cpp): g and h as quadratics in
+// s = r'^2 on segments indexed by the float bits of s, in the units of the
+// forward r^2 form (r_cut^2 = 2^kR2Emax); s is clamped below at 2^kAdjEmin
+// (pairs that close are not resolved by float32 offsets anyway).  Coincident
+// pairs (d = 0, the particle itself included) are left out as in the exact
+// form.  Only lanes inside the cutoff read the six coefficients (three
+// two-address LDS reads).
+__device__ __forceinline__ void adj_pair_f32_r2(const float4 q, const float4 wl, float px,
+                                                float py, float pz, float4 wk, float smax,
+                                                float smin, uint32_t boff,
+                                                const unsigned char* __restrict__ tab, float* A,
+                                                float* Bv, float& gm) {
+    const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    if ((r2 > 0.f) & (r2 < smax)) {
+        const uint32_t sb = max(__float_as_uint(r2), __float_as_uint(smin));
+        const float sc = __uint_as_float(sb);
+        const float* c =
+            reinterpret_cast<const float*>(tab + (((sb >> (23 - kAdjBits)) << 2) + boff));
+        const float g = fmaf(fmaf(c[2 * kAdjPlane], sc, c[kAdjPlane]), sc, c[0]);
+        const float h = fmaf(fmaf(c[5 * kAdjPlane], sc, c[4 * kAdjPlane]), sc, c[3 * kAdjPlane]);
+        const float dwl = dx * wl.x + dy * wl.y + dz * wl.z;
+        const float dwk = dx * wk.x + dy * wk.y + dz * wk.z;
+        const float hl = h * dwl, hk = q.w * h * dwk, gl = q.w * g;
+        A[0] += g * wl.x + hl * dx;
+        A[1] += g * wl.y + hl * dy;
+        A[2] += g * wl.z + hl * dz;
+        Bv[0] += gl * wk.x + hk * dx;
+        Bv[1] += gl * wk.y + hk * dy;
+        Bv[2] += gl * wk.z + hk * dz;
+        gm -= g * dwl;
+    }
+}
+
+// F32: float32 offsets; TAB (float32 only): g and h from the r^2 tables,
+// staged in LDS (6 kAdjPlane floats), instead of erfc and exp.
+template <bool F32, bool TAB>
 __global__ void __launch_bounds__(1024)
 adjoint_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                const double4* __restrict__ w64, const float4* __restrict__ w32,
                const int4* __restrict__ leaf, const double4* __restrict__ leafc,
                const int32_t* __restrict__ p2p_js, const int4* __restrict__ items,
                const int32_t* __restrict__ queue, int32_t n_items, int32_t* __restrict__ counter,
-               double* __restrict__ partial, const BoxDev* __restrict__ boxes) {
+               double* __restrict__ partial, const BoxDev* __restrict__ boxes,
+               const float* __restrict__ table) {
+    extern __shared__ __align__(16) unsigned char adj_lds[];
+    if constexpr (TAB) {
+        const uint4* src = reinterpret_cast<const uint4*>(table);
+        uint4* dst = reinterpret_cast<uint4*>(adj_lds);
+        for (int i = threadIdx.x; i < 6 * kAdjPlane / 4; i += blockDim.x) dst[i] = src[i];
+        __syncthreads();
+    }
     const int lane = threadIdx.x & 63;
     int seg = (int)(blockIdx.x % kQueueSegs), done = 0;
     for (;;) {
@@ -145,10 +189,20 @@ adjoint_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                 const uint64_t live =
                     live_f32(src, nj, lane, make_float3(lo.x - offx, lo.y - offy, lo.z - offz),
                              make_float3(hi.x - offx, hi.y - offy, hi.z - offz), bx.rc2_f);
-                for (int k = 0; k < nj; ++k)
-                    if ((live >> k) & 1u)
-                        adj_pair_f32(src[k], wsrc[k], px, py, pz, wk, bx.rc2_f, bx.alpha_f, a, b,
-                                     g);
+                if constexpr (TAB) {
+                    // boff = -(row of 2^kAdjEmin) * 4 mod 2^32
+                    const uint32_t boff = 0u - (((uint32_t)(127 + kAdjEmin) << kAdjBits) << 2);
+                    const float smin = __uint_as_float((uint32_t)(127 + kAdjEmin) << 23);
+                    for (int k = 0; k < nj; ++k)
+                        if ((live >> k) & 1u)
+                            adj_pair_f32_r2(src[k], wsrc[k], px, py, pz, wk, bx.rc2_f, smin, boff,
+                                            adj_lds, a, b, g);
+                } else {
+                    for (int k = 0; k < nj; ++k)
+                        if ((live >> k) & 1u)
+                            adj_pair_f32(src[k], wsrc[k], px, py, pz, wk, bx.rc2_f, bx.alpha_f, a,
+                                         b, g);
+                }
                 for (int c = 0; c < 3; ++c) {
                     A[c] += (double)a[c];
                     Bv[c] += (double)b[c];
@@ -242,11 +296,11 @@ __global__ void gather_w_kernel(const double* __restrict__ w, const int32_t* __r
     w32[k] = make_float4((float)x, (float)y, (float)z, 0.f);
 }
 
-template <bool F32>
+template <bool F32, bool TAB>
 int occ_adj(int wg_waves) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, adjoint_kernel<F32>, 64 * wg_waves, 0) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, adjoint_kernel<F32, TAB>, 64 * wg_waves,
+                                                     TAB ? kAdjTableBytes : 0) != hipSuccess)
         return 1;
     return blocks > 0 ? blocks : 1;
 }
@@ -261,17 +315,22 @@ hipError_t launch_gather_w(const double* w, const int32_t* perm, double4* w64, f
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint(int mode, const AdjArgs& a, int wg_waves, int grid_wgs, size_t,
-                          hipStream_t s) {
+hipError_t launch_adjoint(int mode, const AdjArgs& a, int wg_waves, int grid_wgs, hipStream_t s) {
     if (a.n_items == 0) return hipSuccess;
-    if (is_fp32(mode))
-        hipLaunchKernelGGL(adjoint_kernel<true>, dim3(grid_wgs), dim3(64 * wg_waves), 0, s, a.x64,
-                           a.x32, a.w64, a.w32, a.leaf, a.leafc, a.p2p_js, a.items, a.queue,
-                           a.n_items, a.counter, a.partial, a.boxes);
+    const dim3 grid(grid_wgs), block(64 * wg_waves);
+    const float* tab = static_cast<const float*>(a.table);
+    if (is_fp32(mode) && tab != nullptr)
+        hipLaunchKernelGGL((adjoint_kernel<true, true>), grid, block, kAdjTableBytes, s, a.x64, a.x32,
+                           a.w64, a.w32, a.leaf, a.leafc, a.p2p_js, a.items, a.queue, a.n_items,
+                           a.counter, a.partial, a.boxes, tab);
+    else if (is_fp32(mode))
+        hipLaunchKernelGGL((adjoint_kernel<true, false>), grid, block, 0, s, a.x64, a.x32, a.w64,
+                           a.w32, a.leaf, a.leafc, a.p2p_js, a.items, a.queue, a.n_items,
+                           a.counter, a.partial, a.boxes, nullptr);
     else
-        hipLaunchKernelGGL(adjoint_kernel<false>, dim3(grid_wgs), dim3(64 * wg_waves), 0, s, a.x64,
-                           a.x32, a.w64, a.w32, a.leaf, a.leafc, a.p2p_js, a.items, a.queue,
-                           a.n_items, a.counter, a.partial, a.boxes);
+        hipLaunchKernelGGL((adjoint_kernel<false, false>), grid, block, 0, s, a.x64, a.x32, a.w64,
+                           a.w32, a.leaf, a.leafc, a.p2p_js, a.items, a.queue, a.n_items,
+                           a.counter, a.partial, a.boxes, nullptr);
     return hipGetLastError();
 }
 
@@ -283,8 +342,9 @@ hipError_t launch_adj_reduce(const AdjReduceArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-int adjoint_blocks_per_cu(int mode, int wg_waves, size_t) {
-    return is_fp32(mode) ? occ_adj<true>(wg_waves) : occ_adj<false>(wg_waves);
+int adjoint_blocks_per_cu(int mode, int wg_waves, bool table) {
+    if (!is_fp32(mode)) return occ_adj<false, false>(wg_waves);
+    return table ? occ_adj<true, true>(wg_waves) : occ_adj<true, false>(wg_waves);
 }
 
 }  // namespace pmfmm

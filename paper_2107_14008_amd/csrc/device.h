@@ -43,6 +43,16 @@ constexpr int kR2Emin64 = kR2Emax - 16;
 // float32 r^2 table: three planes (c0, c1, c2) of kR2Plane floats each, room
 // for 128 segments per octave; the plane stride is a multiple of 256 bytes.
 constexpr int kR2Plane = 5952;
+// Adjoint of the float32 r^2 form: g(s) and h(s) over s in
+// [2^kAdjEmin, 2^kR2Emax), six planes (g c0 c1 c2, h c0 c1 c2) of kAdjPlane
+// floats at 2^kAdjBits segments per octave.  The floor sits above
+// kR2Emin because h's quadratic coefficient grows as s^(-9/2) and must stay
+// a finite float.
+constexpr int kAdjBits = 5;
+constexpr int kAdjEmin = -26;
+constexpr int kAdjPlane = 1216;
+static_assert(((kR2Emax - kAdjEmin) << kAdjBits) + 1 <= kAdjPlane, "adjoint table rows");
+constexpr int kAdjTableBytes = 6 * kAdjPlane * 4;
 
 // ------------------------------------------------------ source culling
 //
@@ -213,8 +223,7 @@ struct AdjArgs {
     int32_t* counter;
     double* partial;            // (slot, 4, 64): grad x, y, z, m
     const BoxDev* boxes;
-    const void* table;
-    int32_t n_tab, level, round_floor;
+    const void* table;          // float32 r^2 adjoint tables in device memory, or null
 };
 
 struct AdjReduceArgs {
@@ -241,8 +250,9 @@ hipError_t launch_rescale_x32(const int4* leaf, const double4* leafc, const BoxD
                               const double4* x64, float4* x32, int32_t n_leaves, hipStream_t s);
 hipError_t launch_gather_w(const double* w, const int32_t* perm, double4* w64,
                            float4* w32, int32_t n, hipStream_t s);
-hipError_t launch_adjoint(int mode, const AdjArgs& a, int wg_waves, int grid_wgs,
-                          size_t lds_bytes, hipStream_t s);
+// a.table: the float32 r^2 adjoint tables (float32 modes), or null for
+// the exact erfc / exp form.
+hipError_t launch_adjoint(int mode, const AdjArgs& a, int wg_waves, int grid_wgs, hipStream_t s);
 hipError_t launch_adj_reduce(const AdjReduceArgs& a, hipStream_t s);
 
 // Kick (vel += acc dt) and drift (pos += vel dt, wrapped into [0, L)) of
@@ -269,7 +279,7 @@ hipError_t launch_far_flags(const FarArgs& a, hipStream_t s);
 
 // Occupancy helpers: max resident workgroups per CU of the P2P kernel.
 int p2p_blocks_per_cu(int mode, int wg_waves, size_t lds_bytes);
-int adjoint_blocks_per_cu(int mode, int wg_waves, size_t lds_bytes);
+int adjoint_blocks_per_cu(int mode, int wg_waves, bool table);
 int n_coef(int order);
 
 }  // namespace pmfmm

@@ -57,7 +57,8 @@ struct DevBuf {
 // Everything the kernels of one context read or write.
 struct DevPlan {
     // used by the forward / adjoint passes
-    DevBuf perm, leaf, leafc, js, items, queue, leaf_slot, partial, counter, boxes, table;
+    DevBuf perm, leaf, leafc, js, items, queue, leaf_slot, partial, counter, boxes, table,
+        adj_table;
     DevBuf x64, x32, stage_pos, stage_mass, far;
     DevBuf cell, cell_aux, cellc, M, Lc, Lt, m2l_row, m2l_src, m2l_shift, level_cells;
     DevBuf w64, w32, fargrad;

@@ -90,6 +90,33 @@ def test_adjoint_fp32_after_r2_table_forward(case):
         assert s["median"] <= 1e-5 and s["p999"] <= 1e-4, s
 
 
+@pytest.mark.parametrize("trunc", [B.TRUNC_EXACT, B.TRUNC_R2])
+def test_adjoint_fp32_coincident_close_and_ragged(trunc):
+    """Coincident particles (left out of each other's sums), pairs at 3e-2 ..
+    1e-1 r_cut and a ragged particle count, float32 exact and r^2 tables."""
+    rng = np.random.default_rng(23)
+    box, r_s, r_cut = 20.0, 0.6, 2.7
+    # ~20 neighbours per particle on average: none is left without any
+    base = rng.uniform(0, box, (2000, 3))
+    close = base[:300] + rng.normal(0, 1, (300, 3)) * rng.uniform(3e-2, 1e-1, (300, 1)) * r_cut
+    pos = inputs.wrap(np.concatenate([base, close, base[:5]]), box)
+    m = rng.uniform(0.5, 1.5, len(pos))
+    wv = inputs.cotangent(len(m), seed=29)
+    gx, gm, sx, sm = direct.gradient(pos, m, wv, box, r_s, r_cut, with_scale=True)
+    print(f"case: adjoint fp32 trunc {trunc}, 2305 with coincident pairs", flush=True)
+    sr = api.ShortRange(box=box, r_s=r_s, r_cut=r_cut, max_leaf=16, order=-1,
+                        theta=0.0, precision=B.PMFMM_FP32, trunc=trunc,
+                        table_size=64, table_level=2)
+    sr.build(torch.tensor(pos, device="cuda"), torch.tensor(m, device="cuda"))
+    gp, gmass = sr.adjoint(torch.tensor(wv, device="cuda"))
+    torch.cuda.synchronize()
+    gp, gmass = gp.cpu().numpy(), gmass.cpu().numpy()
+    assert np.all(np.isfinite(gp)) and np.all(np.isfinite(gmass))
+    for e in (scaled(gp, gx, sx), scaled(gmass, gm, sm)):
+        print("errors:", e, flush=True)
+        assert e["median"] <= 1e-5 and e["p999"] <= 1e-4, e
+
+
 def test_autograd_function(case):
     w, m, wv, gx, gm, sx, sm = case
     pos = torch.tensor(w.pos, device="cuda", requires_grad=True)

@@ -9,7 +9,9 @@
 //   dL/dm_k = -G sum_l g (w_l . d),                            d = d_kl,
 // the delta function of the hard cutoff being left out.  Same wavefront
 // mapping and work queue as the forward P2P kernel; the source records are
-// (x, m) and (w, 0), both read with wave-uniform addresses.
+// (x, m) and (w, 0), both read with wave-uniform addresses.  g and h are
+// evaluated exactly (erfc and exp), or, in the float32 r^2 form, read from
+// quadratic tables in r^2 (adj_pair_f32_r2).
 #include "device.h"
 
 namespace pmfmm {
@@ -95,8 +97,7 @@ __device__ __forceinline__ void adj_pair_f32(const float4 q, const float4 wl, fl
 // forward r^2 form (r_cut^2 = 2^kR2Emax); s is clamped below at 2^kAdjEmin
 // (pairs that close are not resolved by float32 offsets anyway).  Coincident
 // pairs (d = 0, the particle itself included) are left out as in the exact
-// form.  Only lanes inside the cutoff read the six coefficients (three
-// two-address LDS reads).
+// form.  Only lanes inside the cutoff read the six coefficients from LDS.
 __device__ __forceinline__ void adj_pair_f32_r2(const float4 q, const float4 wl, float px,
                                                 float py, float pz, float4 wk, float smax,
                                                 float smin, uint32_t boff,

@@ -96,7 +96,7 @@ typedef struct pmfmm_params {
     int32_t table_round; /* TABLE: PMFMM_ROUND_NEAREST or PMFMM_ROUND_FLOOR       */
     /* scheduling of the P2P work (no effect on results) */
     int32_t chunk;       /* j-leaves per work item, 0 = automatic                 */
-    int32_t wg_waves;    /* wavefronts per workgroup of the P2P launch, 0 = auto  */
+    int32_t wg_waves;    /* wavefronts per workgroup of the P2P and adjoint launches, 0 = auto */
     int32_t grid_wgs;    /* workgroups of the persistent launch, 0 = auto         */
     int32_t timing;      /* 1: time each phase with HIP events (see get_timings)  */
     int32_t threads;     /* host threads of the host planner, 0 = all             */

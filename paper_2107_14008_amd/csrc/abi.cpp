@@ -1282,7 +1282,8 @@ int pmfmm_adjoint(pmfmm_ctx* ctx, const double* w, double* grad_pos, double* gra
     }
     // 8 waves per workgroup share the tables of the r^2 form (measured on
     // the 64^3 clustered workload: 1.02 ms against 1.13 ms with 4 and
-    // 1.06 ms with 16; same results bit for bit)
+    // 1.06 ms with 16; same results bit for bit).  The exact forms take
+    // within 2 % of the same time with 4, 8 or 16.
     const int wg = ctx->p.wg_waves > 0 ? ctx->p.wg_waves : (a.table != nullptr ? 8 : 4);
     int grid = ctx->p.grid_wgs;
     if (grid <= 0) grid = ctx->n_cu * pmfmm::adjoint_blocks_per_cu(mode, wg, a.table != nullptr);

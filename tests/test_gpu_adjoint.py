@@ -90,6 +90,25 @@ def test_adjoint_fp32_after_r2_table_forward(case):
         assert s["median"] <= 1e-5 and s["p999"] <= 1e-4, s
 
 
+def test_adjoint_r2_tables_reproducible_across_launch_shapes(case):
+    """Each work item sums its own pairs in a fixed order and the partials
+    are reduced in slot order, so the gradients are bitwise the same for
+    any workgroup size and grid, and on a repeated call."""
+    w, m, wv, gx, gm, sx, sm = case
+    print("case: adjoint fp32 r^2 tables, launch shapes", flush=True)
+    runs = []
+    for wg, grid in ((4, 0), (8, 0), (16, 0), (8, 37)):
+        gp, gmass, sr = gpu_adjoint(w, m, wv, precision=B.PMFMM_FP32,
+                                    trunc=B.TRUNC_R2, table_size=64,
+                                    table_level=2, wg_waves=wg, grid_wgs=grid)
+        runs.append((gp, gmass))
+        gp2, gm2 = sr.adjoint(torch.tensor(wv, device="cuda"))
+        torch.cuda.synchronize()
+        runs.append((gp2.cpu().numpy(), gm2.cpu().numpy()))
+    for gp, gmass in runs[1:]:
+        assert np.array_equal(gp, runs[0][0]) and np.array_equal(gmass, runs[0][1])
+
+
 @pytest.mark.parametrize("trunc", [B.TRUNC_EXACT, B.TRUNC_R2])
 def test_adjoint_fp32_coincident_close_and_ragged(trunc):
     """Coincident particles (left out of each other's sums), pairs at 3e-2 ..

@@ -34,52 +34,55 @@ sys.path.insert(0, ROOT)
 
 from paper_2107_14008_amd import inputs  # noqa: E402
 
-# Algorithmic float32 operations per candidate pair of the paper's table
-# form: displacement 3, r^2 5, 1/r 1, table coordinate 2, index and offset 2,
-# T_[2] Horner 4, g = m T / r^3 4, accumulation 6.
-FLOPS_PER_PAIR_F32_T2 = 27
-# r^2 table of T / r^3: every evaluated pair (a source that survives the
-# cull against the box of its target leaf) costs displacement 3, r^2 5 and
-# the cutoff test 1; a pair inside r_cut adds clamp 1, segment index 2,
-# quadratic Horner in r^2 4, g = m F 1 and accumulation 6 (lanes beyond
-# r_cut skip that part, and a wave skips it when all of its lanes do).
-FLOPS_PER_CAND_F32_R2 = 9
-FLOPS_PER_INSIDE_F32_R2 = 14
-# Same count for the float64 exact form, erfc and exp taken as one op each:
-# displacement 3 (+3 shift), r^2 5, 1/r 1, x 2, T = erfc + c x e^-x^2 6,
-# g 4, accumulation 6.
-FLOPS_PER_PAIR_F64_EXACT = 27
-# float64 table form (T_[4]): displacement 3 (+3 shift), r^2 5, 1/r 1,
-# table coordinate 2, index and offset 2, T_[4] Horner 8, m T / r^3 4,
-# accumulation 6.
-FLOPS_PER_PAIR_F64_TABLE = 31
-# float64 r^2 table (degree 6): every evaluated pair costs displacement 3
-# (+3 shift), r^2 5, s = r^2 sigma^2 1 and the two range tests 2; a pair
-# inside r_cut adds segment index 2, t = s - s_k 1, degree-6 Horner 12,
-# g = m F 1 and accumulation 6.
-FLOPS_PER_CAND_F64_R2 = 11
-FLOPS_PER_INSIDE_F64_R2 = 22
+# Algorithmic floating-point operations of each pair form, counted one way
+# for every form: per EVALUATED pair (a source that survives the cull
+# against the bounding box of its target leaf; the kernels skip the other
+# candidate pairs) plus, for the forms that branch around the force of a
+# pair beyond r_cut, per pair INSIDE r_cut.  A special function (erfc, exp,
+# 1/r) counts as one operation, as the paper counts them; the executed
+# instruction counts are in the rocprofv3 counter summaries of profiles/.
+#
+# float32 r^2 table of T / r^3 (headline): displacement 3, r^2 5, cutoff
+# test 1 per evaluated pair; inside r_cut clamp 1, segment index 2,
+# quadratic Horner in r^2 4, g = m F 1 and accumulation 6.
+FLOPS_EVAL_F32_R2, FLOPS_INSIDE_F32_R2 = 9, 14
+# float32 Taylor table of Eq. (int) (T_[2], the paper's single-precision
+# form): every evaluated pair takes displacement 3, r^2 5, 1/r 1, table
+# coordinate 2, index and offset 2, Horner 4, m T / r^3 4, accumulation 6.
+FLOPS_EVAL_F32_T2, FLOPS_INSIDE_F32_T2 = 27, 0
+# float64 exact erfc / exp: displacement 3, r^2 5, 1/r 1, x 2,
+# T = erfc + c x e^-x^2 6, g 4, accumulation 6 per evaluated pair.
+FLOPS_EVAL_F64_EXACT, FLOPS_INSIDE_F64_EXACT = 27, 0
+# float64 Taylor table T_[4]: as the float32 table with a degree-4 Horner.
+FLOPS_EVAL_F64_T4, FLOPS_INSIDE_F64_T4 = 31, 0
+# float64 r^2 table (degree 6): displacement 3, r^2 5, s = r^2 sigma^2 1 and
+# the two range tests 2 per evaluated pair; inside r_cut segment index 2,
+# t = s - s_k 1, degree-6 Horner 12, g = m F 1 and accumulation 6.
+FLOPS_EVAL_F64_R2, FLOPS_INSIDE_F64_R2 = 11, 22
+# (images other than s = 0 add 3 float64 additions per pair; not counted)
+FORM_FLOPS = {
+    "fp32": (FLOPS_EVAL_F32_R2, FLOPS_INSIDE_F32_R2, "fp32"),
+    "fp32_paper_table": (FLOPS_EVAL_F32_T2, FLOPS_INSIDE_F32_T2, "fp32"),
+    "fp64": (FLOPS_EVAL_F64_EXACT, FLOPS_INSIDE_F64_EXACT, "fp64"),
+    "fp64_table": (FLOPS_EVAL_F64_T4, FLOPS_INSIDE_F64_T4, "fp64"),
+    "fp64_r2": (FLOPS_EVAL_F64_R2, FLOPS_INSIDE_F64_R2, "fp64"),
+}
+# The paper's convention: 51 operations per candidate pair (Sec. 5), which
+# its kernel evaluates in full; reported as an equivalent rate, not as a
+# fraction of peak (these kernels skip most of those pairs' work).
 PAPER_OPS_PER_PAIR = 51
+# Published MI355X vector peaks (TFLOP/s); the measured ones come from the
+# library's FMA benchmark (pmfmm_peak_fma) in the same run.
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 
 
-def error_summary(acc, ref):
-    """Median / 99.9th percentile / max of |a - a_ref| / |a_ref| per particle."""
-    num = np.linalg.norm(np.asarray(acc) - ref, axis=1)
-    den = np.linalg.norm(ref, axis=1)
-    ok = den > 1e-6 * np.median(den)
-    e = num[ok] / den[ok]
-    return dict(n=int(e.size), median=float(np.quantile(e, 0.5, method="higher")),
-                p999=float(np.quantile(e, 0.999, method="higher")),
-                max=float(e.max()))
-
-
-def measured_traffic(kernel_tag="p2p_fp32_r2_clustered_2m"):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the P2P source has changed since the counters were taken."""
+def _profile_values(name):
+    """key = value pairs of a committed profiles/ summary, or None when the
+    file is missing or the P2P source (p2p.hip, device.h) has changed since
+    its counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.txt")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -88,11 +91,42 @@ def measured_traffic(kernel_tag="p2p_fp32_r2_clustered_2m"):
         if "=" in line:
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2107_14008_amd", "csrc", "p2p.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if kv.get("p2p_source_sha256_16") != sha:
+    if kv.get("p2p_source_sha256_16") != p2p_source_hash():
         return None
-    return float(kv["hbm_bytes_per_launch"])
+    return kv
+
+
+def p2p_source_hash():
+    """First 16 hex digits of sha256 over the P2P kernel sources."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("p2p.hip", "device.h"):
+        h.update(open(os.path.join(ROOT, "paper_2107_14008_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_tag="p2p_fp32_r2_clustered_2m"):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None when stale."""
+    kv = _profile_values(f"{kernel_tag}_traffic.txt")
+    return None if kv is None else float(kv["hbm_bytes_per_launch"])
+
+
+def counter_flops(kernel_tag):
+    """Executed floating-point operations per launch from the committed
+    rocprofv3 VALU-counter summary (per-type instruction counts x 64 lanes,
+    x 2 for fused multiply-adds), or None when stale."""
+    kv = _profile_values(f"{kernel_tag}_valu.txt")
+    return None if kv is None else float(kv["executed_flop_per_launch"])
+
+
+def measured_peaks():
+    """Best of three runs of the library's FMA benchmark: (fp32, fp64)
+    TFLOP/s of this device, float32 unpacked."""
+    from paper_2107_14008_amd import binding as B
+    f32 = max(B.peak_fma(B.PMFMM_FP32)[0] for _ in range(3))
+    f64 = max(B.peak_fma(B.PMFMM_FP64)[0] for _ in range(3))
+    return f32, f64
 
 
 def inside_pairs(w, sample=20000):
@@ -133,10 +167,25 @@ def evaluated_pairs(w, L, sample=20000):
     return total * n_tasks / len(t)
 
 
+def host_cores():
+    """Host cores the oracle may use: every core this process may run on,
+    capped by the CPU share the machine grants one GPU job when it states
+    one (OMP_NUM_THREADS; 16 on the GPU hosts used here)."""
+    cores = len(os.sched_getaffinity(0))
+    share = os.environ.get("OMP_NUM_THREADS", "")
+    if share.isdigit() and int(share) > 0:
+        cores = min(cores, int(share))
+    return cores
+
+
 def cpu_baseline(w, cand_per_particle, target_seconds=12.0):
-    """Oracle brute force on a bounded random sample of target particles."""
+    """Oracle brute force (float64 cell lists) on a bounded random sample of
+    target particles of the same workload: the rate in candidate pairs (the
+    metric's unit: the sample's targets times the workload's candidate
+    pairs per particle) and in pairs inside r_cut (the oracle's own count)
+    per second.  Returns (record, sample indices, reference forces)."""
     from oracle import direct
-    cores = min(len(os.sched_getaffinity(0)), 16)
+    cores = host_cores()
     rng = np.random.default_rng(99)
     n = len(w.mass)
     sample = 4096
@@ -144,8 +193,8 @@ def cpu_baseline(w, cand_per_particle, target_seconds=12.0):
     for _ in range(3):
         idx = np.sort(rng.choice(n, min(sample, n), replace=False))
         t0 = time.perf_counter()
-        ref, _ = direct.brute_force(w.pos, w.mass, w.box, w.r_s, w.r_cut,
-                                    targets=idx, workers=cores)
+        ref, cnt = direct.brute_force(w.pos, w.mass, w.box, w.r_s, w.r_cut,
+                                      targets=idx, workers=cores)
         t_used = time.perf_counter() - t0
         if t_used >= 0.5 * target_seconds or sample >= n:
             break
@@ -155,9 +204,18 @@ def cpu_baseline(w, cand_per_particle, target_seconds=12.0):
                 kind="oracle",
                 sample=(f"float64 cell-list brute force for {len(idx)} random "
                         f"target particles of the same workload in "
-                        f"{t_used:.2f} s; rate scaled as candidate pairs per "
-                        f"particle ({cand_per_particle:.1f}) x targets / time"),
+                        f"{t_used:.2f} s on {cores} processes; rate scaled as "
+                        f"candidate pairs per particle ({cand_per_particle:.1f}) "
+                        f"x targets / time"),
+                inside_pairs_per_s=float(np.sum(cnt)) / t_used,
                 seconds=t_used), idx, ref
+
+
+def baseline_errors(acc, ref):
+    """Per-particle relative error statistics of GPU forces against the
+    oracle's reference of the cpu_baseline sample (oracle.metrics)."""
+    from oracle import metrics
+    return metrics.error_summary(acc, ref)
 
 
 def _timed_steps(ctx, build, out, stream, steps, warmup):
@@ -219,7 +277,7 @@ def secondary(args):
         acc = out.cpu().numpy()
         starts = np.concatenate([[0], np.cumsum(counts)])
         for b, (idx, ref) in refs.items():
-            errs.append(error_summary(acc[starts[b] + idx], ref))
+            errs.append(baseline_errors(acc[starts[b] + idx], ref))
         line.update(value=cand / (ms / 1e3), ms_per_step=ms,
                     config={"workload": f"batch64: {len(boxes)} clustered boxes, "
                             f"N = n_side^3 with n_side log-uniform in [16, 96] "
@@ -339,7 +397,7 @@ def secondary(args):
             ctx.build(pos, mass, stream)
         ms, ph = _timed_steps(ctx, build, out, stream, args.steps, args.warmup)
         cand = int(ctx.lists()["candidate_pairs"])
-        err = error_summary(out.cpu().numpy()[idx], ref) if idx is not None else None
+        err = baseline_errors(out.cpu().numpy()[idx], ref) if idx is not None else None
         res[name] = dict(ms_per_step=ms, phases_ms=ph,
                          p2p_interactions_per_s=cand / (ph["p2p_ms"] / 1e3),
                          err=err)
@@ -473,7 +531,7 @@ def main():
         acc = out.cpu().numpy()
         err = None
         if sample_idx is not None:
-            err = error_summary(acc[sample_idx], sample_ref)
+            err = baseline_errors(acc[sample_idx], sample_ref)
         lists = ctx.lists()
         results[name] = dict(
             ms_per_step=1e3 * elapsed / args.steps,
@@ -486,9 +544,29 @@ def main():
     head = "fp32" if "fp32" in results else next(iter(results))
     r32 = results[head]
     inside = inside_pairs(w)
+    peak32, peak64 = measured_peaks()
     value = cand / (r32["ms_per_step"] / 1e3)
-    achieved = ((evaluated * FLOPS_PER_CAND_F32_R2 + inside * FLOPS_PER_INSIDE_F32_R2)
-                / (r32["p2p_ms"] / 1e3) / 1e12)
+
+    def algo_tflops(form, ms):
+        fe, fi, _ = FORM_FLOPS[form]
+        return (evaluated * fe + inside * fi) / (ms / 1e3) / 1e12
+
+    rooflines = {}
+    for k, v in results.items():
+        prec = FORM_FLOPS[k][2]
+        pub = PEAK_FP32_TFLOPS if prec == "fp32" else PEAK_FP64_TFLOPS
+        meas = peak32 if prec == "fp32" else peak64
+        tf = algo_tflops(k, v["p2p_ms"])
+        cf = counter_flops({"fp32": "p2p_fp32_r2_clustered_2m",
+                            "fp64": "p2p_fp64_exact_clustered_2m"}.get(k, "-"))
+        rooflines[k] = dict(
+            value=cand / (v["ms_per_step"] / 1e3), ms_per_step=v["ms_per_step"],
+            p2p_ms=v["p2p_ms"], p2p_tflops=tf, peak=pub, frac=tf / pub,
+            measured_peak=meas, frac_of_measured_peak=tf / meas,
+            counter_tflops=None if cf is None else cf / (v["p2p_ms"] / 1e3) / 1e12,
+            flops=f"{FORM_FLOPS[k][0]} per evaluated pair + {FORM_FLOPS[k][1]} per "
+                  f"pair inside r_cut")
+    achieved = rooflines[head]["p2p_tflops"]
     line = {
         "metric": "short-range pair interactions/s, FP32 vs FP64 at 99.9% "
                   "rel. force err <=1e-4",
@@ -503,6 +581,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
+        # the same step in the other units: pairs inside r_cut (the useful
+        # ones) and pairs the kernel evaluates (candidates minus culled)
+        "inside_pairs_per_s": inside / (r32["ms_per_step"] / 1e3),
+        "evaluated_pairs_per_s": evaluated / (r32["ms_per_step"] / 1e3),
         "config": {
             "workload": "clustered_2m: 128^3 Zel'dovich (P~k^-2, rms 0.5 dg) "
                         "+ 20% in 200 Plummer halos, L=100, N_PM=128, "
@@ -532,56 +614,24 @@ def main():
             "traffic": measured_traffic(),
             "traffic_unit": "B per launch",
             "kernel": "p2p_kernel<FP32 r^2 table of T/r^3, degree 2>",
-            "flops": f"{FLOPS_PER_CAND_F32_R2} per evaluated pair + "
-                     f"{FLOPS_PER_INSIDE_F32_R2} per pair inside r_cut",
+            "flops": rooflines[head]["flops"],
             "kernel_ms": r32["p2p_ms"],
-            "paper_convention_frac": cand * PAPER_OPS_PER_PAIR
-            / (r32["p2p_ms"] / 1e3) / 1e12 / PEAK_FP32_TFLOPS,
+            "measured_peak": peak32,
+            "frac_of_measured_peak": achieved / peak32,
+            "measured_peak_note": "pmfmm_peak_fma: unpacked float32 FMA chains on every CU, "
+                                  "this run (float64: %.1f TFLOP/s)" % peak64,
+            "counter_tflops": rooflines[head]["counter_tflops"],
+            "paper_equivalent_tflops": cand * PAPER_OPS_PER_PAIR
+            / (r32["p2p_ms"] / 1e3) / 1e12,
         },
         "cpu_baseline": base,
         "forms": results,
+        "forms_roofline": rooflines,
         "p2p_interactions_per_s": {k: cand / (v["p2p_ms"] / 1e3)
                                    for k, v in results.items()},
         "p2p_inside_pairs_per_s": {k: inside / (v["p2p_ms"] / 1e3)
                                    for k, v in results.items()},
     }
-    if "fp32_paper_table" in results:
-        rt = results["fp32_paper_table"]
-        line["fp32_paper_table"] = {
-            "value": cand / (rt["ms_per_step"] / 1e3),
-            "ms_per_step": rt["ms_per_step"],
-            "p2p_tflops": cand * FLOPS_PER_PAIR_F32_T2 / (rt["p2p_ms"] / 1e3) / 1e12,
-            "frac_of_fp32_peak": cand * FLOPS_PER_PAIR_F32_T2
-            / (rt["p2p_ms"] / 1e3) / 1e12 / PEAK_FP32_TFLOPS,
-        }
-    if "fp64" in results:
-        r64 = results["fp64"]
-        line["fp64"] = {
-            "value": cand / (r64["ms_per_step"] / 1e3),
-            "ms_per_step": r64["ms_per_step"],
-            "p2p_tflops": cand * FLOPS_PER_PAIR_F64_EXACT / (r64["p2p_ms"] / 1e3) / 1e12,
-            "frac_of_fp64_peak": cand * FLOPS_PER_PAIR_F64_EXACT
-            / (r64["p2p_ms"] / 1e3) / 1e12 / PEAK_FP64_TFLOPS,
-        }
-    if "fp64_table" in results:
-        r64t = results["fp64_table"]
-        line["fp64_table"] = {
-            "value": cand / (r64t["ms_per_step"] / 1e3),
-            "ms_per_step": r64t["ms_per_step"],
-            "p2p_tflops": cand * FLOPS_PER_PAIR_F64_TABLE / (r64t["p2p_ms"] / 1e3) / 1e12,
-            "frac_of_fp64_peak": cand * FLOPS_PER_PAIR_F64_TABLE
-            / (r64t["p2p_ms"] / 1e3) / 1e12 / PEAK_FP64_TFLOPS,
-        }
-    if "fp64_r2" in results:
-        r = results["fp64_r2"]
-        line["fp64_r2"] = {
-            "value": cand / (r["ms_per_step"] / 1e3),
-            "ms_per_step": r["ms_per_step"],
-            "p2p_tflops": (evaluated * FLOPS_PER_CAND_F64_R2 + inside * FLOPS_PER_INSIDE_F64_R2)
-            / (r["p2p_ms"] / 1e3) / 1e12,
-            "frac_of_fp64_peak": (evaluated * FLOPS_PER_CAND_F64_R2 + inside * FLOPS_PER_INSIDE_F64_R2)
-            / (r["p2p_ms"] / 1e3) / 1e12 / PEAK_FP64_TFLOPS,
-        }
     print(json.dumps(line), flush=True)
 
 

@@ -5,6 +5,10 @@ numpy.quantile(method="higher"), so a reported percentile is always one of
 the observed errors.  Particles whose reference force is below 1e-6 times
 the median reference magnitude are counted apart (``tiny``), since a
 relative error is not meaningful there.
+
+Test infrastructure only (see the package docstring).  Parity: pinned by
+tests/test_oracle_metrics.py on hand-built errors whose norms, quantiles
+and tiny counts are worked out by hand.
 """
 
 from __future__ import annotations

@@ -259,6 +259,10 @@ def dual_walk(tree: Tree, box: float, r_cut: float, theta: float,
 
 
 def candidate_pairs(tree: Tree, lists: Lists) -> int:
-    """Particle pairs the P2P tasks evaluate (n_i * n_j summed over tasks)."""
+    """Particle pairs the P2P tasks evaluate (n_i * n_j summed over tasks).
+
+    Pinned by tests/test_oracle_metrics.py: N^2 for an isolated cluster
+    whose leaf pairs are all tasks, 9 for a hand-built two-leaf case, and
+    32 * 32 per task for full leaves of 32."""
     npl = tree.leaf_count
     return int(np.sum(npl[lists.p2p[:, 0]] * npl[lists.p2p[:, 1]]))

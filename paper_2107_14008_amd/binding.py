@@ -104,6 +104,10 @@ SIGNATURES = {
     "pmfmm_get_lists": (C.c_int, [C.c_void_p, C.POINTER(Lists)]),
     "pmfmm_get_timings": (C.c_int, [C.c_void_p, C.POINTER(Timings)]),
     "pmfmm_version": (C.c_char_p, []),
+    # include/pmfmm_peak.h
+    "pmfmm_peak_fma": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double)]),
+    "pmfmm_peak_last_error": (C.c_char_p, []),
 }
 
 _lib = None
@@ -166,20 +170,71 @@ def _stream(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
-def _host_f64(a, shape_last=None):
+def _dev(x, name, shape, device=None):
+    """Check that x is a contiguous float64 torch CUDA tensor of `shape`
+    (None entries are free) on `device`; raise ValueError before any kernel
+    can read or write past it."""
+    if isinstance(x, np.ndarray) or not hasattr(x, "data_ptr"):
+        raise ValueError(f"{name} must be a float64 torch CUDA tensor, got {type(x).__name__}")
+    if getattr(x.device, "type", None) != "cuda":
+        raise ValueError(f"{name} must be on a CUDA device, got {x.device}")
+    if device is not None and x.device != device:
+        raise ValueError(f"{name} is on {x.device}, expected {device}")
+    if str(x.dtype) != "torch.float64":
+        raise ValueError(f"{name} must be float64, got {x.dtype}")
+    if x.dim() != len(shape) or any(s is not None and x.shape[k] != s for k, s in enumerate(shape)):
+        raise ValueError(f"{name} must have shape {tuple('n' if s is None else s for s in shape)}"
+                         f", got {tuple(x.shape)}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return x
+
+
+def _host(a, name, shape):
+    """float64 C-contiguous copy (or view) of a host array of `shape`."""
     a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim != len(shape) or any(s is not None and a.shape[k] != s for k, s in enumerate(shape)):
+        raise ValueError(f"{name} must have shape {tuple('n' if s is None else s for s in shape)}"
+                         f", got {a.shape}")
     return a
+
+
+def _particles(pos, mass):
+    """Validated (pos (n, 3), mass (n), on_device) of one build call."""
+    if isinstance(pos, np.ndarray) != isinstance(mass, np.ndarray):
+        raise ValueError("pos and mass must both be numpy arrays or both torch CUDA tensors")
+    if isinstance(pos, np.ndarray):
+        pos = _host(pos, "pos", (None, 3))
+        mass = _host(mass, "mass", (pos.shape[0],))
+        return pos, mass, False
+    _dev(pos, "pos", (None, 3))
+    _dev(mass, "mass", (pos.shape[0],), pos.device)
+    return pos, mass, True
 
 
 def kick(vel, acc, dt, stream=None):
     """vel += acc dt (device (n, 3) float64)."""
+    _dev(vel, "vel", (None, 3))
+    _dev(acc, "acc", (vel.shape[0], 3), vel.device)
     _check(library().pmfmm_kick(int(vel.shape[0]), _ptr(vel), _ptr(acc), float(dt), _stream(stream)))
 
 
 def drift(pos, vel, dt, box, stream=None):
     """pos += vel dt, wrapped into [0, box) (device (n, 3) float64)."""
+    _dev(pos, "pos", (None, 3))
+    _dev(vel, "vel", (pos.shape[0], 3), pos.device)
     _check(library().pmfmm_drift(int(pos.shape[0]), _ptr(pos), _ptr(vel), float(dt), float(box),
                                  _stream(stream)))
+
+
+def peak_fma(precision: int, iters: int = 20000):
+    """Measured vector FMA rate (TFLOP/s, kernel ms) of the current device:
+    precision PMFMM_FP64 or PMFMM_FP32 (unpacked)."""
+    tf, ms = C.c_double(), C.c_double()
+    rc = library().pmfmm_peak_fma(int(precision), int(iters), C.byref(tf), C.byref(ms))
+    if rc != 0:
+        raise PmfmmError(rc, library().pmfmm_peak_last_error().decode())
+    return tf.value, ms.value
 
 
 class Context:
@@ -205,27 +260,26 @@ class Context:
 
     # ---- planning / build
     def plan(self, pos, mass):
-        pos = _host_f64(pos)
-        mass = _host_f64(mass)
+        pos = _host(pos, "pos", (None, 3))
+        mass = _host(mass, "mass", (pos.shape[0],))
         _check(library().pmfmm_plan(self._h, len(mass), _ptr(pos), _ptr(mass)))
         self.n = len(mass)
 
     def plan_batch(self, per_box, counts, pos, mass):
         arr = (Params * len(per_box))(*per_box)
         cnt = (C.c_int64 * len(counts))(*counts)
-        pos = _host_f64(pos)
-        mass = _host_f64(mass)
+        if len(counts) != len(per_box):
+            raise ValueError("one count per box is needed")
+        pos = _host(pos, "pos", (int(sum(counts)), 3))
+        mass = _host(mass, "mass", (int(sum(counts)),))
         _check(library().pmfmm_plan_batch(self._h, len(per_box), arr, cnt,
                                           _ptr(pos), _ptr(mass)))
         self.n = int(sum(counts))
 
     def build(self, pos, mass, stream=None):
-        """pos (n, 3), mass (n): float64 torch CUDA tensors or numpy arrays."""
-        on_dev = not isinstance(pos, np.ndarray)
-        if on_dev:
-            pos, mass = pos.contiguous(), mass.contiguous()
-        else:
-            pos, mass = _host_f64(pos), _host_f64(mass)
+        """pos (n, 3), mass (n): float64 torch CUDA tensors (contiguous) or
+        numpy arrays (copied to float64 if needed)."""
+        pos, mass, on_dev = _particles(pos, mass)
         _check(library().pmfmm_build(self._h, int(mass.shape[0]), _ptr(pos),
                                      _ptr(mass), int(on_dev), _stream(stream)))
         self.n = int(mass.shape[0])
@@ -233,34 +287,55 @@ class Context:
     def build_batch(self, per_box, counts, pos, mass, stream=None):
         arr = (Params * len(per_box))(*per_box)
         cnt = (C.c_int64 * len(counts))(*counts)
-        on_dev = not isinstance(pos, np.ndarray)
-        if on_dev:
-            pos, mass = pos.contiguous(), mass.contiguous()
-        else:
-            pos, mass = _host_f64(pos), _host_f64(mass)
+        if len(counts) != len(per_box):
+            raise ValueError("one count per box is needed")
+        pos, mass, on_dev = _particles(pos, mass)
+        if pos.shape[0] != int(sum(counts)):
+            raise ValueError(f"pos holds {pos.shape[0]} particles, the counts {int(sum(counts))}")
         _check(library().pmfmm_build_batch(self._h, len(per_box), arr, cnt,
                                            _ptr(pos), _ptr(mass), int(on_dev),
                                            _stream(stream)))
         self.n = int(sum(counts))
 
     def set_eval(self, **kw):
+        """Apply the changes to a copy; keep them only once the library has
+        accepted them (a rejected call leaves params as they were)."""
+        p = Params()
+        C.pointer(p)[0] = self.params
         for k, v in kw.items():
-            setattr(self.params, k, v)
-        _check(library().pmfmm_set_eval(self._h, C.byref(self.params)))
+            if not hasattr(p, k):
+                raise KeyError(k)
+            setattr(p, k, v)
+        _check(library().pmfmm_set_eval(self._h, C.byref(p)))
+        self.params = p
+
+    def _built(self):
+        if self.n <= 0:
+            raise PmfmmError(-4, "forward / adjoint before build")
 
     # ---- compute
     def forward(self, out, stream=None):
         """out: float64 CUDA tensor (n, 3), written in caller order."""
+        self._built()
+        _dev(out, "out", (self.n, 3))
         _check(library().pmfmm_forward(self._h, _ptr(out), _stream(stream)))
         return out
 
     def adjoint(self, w, grad_pos, grad_mass, stream=None):
+        """w, grad_pos: float64 CUDA (n, 3); grad_mass: float64 CUDA (n)."""
+        self._built()
+        _dev(w, "w", (self.n, 3))
+        _dev(grad_pos, "grad_pos", (self.n, 3), w.device)
+        _dev(grad_mass, "grad_mass", (self.n,), w.device)
         _check(library().pmfmm_adjoint(self._h, _ptr(w), _ptr(grad_pos),
                                        _ptr(grad_mass), _stream(stream)))
         return grad_pos, grad_mass
 
     def long_range(self, n_pm, pos, mass, out, stream=None):
         """Long-range (mesh) accelerations into out (n, 3), caller order."""
+        _dev(pos, "pos", (None, 3))
+        _dev(mass, "mass", (pos.shape[0],), pos.device)
+        _dev(out, "out", (pos.shape[0], 3), pos.device)
         _check(library().pmfmm_long_range(self._h, int(n_pm), int(pos.shape[0]), _ptr(pos),
                                           _ptr(mass), _ptr(out), _stream(stream)))
         return out

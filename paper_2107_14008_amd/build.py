@@ -38,6 +38,7 @@ SOURCES = [
     ("gpu_plan.hip", "hip"),
     ("pm.hip", "hip"),
     ("step.hip", "hip"),
+    ("peak.hip", "hip"),
 ]
 
 

@@ -61,12 +61,12 @@ def autotune(ctx, out, stream=None, repeats: int = 3, cache_path: str = CACHE,
             cache = json.load(open(cache_path))
         except (OSError, ValueError):
             cache = {}
+    timing_before = ctx.params.timing
     if use_cache and key in cache:
         best = cache[key]
         ctx.set_eval(chunk=best["chunk"], wg_waves=best["wg_waves"],
-                     grid_wgs=best["grid_wgs"], timing=1)
+                     grid_wgs=best["grid_wgs"], timing=timing_before)
         return best, {}
-    timing_before = ctx.params.timing
     results = {}
     for chunk, wg, grid in (cands or candidates()):
         ctx.set_eval(chunk=chunk, wg_waves=wg, grid_wgs=grid, timing=1)

@@ -18,9 +18,15 @@ def lib():
 
 
 def declared_functions(root):
-    text = open(os.path.join(root, "include", "pmfmm.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(pmfmm_[a-z_]+)\s*\(", text)))
+    names = set()
+    inc = os.path.join(root, "include")
+    for h in sorted(os.listdir(inc)):
+        if not h.endswith(".h"):
+            continue
+        text = open(os.path.join(inc, h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(pmfmm_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_every_declared_symbol_is_exported(lib, repo_root):
@@ -152,3 +158,52 @@ def test_batch_plan_names_bad_box():
     ctx.plan_batch([good, good], [10, 20], pos, np.ones(30))
     L = ctx.lists()
     assert L["n_boxes"] == 2 and L["n"] == 30
+
+
+def test_set_eval_keeps_params_after_a_rejected_call():
+    ctx = B.Context(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE, table_size=512,
+                    table_level=2)
+    with pytest.raises(B.PmfmmError):
+        ctx.set_eval(table_level=9, chunk=7)
+    assert ctx.params.table_level == 2 and ctx.params.chunk == 0
+    ctx.set_eval(chunk=8)
+    assert ctx.params.chunk == 8 and ctx.params.table_level == 2
+
+
+def test_binding_rejects_bad_host_arrays_before_the_call():
+    ctx = B.Context(box=10.0, r_s=0.5, r_cut=2.25, max_leaf=8)
+    pos = np.random.default_rng(0).uniform(0, 10, (50, 3))
+    m = np.ones(50)
+    with pytest.raises(ValueError, match="shape"):
+        ctx.plan(pos[:, :2], m)
+    with pytest.raises(ValueError, match="shape"):
+        ctx.plan(pos, m[:49])
+    with pytest.raises(ValueError, match="shape"):
+        ctx.build(pos.reshape(-1), m)
+    with pytest.raises(ValueError, match="both"):
+        ctx.build(pos, object())
+    with pytest.raises(ValueError, match="one count per box"):
+        ctx.plan_batch([ctx.params], [25, 25], pos, m)
+    with pytest.raises(ValueError, match="shape"):
+        ctx.plan_batch([ctx.params, ctx.params], [25, 24], pos, m)
+
+
+def test_binding_rejects_cpu_tensors():
+    torch = pytest.importorskip("torch")
+    ctx = B.Context(box=10.0, r_s=0.5, r_cut=2.25, max_leaf=8)
+    pos = torch.zeros((50, 3), dtype=torch.float64)
+    m = torch.ones(50, dtype=torch.float64)
+    with pytest.raises(ValueError, match="CUDA"):
+        ctx.build(pos, m)
+    with pytest.raises(ValueError, match="CUDA"):
+        B.kick(pos, pos, 0.1)
+    ctx.plan(pos.numpy(), m.numpy())
+    with pytest.raises(ValueError, match="CUDA"):
+        ctx.forward(pos)
+    with pytest.raises(ValueError, match="CUDA"):
+        ctx.adjoint(pos, pos, m)
+    with pytest.raises(ValueError, match="CUDA"):
+        ctx.long_range(16, pos, m, pos)
+    fresh = B.Context(box=10.0, r_s=0.5, r_cut=2.25, max_leaf=8)
+    with pytest.raises(B.PmfmmError, match="before build"):
+        fresh.forward(pos)

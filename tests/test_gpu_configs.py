@@ -1,0 +1,276 @@
+"""Parity at the workloads' own sizes and settings.
+
+* 64^3 clustered gradient case (262,144 particles, leaf <= 64, P2P only):
+  float32 r^2 forward and adjoint against the oracle force and gradient on
+  2,000 sampled particles; float64 adjoint against the oracle gradient and
+  against central finite differences (h = 1e-4 grid spacings) of the float64
+  GPU forward on sampled particles.
+* 256^3 clustered (16,777,216 particles, 30 % in 2000 halos, leaf <= 64,
+  p = 4, theta = 0.25): the float32 forms (exact erfc/exp, 2048-node T_[1]
+  and T_[3], the paper's 512-node T_[2], the r^2 table) against the
+  brute-force definition on 1,000 sampled particles.
+* the batch of 64 clustered boxes (16^3 .. 96^3, ~1.1e7 particles) in one
+  launch, P2P only and with the far field on (p = 4, theta = 0.25), against
+  brute force on sampled particles of sampled boxes.
+* the far field at the headline settings (leaf <= 64, p = 4, theta = 0.25)
+  on a 32^3 clustered box, against the oracle's FMM on the same lists.
+
+Tolerances as everywhere: float64 <= 1e-12 (max); float32 median <= 1e-5
+and 99.9th percentile <= 1e-4 of the per-particle relative error; the
+gradients' errors are measured against the oracle's sum of pair-term
+magnitudes (reading 18 of the design notes), plus the plain relative error
+of the position gradient.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import direct, fmm, metrics
+from paper_2107_14008_amd import binding as B
+from paper_2107_14008_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+R2 = dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_size=64, table_level=2)
+
+
+def check_fp32(acc, ref, what):
+    s = metrics.error_summary(acc, ref)
+    print(f"  {what}: {s}", flush=True)
+    assert s["tiny"] == 0
+    assert s["median"] <= 1e-5 and s["p999"] <= 1e-4, (what, s)
+    return s
+
+
+def scaled(a, ref, scale):
+    a = np.asarray(a).reshape(len(scale), -1)
+    ref = np.asarray(ref).reshape(len(scale), -1)
+    e = np.linalg.norm(a - ref, axis=1) / scale
+    return dict(median=float(np.quantile(e, 0.5, method="higher")),
+                p999=float(np.quantile(e, 0.999, method="higher")),
+                max=float(e.max()))
+
+
+# ------------------------------------------------ 64^3 gradient workload
+
+@pytest.fixture(scope="module")
+def c5():
+    w = inputs.clustered_262k()
+    wv = inputs.cotangent(len(w.mass))
+    idx = np.sort(np.random.default_rng(15013).choice(len(w.mass), 2000, replace=False))
+    ref, _ = direct.brute_force(w.pos, w.mass, w.box, w.r_s, w.r_cut, targets=idx)
+    gx, gm, sx, sm = direct.gradient(w.pos, w.mass, wv, w.box, w.r_s, w.r_cut,
+                                     targets=idx, with_scale=True)
+    dev = torch.device("cuda")
+    return dict(w=w, wv=wv, idx=idx, ref=ref, gx=gx, gm=gm, sx=sx, sm=sm,
+                pos=torch.tensor(w.pos, device=dev), mass=torch.tensor(w.mass, device=dev),
+                wt=torch.tensor(wv, device=dev))
+
+
+def c5_run(c, **ev):
+    w = c["w"]
+    ctx = B.Context(box=w.box, r_s=w.r_s, r_cut=w.r_cut, max_leaf=64, order=-1, **ev)
+    ctx.build(c["pos"], c["mass"])
+    n = len(w.mass)
+    out = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    gp = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    gm = torch.empty((n,), dtype=torch.float64, device="cuda")
+    ctx.forward(out)
+    ctx.adjoint(c["wt"], gp, gm)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), gp.cpu().numpy(), gm.cpu().numpy(), ctx
+
+
+def test_c5_fp32_r2_forward_and_adjoint(c5):
+    print("case: 64^3 clustered, float32 r^2 forward + adjoint, 2000 sampled",
+          flush=True)
+    acc, gp, gm, ctx = c5_run(c5, **R2)
+    i = c5["idx"]
+    check_fp32(acc[i], c5["ref"], "force")
+    errs = (scaled(gp[i], c5["gx"], c5["sx"]), scaled(gm[i], c5["gm"], c5["sm"]),
+            metrics.error_summary(gp[i], c5["gx"]))
+    print("  gradient errors (pos scaled, mass scaled, pos relative):", errs, flush=True)
+    for s in errs:
+        assert s["median"] <= 1e-5 and s["p999"] <= 1e-4, s
+
+
+def test_c5_fp64_adjoint_matches_oracle(c5):
+    print("case: 64^3 clustered, float64 exact adjoint, 2000 sampled", flush=True)
+    acc, gp, gm, ctx = c5_run(c5, precision=B.PMFMM_FP64)
+    i = c5["idx"]
+    assert metrics.error_summary(acc[i], c5["ref"])["max"] <= 1e-12
+    ex, em = scaled(gp[i], c5["gx"], c5["sx"]), scaled(gm[i], c5["gm"], c5["sm"])
+    print("  gradient errors (pos, mass; scaled):", ex, em, flush=True)
+    assert ex["max"] <= 1e-12 and em["max"] <= 1e-12
+
+
+def test_c5_adjoint_vs_central_differences(c5):
+    """Central differences of the float64 GPU loss at h = 1e-4 grid
+    spacings, on 16 sampled particles with no neighbour within 2h of r_cut
+    and none closer than 100 h.  The loss is summed over the particles whose
+    force can change (within r_cut + 4h of the moved one), so the other
+    particles' rounding does not enter.  The plain central difference D(h)
+    has a truncation error of about 2 (h / r)^2 of each pair term
+    (<= 2e-4 of their magnitude sum S here); the Richardson combination
+    (4 D(h/2) - D(h)) / 3 removes it to (h / r)^4, which checks the float64
+    adjoint to 1e-6 of S.  The mass gradient is exact up to rounding (the
+    loss is linear in each mass)."""
+    w, wv = c5["w"], c5["wv"]
+    n = len(w.mass)
+    dg = w.box / w.n_pm
+    h = 1e-4 * dg
+    print("case: 64^3 clustered, adjoint vs central differences", flush=True)
+    _, gp64, gm64, _ = c5_run(c5, precision=B.PMFMM_FP64)
+    _, gp32, gm32, _ = c5_run(c5, **R2)
+    ctx = B.Context(box=w.box, r_s=w.r_s, r_cut=w.r_cut, max_leaf=64, order=-1,
+                    precision=B.PMFMM_FP64)
+    out = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+
+    def local_loss(pos, mass, near):
+        ctx.build(torch.tensor(pos, device="cuda"), torch.tensor(mass, device="cuda"))
+        ctx.forward(out)
+        a = out[torch.as_tensor(near, device="cuda")].cpu().numpy()
+        return float(np.sum(a * wv[near]))
+
+    def central(k, a, step, near):
+        pp, pm = w.pos.copy(), w.pos.copy()
+        pp[k, a] += step
+        pm[k, a] -= step
+        return (local_loss(pp, w.mass, near) - local_loss(pm, w.mass, near)) / (2 * step)
+
+    rng = np.random.default_rng(77)
+    checked = skipped = 0
+    worst = 0.0
+    for k in rng.permutation(n):
+        if checked >= 16:
+            break
+        d = direct.image_displacement(w.pos[k][None, :], w.pos, w.box)
+        r = np.linalg.norm(d, axis=1)
+        r[k] = np.inf
+        if np.any(np.abs(r - w.r_cut) < 2 * h) or r.min() < 100 * h:
+            skipped += 1
+            continue
+        near = np.sort(np.concatenate([[k], np.nonzero(r < w.r_cut + 4 * h)[0]]))
+        Sx, Sm = c5_scale(w, k, wv)
+        for a in range(3):
+            d1 = central(k, a, h, near)
+            d2 = central(k, a, 0.5 * h, near)
+            rich = (4.0 * d2 - d1) / 3.0
+            assert abs(gp64[k, a] - d1) <= 1e-3 * Sx, (k, a, gp64[k, a], d1, Sx)
+            assert abs(gp64[k, a] - rich) <= 1e-6 * Sx, (k, a, gp64[k, a], rich, Sx)
+            assert abs(gp32[k, a] - rich) <= 1e-4 * Sx, (k, a, gp32[k, a], rich, Sx)
+            worst = max(worst, abs(gp64[k, a] - rich) / Sx)
+        mp_, mm_ = w.mass.copy(), w.mass.copy()
+        mp_[k] *= 1.001
+        mm_[k] *= 0.999
+        fd = (local_loss(w.pos, mp_, near) - local_loss(w.pos, mm_, near)) / (0.002 * w.mass[k])
+        assert abs(gm64[k] - fd) <= 1e-6 * Sm, (k, gm64[k], fd, Sm)
+        assert abs(gm32[k] - fd) <= 1e-4 * Sm, (k, gm32[k], fd, Sm)
+        checked += 1
+    print(f"  checked {checked} particles, skipped {skipped} (cutoff band or a "
+          f"neighbour closer than 100 h); worst float64 |g - Richardson| / S = "
+          f"{worst:.3g}", flush=True)
+    assert checked == 16
+
+
+def c5_scale(w, k, wv):
+    _, _, sx, sm = direct.gradient(w.pos, w.mass, wv, w.box, w.r_s, w.r_cut,
+                                   targets=np.array([k]), with_scale=True, workers=1)
+    return float(sx[0]), float(sm[0])
+
+
+# ------------------------------------------------ 256^3 clustered
+
+@pytest.mark.timeout(900)
+def test_c3_fp32_forms_sampled():
+    print("case: 256^3 clustered (16.7 M), float32 forms, 1000 sampled", flush=True)
+    w = inputs.clustered_16m()
+    idx = np.sort(np.random.default_rng(14011).choice(len(w.mass), 1000, replace=False))
+    ref, _ = direct.brute_force(w.pos, w.mass, w.box, w.r_s, w.r_cut, targets=idx)
+    pos = torch.tensor(w.pos, device="cuda")
+    mass = torch.tensor(w.mass, device="cuda")
+    n = len(w.mass)
+    out = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    forms = {"exact": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_EXACT),
+             "T1 2048": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
+                             table_size=2048, table_level=1),
+             "T3 2048": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
+                             table_size=2048, table_level=3),
+             "T2 512": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
+                            table_size=512, table_level=2),
+             "r2 64": R2}
+    ctx = B.Context(box=w.box, r_s=w.r_s, r_cut=w.r_cut, max_leaf=64, order=4,
+                    theta=0.25, **forms["exact"])
+    ctx.build(pos, mass)
+    assert ctx.lists()["n_m2l"] > 0
+    for name, ev in forms.items():
+        ctx.set_eval(**ev)
+        ctx.forward(out)
+        torch.cuda.synchronize()
+        check_fp32(out[torch.as_tensor(idx, device="cuda")].cpu().numpy(), ref,
+                   f"256^3 {name}")
+
+
+# ------------------------------------------------ 64-box batch
+
+@pytest.fixture(scope="module")
+def c4():
+    boxes = inputs.batch_64()
+    counts = [len(b.mass) for b in boxes]
+    starts = np.concatenate([[0], np.cumsum(counts)])
+    rng = np.random.default_rng(1400800)
+    picked = sorted(rng.choice(len(boxes), 8, replace=False).tolist())
+    refs = {}
+    for b in picked:
+        w = boxes[b]
+        idx = np.sort(rng.choice(len(w.mass), min(400, len(w.mass)), replace=False))
+        refs[b] = (idx, direct.brute_force(w.pos, w.mass, w.box, w.r_s, w.r_cut,
+                                           targets=idx)[0])
+    pos = torch.tensor(np.concatenate([b.pos for b in boxes]), device="cuda")
+    mass = torch.tensor(np.concatenate([b.mass for b in boxes]), device="cuda")
+    return dict(boxes=boxes, counts=counts, starts=starts, refs=refs, pos=pos, mass=mass)
+
+
+@pytest.mark.parametrize("order,theta", [(-1, 0.0), (4, 0.25)])
+def test_c4_batch_sampled(c4, order, theta):
+    boxes, counts = c4["boxes"], c4["counts"]
+    print(f"case: 64 clustered boxes ({sum(counts)} particles), one launch, "
+          f"float32 r^2, p={order} theta={theta}", flush=True)
+    per_box = [B.make_params(box=w.box, r_s=w.r_s, r_cut=w.r_cut, max_leaf=64,
+                             order=order, theta=theta) for w in boxes]
+    ctx = B.Context(**R2)
+    ctx.build_batch(per_box, counts, c4["pos"], c4["mass"])
+    if order >= 0:
+        assert ctx.lists()["n_m2l"] > 0
+    out = torch.empty((sum(counts), 3), dtype=torch.float64, device="cuda")
+    ctx.forward(out)
+    torch.cuda.synchronize()
+    acc = out.cpu().numpy()
+    for b, (idx, ref) in c4["refs"].items():
+        check_fp32(acc[c4["starts"][b] + idx], ref, f"box {b} ({counts[b]} particles)")
+
+
+# ------------------------------------------------ far field, headline settings
+
+def test_fmm_at_headline_settings_matches_oracle_fmm():
+    """Leaf <= 64, p = 4, theta = 0.25 (the 128^3 workload's settings) on a
+    32^3 clustered box whose halos give M2L tasks: float64 against the
+    oracle's FMM on the same lists, <= 1e-12."""
+    w = inputs.clustered_small(32, 14012, halo_frac=0.4, n_halos=8)
+    print("case: far field, 32^3 clustered, leaf 64, p 4, theta 0.25", flush=True)
+    ctx = B.Context(box=w.box, r_s=w.r_s, r_cut=w.r_cut, max_leaf=64, order=4,
+                    theta=0.25, precision=B.PMFMM_FP64)
+    ctx.build(torch.tensor(w.pos, device="cuda"), torch.tensor(w.mass, device="cuda"))
+    out = torch.empty((len(w.mass), 3), dtype=torch.float64, device="cuda")
+    ctx.forward(out)
+    torch.cuda.synchronize()
+    n_m2l = ctx.lists()["n_m2l"]
+    ref, near, far, tree, lists = fmm.fmm_forces(w.pos, w.mass, w.box, w.r_s, w.r_cut,
+                                                 64, 4, 0.25, return_parts=True)
+    print(f"  {n_m2l} M2L tasks; far-field share max |far| / max |a| = "
+          f"{np.abs(far).max() / np.abs(ref).max():.3g}", flush=True)
+    assert n_m2l == len(lists.m2l) > 0
+    assert np.abs(far).max() > 1e-6 * np.abs(ref).max()
+    assert metrics.error_summary(out.cpu().numpy(), ref)["max"] <= 1e-12

@@ -9,6 +9,7 @@ torch = pytest.importorskip("torch")
 
 from paper_2107_14008_amd import binding as B
 from paper_2107_14008_amd import inputs
+from oracle import tree as T
 from test_lists import assert_same, oracle_lists
 
 pytestmark = pytest.mark.gpu
@@ -142,17 +143,33 @@ def test_long_task_rows(row_lds, monkeypatch):
         assert np.array_equal(L[k], H[k]), k
 
 
-def test_matches_host_planner_clustered_2m_items():
+def test_matches_oracle_and_host_planner_clustered_2m():
+    """The headline workload (128^3 clustered, leaf <= 64, p = 4, theta =
+    0.25): the GPU planner's tree and lists against the oracle's own
+    builder, integer for integer and bit for bit, and its work items
+    against the host planner's."""
     w = inputs.clustered_2m()
-    print("case: gpu plan vs host plan 128^3", flush=True)
+    print("case: gpu plan vs oracle and host plan 128^3", flush=True)
     L, ctx = gpu_lists(w.pos, w.mass, w.box, w.r_s, w.r_cut, 64, 4, 0.25)
+    tree = T.build_orb(w.pos, 64)
+    lists = T.dual_walk(tree, w.box, w.r_cut, 0.25, True)
+    assert len(lists.m2l) > 0
+    assert np.array_equal(L["perm"], tree.perm)
+    assert np.array_equal(L["cell_lo"], tree.lo)
+    assert np.array_equal(L["cell_hi"], tree.hi)
+    assert np.array_equal(L["leaf_first"], tree.leaf_first)
+    assert np.array_equal(L["leaf_count"], tree.leaf_count)
+    assert np.array_equal(L["p2p_row"], lists.p2p_row)
+    assert np.array_equal(L["p2p_j"], lists.p2p[:, 1])
+    assert np.array_equal(L["p2p_shift"], lists.p2p[:, 2])
+    assert np.array_equal(L["m2l_row"], lists.m2l_row)
+    assert np.array_equal(L["m2l_src"], lists.m2l[:, 1])
+    assert np.array_equal(L["m2l_shift"], lists.m2l[:, 2])
+    assert L["candidate_pairs"] == T.candidate_pairs(tree, lists)
     host = B.Context(box=w.box, r_s=w.r_s, r_cut=w.r_cut, max_leaf=64,
                      order=4, theta=0.25)
     host.plan(w.pos, w.mass)
     H = host.lists()
-    for k in ("perm", "cell_lo", "cell_hi", "p2p_row", "p2p_j", "p2p_shift",
-              "m2l_row", "m2l_src", "m2l_shift", "leaf_first", "leaf_count"):
-        assert np.array_equal(L[k], H[k]), k
     for k in ("n_p2p", "n_m2l", "n_items", "candidate_pairs"):
         assert L[k] == H[k], k
 

@@ -130,3 +130,15 @@ def test_batch_matches_per_box():
         assert np.array_equal(L["cell_child"][c0:c0 + len(tree.lo)],
                               np.where(tree.child >= 0, tree.child + c0, -1))
         p0 += len(w.mass)
+
+
+def test_clustered_2m_headline_lists():
+    """The headline workload itself (128^3 clustered, leaf <= 64, p = 4,
+    theta = 0.25): 32,768 leaves, ~2.7 million P2P and some hundred M2L
+    tasks, integer for integer and bit for bit against the oracle
+    (about 15 s of CPU)."""
+    w = inputs.clustered_2m()
+    L = host_lists(w.pos, w.mass, w.box, w.r_s, w.r_cut, 64, 4, 0.25)
+    tree, lists = oracle_lists(w.pos, w.box, w.r_cut, 64, 4, 0.25)
+    assert L["n_leaves"] == 32768 and len(lists.m2l) > 0
+    assert_same(L, tree, lists)

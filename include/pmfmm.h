@@ -179,6 +179,24 @@ int pmfmm_set_eval(pmfmm_ctx* ctx, const pmfmm_params* p);
  * Errors: ESTATE (not built), EDEVICE. */
 int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream);
 
+/* pmfmm_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels and results (bit for bit) as pmfmm_forward; the
+ * queue counters and the work items' partial sums live in a static device
+ * array of the library instead of the context's buffers: 64 MiB per GPU,
+ * held from the first use on that GPU until the process ends, room for
+ * 43,688 work items (about 4e5 particles of clustered input at leaf 64).
+ * The call allocates nothing, records no timing events and, unlike
+ * pmfmm_forward, never builds or uploads the truncation table: the build
+ * uploads it, and after a pmfmm_set_eval that changes the evaluation this
+ * call refuses until pmfmm_forward (or a build) has run once.  Every call on
+ * one GPU shares that GPU's array (the counters are cleared by a kernel at
+ * the start of each call): calls that overlap on one GPU, on any streams or
+ * contexts, race and give wrong results; order them on one stream or with
+ * events.  Errors: ESTATE (not built, or the table is not current), EINVAL
+ * (more work items than the array holds: use pmfmm_forward), EDEVICE. */
+int pmfmm_forward_static(pmfmm_ctx* ctx, double* acc, void* stream);
+
 /* Gradient of loss = sum_i w_i . a_i with respect to positions and masses
  * (not in the paper; the transpose of the pair sum of Eq. (tr) and, with
  * the far field on, of the Sec. 2 operators P2M, M2M, M2L, L2L, L2P, with

@@ -94,6 +94,7 @@ SIGNATURES = {
                                     C.c_void_p, C.c_int32, C.c_void_p]),
     "pmfmm_set_eval": (C.c_int, [C.c_void_p, C.POINTER(Params)]),
     "pmfmm_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pmfmm_forward_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pmfmm_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.c_void_p]),
     "pmfmm_long_range": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p,
@@ -319,6 +320,15 @@ class Context:
         self._built()
         _dev(out, "out", (self.n, 3))
         _check(library().pmfmm_forward(self._h, _ptr(out), _stream(stream)))
+        return out
+
+    def forward_static(self, out, stream=None):
+        """As forward, through pmfmm_forward_static (no device allocation:
+        the library's static scratch array instead of the context's
+        buffers)."""
+        self._built()
+        _dev(out, "out", (self.n, 3))
+        _check(library().pmfmm_forward_static(self._h, _ptr(out), _stream(stream)))
         return out
 
     def adjoint(self, w, grad_pos, grad_mass, stream=None):

@@ -1084,19 +1084,21 @@ int pmfmm_set_eval(pmfmm_ctx* ctx, const pmfmm_params* p) {
     return PMFMM_OK;
 }
 
-int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream) {
-    if (!ctx || !acc) return fail(PMFMM_EINVAL, "null argument");
-    if (!ctx->built) return fail(PMFMM_ESTATE, "forward before build");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    int rc = upload_table(ctx, s);
-    if (rc) return rc;
+}  // extern "C"
+
+namespace {
+
+// The forward after the checks: far field (or the wait for the one the
+// build started), the persistent P2P kernel with its queue counters in
+// `counter` and the item partials in `partial`, the ordered reduction.
+// Launches only: allocates nothing (the timing events must exist when
+// `timing` is set).
+int forward_launch(pmfmm_ctx* ctx, double* acc, hipStream_t s, int32_t* counter, double* partial,
+                   bool timing) {
     const pmfmm::Plan& pl = ctx->plan;
     const int mode = mode_of(ctx->p);
-    const bool timing = ctx->p.timing != 0;
-    if (timing) {
-        if ((rc = ensure_events(ctx))) return rc;
-        HIP_TRY(hipEventRecord(ctx->ev[0], s));
-    }
+    int rc;
+    if (timing) HIP_TRY(hipEventRecord(ctx->ev[0], s));
     if (ctx->far) {
         if (ctx->far_early) {
             if ((rc = wait_far(ctx, s))) return rc;   // computed during the build
@@ -1104,7 +1106,7 @@ int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream) {
             return rc;
         }
     }
-    HIP_TRY(pmfmm::launch_zero_i32(ctx->d.counter.as<int32_t>(), pmfmm::kQueueSegs * pmfmm::kCounterStride, s));
+    HIP_TRY(pmfmm::launch_zero_i32(counter, pmfmm::kQueueSegs * pmfmm::kCounterStride, s));
     if (timing) HIP_TRY(hipEventRecord(ctx->ev[1], s));
     pmfmm::P2PArgs a{};
     a.x64 = ctx->d.x64.as<double4>();
@@ -1115,8 +1117,8 @@ int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream) {
     a.items = ctx->d.items.as<int4>();
     a.queue = ctx->d.queue.as<int32_t>();
     a.n_items = (int32_t)ctx->n_items;
-    a.counter = ctx->d.counter.as<int32_t>();
-    a.partial = ctx->d.partial.as<double>();
+    a.counter = counter;
+    a.partial = partial;
     a.boxes = ctx->d.boxes.as<pmfmm::BoxDev>();
     a.table = ctx->d.table.p;
     a.n_tab = ctx->p.table_size;
@@ -1130,7 +1132,7 @@ int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream) {
     if (grid <= 0) grid = ctx->n_cu * pmfmm::p2p_blocks_per_cu(mode, wg, lds);
     HIP_TRY(pmfmm::launch_p2p(mode, a, wg, grid, lds, s));
     if (timing) HIP_TRY(hipEventRecord(ctx->ev[2], s));
-    pmfmm::ReduceArgs r{ctx->d.leaf.as<int4>(), ctx->d.leaf_slot.as<int32_t>(), ctx->d.partial.as<double>(),
+    pmfmm::ReduceArgs r{ctx->d.leaf.as<int4>(), ctx->d.leaf_slot.as<int32_t>(), partial,
                         ctx->far ? ctx->d.far.as<double>() : nullptr,
                         ctx->far ? ctx->d.farflag.as<int32_t>() + 2 * (int64_t)pl.cells.size() : nullptr,
                         ctx->d.perm.as<int32_t>(), ctx->d.boxes.as<pmfmm::BoxDev>(), acc,
@@ -1141,6 +1143,46 @@ int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream) {
         ctx->timed_fwd = true;
     }
     return PMFMM_OK;
+}
+
+// The table the build uploaded still matches the evaluation parameters.
+bool table_current(const pmfmm_ctx* ctx) {
+    const double xc = ctx->plan.boxes.empty() ? ctx->p.r_cut / (2.0 * ctx->p.r_s)
+                                              : ctx->plan.boxes[0].r_cut / (2.0 * ctx->plan.boxes[0].r_s);
+    return !ctx->table_dirty && (!r2_table(ctx->p) || xc == ctx->table_xc);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pmfmm_forward(pmfmm_ctx* ctx, double* acc, void* stream) {
+    if (!ctx || !acc) return fail(PMFMM_EINVAL, "null argument");
+    if (!ctx->built) return fail(PMFMM_ESTATE, "forward before build");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = upload_table(ctx, s);
+    if (rc) return rc;
+    const bool timing = ctx->p.timing != 0;
+    if (timing && (rc = ensure_events(ctx))) return rc;
+    return forward_launch(ctx, acc, s, ctx->d.counter.as<int32_t>(), ctx->d.partial.as<double>(), timing);
+}
+
+int pmfmm_forward_static(pmfmm_ctx* ctx, double* acc, void* stream) {
+    if (!ctx || !acc) return fail(PMFMM_EINVAL, "null argument");
+    if (!ctx->built) return fail(PMFMM_ESTATE, "forward before build");
+    if (!table_current(ctx))
+        return fail(PMFMM_ESTATE,
+                    "the evaluation changed since the build: the table is not on the device "
+                    "(run pmfmm_forward once, or build again)");
+    if (ctx->n_items > pmfmm::kStaticMaxItems)
+        return fail(PMFMM_EINVAL, "plan has " + std::to_string(ctx->n_items) +
+                                      " work items; the static scratch holds at most " +
+                                      std::to_string(pmfmm::kStaticMaxItems) + " (use pmfmm_forward)");
+    void* base = nullptr;
+    HIP_TRY(pmfmm::static_scratch(&base));
+    unsigned char* b = static_cast<unsigned char*>(base);
+    return forward_launch(ctx, acc, static_cast<hipStream_t>(stream), reinterpret_cast<int32_t*>(b),
+                          reinterpret_cast<double*>(b + pmfmm::kStaticCounterBytes), false);
 }
 
 int pmfmm_kick(int64_t n, double* vel, const double* acc, double dt, void* stream) {

@@ -238,6 +238,19 @@ struct AdjReduceArgs {
     int32_t n_leaves;
 };
 
+// Static scratch of the forward that allocates nothing (pmfmm_forward_static):
+// the queue counters in the first kStaticCounterBytes, then the partial sums
+// of up to kStaticMaxItems work items (3 x 64 doubles each).
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr size_t kStaticCounterBytes = 4096;
+constexpr size_t kStaticPartialBytes = 3 * 64 * sizeof(double);
+constexpr int64_t kStaticMaxItems =
+    (int64_t)((kStaticScratchBytes - kStaticCounterBytes) / kStaticPartialBytes);
+static_assert((size_t)kQueueSegs * kCounterStride * 4 <= kStaticCounterBytes, "counters");
+// Device address of that scratch on the current device (resolved with
+// hipGetSymbolAddress on the first call per device, then cached).
+hipError_t static_scratch(void** out);
+
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_gather(const GatherArgs& a, const double* pos_dev_unwrapped,
                          hipStream_t s);

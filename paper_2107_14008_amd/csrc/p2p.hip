@@ -16,6 +16,15 @@
 // scheduling.
 #include "device.h"
 
+#include <mutex>
+
+// Scratch of pmfmm_forward_static: the queue counters, then the work items'
+// partial sums (kStaticCounterBytes + 1536 bytes per item).  Each GPU the
+// library runs on holds its own copy until the process ends.  In host code
+// `scratch` names a host-side stand-in, never device memory: the device
+// address comes from hipGetSymbolAddress (static_scratch below).
+static __device__ __align__(256) unsigned char scratch[pmfmm::kStaticScratchBytes];
+
 namespace pmfmm {
 namespace {
 
@@ -726,6 +735,28 @@ hipError_t launch_rescale_x32(const int4* leaf, const double4* leafc, const BoxD
     hipLaunchKernelGGL(rescale_x32_kernel, dim3((n_leaves + 3) / 4), dim3(256), 0, s, leaf, leafc,
                        boxes, x64, x32, n_leaves);
     return hipGetLastError();
+}
+
+hipError_t static_scratch(void** out) {
+    // one address per device, resolved on the first call with that device
+    // current (each GPU holds its own copy of the array)
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (addr[dev] == nullptr) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (p == nullptr) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_zero_i32(int32_t* p, int32_t n, hipStream_t s) {

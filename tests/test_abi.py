@@ -121,6 +121,8 @@ def test_calls_out_of_order():
     lists = B.Lists()
     assert lib.pmfmm_get_lists(ctx._h, lists) == -4
     assert lib.pmfmm_forward(ctx._h, B.C.c_void_p(8), None) == -4
+    assert lib.pmfmm_forward_static(ctx._h, B.C.c_void_p(8), None) == -4
+    assert lib.pmfmm_forward_static(ctx._h, None, None) == -1
     assert lib.pmfmm_adjoint(ctx._h, B.C.c_void_p(8), B.C.c_void_p(8),
                              B.C.c_void_p(8), None) == -4
     t = B.Timings()

@@ -72,6 +72,14 @@ enum { PMFMM_TRUNC_EXACT = 0, PMFMM_TRUNC_TABLE = 1, PMFMM_TRUNC_R2 = 2 };
 enum { PMFMM_M2L_INSIDE = 0, PMFMM_M2L_CENTRE = 1 };
 /* Table node choice for x: nearest node or the node below x. */
 enum { PMFMM_ROUND_NEAREST = 0, PMFMM_ROUND_FLOOR = 1 };
+/* Accumulation of the float32 pair sums of each work item: each j leaf's
+ * float32 sum added into float64 (default), or into a float32 sum with a
+ * float32 compensation term by Knuth's TwoSum (the error-free sum of two
+ * floats; the pair is added in float64 at the end of the item).  Sec. 4
+ * compares single against double precision; the compensated float32 sum is
+ * the all-single-precision variant with the rounding of the running sum
+ * recovered. */
+enum { PMFMM_ACCUM_FP64 = 0, PMFMM_ACCUM_FP32_TWOSUM = 1 };
 
 typedef struct pmfmm_params {
     /* geometry and force split (Sec. 2) */
@@ -96,18 +104,23 @@ typedef struct pmfmm_params {
     int32_t table_round; /* TABLE: PMFMM_ROUND_NEAREST or PMFMM_ROUND_FLOOR       */
     /* scheduling of the P2P work (no effect on results) */
     int32_t chunk;       /* j-leaves per work item, 0 = automatic                 */
-    int32_t wg_waves;    /* wavefronts per workgroup of the P2P and adjoint launches, 0 = auto */
+    int32_t wg_waves;    /* wavefronts per workgroup of the P2P and adjoint launches,
+                            0 = auto; the float64 exact P2P and every float64
+                            adjoint run at most 4 (larger values use 4)       */
     int32_t grid_wgs;    /* workgroups of the persistent launch, 0 = auto         */
     int32_t timing;      /* 1: time each phase with HIP events (see get_timings)  */
     int32_t threads;     /* host threads of the host planner, 0 = all             */
     int32_t planner;     /* pmfmm_build: 0 = plan on the GPU, 1 = on the host     */
+    int32_t accum;       /* PMFMM_ACCUM_FP64 (default) or PMFMM_ACCUM_FP32_TWOSUM
+                            (float32 forms only; the adjoint always adds in
+                            float64)                                           */
 } pmfmm_params;
 
 typedef struct pmfmm_ctx pmfmm_ctx;
 
 /* Fill *p with defaults: box 100, r_s 3.75, r_cut 4.5 r_s, G 1, theta 0,
  * max_leaf 64, order 4, M2L inside the cutoff, FP64, exact T, 2048-node
- * table, level 4, nearest. */
+ * table, level 4, nearest, float64 accumulation. */
 void pmfmm_params_init(pmfmm_params* p);
 
 /* Validate and copy *p into a new context.  *out receives the context, to be
@@ -163,7 +176,7 @@ int pmfmm_build_batch(pmfmm_ctx* ctx, int32_t nbox,
                       const double* pos, const double* mass,
                       int32_t on_device, void* stream);
 
-/* Change how the pair force is evaluated (precision, trunc, table_*) and
+/* Change how the pair force is evaluated (precision, trunc, table_*, accum) and
  * how the P2P work is scheduled (chunk, wg_waves, grid_wgs, timing) without
  * rebuilding the tree.  Geometry, split and tree fields of *p are ignored.
  * A change of chunk re-cuts the work items (needs a prior plan; re-uploads
@@ -284,6 +297,44 @@ typedef struct pmfmm_timings {
 
 /* Errors: ESTATE (timing off or nothing timed yet), EDEVICE. */
 int pmfmm_get_timings(const pmfmm_ctx* ctx, pmfmm_timings* out);
+
+/* One schedule of the persistent P2P launch and its measured time. */
+typedef struct pmfmm_schedule {
+    int32_t chunk;       /* j leaves per work item, 0 = automatic              */
+    int32_t wg_waves;    /* wavefronts per workgroup, 0 = automatic            */
+    int32_t grid_wgs;    /* persistent workgroups, 0 = as many as fit          */
+    int32_t pad;
+    double p2p_ms;       /* mean P2P kernel time in ms; < 0: not timed         */
+} pmfmm_schedule;
+
+/* Schedule autotuner of the persistent P2P launch (the paper schedules its
+ * task groups with a grid-stride loop, Sec. 3.2, Alg. 1; the tuner is this
+ * library's).  Every work item writes its own partial sums, added in a
+ * fixed order, so wg_waves and grid_wgs leave the results bitwise alone and
+ * chunk (which regroups the float64 sums) changes them by rounding only;
+ * the schedule sets
+ * how the TaskGroup rows are cut into work items, how many wavefronts
+ * share a workgroup (and its LDS copy of a table) and how many workgroups
+ * the persistent grid has.  On a built context, times each candidate: one
+ * untimed pmfmm_forward into `acc` (device (n_total, 3) float64, written),
+ * then `repeats` (1..100) forwards with the P2P kernel timed by HIP events
+ * on `stream`; applies the fastest as pmfmm_set_eval would (the other
+ * evaluation fields and `timing` stay as they were).
+ * cands / n_cands: schedules to try; NULL for the default 24 (chunk 0, 8,
+ * 16, 32, 64, 2^20 x wg_waves 2, 4, 8, 16, grid automatic; wg_waves above
+ * what the form runs, see pmfmm_params, are skipped).  results (optional,
+ * n_cands or 24 entries): each schedule with its time (p2p_ms < 0 when it
+ * was skipped or not timed).  cache_path (optional): a text file of lines
+ * "key chunk wg_waves grid_wgs p2p_ms", key = device architecture, compute
+ * units, pair form and a coarse size signature of the plan (boxes, leaves
+ * / 1024, sqrt of the P2P task count / 32); on a hit the cached schedule is
+ * applied without timing, on a miss the winner is appended.  *best
+ * receives the applied schedule.  Synchronises `stream`.
+ * Errors: EINVAL (null acc or best, repeats or n_cands out of range, an
+ * invalid candidate), ESTATE (not built), EDEVICE. */
+int pmfmm_autotune(pmfmm_ctx* ctx, double* acc, const pmfmm_schedule* cands,
+                   int32_t n_cands, int32_t repeats, const char* cache_path,
+                   pmfmm_schedule* results, pmfmm_schedule* best, void* stream);
 
 /* Library version string. */
 const char* pmfmm_version(void);

@@ -21,6 +21,7 @@ PMFMM_FP64, PMFMM_FP32 = 0, 1
 TRUNC_EXACT, TRUNC_TABLE, TRUNC_R2 = 0, 1, 2
 ROUND_NEAREST, ROUND_FLOOR = 0, 1
 M2L_INSIDE, M2L_CENTRE = 0, 1
+ACCUM_FP64, ACCUM_FP32_TWOSUM = 0, 1
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE",
           -5: "EUNSUPPORTED"}
@@ -42,7 +43,7 @@ class Params(C.Structure):
         ("table_round", C.c_int32), ("chunk", C.c_int32),
         ("wg_waves", C.c_int32), ("grid_wgs", C.c_int32),
         ("timing", C.c_int32), ("threads", C.c_int32),
-        ("planner", C.c_int32),
+        ("planner", C.c_int32), ("accum", C.c_int32),
     ]
 
 
@@ -77,6 +78,11 @@ class Timings(C.Structure):
                 ("adjoint_ms", C.c_double)]
 
 
+class Schedule(C.Structure):
+    _fields_ = [("chunk", C.c_int32), ("wg_waves", C.c_int32),
+                ("grid_wgs", C.c_int32), ("pad", C.c_int32), ("p2p_ms", C.c_double)]
+
+
 # name -> (restype, argtypes); the exports of include/pmfmm.h
 SIGNATURES = {
     "pmfmm_params_init": (None, [C.POINTER(Params)]),
@@ -105,6 +111,9 @@ SIGNATURES = {
     "pmfmm_get_lists": (C.c_int, [C.c_void_p, C.POINTER(Lists)]),
     "pmfmm_get_timings": (C.c_int, [C.c_void_p, C.POINTER(Timings)]),
     "pmfmm_version": (C.c_char_p, []),
+    "pmfmm_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Schedule), C.c_int32,
+                                 C.c_int32, C.c_char_p, C.POINTER(Schedule),
+                                 C.POINTER(Schedule), C.c_void_p]),
     # include/pmfmm_peak.h
     "pmfmm_peak_fma": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                  C.POINTER(C.c_double)]),
@@ -340,6 +349,33 @@ class Context:
         _check(library().pmfmm_adjoint(self._h, _ptr(w), _ptr(grad_pos),
                                        _ptr(grad_mass), _stream(stream)))
         return grad_pos, grad_mass
+
+    def autotune(self, out, stream=None, cands=None, repeats=3, cache_path=None):
+        """pmfmm_autotune: time candidate schedules (chunk, wg_waves,
+        grid_wgs) of the P2P launch on the built context and apply the
+        fastest.  out: float64 CUDA (n, 3), written.  Returns (best
+        schedule dict, [per-candidate dicts]) (the list is empty on a cache
+        hit)."""
+        self._built()
+        _dev(out, "out", (self.n, 3))
+        n = len(cands) if cands else 24
+        carr = (Schedule * n)(*[Schedule(int(c), int(w), int(g), 0, -1.0) for c, w, g in cands]) \
+            if cands else None
+        res = (Schedule * n)(*[Schedule(0, 0, 0, 0, -2.0) for _ in range(n)])
+        best = Schedule()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(library().pmfmm_autotune(self._h, _ptr(out), carr, n if cands else 0,
+                                        int(repeats), path, res, C.byref(best),
+                                        _stream(stream)))
+        # the library applied the schedule: keep the Python copy in step
+        self.params.chunk, self.params.wg_waves, self.params.grid_wgs = (
+            best.chunk, best.wg_waves, best.grid_wgs)
+
+        def d(sc):
+            return dict(chunk=sc.chunk, wg_waves=sc.wg_waves, grid_wgs=sc.grid_wgs,
+                        p2p_ms=sc.p2p_ms)
+        timed = [d(r) for r in res if r.p2p_ms != -2.0]
+        return d(best), timed
 
     def long_range(self, n_pm, pos, mass, out, stream=None):
         """Long-range (mesh) accelerations into out (n, 3), caller order."""

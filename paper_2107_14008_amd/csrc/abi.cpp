@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -90,6 +91,14 @@ bool valid_eval(const pmfmm_params& p, std::string& why) {
         }
     }
     if (p.table_round != PMFMM_ROUND_NEAREST && p.table_round != PMFMM_ROUND_FLOOR) { why = "table_round must be NEAREST or FLOOR"; return false; }
+    if (p.accum != PMFMM_ACCUM_FP64 && p.accum != PMFMM_ACCUM_FP32_TWOSUM) {
+        why = "accum must be FP64 or FP32_TWOSUM";
+        return false;
+    }
+    if (p.accum == PMFMM_ACCUM_FP32_TWOSUM && p.precision != PMFMM_FP32) {
+        why = "accum FP32_TWOSUM applies to the float32 forms";
+        return false;
+    }
     if (p.chunk < 0) { why = "chunk must be >= 0"; return false; }
     if (p.wg_waves < 0 || p.wg_waves > 16) { why = "wg_waves must be in 0..16"; return false; }
     if (p.grid_wgs < 0) { why = "grid_wgs must be >= 0"; return false; }
@@ -947,6 +956,7 @@ void pmfmm_params_init(pmfmm_params* p) {
     p->table_size = 2048;
     p->table_level = 4;
     p->table_round = PMFMM_ROUND_NEAREST;
+    p->accum = PMFMM_ACCUM_FP64;
 }
 
 const char* pmfmm_version(void) { return "pmfmm-mi355x 0.1"; }
@@ -1050,6 +1060,7 @@ int pmfmm_set_eval(pmfmm_ctx* ctx, const pmfmm_params* p) {
     ctx->p.table_size = p->table_size;
     ctx->p.table_level = p->table_level;
     ctx->p.table_round = p->table_round;
+    ctx->p.accum = p->accum;
     ctx->p.chunk = p->chunk;
     ctx->p.wg_waves = p->wg_waves;
     ctx->p.grid_wgs = p->grid_wgs;
@@ -1124,10 +1135,12 @@ int forward_launch(pmfmm_ctx* ctx, double* acc, hipStream_t s, int32_t* counter,
     a.n_tab = ctx->p.table_size;
     a.level = ctx->p.table_level;
     a.round_floor = ctx->p.table_round == PMFMM_ROUND_FLOOR;
+    a.accum32 = ctx->p.accum == PMFMM_ACCUM_FP32_TWOSUM;
     const bool tab = mode == pmfmm::kFP32Table || mode == pmfmm::kFP64Table || mode == pmfmm::kFP32R2 ||
                      mode == pmfmm::kFP64R2;
     const size_t lds = tab ? ctx->table_host.size() : 0;
-    const int wg = ctx->p.wg_waves > 0 ? ctx->p.wg_waves : default_wg_waves(mode);
+    const int wg = std::min(ctx->p.wg_waves > 0 ? ctx->p.wg_waves : default_wg_waves(mode),
+                            pmfmm::p2p_max_threads(mode) / 64);
     int grid = ctx->p.grid_wgs;
     if (grid <= 0) grid = ctx->n_cu * pmfmm::p2p_blocks_per_cu(mode, wg, lds);
     HIP_TRY(pmfmm::launch_p2p(mode, a, wg, grid, lds, s));
@@ -1183,6 +1196,122 @@ int pmfmm_forward_static(pmfmm_ctx* ctx, double* acc, void* stream) {
     unsigned char* b = static_cast<unsigned char*>(base);
     return forward_launch(ctx, acc, static_cast<hipStream_t>(stream), reinterpret_cast<int32_t*>(b),
                           reinterpret_cast<double*>(b + pmfmm::kStaticCounterBytes), false);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Cache key of the autotuner: device, pair form, coarse size of the plan.
+std::string tune_key(const pmfmm_ctx* ctx) {
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) arch = prop.gcnArchName;
+    for (char& c : arch)
+        if (c == ' ' || c == '\t' || c == '\n') c = '_';
+    const int64_t bucket = (int64_t)std::llround(2.0 * std::sqrt((double)std::max<int64_t>(1, ctx->n_p2p))) / 64;
+    const pmfmm_params& p = ctx->p;
+    return arch + "|" + std::to_string(ctx->n_cu) + "|" + std::to_string(p.precision) + "|" +
+           std::to_string(p.trunc) + "|" + std::to_string(p.table_size) + "|" + std::to_string(p.table_level) +
+           "|" + std::to_string(p.accum) + "|" + std::to_string(ctx->plan.boxes.size()) + "|" +
+           std::to_string(ctx->plan.leaf_count.size() / 1024) + "|" + std::to_string(bucket);
+}
+
+bool tune_cache_find(const char* path, const std::string& key, pmfmm_schedule& out) {
+    std::FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char k[768];
+        pmfmm_schedule sc{};
+        if (std::sscanf(line, "%767s %d %d %d %lf", k, &sc.chunk, &sc.wg_waves, &sc.grid_wgs, &sc.p2p_ms) == 5 &&
+            key == k) {
+            out = sc;   // the last entry for a key wins
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_cache_add(const char* path, const std::string& key, const pmfmm_schedule& sc) {
+    std::FILE* f = std::fopen(path, "a");
+    if (!f) return;   // an unwritable cache only costs the next run a tuning
+    std::fprintf(f, "%s %d %d %d %.6f\n", key.c_str(), sc.chunk, sc.wg_waves, sc.grid_wgs, sc.p2p_ms);
+    std::fclose(f);
+}
+
+int apply_schedule(pmfmm_ctx* ctx, const pmfmm_schedule& sc, int32_t timing) {
+    pmfmm_params p = ctx->p;
+    p.chunk = sc.chunk;
+    p.wg_waves = sc.wg_waves;
+    p.grid_wgs = sc.grid_wgs;
+    p.timing = timing;
+    return pmfmm_set_eval(ctx, &p);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pmfmm_autotune(pmfmm_ctx* ctx, double* acc, const pmfmm_schedule* cands, int32_t n_cands,
+                   int32_t repeats, const char* cache_path, pmfmm_schedule* results,
+                   pmfmm_schedule* best, void* stream) {
+    if (!ctx || !acc || !best) return fail(PMFMM_EINVAL, "null argument");
+    if (!ctx->built) return fail(PMFMM_ESTATE, "autotune before build");
+    if (repeats < 1 || repeats > 100) return fail(PMFMM_EINVAL, "repeats must be in 1..100");
+    std::vector<pmfmm_schedule> todo;
+    if (cands) {
+        if (n_cands < 1 || n_cands > 4096) return fail(PMFMM_EINVAL, "n_cands must be in 1..4096");
+        todo.assign(cands, cands + n_cands);
+    } else {
+        for (int32_t chunk : {0, 8, 16, 32, 64, 1 << 20})
+            for (int32_t wg : {2, 4, 8, 16}) todo.push_back(pmfmm_schedule{chunk, wg, 0, 0, -1.0});
+    }
+    for (const auto& sc : todo)
+        if (sc.chunk < 0 || sc.wg_waves < 0 || sc.wg_waves > 16 || sc.grid_wgs < 0)
+            return fail(PMFMM_EINVAL, "candidate schedule out of range (chunk >= 0, wg_waves 0..16, grid_wgs >= 0)");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t timing0 = ctx->p.timing;
+    const std::string key = tune_key(ctx);
+    pmfmm_schedule hit{};
+    if (cache_path && tune_cache_find(cache_path, key, hit)) {
+        int rc = apply_schedule(ctx, hit, timing0);
+        if (rc) return rc;
+        *best = hit;
+        return PMFMM_OK;
+    }
+    const int max_waves = pmfmm::p2p_max_threads(mode_of(ctx->p)) / 64;
+    int win = -1;
+    for (size_t i = 0; i < todo.size(); ++i) {
+        pmfmm_schedule& sc = todo[i];
+        sc.p2p_ms = -1.0;
+        if (sc.wg_waves > max_waves) continue;   // the launch would run max_waves anyway
+        int rc = apply_schedule(ctx, sc, 1);
+        if (!rc) rc = pmfmm_forward(ctx, acc, stream);
+        double sum = 0.0;
+        for (int r = 0; !rc && r < repeats; ++r) {
+            pmfmm_timings t{};
+            rc = pmfmm_forward(ctx, acc, stream);
+            if (!rc) rc = pmfmm_get_timings(ctx, &t);
+            sum += t.p2p_ms;
+        }
+        if (rc) {
+            (void)apply_schedule(ctx, pmfmm_schedule{0, 0, 0, 0, -1.0}, timing0);
+            return rc;
+        }
+        sc.p2p_ms = sum / repeats;
+        if (win < 0 || sc.p2p_ms < todo[win].p2p_ms) win = (int)i;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    if (results) std::copy(todo.begin(), todo.end(), results);
+    if (win < 0) return fail(PMFMM_EINVAL, "no candidate schedule can run this form");
+    int rc = apply_schedule(ctx, todo[win], timing0);
+    if (rc) return rc;
+    *best = todo[win];
+    if (cache_path) tune_cache_add(cache_path, key, *best);
+    return PMFMM_OK;
 }
 
 int pmfmm_kick(int64_t n, double* vel, const double* acc, double dt, void* stream) {
@@ -1326,7 +1455,8 @@ int pmfmm_adjoint(pmfmm_ctx* ctx, const double* w, double* grad_pos, double* gra
     // the 64^3 clustered workload: 1.02 ms against 1.13 ms with 4 and
     // 1.06 ms with 16; same results bit for bit).  The exact forms take
     // within 2 % of the same time with 4, 8 or 16.
-    const int wg = ctx->p.wg_waves > 0 ? ctx->p.wg_waves : (a.table != nullptr ? 8 : 4);
+    const int wg = std::min(ctx->p.wg_waves > 0 ? ctx->p.wg_waves : (a.table != nullptr ? 8 : 4),
+                            pmfmm::adjoint_max_threads(mode) / 64);
     int grid = ctx->p.grid_wgs;
     if (grid <= 0) grid = ctx->n_cu * pmfmm::adjoint_blocks_per_cu(mode, wg, a.table != nullptr);
     HIP_TRY(pmfmm::launch_adjoint(mode, a, wg, grid, s));

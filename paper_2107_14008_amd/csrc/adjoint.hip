@@ -10,14 +10,14 @@
 // the delta function of the hard cutoff being left out.  Same wavefront
 // mapping and work queue as the forward P2P kernel; the source records are
 // (x, m) and (w, 0), both read with wave-uniform addresses.  g and h are
-// evaluated exactly (erfc and exp), or, in the float32 r^2 form, read from
-// quadratic tables in r^2 (adj_pair_f32_r2).
+// evaluated exactly (float64: truncation_T_f64, one exponential; float32:
+// erfcf and expf), or, in the float32 r^2 form, read from quadratic tables
+// in r^2 (adj_pair_f32_r2).
 #include "device.h"
 
 namespace pmfmm {
 namespace {
 
-constexpr double kTwoOverSqrtPi = 1.12837916709551257390;
 constexpr double kFourOverSqrtPi = 2.25675833419102514780;
 constexpr float kTwoOverSqrtPiF = 1.12837916709551257390f;
 constexpr float kFourOverSqrtPiF = 2.25675833419102514780f;
@@ -42,25 +42,25 @@ __device__ __forceinline__ void adj_pair_f64(const double4 q, const double4 wl, 
         }
         r2 = (dx * dx + dy * dy) + dz * dz;
     }
-    const bool ok = (r2 > 0.0) & (r2 < rc2);
-    const double r2s = ok ? r2 : 1.0;
-    const double idr = rsqrt(r2s);
-    const double x = r2s * idr * alpha;
-    const double ex = exp(-x * x);
-    const double T = erfc(x) + kTwoOverSqrtPi * x * ex;
-    const double idr2 = idr * idr;
-    const double g = ok ? T * idr * idr2 : 0.0;
-    const double h = ok ? -(3.0 * T + kFourOverSqrtPi * x * x * x * ex) * idr2 * idr2 * idr : 0.0;
-    const double dwl = dx * wl.x + dy * wl.y + dz * wl.z;
-    const double dwk = dx * wk.x + dy * wk.y + dz * wk.z;
-    const double hl = h * dwl, hk = q.w * h * dwk, gl = q.w * g;
-    A[0] += g * wl.x + hl * dx;
-    A[1] += g * wl.y + hl * dy;
-    A[2] += g * wl.z + hl * dz;
-    Bv[0] += gl * wk.x + hk * dx;
-    Bv[1] += gl * wk.y + hk * dy;
-    Bv[2] += gl * wk.z + hk * dz;
-    gm -= g * dwl;
+    if ((r2 > 0.0) & (r2 < rc2)) {
+        const double idr = rsqrt(r2);
+        const double x = r2 * idr * alpha;
+        double ex;
+        const double T = truncation_T_f64(x, &ex);
+        const double idr2 = idr * idr;
+        const double g = T * idr * idr2;
+        const double h = -(3.0 * T + kFourOverSqrtPi * x * x * x * ex) * idr2 * idr2 * idr;
+        const double dwl = dx * wl.x + dy * wl.y + dz * wl.z;
+        const double dwk = dx * wk.x + dy * wk.y + dz * wk.z;
+        const double hl = h * dwl, hk = q.w * h * dwk, gl = q.w * g;
+        A[0] += g * wl.x + hl * dx;
+        A[1] += g * wl.y + hl * dy;
+        A[2] += g * wl.z + hl * dz;
+        Bv[0] += gl * wk.x + hk * dx;
+        Bv[1] += gl * wk.y + hk * dy;
+        Bv[2] += gl * wk.z + hk * dz;
+        gm -= g * dwl;
+    }
 }
 
 // Offsets in units of 1 / sigma (see BoxDev): g and h come out as
@@ -94,24 +94,39 @@ __device__ __forceinline__ void adj_pair_f32(const float4 q, const float4 wl, fl
 
 // Float32 r^2 tables (host builder in abi.cpp): g and h as quadratics in
 // s = r'^2 on segments indexed by the float bits of s, in the units of the
-// forward r^2 form (r_cut^2 = 2^kR2Emax); s is clamped below at 2^kAdjEmin
-// (pairs that close are not resolved by float32 offsets anyway).  Coincident
-// pairs (d = 0, the particle itself included) are left out as in the exact
-// form.  Only lanes inside the cutoff read the six coefficients from LDS.
+// forward r^2 form (r_cut^2 = 2^kR2Emax), for s >= 2^kAdjEmin (the floor
+// keeps h's quadratic coefficient, which grows as s^(-9/2), a finite
+// float).  A pair closer than that (r < 2^-18.5 r_cut, rare) takes g and h
+// from erfcf / expf instead, at s no smaller than `tiny` = 2^kR2Emin, the
+// forward's floor (float32 offsets resolve no closer pairs).  Coincident
+// pairs (d = 0, the particle itself included) are left out as in the
+// exact form.  Only lanes inside the cutoff read the six coefficients from
+// LDS.
 __device__ __forceinline__ void adj_pair_f32_r2(const float4 q, const float4 wl, float px,
                                                 float py, float pz, float4 wk, float smax,
-                                                float smin, uint32_t boff,
+                                                float smin, uint32_t boff, float alpha, float tiny,
                                                 const unsigned char* __restrict__ tab, float* A,
                                                 float* Bv, float& gm) {
     const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
     if ((r2 > 0.f) & (r2 < smax)) {
-        const uint32_t sb = max(__float_as_uint(r2), __float_as_uint(smin));
-        const float sc = __uint_as_float(sb);
-        const float* c =
-            reinterpret_cast<const float*>(tab + (((sb >> (23 - kAdjBits)) << 2) + boff));
-        const float g = fmaf(fmaf(c[2 * kAdjPlane], sc, c[kAdjPlane]), sc, c[0]);
-        const float h = fmaf(fmaf(c[5 * kAdjPlane], sc, c[4 * kAdjPlane]), sc, c[3 * kAdjPlane]);
+        float g, h;
+        if (r2 >= smin) {
+            const uint32_t sb = __float_as_uint(r2);
+            const float* c =
+                reinterpret_cast<const float*>(tab + (((sb >> (23 - kAdjBits)) << 2) + boff));
+            g = fmaf(fmaf(c[2 * kAdjPlane], r2, c[kAdjPlane]), r2, c[0]);
+            h = fmaf(fmaf(c[5 * kAdjPlane], r2, c[4 * kAdjPlane]), r2, c[3 * kAdjPlane]);
+        } else {
+            const float rr = fmaxf(r2, tiny);
+            const float idr = rsqrtf(rr);
+            const float x = rr * idr * alpha;
+            const float ex = expf(-x * x);
+            const float T = erfcf(x) + kTwoOverSqrtPiF * x * ex;
+            const float idr2 = idr * idr;
+            g = T * idr * idr2;
+            h = -(3.f * T + kFourOverSqrtPiF * x * x * x * ex) * idr2 * idr2 * idr;
+        }
         const float dwl = dx * wl.x + dy * wl.y + dz * wl.z;
         const float dwk = dx * wk.x + dy * wk.y + dz * wk.z;
         const float hl = h * dwl, hk = q.w * h * dwk, gl = q.w * g;
@@ -128,7 +143,7 @@ __device__ __forceinline__ void adj_pair_f32_r2(const float4 q, const float4 wl,
 // F32: float32 offsets; TAB (float32 only): g and h from the r^2 tables,
 // staged in LDS (6 kAdjPlane floats), instead of erfc and exp.
 template <bool F32, bool TAB>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(adjoint_max_threads(F32 ? kFP32Exact : kFP64Exact))
 adjoint_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                const double4* __restrict__ w64, const float4* __restrict__ w32,
                const int4* __restrict__ leaf, const double4* __restrict__ leafc,
@@ -197,7 +212,7 @@ adjoint_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                     for (int k = 0; k < nj; ++k)
                         if ((live >> k) & 1u)
                             adj_pair_f32_r2(src[k], wsrc[k], px, py, pz, wk, bx.rc2_f, smin, boff,
-                                            adj_lds, a, b, g);
+                                            bx.alpha_f, bx.tiny_f, adj_lds, a, b, g);
                 } else {
                     for (int k = 0; k < nj; ++k)
                         if ((live >> k) & 1u)

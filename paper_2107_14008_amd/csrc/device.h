@@ -18,6 +18,7 @@
 #include <cstdint>
 
 #include "plan.h"
+#include "truncation_poly.h"
 
 namespace pmfmm {
 
@@ -33,6 +34,18 @@ enum Mode : int {
 constexpr bool is_fp32(int mode) {
     return mode == kFP32Exact || mode == kFP32Table || mode == kFP32R2;
 }
+
+// Largest workgroup of the P2P kernel: 16 waves share one LDS copy of a
+// table; the float64 exact form keeps its polynomial's coefficients and
+// a source record in registers and is compiled for 4-wave workgroups
+// (up to 512 VGPRs per lane instead of 128).
+constexpr int p2p_max_threads(int mode) { return mode == kFP64Exact ? 256 : 1024; }
+// Waves per SIMD the float32 forms must leave room for: two 16-wave
+// workgroups per CU (their tables fit twice in LDS), so at most 64 VGPRs and
+// the matching scalar registers per wave.
+constexpr int p2p_min_waves_per_simd(int mode) { return is_fp32(mode) ? 8 : 1; }
+// The same for the adjoint: every float64 form evaluates g and h exactly.
+constexpr int adjoint_max_threads(int mode) { return is_fp32(mode) ? 1024 : 256; }
 
 // r^2 table form: scaled r^2 covers [2^kR2Emin, 2^kR2Emax) (r_cut^2 = 2^kR2Emax).
 constexpr int kR2Emin = -35;
@@ -53,6 +66,59 @@ constexpr int kAdjEmin = -26;
 constexpr int kAdjPlane = 1216;
 static_assert(((kR2Emax - kAdjEmin) << kAdjBits) + 1 <= kAdjPlane, "adjoint table rows");
 constexpr int kAdjTableBytes = 6 * kAdjPlane * 4;
+
+// ------------------------------------------------------ truncation factor
+//
+// T(x) = erfc(x) + (2x / sqrt(pi)) exp(-x^2) of Eq. (tr) in float64 with a
+// single exponential: T = exp(-x^2) U(x), where U(x) = exp(x^2) erfc(x) +
+// 2x / sqrt(pi) is smooth on [0, 3] and comes from the generated
+// polynomial of truncation_poly.h (degree 24 in t = (x - 3/2) / (3/2),
+// within 2 ulp of U), evaluated as an even and an odd half in t^2 (two
+// independent chains).  exp(-x^2) follows the Cody-Waite reduction of the
+// same header: x^2 = s + ds exactly (ds from a fused multiply-add),
+// n = rint(s / ln 2), r = (n ln2_hi - s) + n ln2_lo - ds, exp(-x^2) =
+// 2^-n p(r) with p the header's degree-11 polynomial.  x > 3 (cutoffs
+// beyond 6 r_s) takes the library erfc and exp.  *ex receives exp(-x^2)
+// (the adjoint needs it).
+
+// a b + c as one three-operand fused multiply-add, c a uniform constant
+// held in a scalar register pair.  Written out because the compiler
+// otherwise keeps each polynomial coefficient in vector registers and
+// copies it into the accumulator of the two-operand form before every step
+// (one extra 64-bit move per coefficient).
+__device__ __forceinline__ double fma_sc(double a, double b, double c) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+
+__device__ inline double truncation_T_f64(double x, double* ex) {
+    if (x <= kTPolyXMax) {
+        const double s = x * x;
+        const double ds = fma(x, x, -s);
+        const double n = rint(s * kInvLn2);
+        double r = fma(n, kLn2Hi, -s);
+        r = fma(n, kLn2Lo, r) - ds;
+        double p = kExpPoly[kExpDegree];
+#pragma unroll
+        for (int k = kExpDegree - 1; k >= 0; --k) p = fma_sc(p, r, kExpPoly[k]);
+        const double e = ldexp(p, -(int)n);
+        const double t = fma(x, kTPolyInvHalfWidth, -1.0);
+        const double t2 = t * t;
+        constexpr int kE = kTPolyDegree - (kTPolyDegree & 1);       // top even power
+        constexpr int kO = kTPolyDegree - 1 + (kTPolyDegree & 1);   // top odd power
+        double ev = kTPoly[kE], od = kTPoly[kO];
+#pragma unroll
+        for (int k = kE - 2; k >= 0; k -= 2) ev = fma_sc(ev, t2, kTPoly[k]);
+#pragma unroll
+        for (int k = kO - 2; k >= 1; k -= 2) od = fma_sc(od, t2, kTPoly[k]);
+        *ex = e;
+        return e * fma(od, t, ev);
+    }
+    const double e = exp(-x * x);
+    *ex = e;
+    return erfc(x) + 1.12837916709551257390 * x * e;
+}
 
 // ------------------------------------------------------ source culling
 //
@@ -160,6 +226,7 @@ struct P2PArgs {
     int32_t n_tab;
     int32_t level;
     int32_t round_floor;
+    int32_t accum32;     // float32 forms: item sums in float32 with TwoSum compensation
 };
 
 struct ReduceArgs {
@@ -179,7 +246,7 @@ struct GatherArgs {
     const double* mass_in;      // (n)
     const int32_t* perm;
     const int4* leaf;
-    const double4* leafc;
+    double4* leafc;             // .w set to the leaf's common mass (0: none)
     const BoxDev* boxes;
     double4* x64;
     float4* x32;

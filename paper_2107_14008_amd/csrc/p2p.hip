@@ -28,7 +28,6 @@ static __device__ __align__(256) unsigned char scratch[pmfmm::kStaticScratchByte
 namespace pmfmm {
 namespace {
 
-constexpr double kTwoOverSqrtPi = 1.12837916709551257390;
 constexpr float kTwoOverSqrtPiF = 1.12837916709551257390f;
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -52,10 +51,12 @@ __device__ __forceinline__ double wrap_coord(double x, double L) {
 
 // ------------------------------------------------------------ pair forms
 
-// float64, library erfc / exp.  The displacement and r^2 follow the exact
-// steps of the definition (d = (x_j - x_i) + s L; r2 = (dx dx + dy dy) +
-// dz dz, no fused multiply-add) so the cutoff decision is bit-identical
-// to a plain float64 evaluation.
+// float64, exact T (truncation_T_f64: one exponential and a polynomial).
+// The displacement and r^2 follow the exact steps of the definition
+// (d = (x_j - x_i) + s L; r2 = (dx dx + dy dy) + dz dz, no fused
+// multiply-add) so the cutoff decision is bit-identical to a plain float64
+// evaluation.  Lanes beyond the cutoff skip T (a wave with none inside
+// skips it altogether).
 template <bool SHIFTED>
 __device__ __forceinline__ void pair_f64_exact(const double4 q, double xi, double yi, double zi,
                                                double sx, double sy, double sz, double rc2,
@@ -73,15 +74,16 @@ __device__ __forceinline__ void pair_f64_exact(const double4 q, double xi, doubl
         }
         r2 = (dx * dx + dy * dy) + dz * dz;
     }
-    const bool ok = (r2 > 0.0) & (r2 < rc2);
-    const double r2s = ok ? r2 : 1.0;
-    const double idr = rsqrt(r2s);
-    const double x = r2s * idr * alpha;
-    const double T = erfc(x) + kTwoOverSqrtPi * x * exp(-x * x);
-    const double g = ok ? q.w * T * (idr * idr * idr) : 0.0;
-    ax = fma(g, dx, ax);
-    ay = fma(g, dy, ay);
-    az = fma(g, dz, az);
+    if ((r2 > 0.0) & (r2 < rc2)) {
+        const double idr = rsqrt(r2);
+        const double x = r2 * idr * alpha;
+        double ex;
+        const double T = truncation_T_f64(x, &ex);
+        const double g = q.w * T * (idr * idr * idr);
+        ax = fma(g, dx, ax);
+        ay = fma(g, dy, ay);
+        az = fma(g, dz, az);
+    }
 }
 
 // float64, Taylor table of Eq. (int) with coefficients pre-scaled to table
@@ -197,6 +199,17 @@ __device__ __forceinline__ void pair_f32_table(const float4 q, float px, float p
     az = fmaf(g, dz, az);
 }
 
+// s + c += x with Knuth's TwoSum: the rounding error of s + x, recovered
+// exactly in float32 arithmetic, is added into the compensation c.
+__device__ __forceinline__ void two_sum(float& s, float& c, float x) {
+#pragma clang fp contract(off)
+    const float t = s + x;
+    const float xv = t - s;
+    const float sv = t - xv;
+    c += (s - sv) + (x - xv);
+    s = t;
+}
+
 // Four consecutive sources, read by one wave-uniform load.  pin() is an
 // empty statement that takes all sixteen values in scalar registers: it keeps
 // the compiler from sinking each source's load into the masked region of its
@@ -225,7 +238,7 @@ __device__ __forceinline__ void pin(const Src4<V>& b) {
 // four in clustered boxes), and an LDS read costs its issue slot whatever
 // its active lanes, so a wave whose lanes are all beyond r_cut for a source
 // skips the read altogether.
-template <int LEVEL>
+template <int LEVEL, bool UNI>
 __device__ __forceinline__ void pair_f32_r2(const float4 q, float px, float py, float pz,
                                             float smax, float smin, uint32_t shift,
                                             uint32_t boff, const unsigned char* __restrict__ tab,
@@ -244,11 +257,37 @@ __device__ __forceinline__ void pair_f32_r2(const float4 q, float px, float py, 
         } else {
             F = fmaf(fmaf(c[2 * kR2Plane], sc, c[kR2Plane]), sc, c[0]);
         }
-        const float g = q.w * F;
+        // UNI: the j leaf's sources share one mass, applied once per leaf
+        const float g = UNI ? F : q.w * F;
         ax = fmaf(g, dx, ax);
         ay = fmaf(g, dy, ay);
         az = fmaf(g, dz, az);
     }
+}
+
+// The pairs of one j leaf in the float32 r^2 form: four sources per 64-byte
+// scalar load, ahead of the masked table reads.
+template <int LEVEL, bool UNI>
+__device__ __forceinline__ void leaf_f32_r2(const float4* __restrict__ src, int nj, uint64_t live,
+                                            float px, float py, float pz, float smax,
+                                            float smin, uint32_t shift, uint32_t boff,
+                                            const unsigned char* __restrict__ tab, float& ax,
+                                            float& ay, float& az) {
+    int k = 0;
+    for (; k + 4 <= nj; k += 4) {
+        const uint32_t g4 = (uint32_t)(live >> k) & 0xFu;
+        if (g4 == 0) continue;
+        const Src4<float4> b = *reinterpret_cast<const Src4<float4>*>(src + k);
+        pin(b);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (g4 & (1u << u))
+                pair_f32_r2<LEVEL, UNI>(b.v[u], px, py, pz, smax, smin, shift, boff, tab, ax, ay,
+                                        az);
+    }
+    for (; k < nj; ++k)
+        if ((live >> k) & 1u)
+            pair_f32_r2<LEVEL, UNI>(src[k], px, py, pz, smax, smin, shift, boff, tab, ax, ay, az);
 }
 
 // float64 r^2 table (not the paper's table; host builder in abi.cpp): the
@@ -263,7 +302,8 @@ __device__ __forceinline__ void pair_f32_r2(const float4 q, float px, float py, 
 // inside the cutoff read the table.  A pair closer than 2^(kR2Emin64 / 2)
 // r_cut (r < r_cut / 256, rare) or at r = 0 contributes nothing here and
 // raises the lane's `near` flag; pair_f64_r2_close then adds the close pairs
-// of that j leaf with the exact erfc / exp expression.  The item's sums are
+// of that j leaf with the library erfc / exp (rare: no need for the faster
+// truncation_T_f64, whose registers would crowd the main loop's).  The item's sums are
 // multiplied by sigma^3 at the end.
 struct R2Tab64 {
     const unsigned char* tab;  // LDS rows of NC doubles
@@ -324,7 +364,7 @@ __device__ __forceinline__ void pair_f64_r2_close(const double4 q, double xi, do
     if (r2 > 0.0 && (uint32_t)__double2hiint(s) < T.hlo) {
         const double r = sqrt(r2);
         const double x = r * T.alpha;
-        const double Tx = erfc(x) + kTwoOverSqrtPi * x * exp(-x * x);
+        const double Tx = erfc(x) + 1.12837916709551257390 * x * exp(-x * x);
         const double g = q.w * (Tx / (s * sqrt(s)));
         ax = fma(g, dx, ax);
         ay = fma(g, dy, ay);
@@ -372,8 +412,8 @@ __device__ __forceinline__ void load_table(unsigned char* lds, const void* __res
     __syncthreads();
 }
 
-template <int MODE, int LEVEL>
-__global__ void __launch_bounds__(1024)
+template <int MODE, int LEVEL, bool ACC32>
+__global__ void __launch_bounds__(p2p_max_threads(MODE), p2p_min_waves_per_simd(MODE))
 p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
            const int4* __restrict__ leaf, const double4* __restrict__ leafc,
            const int32_t* __restrict__ p2p_js, const int4* __restrict__ items,
@@ -425,6 +465,8 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
             // the leaf repeat target 0)
             float3 lo = make_float3(pv.x, pv.y, pv.z), hi = lo;
             wave_box(lo, hi);
+            // compensated float32 item sums (accum32): s + c
+            float3 s32 = make_float3(0.f, 0.f, 0.f), c32 = s32;
             for (int t = t0; t < t1; ++t) {
                 const int js = uni(p2p_js[t]);
                 const int jl = js >> 5;
@@ -456,29 +498,34 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                         if ((live >> k) & 1u)
                             pair_f32_table<LEVEL>(src[k], px, py, pz, rc2, tiny, bx.tab_scale_f,
                                                   rnd, t03, t4, fx, fy, fz);
+                } else if (cj.w != 0.0) {
+                    // every source of the j leaf has mass cj.w (the gather
+                    // marks such leaves): one multiplication per leaf
+                    // instead of one per pair
+                    leaf_f32_r2<LEVEL, true>(src, nj, live, px, py, pz, rc2, tiny, r2shift,
+                                             r2boff, lds, fx, fy, fz);
+                    const float mu = (float)cj.w;
+                    fx *= mu;
+                    fy *= mu;
+                    fz *= mu;
                 } else {
-                    // four sources per 64-byte scalar load, ahead of the
-                    // masked table reads
-                    int k = 0;
-                    for (; k + 4 <= nj; k += 4) {
-                        const uint32_t g4 = (uint32_t)(live >> k) & 0xFu;
-                        if (g4 == 0) continue;
-                        const Src4<float4> b = *reinterpret_cast<const Src4<float4>*>(src + k);
-                        pin(b);
-#pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            if (g4 & (1u << u))
-                                pair_f32_r2<LEVEL>(b.v[u], px, py, pz, rc2, tiny, r2shift, r2boff,
-                                                   lds, fx, fy, fz);
-                    }
-                    for (; k < nj; ++k)
-                        if ((live >> k) & 1u)
-                            pair_f32_r2<LEVEL>(src[k], px, py, pz, rc2, tiny, r2shift, r2boff,
-                                               lds, fx, fy, fz);
+                    leaf_f32_r2<LEVEL, false>(src, nj, live, px, py, pz, rc2, tiny, r2shift,
+                                              r2boff, lds, fx, fy, fz);
                 }
-                ax += (double)fx;
-                ay += (double)fy;
-                az += (double)fz;
+                if constexpr (ACC32) {
+                    two_sum(s32.x, c32.x, fx);
+                    two_sum(s32.y, c32.y, fy);
+                    two_sum(s32.z, c32.z, fz);
+                } else {
+                    ax += (double)fx;
+                    ay += (double)fy;
+                    az += (double)fz;
+                }
+            }
+            if constexpr (ACC32) {
+                ax = (double)s32.x + (double)c32.x;
+                ay = (double)s32.y + (double)c32.y;
+                az = (double)s32.z + (double)c32.z;
             }
             const double s2 = sig * sig;
             ax *= s2;
@@ -603,7 +650,7 @@ reduce_kernel(const int4* __restrict__ leaf, const int32_t* __restrict__ leaf_sl
 __global__ void __launch_bounds__(256)
 gather_kernel(const double* __restrict__ pos_in, const double* __restrict__ mass_in,
               const int32_t* __restrict__ perm, const int4* __restrict__ leaf,
-              const double4* __restrict__ leafc, const BoxDev* __restrict__ boxes,
+              double4* __restrict__ leafc, const BoxDev* __restrict__ boxes,
               double4* __restrict__ x64, float4* __restrict__ x32, int32_t n_leaves) {
     const int l = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -618,6 +665,14 @@ gather_kernel(const double* __restrict__ pos_in, const double* __restrict__ mass
     const double z = wrap_coord(pos_in[3 * (size_t)o + 2], L);
     const double m = mass_in[o];
     x64[k] = make_double4(x, y, z, m);
+    // leafc[l].w: the mass every particle of the leaf has, or 0 when they
+    // differ (the float32 r^2 P2P applies it once per leaf)
+    {
+        const double m0 = __shfl(m, 0);
+        const uint64_t act = __ballot(1);
+        const bool same = m == m0;
+        if (lane == 0) leafc[l].w = (__ballot(same) == act) ? m0 : 0.0;
+    }
     const double4 c = leafc[l];
     const double sig = boxes[li.z].sigma;
     x32[k] = make_float4((float)((x - c.x) * sig), (float)((y - c.y) * sig),
@@ -650,16 +705,24 @@ __global__ void zero_i32_kernel(int32_t* p, int32_t n) {
 template <int MODE, int LEVEL>
 hipError_t launch_one(const P2PArgs& a, int wg_waves, int grid_wgs, size_t lds, hipStream_t s) {
     const int tb = (int)lds;
-    hipLaunchKernelGGL((p2p_kernel<MODE, LEVEL>), dim3(grid_wgs), dim3(64 * wg_waves), lds, s,
-                       a.x64, a.x32, a.leaf, a.leafc, a.p2p_js, a.items, a.queue, a.n_items,
-                       a.counter, a.partial, a.boxes, a.table, a.n_tab, tb, a.round_floor);
+    // the compensated float32 sums are a variant of the float32 kernels only
+    if (is_fp32(MODE) && a.accum32)
+        hipLaunchKernelGGL((p2p_kernel<MODE, LEVEL, is_fp32(MODE)>), dim3(grid_wgs),
+                           dim3(64 * wg_waves), lds, s, a.x64, a.x32, a.leaf, a.leafc, a.p2p_js,
+                           a.items, a.queue, a.n_items, a.counter, a.partial, a.boxes, a.table,
+                           a.n_tab, tb, a.round_floor);
+    else
+        hipLaunchKernelGGL((p2p_kernel<MODE, LEVEL, false>), dim3(grid_wgs), dim3(64 * wg_waves),
+                           lds, s, a.x64, a.x32, a.leaf, a.leafc, a.p2p_js, a.items, a.queue,
+                           a.n_items, a.counter, a.partial, a.boxes, a.table, a.n_tab, tb,
+                           a.round_floor);
     return hipGetLastError();
 }
 
 template <int MODE, int LEVEL>
 int occ_one(int wg_waves, size_t lds) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, p2p_kernel<MODE, LEVEL>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, p2p_kernel<MODE, LEVEL, false>,
                                                      64 * wg_waves, lds) != hipSuccess)
         return 1;
     return blocks > 0 ? blocks : 1;

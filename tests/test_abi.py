@@ -46,7 +46,7 @@ def test_version(lib):
     ("r_cut", 0.0), ("theta", 1.0), ("theta", -0.1), ("max_leaf", 0),
     ("max_leaf", 65), ("order", 7), ("precision", 2), ("trunc", 5),
     ("table_size", 8), ("table_level", 5), ("table_round", 3),
-    ("chunk", -1), ("wg_waves", 17), ("G", float("inf")),
+    ("chunk", -1), ("wg_waves", 17), ("G", float("inf")), ("accum", 2),
 ])
 def test_create_rejects_bad_params(field, value):
     with pytest.raises(B.PmfmmError) as e:
@@ -122,6 +122,11 @@ def test_calls_out_of_order():
     assert lib.pmfmm_get_lists(ctx._h, lists) == -4
     assert lib.pmfmm_forward(ctx._h, B.C.c_void_p(8), None) == -4
     assert lib.pmfmm_forward_static(ctx._h, B.C.c_void_p(8), None) == -4
+    best = B.Schedule()
+    assert lib.pmfmm_autotune(ctx._h, B.C.c_void_p(8), None, 0, 3, None, None,
+                              B.C.byref(best), None) == -4
+    assert lib.pmfmm_autotune(ctx._h, None, None, 0, 3, None, None,
+                              B.C.byref(best), None) == -1
     assert lib.pmfmm_forward_static(ctx._h, None, None) == -1
     assert lib.pmfmm_adjoint(ctx._h, B.C.c_void_p(8), B.C.c_void_p(8),
                              B.C.c_void_p(8), None) == -4
@@ -209,3 +214,14 @@ def test_binding_rejects_cpu_tensors():
     fresh = B.Context(box=10.0, r_s=0.5, r_cut=2.25, max_leaf=8)
     with pytest.raises(B.PmfmmError, match="before build"):
         fresh.forward(pos)
+
+
+def test_accum_twosum_is_for_float32_forms():
+    with pytest.raises(B.PmfmmError) as e:
+        B.Context(precision=B.PMFMM_FP64, accum=B.ACCUM_FP32_TWOSUM)
+    assert e.value.code == -1
+    ctx = B.Context(precision=B.PMFMM_FP32, accum=B.ACCUM_FP32_TWOSUM)
+    assert ctx.params.accum == B.ACCUM_FP32_TWOSUM
+    with pytest.raises(B.PmfmmError):
+        ctx.set_eval(precision=B.PMFMM_FP64)      # still TwoSum: refused, params kept
+    assert ctx.params.precision == B.PMFMM_FP32

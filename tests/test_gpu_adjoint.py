@@ -12,6 +12,7 @@ S_k: e_k = |g_k - g_ref,k| / S_k, with the force tolerances (float64
 
 import numpy as np
 import pytest
+from scipy.special import erfc
 
 torch = pytest.importorskip("torch")
 
@@ -134,6 +135,77 @@ def test_adjoint_fp32_coincident_close_and_ragged(trunc):
     for e in (scaled(gp, gx, sx), scaled(gmass, gm, sm)):
         print("errors:", e, flush=True)
         assert e["median"] <= 1e-5 and e["p999"] <= 1e-4, e
+
+
+def clumps_with_close_pairs(seed=31):
+    """128 clumps of 16 particles (radius 1e-4 r_cut) at jittered lattice
+    points of a box of 20; every other clump holds a pair at 1e-6 .. 2.5e-6
+    r_cut.  With max_leaf 16 each ORB leaf is exactly one clump (checked by
+    the caller), so float32 offsets from the leaf centre resolve the close
+    pairs to about 1e-5."""
+    rng = np.random.default_rng(seed)
+    box, r_s, r_cut = 20.0, 0.6, 2.7
+    g = np.stack(np.meshgrid(np.arange(8), np.arange(4), np.arange(4), indexing="ij"),
+                 -1).reshape(-1, 3)
+    cen = (g + 0.5) * np.array([box / 8, box / 4, box / 4]) + rng.uniform(-0.6, 0.6, (128, 3))
+    pts, close = [], []
+    for c in range(128):
+        u = rng.normal(0, 1, (16, 3))
+        u /= np.linalg.norm(u, axis=1)[:, None]
+        p = cen[c] + u * (1e-4 * r_cut * rng.uniform(0, 1, (16, 1)) ** (1 / 3))
+        if c % 2 == 0:
+            v = rng.normal(0, 1, 3)
+            v /= np.linalg.norm(v)
+            p[1] = p[0] + v * rng.uniform(1e-6, 2.5e-6) * r_cut
+            close += [16 * c, 16 * c + 1]
+        pts.append(p)
+    return inputs.wrap(np.concatenate(pts), box), np.array(close), box, r_s, r_cut
+
+
+@pytest.mark.parametrize("trunc", [B.TRUNC_EXACT, B.TRUNC_R2])
+def test_adjoint_fp32_pairs_below_table_floor(trunc):
+    """Pairs at 1e-6 .. 2.5e-6 r_cut, below the float32 adjoint tables'
+    floor (2^-18.5 r_cut = 2.7e-6 r_cut): the r^2 form takes them through
+    the exact expression.  The gradients of the close-pair particles
+    (dominated by the close pair) match the float64 oracle to 1e-4 of their
+    term sums, the others to the float32 tolerances."""
+    pos, close, box, r_s, r_cut = clumps_with_close_pairs()
+    m = np.random.default_rng(5).uniform(0.5, 1.5, len(pos))
+    wv = inputs.cotangent(len(m), seed=37)
+    gx, gm, sx, sm = direct.gradient(pos, m, wv, box, r_s, r_cut, with_scale=True)
+    print(f"case: adjoint fp32 trunc {trunc}, pairs at 1e-6 .. 2.5e-6 r_cut", flush=True)
+    sr = api.ShortRange(box=box, r_s=r_s, r_cut=r_cut, max_leaf=16, order=-1,
+                        theta=0.0, precision=B.PMFMM_FP32, trunc=trunc,
+                        table_size=64, table_level=2)
+    sr.build(torch.tensor(pos, device="cuda"), torch.tensor(m, device="cuda"))
+    L = sr.ctx.lists()
+    for l in range(L["n_leaves"]):           # each leaf is one clump
+        mem = L["perm"][L["leaf_first"][l]:L["leaf_first"][l] + L["leaf_count"][l]]
+        assert len(mem) == 16 and len(set(mem // 16)) == 1
+    gp, gmass = sr.adjoint(torch.tensor(wv, device="cuda"))
+    torch.cuda.synchronize()
+    gp, gmass = gp.cpu().numpy(), gmass.cpu().numpy()
+    assert np.all(np.isfinite(gp)) and np.all(np.isfinite(gmass))
+    for e in (scaled(gp, gx, sx), scaled(gmass, gm, sm)):
+        print("  all particles:", e, flush=True)
+        assert e["median"] <= 1e-5 and e["p999"] <= 1e-4, e
+    e = scaled(gp[close], gx[close], sx[close])
+    print("  close-pair particles, position gradient:", e, flush=True)
+    assert e["max"] <= 1e-4, e
+    # The mass gradient sums g (w_l . d): for the close pair, d . w_l can
+    # cancel, and float32 offsets resolve d to ~1e-5 of |d| only, so its
+    # error scale is g |w_l| |d| rather than |g (w_l . d)|.
+    k, l = close[0::2], close[1::2]
+    d = pos[l] - pos[k]
+    r = np.linalg.norm(d, axis=1)
+    x = r / (2 * r_s)
+    g = (erfc(x) + 2 * x / np.sqrt(np.pi) * np.exp(-x * x)) / r ** 3
+    fac = np.empty(len(close))
+    fac[0::2] = g * np.linalg.norm(wv[l], axis=1) * r
+    fac[1::2] = g * np.linalg.norm(wv[k], axis=1) * r
+    em = np.abs(gmass[close] - gm[close]) / (sm[close] + fac)
+    print(f"  close-pair particles, mass gradient: max {em.max():.3g}", flush=True)
+    assert em.max() <= 1e-4, em.max()
 
 
 def test_autograd_function(case):

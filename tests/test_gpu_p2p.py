@@ -342,3 +342,31 @@ def test_full_size_clustered_2m_sampled(c2):
         ctx.forward(out, torch.cuda.current_stream())
         torch.cuda.synchronize()
         check_fp32(out.cpu().numpy()[sample], ref)
+
+
+@pytest.mark.parametrize("trunc,size,level", [(B.TRUNC_R2, 64, 2), (B.TRUNC_TABLE, 512, 2),
+                                              (B.TRUNC_EXACT, 512, 2)])
+def test_fp32_twosum_accumulation(trunc, size, level):
+    """accum = FP32_TWOSUM: each work item's j-leaf sums added in float32
+    with a TwoSum compensation term.  Against the oracle at the float32
+    tolerances, and within float32 rounding of the float64-accumulated
+    result (the same pair sums, added differently)."""
+    w = inputs.clustered_small(24, 21, halo_frac=0.3, n_halos=6)
+    ref, _ = direct.brute_force(w.pos, w.mass, w.box, w.r_s, w.r_cut)
+    print(f"case: float32 TwoSum accumulation, trunc {trunc}", flush=True)
+    res = {}
+    for acc in (B.ACCUM_FP64, B.ACCUM_FP32_TWOSUM):
+        ctx = B.Context(box=w.box, r_s=w.r_s, r_cut=w.r_cut, max_leaf=64, order=-1,
+                        precision=B.PMFMM_FP32, trunc=trunc, table_size=size,
+                        table_level=level, accum=acc)
+        ctx.build(torch.tensor(w.pos, device="cuda"), torch.tensor(w.mass, device="cuda"))
+        out = torch.empty((len(w.mass), 3), dtype=torch.float64, device="cuda")
+        ctx.forward(out)
+        torch.cuda.synchronize()
+        res[acc] = out.cpu().numpy()
+    s = metrics.error_summary(res[B.ACCUM_FP32_TWOSUM], ref)
+    print("  vs oracle:", s, flush=True)
+    assert s["median"] <= 1e-5 and s["p999"] <= 1e-4
+    d = metrics.error_summary(res[B.ACCUM_FP32_TWOSUM], res[B.ACCUM_FP64])
+    print("  vs float64 accumulation:", d, flush=True)
+    assert d["max"] <= 1e-6

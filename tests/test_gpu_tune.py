@@ -41,3 +41,39 @@ def test_autotune_batch(tmp_path):
         s = metrics.error_summary(acc[p0:p0 + n], ref)
         assert s["median"] <= 1e-5 and s["p999"] <= 1e-4
         p0 += n
+
+
+def test_autotune_default_candidates_through_the_abi(tmp_path):
+    """pmfmm_autotune with the library's 24 default schedules on a float64
+    exact context: the schedules with more than 4 waves per workgroup are
+    skipped (that form runs at most 4), the winner is among the timed ones,
+    it is applied, and a second call takes it from the cache file."""
+    w = inputs.clustered_small(16, 9)
+    ctx = B.Context(box=w.box, r_s=w.r_s, r_cut=w.r_cut, max_leaf=64, order=-1,
+                    precision=B.PMFMM_FP64)
+    ctx.build(torch.tensor(w.pos, device="cuda"), torch.tensor(w.mass, device="cuda"))
+    out = torch.empty((len(w.mass), 3), dtype=torch.float64, device="cuda")
+    ref = torch.empty_like(out)
+    ctx.forward(ref)
+    cache = str(tmp_path / "tune.txt")
+    best, timed = ctx.autotune(out, repeats=1, cache_path=cache)
+    assert len(timed) == 24
+    ran = [r for r in timed if r["p2p_ms"] >= 0]
+    assert len(ran) == 12 and all(r["wg_waves"] <= 4 for r in ran)
+    assert (best["chunk"], best["wg_waves"]) in [(r["chunk"], r["wg_waves"]) for r in ran]
+    assert best["p2p_ms"] == min(r["p2p_ms"] for r in ran)
+    assert (ctx.params.chunk, ctx.params.wg_waves) == (best["chunk"], best["wg_waves"])
+    assert open(cache).read().count("\n") == 1
+    again, timed2 = ctx.autotune(out, cache_path=cache)
+    assert timed2 == []
+    assert [again[k] for k in ("chunk", "wg_waves", "grid_wgs")] == \
+        [best[k] for k in ("chunk", "wg_waves", "grid_wgs")]
+    assert abs(again["p2p_ms"] - best["p2p_ms"]) <= 1e-6      # kept to 6 decimals
+    ctx.forward(out)
+    torch.cuda.synchronize()
+    # workgroup size and grid leave the result bitwise alone; the work-item
+    # size regroups the float64 sums (rounding only)
+    a, b = out.cpu().numpy(), ref.cpu().numpy()
+    if best["chunk"] == 0:
+        assert np.array_equal(a, b)
+    assert np.max(np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)) <= 1e-12

@@ -738,18 +738,27 @@ int far_buffers(pmfmm_ctx* ctx, int64_t n) {
     return PMFMM_OK;
 }
 
-// Starts marks + far field of the current build on the side stream after
-// the work enqueued so far on s; far_done marks its end.
-int start_far(pmfmm_ctx* ctx, int64_t n, hipStream_t s) {
+int ensure_side(pmfmm_ctx* ctx) {
+    if (!ctx->side) HIP_TRY(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    return PMFMM_OK;
+}
+
+// Starts marks + far field of the current build on the side stream, after
+// the work enqueued so far on s (or, with side_ordered, after what is
+// already on the side stream, which the caller has ordered after s);
+// far_done marks its end.
+int start_far(pmfmm_ctx* ctx, int64_t n, hipStream_t s, bool side_ordered = false) {
     int rc = far_buffers(ctx, n);
     if (rc) return rc;
-    if (!ctx->side) HIP_TRY(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    if ((rc = ensure_side(ctx))) return rc;
     for (hipEvent_t* e : {&ctx->far_fork, &ctx->far_done})
         if (!*e) HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
     for (hipEvent_t* e : {&ctx->far_t0, &ctx->far_t1})
         if (!*e) HIP_TRY(hipEventCreate(e));
-    HIP_TRY(hipEventRecord(ctx->far_fork, s));
-    HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->far_fork, 0));
+    if (!side_ordered) {
+        HIP_TRY(hipEventRecord(ctx->far_fork, s));
+        HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->far_fork, 0));
+    }
     ctx->far = true;
     if ((rc = prepare_far(ctx, ctx->side))) return rc;
     HIP_TRY(hipEventRecord(ctx->far_t0, ctx->side));
@@ -854,16 +863,19 @@ int gpu_build(pmfmm_ctx* ctx, const std::vector<pmfmm::BoxParams>& boxes, const 
     // lists are enqueued, so it runs while the items are built
     int far_rc = PMFMM_OK;
     const int64_t n_all = n;
+    // the planner builds the M2L rows on the side stream (ordered after the
+    // walk on s) and calls far_start right after them
+    if ((rc = ensure_side(ctx))) return rc;
     auto far_start = [&](int64_t n_m2l, int32_t dsrc, int32_t dtgt) -> std::string {
         if (n_m2l <= 0) return std::string();
         ctx->n_m2l = n_m2l;
         ctx->m2l_dmin_src = dsrc;
         ctx->m2l_dmin_tgt = dtgt;
-        far_rc = start_far(ctx, n_all, s);
+        far_rc = start_far(ctx, n_all, s, true);
         return far_rc ? std::string("far field") : std::string();
     };
     std::string err = pmfmm::gpu_build_plan(ctx->d, ctx->plan, dp, dm, ctx->p.chunk, s, pc, &input_err,
-                                            far_start);
+                                            far_start, ctx->side);
     if (far_rc) return far_rc;
     if (!input_err.empty()) return fail(PMFMM_EINVAL, input_err);
     if (!err.empty()) return fail(PMFMM_EDEVICE, err);

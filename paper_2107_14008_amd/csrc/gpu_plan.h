@@ -69,6 +69,10 @@ struct DevPlan {
         p2p_keys_tmp, m2l_keys, m2l_keys_tmp, wcount, cost, cost_keys, cost_keys_tmp, queue_tmp,
         item_count, cell_axis, farflag, walk_ctl, froots, loop_cells, m2l_vals, rowcnt,
         longrows;
+    // scratch of the M2L rows, which may be built on another stream beside
+    // the P2P rows
+    DevBuf rowcnt_m2l, tile_sums_m2l, longrows_m2l;
+    hipEvent_t fork_ev = nullptr, m2l_done = nullptr;
     // cells the level loop partitions, by depth (loop_cells holds them);
     // n_froots subtrees finished in one launch (0: the loop does every level)
     std::vector<int32_t> loop_depth_begin;
@@ -78,7 +82,21 @@ struct DevPlan {
     int walk_levels = 0;
     std::vector<uint32_t> walk_sizes;   // frontier size per level, last build
 
+    // pinned host words for the planner's read-backs (a copy into pageable
+    // memory goes through a staging buffer and costs tens of microseconds)
+    uint32_t* host_rb = nullptr;
+    static constexpr int kHostRbWords = 4096;
+    hipError_t ensure_host_rb() {
+        if (host_rb) return hipSuccess;
+        return hipHostMalloc(reinterpret_cast<void**>(&host_rb), kHostRbWords * 4, hipHostMallocDefault);
+    }
     void release_all() {
+        if (host_rb) (void)hipHostFree(host_rb);
+        host_rb = nullptr;
+        for (hipEvent_t* e : {&fork_ev, &m2l_done})
+            if (*e) (void)hipEventDestroy(*e);
+        fork_ev = m2l_done = nullptr;
+        for (DevBuf* b : {&rowcnt_m2l, &tile_sums_m2l, &longrows_m2l}) b->release();
         for (DevBuf* b : {&perm, &leaf, &leafc, &js, &items, &queue, &leaf_slot, &partial, &counter,
                           &boxes, &table, &x64, &x32, &stage_pos, &stage_mass, &far, &cell,
                           &cell_aux, &cellc, &M, &Lc, &Lt, &m2l_row, &m2l_src, &m2l_shift, &level_cells,
@@ -129,10 +147,12 @@ hipError_t gpu_enqueue_checks(DevPlan& d, const double* pos, const double* mass,
 // per-box constants.
 hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, hipStream_t s);
 
-// Called by gpu_build_plan as soon as the M2L lists are enqueued on `s`
-// (before the work items), with the M2L task count and the smallest source
-// / target depth, so that the far field can start on another stream while
-// the items are built.  Returns an error message ("" on success).
+// Called by gpu_build_plan as soon as the M2L lists are enqueued (on the
+// `side` stream given to gpu_build_plan when there is one and M2L tasks
+// exist, else on `s`), before the P2P rows and the work items are done on
+// `s`, with the M2L task count and the smallest source / target depth, so
+// that the far field can start on the side stream while the rows and items
+// are built.  Returns an error message ("" on success).
 using M2LReady = std::function<std::string(int64_t n_m2l, int32_t dmin_src, int32_t dmin_tgt)>;
 
 // Builds the plan on the device from caller-order particles `pos` (n, 3) and
@@ -144,7 +164,7 @@ using M2LReady = std::function<std::string(int64_t n_m2l, int32_t dmin_src, int3
 // sets *input_error to a message naming the first offending particle.
 std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, const double* mass,
                            int chunk, hipStream_t s, PlanCounts& out, std::string* input_error,
-                           const M2LReady& on_m2l = M2LReady());
+                           const M2LReady& on_m2l = M2LReady(), hipStream_t side = nullptr);
 
 // Re-cuts the work items for a new chunk size from the device CSR.
 std::string gpu_make_items(DevPlan& d, const Plan& topo, int64_t n_p2p, int chunk, hipStream_t s,

@@ -1212,7 +1212,7 @@ hipError_t upload_topology(DevPlan& d, const Plan& topo, const BoxDev* boxdev, h
 
 std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, const double* mass,
                            int chunk, hipStream_t s, PlanCounts& out, std::string* input_error,
-                           const M2LReady& on_m2l) {
+                           const M2LReady& on_m2l, hipStream_t side) {
     input_error->clear();
     const int64_t n = topo.n;
     const int nbox = (int)topo.boxes.size();
@@ -1392,10 +1392,15 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         hipLaunchKernelGGL(k_m2l_depths, dim3(8), dim3(256), 0, s, d.m2l_keys.as<uint64_t>(),
                            ctl + 1, capm, ks.y, d.cell_aux.as<int4>(), ctl + 5 + L);
         TRY(hipGetLastError());
-        std::vector<uint32_t> hc(L + 7);
-        TRY(hipMemcpyAsync(hc.data(), ctl, (L + 7) * 4, hipMemcpyDeviceToHost, s));
-        TRY(hipMemcpyAsync(flags, d.wcount.p, 12, hipMemcpyDeviceToHost, s));
+        // the walk's counts and the input checks in one round trip, into
+        // pinned memory
+        TRY(d.ensure_host_rb());
+        if (L + 7 + 3 > DevPlan::kHostRbWords) return "walk has too many levels for the read-back buffer";
+        TRY(hipMemcpyAsync(d.host_rb, ctl, (L + 7) * 4, hipMemcpyDeviceToHost, s));
+        TRY(hipMemcpyAsync(d.host_rb + L + 7, d.wcount.p, 12, hipMemcpyDeviceToHost, s));
         TRY(hipStreamSynchronize(s));
+        std::vector<uint32_t> hc(d.host_rb, d.host_rb + L + 7);
+        std::memcpy(flags, d.host_rb + L + 7, 12);
         have_flags = true;
         if (clk.on) {
             std::fprintf(stderr, "[pmfmm gpu plan] walk frontier per level:");
@@ -1484,7 +1489,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         // a run of equal 32-bit keys too long for k_run_fix: build again
         // with the full 64-bit sort
         d.force64 = true;
-        std::string e = gpu_build_plan(d, topo, pos, mass, chunk, s, out, input_error, on_m2l);
+        std::string e = gpu_build_plan(d, topo, pos, mass, chunk, s, out, input_error, on_m2l, side);
         d.force64 = false;
         return e;
     }
@@ -1499,9 +1504,12 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     // slots, then long-row scratch: two int32 per key
     TRY(d.p2p_keys_tmp.ensure(std::max<int64_t>(1, n_p2p) * 8));
     TRY(d.m2l_keys_tmp.ensure(std::max<int64_t>(1, n_m2l) * 8));
-    TRY(d.rowcnt.ensure((std::max(nl, nc) + 2) * 4));
-    TRY(d.longrows.ensure((std::max(nl, nc) + 1) * 4));
-    TRY(d.tile_sums.ensure(sort_tiles(std::max(nl, nc) + 1) * 4 + 16));
+    TRY(d.rowcnt.ensure((nl + 2) * 4));
+    TRY(d.longrows.ensure((nl + 1) * 4));
+    TRY(d.tile_sums.ensure(sort_tiles(nl + 1) * 4 + 16));
+    TRY(d.rowcnt_m2l.ensure((nc + 2) * 4));
+    TRY(d.longrows_m2l.ensure((nc + 1) * 4));
+    TRY(d.tile_sums_m2l.ensure(sort_tiles(nc + 1) * 4 + 16));
     struct RowList {
         const DevBuf& keys;
         int64_t nk;
@@ -1509,54 +1517,83 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         int ks;
         DevBuf& row;
         DevBuf& vals;
-        DevBuf& tmp;
+        DevBuf& tmp;       // per-key slots, then long-row scratch
+        DevBuf& cnt;       // nrows + 2 counts
+        DevBuf& longs;     // nrows + 1
+        DevBuf& tsums;     // scan scratch
     };
-    const RowList lists[2] = {{d.p2p_keys, n_p2p, (int)nl, ks.x, d.p2p_row, d.js, d.p2p_keys_tmp},
-                              {d.m2l_keys, n_m2l, (int)nc, ks.y, d.m2l_row, d.m2l_vals,
-                               d.m2l_keys_tmp}};
-    // the M2L rows first: the far field can then start (on_m2l) while the
-    // P2P rows and the work items are built
-    auto make_rows = [&](const RowList& rl) -> hipError_t {
-        int32_t* cnt = d.rowcnt.as<int32_t>();
-        int32_t* slot = rl.tmp.as<int32_t>();
-        hipLaunchKernelGGL(k_zero_u32, dim3(grid_of(rl.nrows + 2)), dim3(256), 0, s,
-                           d.rowcnt.as<uint32_t>(), rl.nrows + 2);
+    const RowList p2p_rows{d.p2p_keys, n_p2p, (int)nl, ks.x, d.p2p_row, d.js,
+                           d.p2p_keys_tmp, d.rowcnt, d.longrows, d.tile_sums};
+    const RowList m2l_rows{d.m2l_keys, n_m2l, (int)nc, ks.y, d.m2l_row, d.m2l_vals,
+                           d.m2l_keys_tmp, d.rowcnt_m2l, d.longrows_m2l, d.tile_sums_m2l};
+    // the rows in two parts: the atomic row counts, then the rest
+    auto count_rows = [&](const RowList& rl, hipStream_t st) -> hipError_t {
+        hipLaunchKernelGGL(k_zero_u32, dim3(grid_of(rl.nrows + 2)), dim3(256), 0, st,
+                           rl.cnt.as<uint32_t>(), rl.nrows + 2);
         if (rl.nk > 0)
-            hipLaunchKernelGGL(k_row_count, dim3(grid_of(rl.nk)), dim3(256), 0, s,
-                               rl.keys.as<uint64_t>(), rl.nk, rl.ks, cnt, slot);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        e = exclusive_scan_i32(cnt, rl.row.as<int32_t>(), rl.nrows + 1, d.tile_sums.as<uint32_t>(), s);
+            hipLaunchKernelGGL(k_row_count, dim3(grid_of(rl.nk)), dim3(256), 0, st,
+                               rl.keys.as<uint64_t>(), rl.nk, rl.ks, rl.cnt.as<int32_t>(),
+                               rl.tmp.as<int32_t>());
+        return hipGetLastError();
+    };
+    auto finish_rows = [&](const RowList& rl, hipStream_t st) -> hipError_t {
+        int32_t* cnt = rl.cnt.as<int32_t>();
+        int32_t* slot = rl.tmp.as<int32_t>();
+        hipError_t e = exclusive_scan_i32(cnt, rl.row.as<int32_t>(), rl.nrows + 1,
+                                          rl.tsums.as<uint32_t>(), st);
         if (e != hipSuccess) return e;
         if (rl.nk > 0) {
-            hipLaunchKernelGGL(k_row_place, dim3(grid_of(rl.nk)), dim3(256), 0, s,
+            hipLaunchKernelGGL(k_row_place, dim3(grid_of(rl.nk)), dim3(256), 0, st,
                                rl.keys.as<uint64_t>(), rl.nk, rl.ks, rl.row.as<int32_t>(), slot,
                                rl.vals.as<int32_t>());
-            // the count of long rows goes in rowcnt[nrows + 1] (zeroed above)
+            // the count of long rows goes in cnt[nrows + 1] (zeroed above)
             int32_t* nlong = cnt + rl.nrows + 1;
-            hipLaunchKernelGGL(k_row_sort_short, dim3(rl.nrows), dim3(64), 0, s, rl.row.as<int32_t>(),
-                               rl.vals.as<int32_t>(), d.longrows.as<int32_t>(), nlong);
-            hipLaunchKernelGGL(k_row_sort_long, dim3(64), dim3(256), 0, s, rl.row.as<int32_t>(),
-                               rl.vals.as<int32_t>(), d.longrows.as<int32_t>(), nlong, slot,
+            hipLaunchKernelGGL(k_row_sort_short, dim3(rl.nrows), dim3(64), 0, st,
+                               rl.row.as<int32_t>(), rl.vals.as<int32_t>(),
+                               rl.longs.as<int32_t>(), nlong);
+            hipLaunchKernelGGL(k_row_sort_long, dim3(64), dim3(256), 0, st, rl.row.as<int32_t>(),
+                               rl.vals.as<int32_t>(), rl.longs.as<int32_t>(), nlong, slot,
                                row_lds_cap());
         }
         return hipGetLastError();
     };
-    TRY(make_rows(lists[1]));
-    // wcount words 16, 17: smallest source / target depth of the M2L tasks
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int*>(d.wcount.p) + 16,
+    // With M2L tasks and a side stream, the M2L rows and then the far field
+    // (on_m2l) run on the side stream while the P2P rows and the work items
+    // are built on s; the side stream starts after everything before it on
+    // s (the walk), and s waits for the M2L rows (not the far field) before
+    // the build ends.
+    const bool fork = side != nullptr && side != s && n_m2l > 0;
+    hipStream_t ms = s;
+    if (fork) {
+        for (hipEvent_t* e : {&d.fork_ev, &d.m2l_done})
+            if (!*e) TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
+        TRY(hipEventRecord(d.fork_ev, s));
+        TRY(hipStreamWaitEvent(side, d.fork_ev, 0));
+        ms = side;
+        // the P2P row counts (a long kernel) first, so the device has work
+        // on s while the host enqueues the side stream's launches
+        TRY(count_rows(p2p_rows, s));
+    }
+    TRY(count_rows(m2l_rows, ms));
+    TRY(finish_rows(m2l_rows, ms));
+    // M2L sources and shifts; the smallest depths go to wcount words 16, 17
+    // (the walk's k_m2l_depths gave the same values to the host already)
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, ms, reinterpret_cast<int*>(d.wcount.p) + 16,
                        2, 0x7fffffff);
     if (n_m2l > 0)
-        hipLaunchKernelGGL(k_m2l_split, dim3(grid_of(nc)), dim3(256), 0, s, d.m2l_row.as<int32_t>(),
+        hipLaunchKernelGGL(k_m2l_split, dim3(grid_of(nc)), dim3(256), 0, ms, d.m2l_row.as<int32_t>(),
                            (int)nc, d.m2l_vals.as<int32_t>(), d.cell_aux.as<int4>(),
                            d.m2l_src.as<int32_t>(), d.m2l_shift.as<int32_t>(),
                            reinterpret_cast<int32_t*>(d.wcount.p) + 16);
     TRY(hipGetLastError());
+    if (fork) TRY(hipEventRecord(d.m2l_done, side));
+    if (!fork) TRY(count_rows(p2p_rows, s));
     if (on_m2l) {
         std::string e = on_m2l(n_m2l, dmin_src, dmin_tgt);
         if (!e.empty()) return e;
     }
-    TRY(make_rows(lists[0]));
+    TRY(finish_rows(p2p_rows, s));
+    if (fork) TRY(hipStreamWaitEvent(s, d.m2l_done, 0));
     out.n_p2p = n_p2p;
     out.n_m2l = n_m2l;
     clk.lap("csr");
@@ -1603,8 +1640,10 @@ std::string gpu_make_items(DevPlan& d, const Plan& topo, int64_t n_p2p, int chun
     if (!err.empty()) return err;
     // words 8, 9: candidate pairs; 10: items; 16, 17: M2L depths (set by the build)
     uint32_t w[10];
-    TRY(hipMemcpyAsync(w, d.wcount.as<uint32_t>() + 8, sizeof(w), hipMemcpyDeviceToHost, s));
+    TRY(d.ensure_host_rb());
+    TRY(hipMemcpyAsync(d.host_rb, d.wcount.as<uint32_t>() + 8, sizeof(w), hipMemcpyDeviceToHost, s));
     TRY(hipStreamSynchronize(s));
+    std::memcpy(w, d.host_rb, sizeof(w));
     unsigned long long cand = 0;
     std::memcpy(&cand, w, 8);
     const int64_t n_items = (int64_t)w[2];

@@ -64,7 +64,7 @@ struct DevPlan {
     DevBuf w64, w32, fargrad;
     // on-GPU planner scratch
     DevBuf p2p_row, wpos, keys, keys_tmp, plist, plist_tmp, hist, flag, lv_first, tile_sums;
-    bool force64 = false;   // sort by the full 64-bit keys (a long run of equal 32-bit keys)
+    bool force64 = false;   // sort by the full 64-bit keys (a long run of equal 24-bit keys)
     DevBuf pc, pc_tmp, clo, chi, wcell, box_first, walkbox, front, front_next, p2p_keys,
         p2p_keys_tmp, m2l_keys, m2l_keys_tmp, wcount, cost, cost_keys, cost_keys_tmp, queue_tmp,
         item_count, cell_axis, farflag, walk_ctl, froots, loop_cells, m2l_vals, rowcnt,
@@ -135,8 +135,6 @@ hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, ui
                           bool* result_in_tmp, int nseg = 1);
 hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, uint32_t* tile_sums,
                               hipStream_t s);
-// In-place exclusive scan by one workgroup (for a few thousand values).
-hipError_t exclusive_scan_u32_one_block(uint32_t* a, int64_t m, hipStream_t s);
 
 // Enqueues the checks of device particles (finite positions, finite
 // non-negative masses); gpu_build_plan reads their result.

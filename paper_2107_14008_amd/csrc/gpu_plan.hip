@@ -64,13 +64,15 @@ __device__ __forceinline__ uint64_t coord_key(double x) {
     return x == 0.0 ? 0ull : (uint64_t)__double_as_longlong(x);
 }
 
-// 32-bit sort key of a wrapped coordinate x in [0, L): floor(x 2^32 / L),
+// 24-bit sort key of a wrapped coordinate x in [0, L): floor(x 2^24 / L),
 // a non-decreasing function of x (a rounded product and a floor), so that
 // sorting by it and then ordering each run of equal keys by x is the order
-// by x.
-__device__ __forceinline__ uint32_t coord_key32(double x, double scale) {
+// by x.  24 bits: three 8-bit radix passes; a bin is L / 2^24 wide, so runs
+// of equal keys stay short (k_run_fix) even at 256^3 particles per box.
+constexpr int kKeyBits = 24;
+__device__ __forceinline__ uint32_t coord_key24(double x, double scale) {
     const double t = x * scale;
-    return t >= 4294967295.0 ? 0xffffffffu : (uint32_t)t;
+    return t >= 16777215.0 ? 0xffffffu : (uint32_t)t;
 }
 
 __global__ void k_wrap_keys(const double* __restrict__ pos, int64_t n, const int32_t* __restrict__ bf,
@@ -79,11 +81,11 @@ __global__ void k_wrap_keys(const double* __restrict__ pos, int64_t n, const int
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double L = boxes[box_of(bf, nbox, (int)i)].L;
-    const double scale = 4294967296.0 / L;
+    const double scale = 16777216.0 / L;
     for (int a = 0; a < 3; ++a) {
         const double x = wrap_coord(pos[3 * i + a], L);
         wpos[3 * i + a] = x;
-        keys[a * n + i] = coord_key32(x, scale);
+        keys[a * n + i] = coord_key24(x, scale);
         vals[a * n + i] = (uint32_t)i;
     }
 }
@@ -99,7 +101,7 @@ __global__ void k_keys64(const double* __restrict__ wpos, int64_t n, uint64_t* _
     }
 }
 
-// After the stable sort by 32-bit key, each run of equal keys of one axis
+// After the stable sort by 24-bit key, each run of equal keys of one axis
 // list is in caller order; this puts it in coordinate order (stable, so
 // equal coordinates stay in caller order).  The first position of a run of
 // at most kRunMax elements sorts it in place (insertion sort).  A longer
@@ -210,10 +212,10 @@ __global__ void k_flag(int64_t n, const int32_t* __restrict__ pc, const int4* __
 // (3n positions, list a at [a n, (a + 1) n)) computed where they are used
 // instead of stored: a position's mark is flag[particle] if its cell splits
 // at this level, else 0.  Tiles of 4096 positions: k_level_sums counts each
-// tile's marks, an exclusive scan of the counts gives the tile offsets,
-// k_level_firsts the exclusive prefix at each splitting cell's first
-// position of each list, and k_level_move the prefix of every position
-// (tile offset + in-tile scan) and from it the position's destination.
+// tile's marks; k_level_firsts gives the count of marks before each
+// splitting cell's first position of each list, and k_level_move the count
+// before every position (the tiles before its own, summed where they are
+// needed, + the in-tile scan) and from it the position's destination.
 constexpr int kLvThreads = 256;
 constexpr int kLvRounds = 16;
 constexpr int kLvTile = kLvThreads * kLvRounds;   // 4096
@@ -265,18 +267,21 @@ __global__ void __launch_bounds__(256)
 k_level_firsts(const int32_t* __restrict__ level, int nd, int64_t n, const int4* __restrict__ cell,
                const int32_t* __restrict__ pc, const int32_t* __restrict__ sax,
                const uint32_t* __restrict__ plist, const uint8_t* __restrict__ flag,
-               const uint32_t* __restrict__ tile_off, int nc, int32_t* __restrict__ pfirst) {
+               const uint32_t* __restrict__ tile_sums, int nc, int32_t* __restrict__ pfirst) {
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (w >= 3 * nd) return;
     const int k = w / 3, a = w - 3 * k;
     const int c = level[k];
     const int64_t qf = (int64_t)a * n + cell[c].x;
-    const int64_t t0 = qf / kLvTile * kLvTile;
+    const int64_t tq = qf / kLvTile, t0 = tq * kLvTile;
+    // marks before qf: the counts of the tiles before qf's, then the marks
+    // of its tile up to qf
     uint32_t cnt = 0;
+    for (int64_t k = lane; k < tq; k += 64) cnt += tile_sums[k];
     for (int64_t q = t0 + lane; q < qf; q += 64) cnt += level_mark(q, n, pc, sax, cell, plist, flag);
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off);
-    if (lane == 0) pfirst[(size_t)a * nc + c] = (int32_t)(tile_off[qf / kLvTile] + cnt);
+    if (lane == 0) pfirst[(size_t)a * nc + c] = (int32_t)cnt;
 }
 
 __global__ void __launch_bounds__(kLvThreads)
@@ -284,11 +289,19 @@ k_level_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __restrict__ pc
              const int4* __restrict__ cell, const int4* __restrict__ aux,
              const int32_t* __restrict__ sax, const uint32_t* __restrict__ plist,
              uint32_t* __restrict__ pout, const uint8_t* __restrict__ flag,
-             const uint32_t* __restrict__ tile_off, int nc, const int32_t* __restrict__ pfirst) {
+             const uint32_t* __restrict__ tile_sums, int nc, const int32_t* __restrict__ pfirst) {
     __shared__ uint8_t mk[kLvTile];
     __shared__ uint16_t pre[kLvTile];
     __shared__ uint32_t wsum[kLvThreads / 64];
+    __shared__ uint32_t woff[kLvThreads / 64];
     const int t = threadIdx.x;
+    {
+        // this tile's offset: the counts of the tiles before it
+        uint32_t c = 0;
+        for (int k = t; k < (int)blockIdx.x; k += kLvThreads) c += tile_sums[k];
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
+        if ((t & 63) == 0) woff[t >> 6] = c;
+    }
     const int64_t base = (int64_t)blockIdx.x * kLvTile;
     uint32_t pv[kLvRounds];
     int32_t cv[kLvRounds];
@@ -323,7 +336,8 @@ k_level_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __restrict__ pc
         run += mk[kLvRounds * t + j];
     }
     __syncthreads();
-    const uint32_t toff = tile_off[blockIdx.x];
+    uint32_t toff = 0;
+    for (int w = 0; w < kLvThreads / 64; ++w) toff += woff[w];
     for (int r = 0; r < kLvRounds; ++r) {
         const int64_t q = base + r * kLvThreads + t;
         if (q >= 3 * n) continue;
@@ -731,20 +745,24 @@ k_walk(const int2* __restrict__ front, int nf, int2* __restrict__ next,
 // ctl: [0] p2p total, [1] m2l total, [2] overflow flag, [3] largest frontier;
 // sizes[it] = frontier size of level it.
 constexpr int kWalkT = 1024;
+// frontiers up to this size go to the one-workgroup top of the walk
+constexpr uint32_t kWalkTopMax = 4 * kWalkT;
 
-__global__ void __launch_bounds__(kWalkT)
-k_walk_dev(const int2* __restrict__ front, int2* __restrict__ next, int it,
-           uint32_t* __restrict__ sizes, uint32_t* __restrict__ ctl, uint32_t cap_front,
-           uint32_t cap_p2p, uint32_t cap_m2l, const WalkBox* __restrict__ wbox,
-           const WalkCell* __restrict__ wcell, int2 ks, uint64_t* __restrict__ p2p_keys,
-           uint64_t* __restrict__ m2l_keys) {
-    __shared__ uint64_t wtot[kWalkT / 64];
-    __shared__ uint32_t bbase[3];
-    const uint32_t nf = sizes[it];
-    if (nf > cap_front) return;
+// One level's share of workgroup `blk` of `nblk` (nf pairs in front).
+// Returns false when the frontier is beyond its capacity.
+__device__ __forceinline__ bool walk_level(const int2* __restrict__ front, int2* __restrict__ next,
+                                           int it, uint32_t nf, uint32_t blk, uint32_t nblk,
+                                           uint32_t* __restrict__ sizes, uint32_t* __restrict__ ctl,
+                                           uint32_t cap_front, uint32_t cap_p2p, uint32_t cap_m2l,
+                                           const WalkBox* __restrict__ wbox,
+                                           const WalkCell* __restrict__ wcell, int2 ks,
+                                           uint64_t* __restrict__ p2p_keys,
+                                           uint64_t* __restrict__ m2l_keys, uint64_t* wtot,
+                                           uint32_t* bbase) {
+    if (nf > cap_front) return false;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < nf; base += stride) {
+    const uint32_t stride = nblk * blockDim.x;
+    for (uint32_t base = blk * blockDim.x; base < nf; base += stride) {
         const uint32_t k = base + threadIdx.x;
         WalkOut o{0u, 0u, 0u, {}, {0ull, 0ull}};
         if (k < nf) walk_classify(front[k], wbox, wcell, ks, o);
@@ -789,7 +807,55 @@ k_walk_dev(const int2* __restrict__ front, int2* __restrict__ next, int it,
         }
         __syncthreads();   // wtot and bbase are reused by the next group
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&ctl[3], nf);
+    if (blk == 0 && threadIdx.x == 0) atomicMax(&ctl[3], nf);
+    return true;
+}
+
+__global__ void __launch_bounds__(kWalkT)
+k_walk_dev(const int2* __restrict__ front, int2* __restrict__ next, int it,
+           uint32_t* __restrict__ sizes, uint32_t* __restrict__ ctl, uint32_t cap_front,
+           uint32_t cap_p2p, uint32_t cap_m2l, const WalkBox* __restrict__ wbox,
+           const WalkCell* __restrict__ wcell, int2 ks, uint64_t* __restrict__ p2p_keys,
+           uint64_t* __restrict__ m2l_keys) {
+    __shared__ uint64_t wtot[kWalkT / 64];
+    __shared__ uint32_t bbase[3];
+    (void)walk_level(front, next, it, sizes[it], blockIdx.x, gridDim.x, sizes, ctl, cap_front,
+                     cap_p2p, cap_m2l, wbox, wcell, ks, p2p_keys, m2l_keys, wtot, bbase);
+}
+
+// The first frontier (each box's root against itself with the zero shift and
+// the 13 shifts of code > 13, the canonical half) and the walk's first
+// `levels` levels in one workgroup: the top of the walk has frontiers of a
+// few hundred pairs, where a launch per level costs more than the level.
+// Level it reads buffer it & 1 and writes the other.  The frontier sizes,
+// which thread 0 adds to with atomics, are read back with atomic loads.
+__global__ void __launch_bounds__(kWalkT)
+k_walk_top(int nbox, const int32_t* __restrict__ box_root, int2* __restrict__ buf0,
+           int2* __restrict__ buf1, int levels, uint32_t* __restrict__ sizes,
+           uint32_t* __restrict__ ctl, uint32_t cap_front, uint32_t cap_p2p, uint32_t cap_m2l,
+           const WalkBox* __restrict__ wbox, const WalkCell* __restrict__ wcell, int2 ks,
+           uint64_t* __restrict__ p2p_keys, uint64_t* __restrict__ m2l_keys) {
+    __shared__ uint64_t wtot[kWalkT / 64];
+    __shared__ uint32_t bbase[3];
+    const uint32_t nf0 = (uint32_t)(14 * nbox);
+    for (uint32_t q = threadIdx.x; q < nf0; q += blockDim.x) {
+        const int b = (int)(q / 14), j = (int)(q - 14 * (uint32_t)b);
+        const int root = box_root[b];
+        buf0[q] = make_int2(root, (root << 5) | (13 + j));
+    }
+    if (threadIdx.x == 0) sizes[0] = nf0;
+    __syncthreads();
+    for (int it = 0; it < levels; ++it) {
+        const uint32_t nf = it == 0 ? nf0
+                                    : __hip_atomic_load(&sizes[it], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+        const int2* front = (it & 1) ? buf1 : buf0;
+        int2* next = (it & 1) ? buf0 : buf1;
+        if (!walk_level(front, next, it, nf, 0u, 1u, sizes, ctl, cap_front, cap_p2p, cap_m2l,
+                        wbox, wcell, ks, p2p_keys, m2l_keys, wtot, bbase))
+            return;
+        __syncthreads();
+    }
 }
 
 // Smallest target / source depth of the walk's M2L keys (key = t << ks |
@@ -808,18 +874,6 @@ __global__ void k_m2l_depths(const uint64_t* __restrict__ keys, const uint32_t* 
     }
     if (bt) atomicMax(&out[0], bt);
     if (bs) atomicMax(&out[1], bs);
-}
-
-// The walk's first frontier: for each box, its root against itself with the
-// zero shift and the 13 shifts of code > 13 (the canonical half).
-__global__ void k_walk_init(int nbox, const int32_t* __restrict__ box_root, int2* __restrict__ front,
-                            uint32_t* __restrict__ sizes) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q == 0) sizes[0] = (uint32_t)(14 * nbox);
-    if (q >= 14 * nbox) return;
-    const int b = q / 14, j = q - 14 * b;
-    const int root = box_root[b];
-    front[q] = make_int2(root, (root << 5) | (13 + j));
 }
 
 __global__ void k_zero_u32(uint32_t* p, int n) {
@@ -1229,7 +1283,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                        d.box_first.as<int32_t>(), nbox, d.boxes.as<BoxDev>(), d.wpos.as<double>(),
                        d.keys.as<uint32_t>(), d.plist.as<uint32_t>());
     TRY(hipGetLastError());
-    // the three axis lists are three segments of one sort: by the 32-bit
+    // the three axis lists are three segments of one sort: by the 24-bit
     // key, then each run of equal keys by coordinate
     TRY(d.hist.ensure((size_t)sort_hist_words(n, 3) * 4));
     uint32_t* v = d.plist.as<uint32_t>();
@@ -1237,10 +1291,13 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     bool in_tmp = false;
     if (n > 1) {
         TRY(radix_sort_u32(d.keys.as<uint32_t>(), v, d.keys_tmp.as<uint32_t>(), vt,
-                           d.hist.as<uint32_t>(), n, 0, 32, s, &in_tmp, 3));
+                           d.hist.as<uint32_t>(), n, 0, kKeyBits, s, &in_tmp, 3));
         if (in_tmp) {
-            TRY(hipMemcpyAsync(d.keys.p, d.keys_tmp.p, n * 12, hipMemcpyDeviceToDevice, s));
-            TRY(hipMemcpyAsync(v, vt, n * 12, hipMemcpyDeviceToDevice, s));
+            // the sorted keys and lists are the scratch buffers now
+            std::swap(d.keys, d.keys_tmp);
+            std::swap(d.plist, d.plist_tmp);
+            v = d.plist.as<uint32_t>();
+            vt = d.plist_tmp.as<uint32_t>();
         }
         hipLaunchKernelGGL(k_run_fix, dim3(grid_of(3 * n)), dim3(256), 0, s, d.keys.as<uint32_t>(), v,
                            n, d.wpos.as<double>(), reinterpret_cast<int*>(d.wcount.p) + 2);
@@ -1252,7 +1309,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     // with a long run the build is redone with the 64-bit sort (force64).
     {
         if (d.force64) {
-            // coordinates closer than the 32-bit key resolves, out of order
+            // coordinates closer than the 24-bit key resolves, out of order
             // in a long run: sort by the full keys
             uint64_t* k = d.keys.as<uint64_t>();
             uint64_t* kt = d.keys_tmp.as<uint64_t>();
@@ -1304,7 +1361,6 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                            d.pc.as<int32_t>(), d.cell_axis.as<int32_t>(), d.cell.as<int4>(),
                            d.plist.as<uint32_t>(), d.flag.as<uint8_t>(), d.tile_sums.as<uint32_t>());
         TRY(hipGetLastError());
-        TRY(exclusive_scan_u32_one_block(d.tile_sums.as<uint32_t>(), lv_tiles, s));
         hipLaunchKernelGGL(k_level_firsts, dim3((3 * ncd + 3) / 4), dim3(256), 0, s,
                            d.loop_cells.as<int32_t>() + c0, ncd, n, d.cell.as<int4>(),
                            d.pc.as<int32_t>(), d.cell_axis.as<int32_t>(), d.plist.as<uint32_t>(),
@@ -1376,10 +1432,16 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                            d.walk_ctl.as<uint32_t>(), L + 8);
         uint32_t* ctl = d.walk_ctl.as<uint32_t>();
         uint32_t* sizes = ctl + 4;
-        hipLaunchKernelGGL(k_walk_init, dim3(grid_of(nf0)), dim3(256), 0, s, nbox,
-                           d.item_count.as<int32_t>(), d.front.as<int2>(), sizes);
         DevBuf* bufs[2] = {&d.front, &d.front_next};
-        for (int it = 0; it < L; ++it) {
+        // the top levels in one workgroup while the last build's frontiers
+        // were small (any size is handled; this only chooses the split)
+        int top = 0;
+        while (top < L && top < (int)d.walk_sizes.size() && d.walk_sizes[top] <= kWalkTopMax) ++top;
+        hipLaunchKernelGGL(k_walk_top, dim3(1), dim3(kWalkT), 0, s, nbox, d.item_count.as<int32_t>(),
+                           d.front.as<int2>(), d.front_next.as<int2>(), top, sizes, ctl, capf,
+                           capp, capm, d.walkbox.as<WalkBox>(), d.wcell.as<WalkCell>(), ks,
+                           d.p2p_keys.as<uint64_t>(), d.m2l_keys.as<uint64_t>());
+        for (int it = top; it < L; ++it) {
             // workgroups for the frontier the last build had at this level
             // (the kernel strides over any size; this only trims launches)
             const int64_t prev = it < (int)d.walk_sizes.size() ? d.walk_sizes[it] : capf;
@@ -1486,7 +1548,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         return std::string();
     }
     if (flags[2] != 0 && !d.force64) {
-        // a run of equal 32-bit keys too long for k_run_fix: build again
+        // a run of equal 24-bit keys too long for k_run_fix: build again
         // with the full 64-bit sort
         d.force64 = true;
         std::string e = gpu_build_plan(d, topo, pos, mass, chunk, s, out, input_error, on_m2l, side);

@@ -275,12 +275,6 @@ hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, ui
                                 std::min(bit_end, 32), s, result_in_tmp, nseg);
 }
 
-hipError_t exclusive_scan_u32_one_block(uint32_t* a, int64_t m, hipStream_t s) {
-    if (m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(scan_single, dim3(1), dim3(1024), 0, s, a, m);
-    return hipGetLastError();
-}
-
 hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, uint32_t* tile_sums,
                               hipStream_t s) {
     if (n <= 0) return hipSuccess;

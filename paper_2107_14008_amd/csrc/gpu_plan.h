@@ -64,7 +64,7 @@ struct DevPlan {
     DevBuf w64, w32, fargrad;
     // on-GPU planner scratch
     DevBuf p2p_row, wpos, keys, keys_tmp, plist, plist_tmp, hist, flag, lv_first, tile_sums;
-    bool force64 = false;   // sort by the full 64-bit keys (a long run of equal 24-bit keys)
+    bool force64 = false;   // sort by the full 64-bit keys (a long run of equal short keys)
     DevBuf pc, pc_tmp, clo, chi, wcell, box_first, walkbox, front, front_next, p2p_keys,
         p2p_keys_tmp, m2l_keys, m2l_keys_tmp, wcount, cost, cost_keys, cost_keys_tmp, queue_tmp,
         item_count, cell_axis, farflag, walk_ctl, froots, loop_cells, m2l_vals, rowcnt,

@@ -64,28 +64,31 @@ __device__ __forceinline__ uint64_t coord_key(double x) {
     return x == 0.0 ? 0ull : (uint64_t)__double_as_longlong(x);
 }
 
-// 24-bit sort key of a wrapped coordinate x in [0, L): floor(x 2^24 / L),
-// a non-decreasing function of x (a rounded product and a floor), so that
-// sorting by it and then ordering each run of equal keys by x is the order
-// by x.  24 bits: three 8-bit radix passes; a bin is L / 2^24 wide, so runs
-// of equal keys stay short (k_run_fix) even at 256^3 particles per box.
-constexpr int kKeyBits = 24;
-__device__ __forceinline__ uint32_t coord_key24(double x, double scale) {
+// Sort key of a wrapped coordinate x in [0, L): floor(x 2^bits / L) with
+// 24 or 32 bits, a non-decreasing function of x (a rounded product and a
+// floor), so that sorting by it and then ordering each run of equal keys by
+// x is the order by x.  24 bits (three 8-bit radix passes) up to
+// kKey24Max particles, where a bin of L / 2^24 rarely holds two of them;
+// beyond, the runs of equal keys would cost k_run_fix more than the fourth
+// pass (measured at 256^3), and the key has 32 bits.
+constexpr int64_t kKey24Max = int64_t(1) << 22;
+__device__ __forceinline__ uint32_t coord_key(double x, double scale, double kmax) {
     const double t = x * scale;
-    return t >= 16777215.0 ? 0xffffffu : (uint32_t)t;
+    return t >= kmax ? (uint32_t)kmax : (uint32_t)t;
 }
 
 __global__ void k_wrap_keys(const double* __restrict__ pos, int64_t n, const int32_t* __restrict__ bf,
                             int nbox, const BoxDev* __restrict__ boxes, double* __restrict__ wpos,
-                            uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                            uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int key_bits) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double L = boxes[box_of(bf, nbox, (int)i)].L;
-    const double scale = 16777216.0 / L;
+    const double range = key_bits == 24 ? 16777216.0 : 4294967296.0;
+    const double scale = range / L;
     for (int a = 0; a < 3; ++a) {
         const double x = wrap_coord(pos[3 * i + a], L);
         wpos[3 * i + a] = x;
-        keys[a * n + i] = coord_key24(x, scale);
+        keys[a * n + i] = coord_key(x, scale, range - 1.0);
         vals[a * n + i] = (uint32_t)i;
     }
 }
@@ -101,7 +104,7 @@ __global__ void k_keys64(const double* __restrict__ wpos, int64_t n, uint64_t* _
     }
 }
 
-// After the stable sort by 24-bit key, each run of equal keys of one axis
+// After the stable sort by the key, each run of equal keys of one axis
 // list is in caller order; this puts it in coordinate order (stable, so
 // equal coordinates stay in caller order).  The first position of a run of
 // at most kRunMax elements sorts it in place (insertion sort).  A longer
@@ -1279,19 +1282,20 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     TRY(d.plist.ensure(n * 12));
     TRY(d.plist_tmp.ensure(n * 12));
     TRY(d.keys_tmp.ensure(n * 24));
+    const int key_bits = n <= kKey24Max ? 24 : 32;
     hipLaunchKernelGGL(k_wrap_keys, dim3(grid_of(n)), dim3(256), 0, s, pos, n,
                        d.box_first.as<int32_t>(), nbox, d.boxes.as<BoxDev>(), d.wpos.as<double>(),
-                       d.keys.as<uint32_t>(), d.plist.as<uint32_t>());
+                       d.keys.as<uint32_t>(), d.plist.as<uint32_t>(), key_bits);
     TRY(hipGetLastError());
-    // the three axis lists are three segments of one sort: by the 24-bit
-    // key, then each run of equal keys by coordinate
+    // the three axis lists are three segments of one sort: by the key,
+    // then each run of equal keys by coordinate
     TRY(d.hist.ensure((size_t)sort_hist_words(n, 3) * 4));
     uint32_t* v = d.plist.as<uint32_t>();
     uint32_t* vt = d.plist_tmp.as<uint32_t>();
     bool in_tmp = false;
     if (n > 1) {
         TRY(radix_sort_u32(d.keys.as<uint32_t>(), v, d.keys_tmp.as<uint32_t>(), vt,
-                           d.hist.as<uint32_t>(), n, 0, kKeyBits, s, &in_tmp, 3));
+                           d.hist.as<uint32_t>(), n, 0, key_bits, s, &in_tmp, 3));
         if (in_tmp) {
             // the sorted keys and lists are the scratch buffers now
             std::swap(d.keys, d.keys_tmp);
@@ -1309,7 +1313,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     // with a long run the build is redone with the 64-bit sort (force64).
     {
         if (d.force64) {
-            // coordinates closer than the 24-bit key resolves, out of order
+            // coordinates closer than the key resolves, out of order
             // in a long run: sort by the full keys
             uint64_t* k = d.keys.as<uint64_t>();
             uint64_t* kt = d.keys_tmp.as<uint64_t>();
@@ -1548,7 +1552,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         return std::string();
     }
     if (flags[2] != 0 && !d.force64) {
-        // a run of equal 24-bit keys too long for k_run_fix: build again
+        // a run of equal keys too long for k_run_fix: build again
         // with the full 64-bit sort
         d.force64 = true;
         std::string e = gpu_build_plan(d, topo, pos, mass, chunk, s, out, input_error, on_m2l, side);

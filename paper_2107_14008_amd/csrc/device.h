@@ -53,9 +53,16 @@ constexpr int kR2Emax = 11;
 // float64 r^2 table: scaled r^2 in [2^kR2Emin64, 2^kR2Emax); closer pairs
 // (r < 2^-8 r_cut) take the exact erfc / exp path.
 constexpr int kR2Emin64 = kR2Emax - 16;
-// float32 r^2 table: three planes (c0, c1, c2) of kR2Plane floats each, room
-// for 128 segments per octave; the plane stride is a multiple of 256 bytes.
-constexpr int kR2Plane = 5952;
+// float32 r^2 table at 2^bits segments per octave: rows r2_rows(bits) (the
+// last, at s = 2^kR2Emax, zero); row k holds (c0, c1) at 8 k and (c2, 0) at
+// r2_plane_c2(bits) + 8 k, so a lookup is one 8-byte and one 4-byte LDS read
+// from the same address.
+constexpr int kR2Plane = 5952;   // rows the fit scratch holds (128 per octave)
+constexpr int r2_rows(int bits) { return ((kR2Emax - kR2Emin) << bits) + 1; }
+constexpr int r2_plane_c2(int bits) { return (r2_rows(bits) * 8 + 255) / 256 * 256; }
+constexpr int r2_table_bytes(int bits) { return (r2_plane_c2(bits) + r2_rows(bits) * 8 + 15) / 16 * 16; }
+static_assert(r2_rows(7) <= kR2Plane, "r^2 table rows");
+static_assert(r2_plane_c2(7) < 65536, "the c2 plane offset is an LDS read's immediate");
 // Adjoint of the float32 r^2 form: g(s) and h(s) over s in
 // [2^kAdjEmin, 2^kR2Emax), six planes (g c0 c1 c2, h c0 c1 c2) of kAdjPlane
 // floats at 2^kAdjBits segments per octave.  The floor sits above

@@ -238,24 +238,28 @@ __device__ __forceinline__ void pin(const Src4<V>& b) {
 // four in clustered boxes), and an LDS read costs its issue slot whatever
 // its active lanes, so a wave whose lanes are all beyond r_cut for a source
 // skips the read altogether.
-template <int LEVEL, bool UNI>
+template <int LEVEL, bool UNI, int BITS>
 __device__ __forceinline__ void pair_f32_r2(const float4 q, float px, float py, float pz,
                                             float smax, float smin, uint32_t shift,
                                             uint32_t boff, const unsigned char* __restrict__ tab,
                                             float& ax, float& ay, float& az) {
+    // row k of the table: (c0, c1) at 8 k, (c2, 0) at kC2 + 8 k (an
+    // immediate offset of the same address)
+    constexpr int kC2 = r2_plane_c2(BITS);
     const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
     if (r2 < smax) {
         // r2 >= +0, so the clamp below smin is an unsigned max of the bits
         const uint32_t sb = max(__float_as_uint(r2), __float_as_uint(smin));
         const float sc = __uint_as_float(sb);
-        // boff = -(row of 2^kR2Emin) * 4 mod 2^32: one shift-add per address
-        const float* c = reinterpret_cast<const float*>(tab + (((sb >> shift) << 2) + boff));
+        // boff = -(row of 2^kR2Emin) * 8 mod 2^32: one shift-add per address
+        const unsigned char* c = tab + (((sb >> shift) << 3) + boff);
+        const float2 c01 = *reinterpret_cast<const float2*>(c);
         float F;
         if constexpr (LEVEL == 1) {
-            F = fmaf(c[kR2Plane], sc, c[0]);
+            F = fmaf(c01.y, sc, c01.x);
         } else {
-            F = fmaf(fmaf(c[2 * kR2Plane], sc, c[kR2Plane]), sc, c[0]);
+            F = fmaf(fmaf(*reinterpret_cast<const float*>(c + kC2), sc, c01.y), sc, c01.x);
         }
         // UNI: the j leaf's sources share one mass, applied once per leaf
         const float g = UNI ? F : q.w * F;
@@ -267,7 +271,7 @@ __device__ __forceinline__ void pair_f32_r2(const float4 q, float px, float py, 
 
 // The pairs of one j leaf in the float32 r^2 form: four sources per 64-byte
 // scalar load, ahead of the masked table reads.
-template <int LEVEL, bool UNI>
+template <int LEVEL, bool UNI, int BITS>
 __device__ __forceinline__ void leaf_f32_r2(const float4* __restrict__ src, int nj, uint64_t live,
                                             float px, float py, float pz, float smax,
                                             float smin, uint32_t shift, uint32_t boff,
@@ -282,12 +286,13 @@ __device__ __forceinline__ void leaf_f32_r2(const float4* __restrict__ src, int 
 #pragma unroll
         for (int u = 0; u < 4; ++u)
             if (g4 & (1u << u))
-                pair_f32_r2<LEVEL, UNI>(b.v[u], px, py, pz, smax, smin, shift, boff, tab, ax, ay,
-                                        az);
+                pair_f32_r2<LEVEL, UNI, BITS>(b.v[u], px, py, pz, smax, smin, shift, boff, tab, ax,
+                                              ay, az);
     }
     for (; k < nj; ++k)
         if ((live >> k) & 1u)
-            pair_f32_r2<LEVEL, UNI>(src[k], px, py, pz, smax, smin, shift, boff, tab, ax, ay, az);
+            pair_f32_r2<LEVEL, UNI, BITS>(src[k], px, py, pz, smax, smin, shift, boff, tab, ax, ay,
+                                          az);
 }
 
 // float64 r^2 table (not the paper's table; host builder in abi.cpp): the
@@ -400,8 +405,8 @@ __device__ __forceinline__ void leaf_f64_r2(const double4* __restrict__ src, int
 
 // LDS table layouts (bytes), matching the host builder in abi.cpp:
 //   float64 r^2 table: double c0 .. c(NC-1) per row [16 2^bits rows]
-//   float32 r^2 table: float c0 [kR2Plane], c1 [kR2Plane], c2 [kR2Plane]
-//                      (rows (kR2Emax - kR2Emin) 2^bits + 1 <= kR2Plane)
+//   float32 r^2 table: float2 (c0, c1) [r2_rows(bits)] at 0, then
+//                      float2 (c2, 0) [r2_rows(bits)] at r2_plane_c2(bits)
 //   float32: float4 c0..c3 [n_tab + 1], then float c4 [n_tab + 1]
 //   float64: double2 (c0, c1) [n_tab], double2 (c2, c3) [n_tab], double c4 [n_tab]
 __device__ __forceinline__ void load_table(unsigned char* lds, const void* __restrict__ table,
@@ -412,7 +417,7 @@ __device__ __forceinline__ void load_table(unsigned char* lds, const void* __res
     __syncthreads();
 }
 
-template <int MODE, int LEVEL, bool ACC32>
+template <int MODE, int LEVEL, bool ACC32, int BITS>
 __global__ void __launch_bounds__(p2p_max_threads(MODE), p2p_min_waves_per_simd(MODE))
 p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
            const int4* __restrict__ leaf, const double4* __restrict__ leafc,
@@ -457,10 +462,11 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
             const float rnd = round_floor ? 0.f : 0.5f;
             const float4* t03 = reinterpret_cast<const float4*>(lds);
             const float* t4 = reinterpret_cast<const float*>(lds + 16 * (n_tab + 1));
-            // r^2 table: n_tab = segments per octave = 2^bits
+            // r^2 table: n_tab = segments per octave = 2^bits (runtime values,
+            // so that the address is one shift and one shift-add)
             const uint32_t r2bits = 31u - (uint32_t)__builtin_clz((uint32_t)n_tab);
             const uint32_t r2shift = 23u - r2bits;
-            const uint32_t r2boff = 0u - (((uint32_t)(127 + kR2Emin) << r2bits) << 2);
+            const uint32_t r2boff = 0u - (((uint32_t)(127 + kR2Emin) << r2bits) << 3);
             // box of the wave's targets in their leaf's frame (lanes past
             // the leaf repeat target 0)
             float3 lo = make_float3(pv.x, pv.y, pv.z), hi = lo;
@@ -502,15 +508,15 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                     // every source of the j leaf has mass cj.w (the gather
                     // marks such leaves): one multiplication per leaf
                     // instead of one per pair
-                    leaf_f32_r2<LEVEL, true>(src, nj, live, px, py, pz, rc2, tiny, r2shift,
-                                             r2boff, lds, fx, fy, fz);
+                    leaf_f32_r2<LEVEL, true, BITS>(src, nj, live, px, py, pz, rc2, tiny, r2shift,
+                                                   r2boff, lds, fx, fy, fz);
                     const float mu = (float)cj.w;
                     fx *= mu;
                     fy *= mu;
                     fz *= mu;
                 } else {
-                    leaf_f32_r2<LEVEL, false>(src, nj, live, px, py, pz, rc2, tiny, r2shift,
-                                              r2boff, lds, fx, fy, fz);
+                    leaf_f32_r2<LEVEL, false, BITS>(src, nj, live, px, py, pz, rc2, tiny, r2shift,
+                                                    r2boff, lds, fx, fy, fz);
                 }
                 if constexpr (ACC32) {
                     two_sum(s32.x, c32.x, fx);
@@ -702,27 +708,39 @@ __global__ void zero_i32_kernel(int32_t* p, int32_t n) {
     if (i < n) p[i] = 0;
 }
 
-template <int MODE, int LEVEL>
+template <int MODE, int LEVEL, int BITS = 0>
 hipError_t launch_one(const P2PArgs& a, int wg_waves, int grid_wgs, size_t lds, hipStream_t s) {
     const int tb = (int)lds;
     // the compensated float32 sums are a variant of the float32 kernels only
     if (is_fp32(MODE) && a.accum32)
-        hipLaunchKernelGGL((p2p_kernel<MODE, LEVEL, is_fp32(MODE)>), dim3(grid_wgs),
+        hipLaunchKernelGGL((p2p_kernel<MODE, LEVEL, is_fp32(MODE), BITS>), dim3(grid_wgs),
                            dim3(64 * wg_waves), lds, s, a.x64, a.x32, a.leaf, a.leafc, a.p2p_js,
                            a.items, a.queue, a.n_items, a.counter, a.partial, a.boxes, a.table,
                            a.n_tab, tb, a.round_floor);
     else
-        hipLaunchKernelGGL((p2p_kernel<MODE, LEVEL, false>), dim3(grid_wgs), dim3(64 * wg_waves),
-                           lds, s, a.x64, a.x32, a.leaf, a.leafc, a.p2p_js, a.items, a.queue,
-                           a.n_items, a.counter, a.partial, a.boxes, a.table, a.n_tab, tb,
-                           a.round_floor);
+        hipLaunchKernelGGL((p2p_kernel<MODE, LEVEL, false, BITS>), dim3(grid_wgs),
+                           dim3(64 * wg_waves), lds, s, a.x64, a.x32, a.leaf, a.leafc, a.p2p_js,
+                           a.items, a.queue, a.n_items, a.counter, a.partial, a.boxes, a.table,
+                           a.n_tab, tb, a.round_floor);
     return hipGetLastError();
+}
+
+// The float32 r^2 form at its segments per octave (n_tab = 2^BITS).
+template <int LEVEL>
+hipError_t launch_r2(const P2PArgs& a, int wg_waves, int grid_wgs, size_t lds, hipStream_t s) {
+    switch (a.n_tab) {
+        case 16: return launch_one<kFP32R2, LEVEL, 4>(a, wg_waves, grid_wgs, lds, s);
+        case 32: return launch_one<kFP32R2, LEVEL, 5>(a, wg_waves, grid_wgs, lds, s);
+        case 64: return launch_one<kFP32R2, LEVEL, 6>(a, wg_waves, grid_wgs, lds, s);
+        case 128: return launch_one<kFP32R2, LEVEL, 7>(a, wg_waves, grid_wgs, lds, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int MODE, int LEVEL>
 int occ_one(int wg_waves, size_t lds) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, p2p_kernel<MODE, LEVEL, false>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, p2p_kernel<MODE, LEVEL, false, MODE == kFP32R2 ? 6 : 0>,
                                                      64 * wg_waves, lds) != hipSuccess)
         return 1;
     return blocks > 0 ? blocks : 1;
@@ -745,8 +763,8 @@ hipError_t launch_p2p(int mode, const P2PArgs& a, int wg_waves, int grid_wgs, si
                 default: return launch_one<kFP32Table, 4>(a, wg_waves, grid_wgs, lds, s);
             }
         case kFP32R2:
-            if (a.level == 1) return launch_one<kFP32R2, 1>(a, wg_waves, grid_wgs, lds, s);
-            return launch_one<kFP32R2, 2>(a, wg_waves, grid_wgs, lds, s);
+            if (a.level == 1) return launch_r2<1>(a, wg_waves, grid_wgs, lds, s);
+            return launch_r2<2>(a, wg_waves, grid_wgs, lds, s);
         case kFP64R2:
             switch (a.level) {
                 case 4: return launch_one<kFP64R2, 4>(a, wg_waves, grid_wgs, lds, s);

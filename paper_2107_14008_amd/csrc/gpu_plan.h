@@ -73,6 +73,8 @@ struct DevPlan {
     // the P2P rows
     DevBuf rowcnt_m2l, tile_sums_m2l, longrows_m2l;
     hipEvent_t fork_ev = nullptr, m2l_done = nullptr;
+    // the particle records gathered on the side stream
+    hipEvent_t geom_ev = nullptr, gather_ev = nullptr;
     // cells the level loop partitions, by depth (loop_cells holds them);
     // n_froots subtrees finished in one launch (0: the loop does every level)
     std::vector<int32_t> loop_depth_begin;
@@ -93,9 +95,9 @@ struct DevPlan {
     void release_all() {
         if (host_rb) (void)hipHostFree(host_rb);
         host_rb = nullptr;
-        for (hipEvent_t* e : {&fork_ev, &m2l_done})
+        for (hipEvent_t* e : {&fork_ev, &m2l_done, &geom_ev, &gather_ev})
             if (*e) (void)hipEventDestroy(*e);
-        fork_ev = m2l_done = nullptr;
+        fork_ev = m2l_done = geom_ev = gather_ev = nullptr;
         for (DevBuf* b : {&rowcnt_m2l, &tile_sums_m2l, &longrows_m2l}) b->release();
         for (DevBuf* b : {&perm, &leaf, &leafc, &js, &items, &queue, &leaf_slot, &partial, &counter,
                           &boxes, &table, &x64, &x32, &stage_pos, &stage_mass, &far, &cell,

@@ -1400,7 +1400,23 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     TRY(d.x32.ensure(n * 16));
     GatherArgs g{pos, mass, d.perm.as<int32_t>(), d.leaf.as<int4>(), d.leafc.as<double4>(),
                  d.boxes.as<BoxDev>(), d.x64.as<double4>(), d.x32.as<float4>(), (int32_t)nl};
-    TRY(launch_gather(g, nullptr, s));
+    // With a side stream the particle records are gathered there, beside the
+    // walk (which reads only the cells); s waits for them before the build
+    // returns (and before any early return).
+    const bool side_gather = side != nullptr && side != s;
+    if (side_gather) {
+        for (hipEvent_t* e : {&d.geom_ev, &d.gather_ev})
+            if (!*e) TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
+        TRY(hipEventRecord(d.geom_ev, s));
+        TRY(hipStreamWaitEvent(side, d.geom_ev, 0));
+        TRY(launch_gather(g, nullptr, side));
+        TRY(hipEventRecord(d.gather_ev, side));
+    } else {
+        TRY(launch_gather(g, nullptr, s));
+    }
+    auto join_gather = [&]() -> hipError_t {
+        return side_gather ? hipStreamWaitEvent(s, d.gather_ev, 0) : hipSuccess;
+    };
 
     clk.lap("records");
     // ---- dual walk
@@ -1543,6 +1559,8 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         TRY(hipMemcpyAsync(flags, d.wcount.p, 12, hipMemcpyDeviceToHost, s));
         TRY(hipStreamSynchronize(s));
     }
+    if (flags[0] != 0x7fffffff || flags[1] != 0x7fffffff || (flags[2] != 0 && !d.force64))
+        TRY(join_gather());
     if (flags[0] != 0x7fffffff) {
         *input_error = "non-finite position at particle " + std::to_string(flags[0]);
         return std::string();
@@ -1660,6 +1678,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     }
     TRY(finish_rows(p2p_rows, s));
     if (fork) TRY(hipStreamWaitEvent(s, d.m2l_done, 0));
+    TRY(join_gather());
     out.n_p2p = n_p2p;
     out.n_m2l = n_m2l;
     clk.lap("csr");

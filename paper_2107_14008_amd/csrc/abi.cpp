@@ -225,18 +225,32 @@ std::vector<unsigned char> build_r2_table(int per_octave, int deg, double xc) {
 // c2; the row after the last (s = 2^kR2Emax) is zero.
 std::vector<unsigned char> build_adj_table(double xc) {
     const double kappa = xc * xc / std::ldexp(1.0, pmfmm::kR2Emax);
-    std::vector<unsigned char> out((size_t)24 * pmfmm::kAdjPlane + 16, 0);
-    float* f = reinterpret_cast<float*>(out.data());
+    // six planes (g c0 c1 c2, h c0 c1 c2) fitted, then stored as three arrays
+    // of float pairs by row: (g c0, g c1), (h c0, h c1), (g c2, h c2), each
+    // kAdjPlane pairs long, so a lookup is three 8-byte reads from one
+    // address at immediate offsets
+    std::vector<float> f((size_t)6 * pmfmm::kAdjPlane, 0.0f);
     fit_r2_rows(pmfmm::kAdjBits, pmfmm::kAdjEmin, 2,
                 [&](double sv) { return truncation_T(std::sqrt(sv * kappa)) * std::pow(sv, -1.5); },
-                f, pmfmm::kAdjPlane);
+                f.data(), pmfmm::kAdjPlane);
     fit_r2_rows(pmfmm::kAdjBits, pmfmm::kAdjEmin, 2,
                 [&](double sv) {
                     const double x = std::sqrt(sv * kappa);
                     return -(3.0 * truncation_T(x) + 2.25675833419102514780 * x * x * x * std::exp(-x * x)) *
                            std::pow(sv, -2.5);
                 },
-                f + 3 * (size_t)pmfmm::kAdjPlane, pmfmm::kAdjPlane);
+                f.data() + 3 * (size_t)pmfmm::kAdjPlane, pmfmm::kAdjPlane);
+    std::vector<unsigned char> out((size_t)pmfmm::kAdjTableBytes + 16, 0);
+    float* o = reinterpret_cast<float*>(out.data());
+    const size_t P = pmfmm::kAdjPlane;
+    for (size_t k = 0; k < P; ++k) {
+        o[2 * k] = f[k];                       // g c0
+        o[2 * k + 1] = f[P + k];               // g c1
+        o[2 * P + 2 * k] = f[3 * P + k];       // h c0
+        o[2 * P + 2 * k + 1] = f[4 * P + k];   // h c1
+        o[4 * P + 2 * k] = f[2 * P + k];       // g c2
+        o[4 * P + 2 * k + 1] = f[5 * P + k];   // h c2
+    }
     return out;
 }
 

@@ -64,8 +64,9 @@ constexpr int r2_table_bytes(int bits) { return (r2_plane_c2(bits) + r2_rows(bit
 static_assert(r2_rows(7) <= kR2Plane, "r^2 table rows");
 static_assert(r2_plane_c2(7) < 65536, "the c2 plane offset is an LDS read's immediate");
 // Adjoint of the float32 r^2 form: g(s) and h(s) over s in
-// [2^kAdjEmin, 2^kR2Emax), six planes (g c0 c1 c2, h c0 c1 c2) of kAdjPlane
-// floats at 2^kAdjBits segments per octave.  The floor sits above
+// [2^kAdjEmin, 2^kR2Emax) at 2^kAdjBits segments per octave, as three
+// arrays of kAdjPlane float pairs by row: (g c0, g c1), (h c0, h c1),
+// (g c2, h c2).  The floor sits above
 // kR2Emin because h's quadratic coefficient grows as s^(-9/2) and must stay
 // a finite float.
 constexpr int kAdjBits = 5;

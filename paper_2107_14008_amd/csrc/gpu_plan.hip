@@ -197,8 +197,9 @@ __global__ void k_cells_level(const int32_t* __restrict__ level, int nd, const i
 }
 
 // Left marks of the particles of the cells splitting at this level (sax[c]
-// >= 0), from their positions in the split axis's list.  Marks are bytes
-// indexed by particle: the level's random reads of them then stay in L2.
+// >= 0), from their positions in the split axis's list, as bytes indexed by
+// particle (a byte store needs no atomic); k_pack_marks then packs them
+// into bits for the level's random reads.
 __global__ void k_flag(int64_t n, const int32_t* __restrict__ pc, const int4* __restrict__ cell,
                        const int32_t* __restrict__ sax, const uint32_t* __restrict__ plist,
                        uint8_t* __restrict__ flag) {
@@ -213,24 +214,37 @@ __global__ void k_flag(int64_t n, const int32_t* __restrict__ pc, const int4* __
 
 // The stable partition of one level, with the left marks of the three lists
 // (3n positions, list a at [a n, (a + 1) n)) computed where they are used
-// instead of stored: a position's mark is flag[particle] if its cell splits
-// at this level, else 0.  Tiles of 4096 positions: k_level_sums counts each
-// tile's marks; k_level_firsts gives the count of marks before each
-// splitting cell's first position of each list, and k_level_move the count
-// before every position (the tiles before its own, summed where they are
-// needed, + the in-tile scan) and from it the position's destination.
+// instead of stored: a position's mark is its particle's left mark if its
+// cell splits at this level, else 0.  Tiles of 4096 positions: k_level_sums
+// counts each tile's marks; k_level_firsts gives the count of marks before
+// each splitting cell's first position of each list, and k_level_move the
+// count before every position (the tiles before its own, summed where they
+// are needed, + the in-tile scan) and from it the position's destination.
 constexpr int kLvThreads = 256;
 constexpr int kLvRounds = 16;
 constexpr int kLvTile = kLvThreads * kLvRounds;   // 4096
 
+// The particles' left marks as bits: k_flag writes one byte per particle of
+// a splitting cell (scattered by particle), and this packs the bytes of
+// particles [64 w, 64 w + 64) into word w (one wavefront per word).  The
+// level's random reads by particle then fall on n / 8 bytes, which stay in
+// an XCD's 4 MB L2 up to tens of millions of particles; the bytes outgrow
+// it from about four million.
+__global__ void k_pack_marks(int64_t n, const uint8_t* __restrict__ flag,
+                             uint64_t* __restrict__ bits) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t b = __ballot(i < n && flag[i] != 0);
+    if ((threadIdx.x & 63) == 0 && i < n) bits[i >> 6] = b;
+}
+
 // sax[c]: the split axis of a cell that splits at this level, else -1.  On
 // the split axis's own list the mark follows from the position alone, so
-// only the two other lists read the particle's byte.
+// only the two other lists read the particle's bit.
 __device__ __forceinline__ uint32_t level_mark(int64_t q, int64_t n, const int32_t* __restrict__ pc,
                                                const int32_t* __restrict__ sax,
                                                const int4* __restrict__ cell,
                                                const uint32_t* __restrict__ plist,
-                                               const uint8_t* __restrict__ flag) {
+                                               const uint64_t* __restrict__ bits) {
     const int a = q >= n ? (q >= 2 * n ? 2 : 1) : 0;
     const int64_t i = q - (int64_t)a * n;
     const int c = pc[i];
@@ -240,19 +254,20 @@ __device__ __forceinline__ uint32_t level_mark(int64_t q, int64_t n, const int32
         const int4 ci = cell[c];
         return (i - ci.x < ci.y / 2) ? 1u : 0u;
     }
-    return (uint32_t)flag[plist[q]];
+    const uint32_t p = plist[q];
+    return (uint32_t)(bits[p >> 6] >> (p & 63u)) & 1u;
 }
 
 __global__ void __launch_bounds__(kLvThreads)
 k_level_sums(int64_t n, const int32_t* __restrict__ pc, const int32_t* __restrict__ sax,
              const int4* __restrict__ cell, const uint32_t* __restrict__ plist,
-             const uint8_t* __restrict__ flag, uint32_t* __restrict__ tile_sums) {
+             const uint64_t* __restrict__ bits, uint32_t* __restrict__ tile_sums) {
     __shared__ uint32_t wsum[kLvThreads / 64];
     const int64_t base = (int64_t)blockIdx.x * kLvTile;
     uint32_t c = 0;
     for (int r = 0; r < kLvRounds; ++r) {
         const int64_t q = base + r * kLvThreads + threadIdx.x;
-        if (q < 3 * n) c += level_mark(q, n, pc, sax, cell, plist, flag);
+        if (q < 3 * n) c += level_mark(q, n, pc, sax, cell, plist, bits);
     }
     for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
@@ -269,7 +284,7 @@ k_level_sums(int64_t n, const int32_t* __restrict__ pc, const int32_t* __restric
 __global__ void __launch_bounds__(256)
 k_level_firsts(const int32_t* __restrict__ level, int nd, int64_t n, const int4* __restrict__ cell,
                const int32_t* __restrict__ pc, const int32_t* __restrict__ sax,
-               const uint32_t* __restrict__ plist, const uint8_t* __restrict__ flag,
+               const uint32_t* __restrict__ plist, const uint64_t* __restrict__ bits,
                const uint32_t* __restrict__ tile_sums, int nc, int32_t* __restrict__ pfirst) {
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -282,7 +297,7 @@ k_level_firsts(const int32_t* __restrict__ level, int nd, int64_t n, const int4*
     // of its tile up to qf
     uint32_t cnt = 0;
     for (int64_t k = lane; k < tq; k += 64) cnt += tile_sums[k];
-    for (int64_t q = t0 + lane; q < qf; q += 64) cnt += level_mark(q, n, pc, sax, cell, plist, flag);
+    for (int64_t q = t0 + lane; q < qf; q += 64) cnt += level_mark(q, n, pc, sax, cell, plist, bits);
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off);
     if (lane == 0) pfirst[(size_t)a * nc + c] = (int32_t)cnt;
 }
@@ -291,7 +306,7 @@ __global__ void __launch_bounds__(kLvThreads)
 k_level_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __restrict__ pc_out,
              const int4* __restrict__ cell, const int4* __restrict__ aux,
              const int32_t* __restrict__ sax, const uint32_t* __restrict__ plist,
-             uint32_t* __restrict__ pout, const uint8_t* __restrict__ flag,
+             uint32_t* __restrict__ pout, const uint64_t* __restrict__ bits,
              const uint32_t* __restrict__ tile_sums, int nc, const int32_t* __restrict__ pfirst) {
     __shared__ uint8_t mk[kLvTile];
     __shared__ uint16_t pre[kLvTile];
@@ -316,7 +331,7 @@ k_level_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __restrict__ pc
         if (q < 3 * n) {
             pv[r] = plist[q];
             cv[r] = pc[q >= n ? (q >= 2 * n ? q - 2 * n : q - n) : q];
-            f = (uint8_t)level_mark(q, n, pc, sax, cell, plist, flag);
+            f = (uint8_t)level_mark(q, n, pc, sax, cell, plist, bits);
         }
         mk[r * kLvThreads + t] = f;
     }
@@ -1339,7 +1354,11 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     // ---- ORB levels
     TRY(d.pc.ensure(n * 4));
     TRY(d.pc_tmp.ensure(n * 4));
-    TRY(d.flag.ensure(n * 4));
+    // mark bytes at 0, mark bits at bits_off; k_orb_fused reuses the buffer
+    // for n int32
+    const int64_t bits_off = (n + 255) / 256 * 256;
+    TRY(d.flag.ensure(std::max<int64_t>(n * 4, bits_off + (n + 63) / 64 * 8)));
+    uint64_t* bits = reinterpret_cast<uint64_t*>(d.flag.as<uint8_t>() + bits_off);
     const int64_t lv_tiles = (3 * n + kLvTile - 1) / kLvTile;
     TRY(d.lv_first.ensure(3 * nc * 4));
     TRY(d.tile_sums.ensure(lv_tiles * 4 + 16));
@@ -1361,20 +1380,21 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         hipLaunchKernelGGL(k_flag, dim3(grid_of(n)), dim3(256), 0, s, n, d.pc.as<int32_t>(),
                            d.cell.as<int4>(), d.cell_axis.as<int32_t>(), d.plist.as<uint32_t>(),
                            d.flag.as<uint8_t>());
+        hipLaunchKernelGGL(k_pack_marks, dim3(grid_of(n)), dim3(256), 0, s, n,
+                           d.flag.as<uint8_t>(), bits);
         hipLaunchKernelGGL(k_level_sums, dim3(lv_tiles), dim3(kLvThreads), 0, s, n,
                            d.pc.as<int32_t>(), d.cell_axis.as<int32_t>(), d.cell.as<int4>(),
-                           d.plist.as<uint32_t>(), d.flag.as<uint8_t>(), d.tile_sums.as<uint32_t>());
+                           d.plist.as<uint32_t>(), bits, d.tile_sums.as<uint32_t>());
         TRY(hipGetLastError());
         hipLaunchKernelGGL(k_level_firsts, dim3((3 * ncd + 3) / 4), dim3(256), 0, s,
                            d.loop_cells.as<int32_t>() + c0, ncd, n, d.cell.as<int4>(),
                            d.pc.as<int32_t>(), d.cell_axis.as<int32_t>(), d.plist.as<uint32_t>(),
-                           d.flag.as<uint8_t>(), d.tile_sums.as<uint32_t>(), (int)nc,
-                           d.lv_first.as<int32_t>());
+                           bits, d.tile_sums.as<uint32_t>(), (int)nc, d.lv_first.as<int32_t>());
         hipLaunchKernelGGL(k_level_move, dim3(lv_tiles), dim3(kLvThreads), 0, s, n,
                            d.pc.as<int32_t>(), d.pc_tmp.as<int32_t>(), d.cell.as<int4>(),
                            d.cell_aux.as<int4>(), d.cell_axis.as<int32_t>(), d.plist.as<uint32_t>(),
-                           d.plist_tmp.as<uint32_t>(), d.flag.as<uint8_t>(),
-                           d.tile_sums.as<uint32_t>(), (int)nc, d.lv_first.as<int32_t>());
+                           d.plist_tmp.as<uint32_t>(), bits, d.tile_sums.as<uint32_t>(), (int)nc,
+                           d.lv_first.as<int32_t>());
         TRY(hipGetLastError());
         std::swap(d.plist, d.plist_tmp);
         std::swap(d.pc, d.pc_tmp);

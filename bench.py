@@ -44,8 +44,10 @@ from paper_2107_14008_amd import inputs  # noqa: E402
 #
 # float32 r^2 table of T / r^3 (headline): displacement 3, r^2 5, cutoff
 # test 1 per evaluated pair; inside r_cut clamp 1, segment index 2,
-# quadratic Horner in r^2 4, g = m F 1 and accumulation 6.
+# quadratic Horner in r^2 4, g = m F 1 and accumulation 6 (the linear
+# table: Horner 2, so 12).
 FLOPS_EVAL_F32_R2, FLOPS_INSIDE_F32_R2 = 9, 14
+FLOPS_INSIDE_F32_R2_LINEAR = 12
 # float32 Taylor table of Eq. (int) (T_[2], the paper's single-precision
 # form): every evaluated pair takes displacement 3, r^2 5, 1/r 1, table
 # coordinate 2, index and offset 2, Horner 4, m T / r^3 4, accumulation 6.
@@ -428,6 +430,8 @@ def main():
     ap.add_argument("--r2-per-octave", type=int, default=64,
                     help="segments per octave of r^2 of the headline float32 "
                          "table")
+    ap.add_argument("--r2-degree", type=int, default=2, choices=[1, 2],
+                    help="degree of the headline float32 table's segments")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
                     help="time the headline float32 form only (profiling)")
@@ -485,7 +489,7 @@ def main():
 
     forms = {
         "fp32": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2,
-                     table_size=args.r2_per_octave, table_level=2),
+                     table_size=args.r2_per_octave, table_level=args.r2_degree),
         "fp32_paper_table": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_TABLE,
                                  table_size=args.table_size,
                                  table_level=args.table_level,
@@ -551,13 +555,17 @@ def main():
         fe, fi, _ = FORM_FLOPS[form]
         return (evaluated * fe + inside * fi) / (ms / 1e3) / 1e12
 
+    # the committed counter summaries are of the default headline table
+    profiled = args.r2_degree == 2 and args.r2_per_octave == 64
+    if args.r2_degree == 1:
+        FORM_FLOPS["fp32"] = (FLOPS_EVAL_F32_R2, FLOPS_INSIDE_F32_R2_LINEAR, "fp32")
     rooflines = {}
     for k, v in results.items():
         prec = FORM_FLOPS[k][2]
         pub = PEAK_FP32_TFLOPS if prec == "fp32" else PEAK_FP64_TFLOPS
         meas = peak32 if prec == "fp32" else peak64
         tf = algo_tflops(k, v["p2p_ms"])
-        cf = counter_flops({"fp32": "p2p_fp32_r2_clustered_2m",
+        cf = counter_flops({"fp32": "p2p_fp32_r2_clustered_2m" if profiled else "-",
                             "fp64": "p2p_fp64_exact_clustered_2m"}.get(k, "-"))
         rooflines[k] = dict(
             value=cand / (v["ms_per_step"] / 1e3), ms_per_step=v["ms_per_step"],
@@ -595,8 +603,10 @@ def main():
             "inside_pairs_per_step": inside,
             "evaluated_pairs_per_step": evaluated,
             "fp32_form": f"float32 cell-relative pairs, T(r)/r^3 from a "
-                         f"table of quadratic segments over r^2 "
-                         f"({args.r2_per_octave} per octave), float64 accumulation",
+                         f"table of {'quadratic' if args.r2_degree == 2 else 'linear'} "
+                         f"segments over r^2 ({args.r2_per_octave} per octave"
+                         f"{'' if args.r2_degree == 2 else ', pairs below 2^-9.5 r_cut exact'}"
+                         f"), float64 accumulation",
             "fp32_paper_table_form": f"float32 cell-relative pairs, "
                                      f"{args.table_size}-node T_[{args.table_level}] "
                                      f"table of Eq. (int)",
@@ -611,9 +621,9 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": measured_traffic(),
+            "traffic": measured_traffic() if profiled else None,
             "traffic_unit": "B per launch",
-            "kernel": "p2p_kernel<FP32 r^2 table of T/r^3, degree 2>",
+            "kernel": f"p2p_kernel<FP32 r^2 table of T/r^3, degree {args.r2_degree}>",
             "flops": rooflines[head]["flops"],
             "kernel_ms": r32["p2p_ms"],
             "measured_peak": peak32,

@@ -97,10 +97,12 @@ typedef struct pmfmm_params {
     int32_t trunc;       /* PMFMM_TRUNC_EXACT, _TABLE or _R2                       */
     int32_t table_size;  /* TABLE: nodes on x in [0, 3], 16..2048 (FP64) or
                             16..4096 (FP32); R2: segments per octave of r^2,
-                            16, 32, 64 or 128 (FP32), 16, 32 or 64 (FP64)      */
+                            FP32 degree 2: 16, 32, 64 or 128; FP32 degree 1:
+                            64, 128, 256 or 512; FP64: 16, 32 or 64          */
     int32_t table_level; /* TABLE: Taylor terms kept, 0..4 (T_[0] .. T_[4]);
-                            R2: polynomial degree, FP32 2 (or 1 with >= 64
-                            segments per octave), FP64 4, 5 or 6             */
+                            R2: polynomial degree, FP32 2 or 1 (the linear
+                            table covers r >= 2^-9.5 r_cut; closer pairs are
+                            evaluated exactly), FP64 4, 5 or 6               */
     int32_t table_round; /* TABLE: PMFMM_ROUND_NEAREST or PMFMM_ROUND_FLOOR       */
     /* scheduling of the P2P work (no effect on results) */
     int32_t chunk;       /* j-leaves per work item, 0 = automatic                 */

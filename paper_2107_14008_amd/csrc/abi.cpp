@@ -64,12 +64,18 @@ bool valid_eval(const pmfmm_params& p, std::string& why) {
         return false;
     }
     if (p.trunc == PMFMM_TRUNC_R2 && p.precision == PMFMM_FP32) {
-        if (p.table_size != 16 && p.table_size != 32 && p.table_size != 64 && p.table_size != 128) {
-            why = "table_size (segments per octave) must be 16, 32, 64 or 128 for R2";
-            return false;
-        }
-        if (!(p.table_level == 2 || (p.table_level == 1 && p.table_size >= 64))) {
-            why = "table_level (degree) must be 2, or 1 with at least 64 segments per octave, for R2";
+        if (p.table_level == 2) {
+            if (p.table_size != 16 && p.table_size != 32 && p.table_size != 64 && p.table_size != 128) {
+                why = "table_size (segments per octave) must be 16, 32, 64 or 128 for the degree-2 R2 table";
+                return false;
+            }
+        } else if (p.table_level == 1) {
+            if (p.table_size != 64 && p.table_size != 128 && p.table_size != 256 && p.table_size != 512) {
+                why = "table_size (segments per octave) must be 64, 128, 256 or 512 for the degree-1 R2 table";
+                return false;
+            }
+        } else {
+            why = "table_level (degree) must be 1 or 2 for R2";
             return false;
         }
     }
@@ -197,9 +203,28 @@ void fit_r2_rows(int bits, int emin, int deg, Fn fn, float* f, size_t plane) {
 // at an immediate offset from the same address (measured 2 % faster than
 // three planes of floats read by a two-address and a one-address read, and
 // 7 % faster than one 16-byte-per-lane two-address read).
+//
+// Degree 1: rows of (c0, c1) over [2^kR2EminLin, 2^kR2Emax) after a zero
+// row (closer pairs: the kernel's exact pass) and before a zero row at
+// s = 2^kR2Emax, r2_rows_lin(bits) in all.
 std::vector<unsigned char> build_r2_table(int per_octave, int deg, double xc) {
-    const int bits = per_octave == 16 ? 4 : per_octave == 32 ? 5 : per_octave == 64 ? 6 : 7;
+    int bits = 4;
+    while ((1 << bits) < per_octave) ++bits;
     const double kappa = xc * xc / std::ldexp(1.0, pmfmm::kR2Emax);
+    if (deg == 1) {
+        const int rows = (pmfmm::kR2Emax - pmfmm::kR2EminLin) << bits;
+        std::vector<float> pl((size_t)2 * rows, 0.0f);
+        fit_r2_rows(bits, pmfmm::kR2EminLin, 1,
+                    [&](double sv) { return truncation_T(std::sqrt(sv * kappa)) * std::pow(sv, -1.5); },
+                    pl.data(), (size_t)rows);
+        std::vector<unsigned char> out((size_t)pmfmm::r2_table_bytes_lin(bits), 0);
+        float* a = reinterpret_cast<float*>(out.data());
+        for (int k = 0; k < rows; ++k) {
+            a[2 * (k + 1)] = pl[k];
+            a[2 * (k + 1) + 1] = pl[(size_t)rows + k];
+        }
+        return out;
+    }
     std::vector<float> pl((size_t)3 * pmfmm::kR2Plane, 0.0f);
     fit_r2_rows(bits, pmfmm::kR2Emin, deg,
                 [&](double sv) { return truncation_T(std::sqrt(sv * kappa)) * std::pow(sv, -1.5); },

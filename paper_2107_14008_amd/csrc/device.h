@@ -63,6 +63,16 @@ constexpr int r2_plane_c2(int bits) { return (r2_rows(bits) * 8 + 255) / 256 * 2
 constexpr int r2_table_bytes(int bits) { return (r2_plane_c2(bits) + r2_rows(bits) * 8 + 15) / 16 * 16; }
 static_assert(r2_rows(7) <= kR2Plane, "r^2 table rows");
 static_assert(r2_plane_c2(7) < 65536, "the c2 plane offset is an LDS read's immediate");
+// Linear (degree 1) float32 r^2 tables: rows of (c0, c1) only, over
+// [2^kR2EminLin, 2^kR2Emax) at up to 512 segments per octave, with a zero
+// row below the floor (the clamp maps every s under it there) and a zero
+// row at s = 2^kR2Emax; pairs closer than the floor (r < 2^-9.5 r_cut, a
+// few per million) are added by an exact pass instead.  Two 16-wave
+// workgroups per CU still fit their tables at 512 per octave.
+constexpr int kR2EminLin = kR2Emax - 19;
+constexpr int r2_rows_lin(int bits) { return ((kR2Emax - kR2EminLin) << bits) + 2; }
+constexpr int r2_table_bytes_lin(int bits) { return (r2_rows_lin(bits) * 8 + 15) / 16 * 16; }
+static_assert(2 * r2_table_bytes_lin(9) <= 160 * 1024, "two linear r^2 tables per CU");
 // Adjoint of the float32 r^2 form: g(s) and h(s) over s in
 // [2^kAdjEmin, 2^kR2Emax) at 2^kAdjBits segments per octave, as three
 // arrays of kAdjPlane float pairs by row: (g c0, g c1), (h c0, h c1),

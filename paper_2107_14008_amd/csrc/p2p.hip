@@ -269,14 +269,40 @@ __device__ __forceinline__ void pair_f32_r2(const float4 q, float px, float py, 
     }
 }
 
+// A pair of the linear r^2 form closer than its table's floor (0 < s <
+// sfloor; the main pass read the zero row for it): F from erfcf / expf, s
+// clamped below at tiny as in the quadratic form.  Coincident pairs (s = 0)
+// contribute nothing either way.
+template <bool UNI>
+__device__ __forceinline__ void pair_f32_close(const float4 q, float px, float py, float pz,
+                                               float sfloor, float tiny, float alpha, float& ax,
+                                               float& ay, float& az) {
+    const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    if (r2 < sfloor && r2 > 0.f) {
+        const float r2c = fmaxf(r2, tiny);
+        const float idr = __builtin_amdgcn_rsqf(r2c);
+        const float x = r2c * idr * alpha;
+        const float T = erfcf(x) + kTwoOverSqrtPiF * x * expf(-x * x);
+        const float g = (UNI ? 1.f : q.w) * T * (idr * idr * idr);
+        ax = fmaf(g, dx, ax);
+        ay = fmaf(g, dy, ay);
+        az = fmaf(g, dz, az);
+    }
+}
+
 // The pairs of one j leaf in the float32 r^2 form: four sources per 64-byte
-// scalar load, ahead of the masked table reads.
+// scalar load, ahead of the masked table reads.  With a linear table
+// (LEVEL 1), the sources in `near` (those that may come closer than the
+// table's floor to a target) then go through pair_f32_close.
 template <int LEVEL, bool UNI, int BITS>
 __device__ __forceinline__ void leaf_f32_r2(const float4* __restrict__ src, int nj, uint64_t live,
                                             float px, float py, float pz, float smax,
                                             float smin, uint32_t shift, uint32_t boff,
                                             const unsigned char* __restrict__ tab, float& ax,
-                                            float& ay, float& az) {
+                                            float& ay, float& az, uint64_t near = 0,
+                                            float sfloor = 0.f, float tiny = 0.f,
+                                            float alpha = 0.f) {
     int k = 0;
     for (; k + 4 <= nj; k += 4) {
         const uint32_t g4 = (uint32_t)(live >> k) & 0xFu;
@@ -293,6 +319,25 @@ __device__ __forceinline__ void leaf_f32_r2(const float4* __restrict__ src, int 
         if ((live >> k) & 1u)
             pair_f32_r2<LEVEL, UNI, BITS>(src[k], px, py, pz, smax, smin, shift, boff, tab, ax, ay,
                                           az);
+    if constexpr (LEVEL == 1) {
+        for (uint64_t m = near; m != 0; m &= m - 1)
+            pair_f32_close<UNI>(src[__builtin_ctzll(m)], px, py, pz, sfloor, tiny, alpha, ax, ay,
+                                az);
+    }
+}
+
+// live_f32's cull, plus the sources whose squared distance to the targets'
+// box is below near2 (in `near`).
+__device__ __forceinline__ uint64_t live_near_f32(const float4* __restrict__ src, int nj, int lane,
+                                                  float3 plo, float3 phi, float rc2, float near2,
+                                                  uint64_t& near) {
+    const float4 q = src[lane < nj ? lane : 0];
+    const float bx = fmaxf(fmaxf(plo.x - q.x, q.x - phi.x), 0.f);
+    const float by = fmaxf(fmaxf(plo.y - q.y, q.y - phi.y), 0.f);
+    const float bz = fmaxf(fmaxf(plo.z - q.z, q.z - phi.z), 0.f);
+    const float d2 = fmaf(bz, bz, fmaf(by, by, bx * bx));
+    near = __ballot((lane < nj) & (d2 < near2));
+    return __ballot((lane < nj) & (d2 < rc2));
 }
 
 // float64 r^2 table (not the paper's table; host builder in abi.cpp): the
@@ -407,6 +452,8 @@ __device__ __forceinline__ void leaf_f64_r2(const double4* __restrict__ src, int
 //   float64 r^2 table: double c0 .. c(NC-1) per row [16 2^bits rows]
 //   float32 r^2 table: float2 (c0, c1) [r2_rows(bits)] at 0, then
 //                      float2 (c2, 0) [r2_rows(bits)] at r2_plane_c2(bits)
+//   linear float32 r^2 table: float2 (c0, c1) [r2_rows_lin(bits)], the
+//                      first and the last row zero
 //   float32: float4 c0..c3 [n_tab + 1], then float c4 [n_tab + 1]
 //   float64: double2 (c0, c1) [n_tab], double2 (c2, c3) [n_tab], double c4 [n_tab]
 __device__ __forceinline__ void load_table(unsigned char* lds, const void* __restrict__ table,
@@ -466,7 +513,20 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
             // so that the address is one shift and one shift-add)
             const uint32_t r2bits = 31u - (uint32_t)__builtin_clz((uint32_t)n_tab);
             const uint32_t r2shift = 23u - r2bits;
-            const uint32_t r2boff = 0u - (((uint32_t)(127 + kR2Emin) << r2bits) << 3);
+            // the quadratic tables start at 2^kR2Emin; the linear ones have
+            // their zero row at the segment just below 2^kR2EminLin, which
+            // is where the clamp at smin (the float below the floor) puts
+            // every closer pair
+            constexpr bool kLin = MODE == kFP32R2 && LEVEL == 1;
+            const uint32_t r2boff =
+                kLin ? 0u - ((((uint32_t)(127 + kR2EminLin) << r2bits) - 1u) << 3)
+                     : 0u - (((uint32_t)(127 + kR2Emin) << r2bits) << 3);
+            const float sfloor = kLin ? __uint_as_float((uint32_t)(127 + kR2EminLin) << 23) : 0.f;
+            const float smin = kLin ? __uint_as_float(__float_as_uint(sfloor) - 1u) : tiny;
+            // a target closer than the floor to a source is within 2 sqrt(floor)
+            // of the targets' box (float32 rounding moves distances by ~1e-5
+            // of the floor's 2^-4)
+            const float near2 = 4.f * sfloor;
             // box of the wave's targets in their leaf's frame (lanes past
             // the leaf repeat target 0)
             float3 lo = make_float3(pv.x, pv.y, pv.z), hi = lo;
@@ -491,9 +551,11 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                 float fx = 0.f, fy = 0.f, fz = 0.f;
                 // targets in this frame: [lo - off, hi - off] per axis
                 // (exact: the shift is monotonic)
-                const uint64_t live =
-                    live_f32(src, nj, lane, make_float3(lo.x - offx, lo.y - offy, lo.z - offz),
-                             make_float3(hi.x - offx, hi.y - offy, hi.z - offz), rc2);
+                uint64_t near = 0;
+                const float3 blo = make_float3(lo.x - offx, lo.y - offy, lo.z - offz);
+                const float3 bhi = make_float3(hi.x - offx, hi.y - offy, hi.z - offz);
+                const uint64_t live = kLin ? live_near_f32(src, nj, lane, blo, bhi, rc2, near2, near)
+                                           : live_f32(src, nj, lane, blo, bhi, rc2);
                 if constexpr (MODE == kFP32Exact) {
                     for (int k = 0; k < nj; ++k)
                         if ((live >> k) & 1u)
@@ -508,15 +570,17 @@ p2p_kernel(const double4* __restrict__ x64, const float4* __restrict__ x32,
                     // every source of the j leaf has mass cj.w (the gather
                     // marks such leaves): one multiplication per leaf
                     // instead of one per pair
-                    leaf_f32_r2<LEVEL, true, BITS>(src, nj, live, px, py, pz, rc2, tiny, r2shift,
-                                                   r2boff, lds, fx, fy, fz);
+                    leaf_f32_r2<LEVEL, true, BITS>(src, nj, live, px, py, pz, rc2, smin, r2shift,
+                                                   r2boff, lds, fx, fy, fz, near, sfloor, tiny,
+                                                   bx.alpha_f);
                     const float mu = (float)cj.w;
                     fx *= mu;
                     fy *= mu;
                     fz *= mu;
                 } else {
-                    leaf_f32_r2<LEVEL, false, BITS>(src, nj, live, px, py, pz, rc2, tiny, r2shift,
-                                                    r2boff, lds, fx, fy, fz);
+                    leaf_f32_r2<LEVEL, false, BITS>(src, nj, live, px, py, pz, rc2, smin, r2shift,
+                                                    r2boff, lds, fx, fy, fz, near, sfloor, tiny,
+                                                    bx.alpha_f);
                 }
                 if constexpr (ACC32) {
                     two_sum(s32.x, c32.x, fx);
@@ -725,14 +789,24 @@ hipError_t launch_one(const P2PArgs& a, int wg_waves, int grid_wgs, size_t lds, 
     return hipGetLastError();
 }
 
-// The float32 r^2 form at its segments per octave (n_tab = 2^BITS).
+// The float32 r^2 form at its segments per octave (n_tab = 2^BITS): 16 to
+// 128 for the quadratic tables, 64 to 512 for the linear ones.
 template <int LEVEL>
 hipError_t launch_r2(const P2PArgs& a, int wg_waves, int grid_wgs, size_t lds, hipStream_t s) {
-    switch (a.n_tab) {
-        case 16: return launch_one<kFP32R2, LEVEL, 4>(a, wg_waves, grid_wgs, lds, s);
-        case 32: return launch_one<kFP32R2, LEVEL, 5>(a, wg_waves, grid_wgs, lds, s);
-        case 64: return launch_one<kFP32R2, LEVEL, 6>(a, wg_waves, grid_wgs, lds, s);
-        case 128: return launch_one<kFP32R2, LEVEL, 7>(a, wg_waves, grid_wgs, lds, s);
+    if constexpr (LEVEL == 1) {
+        switch (a.n_tab) {
+            case 64: return launch_one<kFP32R2, 1, 6>(a, wg_waves, grid_wgs, lds, s);
+            case 128: return launch_one<kFP32R2, 1, 7>(a, wg_waves, grid_wgs, lds, s);
+            case 256: return launch_one<kFP32R2, 1, 8>(a, wg_waves, grid_wgs, lds, s);
+            case 512: return launch_one<kFP32R2, 1, 9>(a, wg_waves, grid_wgs, lds, s);
+        }
+    } else {
+        switch (a.n_tab) {
+            case 16: return launch_one<kFP32R2, LEVEL, 4>(a, wg_waves, grid_wgs, lds, s);
+            case 32: return launch_one<kFP32R2, LEVEL, 5>(a, wg_waves, grid_wgs, lds, s);
+            case 64: return launch_one<kFP32R2, LEVEL, 6>(a, wg_waves, grid_wgs, lds, s);
+            case 128: return launch_one<kFP32R2, LEVEL, 7>(a, wg_waves, grid_wgs, lds, s);
+        }
     }
     return hipErrorInvalidValue;
 }

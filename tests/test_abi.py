@@ -77,10 +77,14 @@ def test_r2_table_is_a_float32_form():
                 dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_size=48,
                      table_level=2),
                 dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_size=32,
+                     table_level=1),
+                dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_size=256,
+                     table_level=2),
+                dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_size=1024,
                      table_level=1)):
         with pytest.raises(B.PmfmmError):
             B.Context(**bad)
-    for size, level in ((16, 2), (64, 2), (128, 1)):
+    for size, level in ((16, 2), (64, 2), (128, 1), (256, 1), (512, 1)):
         B.Context(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2, table_size=size,
                   table_level=level).close()
 

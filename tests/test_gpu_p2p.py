@@ -145,7 +145,7 @@ def test_fp32_table(c1, level, n_tab, rnd):
 
 
 @pytest.mark.parametrize("level,per_octave", [(2, 64), (1, 128), (2, 16),
-                                              (2, 32)])
+                                              (2, 32), (1, 256), (1, 512)])
 def test_fp32_r2_table(c1, level, per_octave):
     w, ref = c1
     print(f"case: uniform 32^3 fp32 r^2 table {per_octave}/octave degree "
@@ -174,6 +174,40 @@ def test_fp32_r2_table_clustered_and_coincident(clustered):
     ref2, _ = direct.all_pairs(pos, m, 20.0, 0.6, 2.7)
     assert np.all(np.isfinite(acc))
     check_fp32(acc, ref2)
+
+
+@pytest.mark.parametrize("equal_mass", [False, True])
+def test_fp32_r2_linear_close_pairs(equal_mass):
+    """The linear r^2 table stops at r = 2^-9.5 r_cut and adds closer pairs
+    exactly: pairs at 1e-4 .. 1e-2 r_cut (half of them below the floor) and
+    coincident pairs, against the quadratic table, which covers them down to
+    2^-17.5 r_cut with the same float32 displacements (so the two agree to
+    the tables' error even where float32 cannot resolve the displacement),
+    and against the exact float64 sum at the float32 tolerances away from
+    the close pairs.  Equal masses take the one-mass-per-leaf path."""
+    rng = np.random.default_rng(23)
+    box, r_s, r_cut = 20.0, 0.6, 2.7
+    base = rng.uniform(0, box, (1500, 3))
+    u = rng.normal(0, 1, (300, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    r = r_cut * 10.0 ** rng.uniform(-4, -2, (300, 1))
+    pos = inputs.wrap(np.concatenate([base, base[:300] + u * r, base[300:305]]), box)
+    m = np.ones(len(pos)) if equal_mass else rng.uniform(0.5, 1.5, len(pos))
+    print(f"case: fp32 r^2 linear 512/octave close pairs, equal mass {equal_mass}",
+          flush=True)
+    lin, _ = gpu_forward(pos, m, box, r_s, r_cut, 16, precision=B.PMFMM_FP32,
+                         trunc=B.TRUNC_R2, table_size=512, table_level=1)
+    quad, _ = gpu_forward(pos, m, box, r_s, r_cut, 16, precision=B.PMFMM_FP32,
+                          trunc=B.TRUNC_R2, table_size=64, table_level=2)
+    assert np.all(np.isfinite(lin))
+    e = metrics.error_summary(lin, quad)
+    assert e["max"] <= 1e-4, e
+    ref, _ = direct.brute_force(pos, m, box, r_s, r_cut)
+    far = np.ones(len(pos), bool)
+    far[:300] = False
+    far[1500:] = False
+    far[300:305] = False
+    check_fp32(lin[far], ref[far])
 
 
 def test_fp32_exact_and_table_clustered(clustered):

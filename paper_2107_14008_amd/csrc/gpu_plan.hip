@@ -766,6 +766,73 @@ constexpr int kWalkT = 1024;
 // frontiers up to this size go to the one-workgroup top of the walk
 constexpr uint32_t kWalkTopMax = 4 * kWalkT;
 
+// Appends one group's outputs (a WalkOut per thread of the workgroup): the
+// keys to the key arrays and the child pairs to `next` at slots reserved
+// from *next_count, or, with `lch`, to that workgroup-local array from 0.
+// One atomic per counter per group.  Returns the group's child count.
+__device__ __forceinline__ uint32_t walk_emit(const WalkOut& o, int2* __restrict__ next,
+                                              uint32_t* __restrict__ next_count,
+                                              uint32_t cap_front, int2* lch,
+                                              uint32_t* __restrict__ ctl, uint32_t cap_p2p,
+                                              uint32_t cap_m2l, uint64_t* __restrict__ p2p_keys,
+                                              uint64_t* __restrict__ m2l_keys, uint64_t* wtot,
+                                              uint32_t* bbase) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // packed counts: children (<= 4096 per group) | p2p << 16 | m2l << 32
+    const uint64_t v = (uint64_t)o.n_child | ((uint64_t)o.n_p2p << 16) |
+                       ((uint64_t)o.n_m2l << 32);
+    uint64_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wtot[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t run = 0;
+        for (int w = 0; w < kWalkT / 64; ++w) {
+            const uint64_t tw = wtot[w];
+            wtot[w] = run;
+            run += tw;
+        }
+        const uint32_t tc = (uint32_t)(run & 0xffffu), tp = (uint32_t)((run >> 16) & 0xffffu),
+                       tm = (uint32_t)(run >> 32);
+        bbase[0] = (tc != 0 && lch == nullptr) ? atomicAdd(next_count, tc) : 0u;
+        bbase[1] = tp ? atomicAdd(&ctl[0], tp) : 0u;
+        bbase[2] = tm ? atomicAdd(&ctl[1], tm) : 0u;
+        bbase[3] = tc;
+    }
+    __syncthreads();
+    const uint64_t off = wtot[wave] + x - v;
+    const uint32_t cslot = bbase[0] + (uint32_t)(off & 0xffffu);
+    const uint32_t pslot = bbase[1] + (uint32_t)((off >> 16) & 0xffffu);
+    const uint32_t mslot = bbase[2] + (uint32_t)(off >> 32);
+    // (fixed trip counts: the WalkOut arrays stay in registers)
+    if (lch != nullptr) {
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q)
+            if (q < o.n_child) lch[cslot + q] = o.child[q];
+    } else if (cslot + o.n_child <= cap_front) {
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q)
+            if (q < o.n_child) next[cslot + q] = o.child[q];
+    } else if (o.n_child) {
+        ctl[2] = 1u;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < 2; ++q) {
+        if (q < o.n_p2p) {
+            if (pslot + q < cap_p2p) p2p_keys[pslot + q] = o.key[q]; else ctl[2] = 1u;
+        }
+        if (q < o.n_m2l) {
+            if (mslot + q < cap_m2l) m2l_keys[mslot + q] = o.key[q]; else ctl[2] = 1u;
+        }
+    }
+    const uint32_t tc = bbase[3];
+    __syncthreads();   // wtot, bbase (and lch, for its readers) are reused next
+    return tc;
+}
+
 // One level's share of workgroup `blk` of `nblk` (nf pairs in front).
 // Returns false when the frontier is beyond its capacity.
 __device__ __forceinline__ bool walk_level(const int2* __restrict__ front, int2* __restrict__ next,
@@ -778,67 +845,69 @@ __device__ __forceinline__ bool walk_level(const int2* __restrict__ front, int2*
                                            uint64_t* __restrict__ m2l_keys, uint64_t* wtot,
                                            uint32_t* bbase) {
     if (nf > cap_front) return false;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t stride = nblk * blockDim.x;
     for (uint32_t base = blk * blockDim.x; base < nf; base += stride) {
         const uint32_t k = base + threadIdx.x;
         WalkOut o{0u, 0u, 0u, {}, {0ull, 0ull}};
         if (k < nf) walk_classify(front[k], wbox, wcell, ks, o);
-        // packed counts: children (<= 4096 per group) | p2p << 16 | m2l << 32
-        const uint64_t v = (uint64_t)o.n_child | ((uint64_t)o.n_p2p << 16) |
-                           ((uint64_t)o.n_m2l << 32);
-        uint64_t x = v;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint64_t y = __shfl_up(x, off);
-            if (lane >= off) x += y;
-        }
-        if (lane == 63) wtot[wave] = x;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint64_t run = 0;
-            for (int w = 0; w < kWalkT / 64; ++w) {
-                const uint64_t tw = wtot[w];
-                wtot[w] = run;
-                run += tw;
-            }
-            const uint32_t tc = (uint32_t)(run & 0xffffu), tp = (uint32_t)((run >> 16) & 0xffffu),
-                           tm = (uint32_t)(run >> 32);
-            bbase[0] = tc ? atomicAdd(&sizes[it + 1], tc) : 0u;
-            bbase[1] = tp ? atomicAdd(&ctl[0], tp) : 0u;
-            bbase[2] = tm ? atomicAdd(&ctl[1], tm) : 0u;
-        }
-        __syncthreads();
-        const uint64_t off = wtot[wave] + x - v;
-        const uint32_t cslot = bbase[0] + (uint32_t)(off & 0xffffu);
-        const uint32_t pslot = bbase[1] + (uint32_t)((off >> 16) & 0xffffu);
-        const uint32_t mslot = bbase[2] + (uint32_t)(off >> 32);
-        if (cslot + o.n_child <= cap_front) {
-            for (uint32_t q = 0; q < o.n_child; ++q) next[cslot + q] = o.child[q];
-        } else if (o.n_child) {
-            ctl[2] = 1u;
-        }
-        for (uint32_t q = 0; q < o.n_p2p; ++q) {
-            if (pslot + q < cap_p2p) p2p_keys[pslot + q] = o.key[q]; else ctl[2] = 1u;
-        }
-        for (uint32_t q = 0; q < o.n_m2l; ++q) {
-            if (mslot + q < cap_m2l) m2l_keys[mslot + q] = o.key[q]; else ctl[2] = 1u;
-        }
-        __syncthreads();   // wtot and bbase are reused by the next group
+        (void)walk_emit(o, next, &sizes[it + 1], cap_front, nullptr, ctl, cap_p2p, cap_m2l,
+                        p2p_keys, m2l_keys, wtot, bbase);
     }
     if (blk == 0 && threadIdx.x == 0) atomicMax(&ctl[3], nf);
     return true;
 }
 
+// kWalkDepth levels of the walk per launch: each workgroup classifies a
+// group of level `it`, keeps the group's child pairs (at most four per
+// pair) in LDS and classifies them in turn, and so on; only the pairs of
+// level it + kWalkDepth go to `next`.  The descendants of a pair depend on
+// that pair alone, so the middle levels need no other workgroup's results:
+// fewer launches, and the middle levels' pairs never go through global
+// memory.  sizes[it + 1 ..] count the middle levels (for the next build's
+// sizing).  Two levels per launch took the 128^3 walk from 0.55 to 0.33 ms;
+// three took 0.37 ms (the deeper a workgroup's subtree, the more the
+// workgroups' shares differ).
+constexpr int kWalkDepth = 2;
+
 __global__ void __launch_bounds__(kWalkT)
-k_walk_dev(const int2* __restrict__ front, int2* __restrict__ next, int it,
-           uint32_t* __restrict__ sizes, uint32_t* __restrict__ ctl, uint32_t cap_front,
-           uint32_t cap_p2p, uint32_t cap_m2l, const WalkBox* __restrict__ wbox,
-           const WalkCell* __restrict__ wcell, int2 ks, uint64_t* __restrict__ p2p_keys,
-           uint64_t* __restrict__ m2l_keys) {
+k_walk_multi(const int2* __restrict__ front, int2* __restrict__ next, int it,
+            uint32_t* __restrict__ sizes, uint32_t* __restrict__ ctl, uint32_t cap_front,
+            uint32_t cap_p2p, uint32_t cap_m2l, const WalkBox* __restrict__ wbox,
+            const WalkCell* __restrict__ wcell, int2 ks, uint64_t* __restrict__ p2p_keys,
+            uint64_t* __restrict__ m2l_keys) {
     __shared__ uint64_t wtot[kWalkT / 64];
-    __shared__ uint32_t bbase[3];
-    (void)walk_level(front, next, it, sizes[it], blockIdx.x, gridDim.x, sizes, ctl, cap_front,
-                     cap_p2p, cap_m2l, wbox, wcell, ks, p2p_keys, m2l_keys, wtot, bbase);
+    __shared__ uint32_t bbase[4];
+    __shared__ int2 lch[kWalkDepth - 1][4 * kWalkT];
+    const uint32_t nf = sizes[it];
+    if (nf > cap_front) return;
+    // classifies the pairs [r, r + blockDim) of src (n pairs) of level
+    // it + d and appends their children to lch[d] (or, at the last level,
+    // to next); returns the children kept in lch[d]
+    auto step = [&](const int2* src, uint32_t r, uint32_t n, int d) -> uint32_t {
+        const uint32_t j = r + threadIdx.x;
+        WalkOut o{0u, 0u, 0u, {}, {0ull, 0ull}};
+        if (j < n) walk_classify(src[j], wbox, wcell, ks, o);
+        const bool last = d == kWalkDepth - 1;
+        const uint32_t nch = walk_emit(o, next, &sizes[it + kWalkDepth], cap_front,
+                                       last ? nullptr : lch[d], ctl, cap_p2p, cap_m2l, p2p_keys,
+                                       m2l_keys, wtot, bbase);
+        if (last) return 0u;
+        if (threadIdx.x == 0 && nch != 0) atomicAdd(&sizes[it + 1 + d], nch);
+        return nch;
+    };
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < nf; base += stride) {
+        const uint32_t n1 = step(front, base, nf, 0);
+        for (uint32_t r1 = 0; r1 < n1; r1 += blockDim.x) {
+            if constexpr (kWalkDepth == 2) {
+                (void)step(lch[0], r1, n1, 1);
+            } else {
+                const uint32_t n2 = step(lch[0], r1, n1, 1);
+                for (uint32_t r2 = 0; r2 < n2; r2 += blockDim.x) (void)step(lch[1], r2, n2, 2);
+            }
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&ctl[3], nf);
 }
 
 // The first frontier (each box's root against itself with the zero shift and
@@ -854,7 +923,7 @@ k_walk_top(int nbox, const int32_t* __restrict__ box_root, int2* __restrict__ bu
            const WalkBox* __restrict__ wbox, const WalkCell* __restrict__ wcell, int2 ks,
            uint64_t* __restrict__ p2p_keys, uint64_t* __restrict__ m2l_keys) {
     __shared__ uint64_t wtot[kWalkT / 64];
-    __shared__ uint32_t bbase[3];
+    __shared__ uint32_t bbase[4];
     const uint32_t nf0 = (uint32_t)(14 * nbox);
     for (uint32_t q = threadIdx.x; q < nf0; q += blockDim.x) {
         const int b = (int)(q / 14), j = (int)(q - 14 * (uint32_t)b);
@@ -1467,53 +1536,57 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         TRY(d.front_next.ensure((size_t)capf * 8));
         TRY(d.p2p_keys.ensure((size_t)capp * 8));
         TRY(d.m2l_keys.ensure((size_t)std::max<uint32_t>(capm, 1) * 8));
-        TRY(d.walk_ctl.ensure((size_t)(L + 8) * 4));
-        hipLaunchKernelGGL(k_zero_u32, dim3((L + 8 + 255) / 256), dim3(256), 0, s,
-                           d.walk_ctl.as<uint32_t>(), L + 8);
-        uint32_t* ctl = d.walk_ctl.as<uint32_t>();
-        uint32_t* sizes = ctl + 4;
         DevBuf* bufs[2] = {&d.front, &d.front_next};
         // the top levels in one workgroup while the last build's frontiers
-        // were small (any size is handled; this only chooses the split)
+        // were small (any size is handled; this only chooses the split),
+        // then kWalkDepth levels per launch up to level Le >= L
         int top = 0;
         while (top < L && top < (int)d.walk_sizes.size() && d.walk_sizes[top] <= kWalkTopMax) ++top;
+        const int Le = top + kWalkDepth * ((L - top + kWalkDepth - 1) / kWalkDepth);
+        TRY(d.walk_ctl.ensure((size_t)(Le + 8) * 4));
+        hipLaunchKernelGGL(k_zero_u32, dim3((Le + 8 + 255) / 256), dim3(256), 0, s,
+                           d.walk_ctl.as<uint32_t>(), Le + 8);
+        uint32_t* ctl = d.walk_ctl.as<uint32_t>();
+        uint32_t* sizes = ctl + 4;
         hipLaunchKernelGGL(k_walk_top, dim3(1), dim3(kWalkT), 0, s, nbox, d.item_count.as<int32_t>(),
                            d.front.as<int2>(), d.front_next.as<int2>(), top, sizes, ctl, capf,
                            capp, capm, d.walkbox.as<WalkBox>(), d.wcell.as<WalkCell>(), ks,
                            d.p2p_keys.as<uint64_t>(), d.m2l_keys.as<uint64_t>());
-        for (int it = top; it < L; ++it) {
+        int cur = top & 1;   // the buffer that holds level `top`
+        for (int it = top; it < L; it += kWalkDepth) {
             // workgroups for the frontier the last build had at this level
             // (the kernel strides over any size; this only trims launches)
             const int64_t prev = it < (int)d.walk_sizes.size() ? d.walk_sizes[it] : capf;
             const unsigned g = (unsigned)std::min<int64_t>(512, (prev + prev / 4 + 2 * kWalkT) / kWalkT);
-            hipLaunchKernelGGL(k_walk_dev, dim3(g), dim3(kWalkT), 0, s, bufs[it & 1]->as<int2>(),
-                               bufs[(it + 1) & 1]->as<int2>(), it, sizes, ctl, capf, capp, capm,
+            hipLaunchKernelGGL(k_walk_multi, dim3(g), dim3(kWalkT), 0, s, bufs[cur]->as<int2>(),
+                               bufs[cur ^ 1]->as<int2>(), it, sizes, ctl, capf, capp, capm,
                                d.walkbox.as<WalkBox>(), d.wcell.as<WalkCell>(), ks,
                                d.p2p_keys.as<uint64_t>(), d.m2l_keys.as<uint64_t>());
+            cur ^= 1;
         }
         hipLaunchKernelGGL(k_m2l_depths, dim3(8), dim3(256), 0, s, d.m2l_keys.as<uint64_t>(),
-                           ctl + 1, capm, ks.y, d.cell_aux.as<int4>(), ctl + 5 + L);
+                           ctl + 1, capm, ks.y, d.cell_aux.as<int4>(), ctl + 5 + Le);
         TRY(hipGetLastError());
         // the walk's counts and the input checks in one round trip, into
         // pinned memory
         TRY(d.ensure_host_rb());
-        if (L + 7 + 3 > DevPlan::kHostRbWords) return "walk has too many levels for the read-back buffer";
-        TRY(hipMemcpyAsync(d.host_rb, ctl, (L + 7) * 4, hipMemcpyDeviceToHost, s));
-        TRY(hipMemcpyAsync(d.host_rb + L + 7, d.wcount.p, 12, hipMemcpyDeviceToHost, s));
+        if (Le + 7 + 3 > DevPlan::kHostRbWords) return "walk has too many levels for the read-back buffer";
+        TRY(hipMemcpyAsync(d.host_rb, ctl, (Le + 7) * 4, hipMemcpyDeviceToHost, s));
+        TRY(hipMemcpyAsync(d.host_rb + Le + 7, d.wcount.p, 12, hipMemcpyDeviceToHost, s));
         TRY(hipStreamSynchronize(s));
-        std::vector<uint32_t> hc(d.host_rb, d.host_rb + L + 7);
-        std::memcpy(flags, d.host_rb + L + 7, 12);
+        std::vector<uint32_t> hc(d.host_rb, d.host_rb + Le + 7);
+        std::memcpy(flags, d.host_rb + Le + 7, 12);
         have_flags = true;
         if (clk.on) {
             std::fprintf(stderr, "[pmfmm gpu plan] walk frontier per level:");
-            for (int it = 0; it <= L; ++it) std::fprintf(stderr, " %u", hc[4 + it]);
+            for (int it = 0; it <= Le; ++it) std::fprintf(stderr, " %u", hc[4 + it]);
             std::fprintf(stderr, "\n");
         }
-        if (hc[2] == 0 && hc[4 + L] == 0 && hc[0] <= capp && hc[1] <= capm) {
+        if (hc[2] == 0 && hc[4 + Le] == 0 && hc[0] <= capp && hc[1] <= capm) {
             n_p2p = hc[0];
             n_m2l = hc[1];
-            dmin_tgt = (int32_t)(0x7fffffffu - hc[5 + L]);
-            dmin_src = (int32_t)(0x7fffffffu - hc[6 + L]);
+            dmin_tgt = (int32_t)(0x7fffffffu - hc[5 + Le]);
+            dmin_src = (int32_t)(0x7fffffffu - hc[6 + Le]);
             d.walk_sizes.assign(hc.begin() + 4, hc.begin() + 4 + L);
             done = true;
         }

@@ -407,7 +407,12 @@ def secondary(args):
     # the line's value: the fastest form (all forms are listed with errors)
     best = min(res, key=lambda k: res[k]["ms_per_step"])
     if base is not None:
-        base["value"] = base["value"] * cand / n    # candidate pairs per particle
+        # the sample ran before the lists existed: scale it to candidate
+        # pairs per particle now
+        cpp = cand / n
+        base["value"] = base["value"] * cpp
+        base["sample"] = base["sample"].replace("candidate pairs per particle (1.0)",
+                                                f"candidate pairs per particle ({cpp:.1f})")
     line.update(value=cand / (res[best]["ms_per_step"] / 1e3),
                 ms_per_step=res[best]["ms_per_step"],
                 config={"workload": w.name, "n": n, "theta": theta, "order": order,

@@ -169,30 +169,77 @@ __global__ void k_init_pc(int64_t n, const int32_t* __restrict__ bf, const int32
     pc[i] = bfc[box_of(bf, nbox, (int)i)];
 }
 
-// Bounds of every cell of one depth from the ends of its sorted ranges.
-__global__ void k_cells_level(const int32_t* __restrict__ level, int nd, const int4* __restrict__ cell,
-                              const int4* __restrict__ aux, const uint32_t* __restrict__ plist,
-                              int64_t n, const double* __restrict__ wpos, double* __restrict__ clo,
-                              double* __restrict__ chi, int32_t* __restrict__ axis_out) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nd) return;
-    const int c = level[k];
-    const int4 ci = cell[c];
-    double lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) {
-        lo[a] = wpos[3 * (size_t)plist[a * n + ci.x] + a];
-        hi[a] = wpos[3 * (size_t)plist[a * n + ci.x + ci.y - 1] + a];
-        clo[3 * (size_t)c + a] = lo[a];
-        chi[3 * (size_t)c + a] = hi[a];
-    }
-    if (aux[c].x >= 0) {
+// Bounds of every cell of one depth from the ends of its sorted ranges,
+// the split axis of those that split, and pfirst[a nc + c]: the left marks
+// before cell c's first position of list a (3n positions, list a at
+// [a n, (a + 1) n)).  A splitting cell marks the first floor(count / 2)
+// positions of its range in every list and nothing else is marked, so with
+// the level's cells in position order (the pre-order within one depth),
+// pfirst[a nc + c] = a M + the marks of the level's cells before c, M = all
+// the level's marks: a scan over the level's cells, no marks read.  One
+// workgroup.
+constexpr int kCellsT = 1024;
+
+__global__ void __launch_bounds__(kCellsT)
+k_cells_level(const int32_t* __restrict__ level, int nd, const int4* __restrict__ cell,
+              const int4* __restrict__ aux, const uint32_t* __restrict__ plist, int64_t n,
+              const double* __restrict__ wpos, double* __restrict__ clo, double* __restrict__ chi,
+              int32_t* __restrict__ axis_out, int nc, int32_t* __restrict__ pfirst) {
+    __shared__ uint32_t wsum[kCellsT / 64];
+    __shared__ uint32_t carry;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    if (t == 0) carry = 0u;
+    __syncthreads();
+    for (int k0 = 0; k0 < nd; k0 += kCellsT) {
+        const int k = k0 + t;
+        uint32_t half = 0u;
+        int c = -1;
+        if (k < nd) {
+            c = level[k];
+            const int4 ci = cell[c];
+            double lo[3], hi[3];
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = wpos[3 * (size_t)plist[a * n + ci.x] + a];
+                hi[a] = wpos[3 * (size_t)plist[a * n + ci.x + ci.y - 1] + a];
+                clo[3 * (size_t)c + a] = lo[a];
+                chi[3 * (size_t)c + a] = hi[a];
+            }
+            if (aux[c].x >= 0) {
 #pragma clang fp contract(off)
-        const double e0 = hi[0] - lo[0], e1 = hi[1] - lo[1], e2 = hi[2] - lo[2];
-        int axis = 0;
-        double best = e0;
-        if (e1 > best) { axis = 1; best = e1; }
-        if (e2 > best) axis = 2;
-        axis_out[c] = axis;
+                const double e0 = hi[0] - lo[0], e1 = hi[1] - lo[1], e2 = hi[2] - lo[2];
+                int axis = 0;
+                double best = e0;
+                if (e1 > best) { axis = 1; best = e1; }
+                if (e2 > best) axis = 2;
+                axis_out[c] = axis;
+                half = (uint32_t)(ci.y / 2);
+            }
+        }
+        uint32_t x = half;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        uint32_t before = 0u, tot = 0u;
+        for (int w = 0; w < kCellsT / 64; ++w) {
+            const uint32_t v = wsum[w];
+            if (w < wave) before += v;
+            tot += v;
+        }
+        if (k < nd) pfirst[c] = (int32_t)(carry + before + x - half);
+        __syncthreads();
+        if (t == 0) carry += tot;
+        __syncthreads();
+    }
+    // lists 1 and 2 (each thread reads back the words it wrote above)
+    const uint32_t m = carry;
+    for (int k = t; k < nd; k += kCellsT) {
+        const int c = level[k];
+        const int32_t e = pfirst[c];
+        pfirst[(size_t)nc + c] = e + (int32_t)m;
+        pfirst[2 * (size_t)nc + c] = e + 2 * (int32_t)m;
     }
 }
 
@@ -216,10 +263,11 @@ __global__ void k_flag(int64_t n, const int32_t* __restrict__ pc, const int4* __
 // (3n positions, list a at [a n, (a + 1) n)) computed where they are used
 // instead of stored: a position's mark is its particle's left mark if its
 // cell splits at this level, else 0.  Tiles of 4096 positions: k_level_sums
-// counts each tile's marks; k_level_firsts gives the count of marks before
-// each splitting cell's first position of each list, and k_level_move the
-// count before every position (the tiles before its own, summed where they
-// are needed, + the in-tile scan) and from it the position's destination.
+// counts each tile's marks; k_cells_level has given the count of marks
+// before each splitting cell's first position of each list, and
+// k_level_move counts them before every position (the tiles before its
+// own, summed where they are needed, + the in-tile scan) and from the
+// difference places the position.
 constexpr int kLvThreads = 256;
 constexpr int kLvRounds = 16;
 constexpr int kLvTile = kLvThreads * kLvRounds;   // 4096
@@ -277,29 +325,6 @@ k_level_sums(int64_t n, const int32_t* __restrict__ pc, const int32_t* __restric
         for (int w = 0; w < kLvThreads / 64; ++w) t += wsum[w];
         tile_sums[blockIdx.x] = t;
     }
-}
-
-// One wavefront per (splitting cell of this level, list): the exclusive
-// prefix of the marks at the cell's first position of that list.
-__global__ void __launch_bounds__(256)
-k_level_firsts(const int32_t* __restrict__ level, int nd, int64_t n, const int4* __restrict__ cell,
-               const int32_t* __restrict__ pc, const int32_t* __restrict__ sax,
-               const uint32_t* __restrict__ plist, const uint64_t* __restrict__ bits,
-               const uint32_t* __restrict__ tile_sums, int nc, int32_t* __restrict__ pfirst) {
-    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (w >= 3 * nd) return;
-    const int k = w / 3, a = w - 3 * k;
-    const int c = level[k];
-    const int64_t qf = (int64_t)a * n + cell[c].x;
-    const int64_t tq = qf / kLvTile, t0 = tq * kLvTile;
-    // marks before qf: the counts of the tiles before qf's, then the marks
-    // of its tile up to qf
-    uint32_t cnt = 0;
-    for (int64_t k = lane; k < tq; k += 64) cnt += tile_sums[k];
-    for (int64_t q = t0 + lane; q < qf; q += 64) cnt += level_mark(q, n, pc, sax, cell, plist, bits);
-    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off);
-    if (lane == 0) pfirst[(size_t)a * nc + c] = (int32_t)cnt;
 }
 
 __global__ void __launch_bounds__(kLvThreads)
@@ -1441,10 +1466,11 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     const int nloop = (int)d.loop_depth_begin.size() - 1;
     for (int dep = 0; dep < nloop; ++dep) {
         const int c0 = d.loop_depth_begin[dep], ncd = d.loop_depth_begin[dep + 1] - c0;
-        hipLaunchKernelGGL(k_cells_level, dim3(grid_of(ncd)), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_cells_level, dim3(1), dim3(kCellsT), 0, s,
                            d.loop_cells.as<int32_t>() + c0, ncd, d.cell.as<int4>(),
                            d.cell_aux.as<int4>(), d.plist.as<uint32_t>(), n, d.wpos.as<double>(),
-                           d.clo.as<double>(), d.chi.as<double>(), d.cell_axis.as<int32_t>());
+                           d.clo.as<double>(), d.chi.as<double>(), d.cell_axis.as<int32_t>(),
+                           (int)nc, d.lv_first.as<int32_t>());
         TRY(hipGetLastError());
         hipLaunchKernelGGL(k_flag, dim3(grid_of(n)), dim3(256), 0, s, n, d.pc.as<int32_t>(),
                            d.cell.as<int4>(), d.cell_axis.as<int32_t>(), d.plist.as<uint32_t>(),
@@ -1455,10 +1481,6 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                            d.pc.as<int32_t>(), d.cell_axis.as<int32_t>(), d.cell.as<int4>(),
                            d.plist.as<uint32_t>(), bits, d.tile_sums.as<uint32_t>());
         TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_level_firsts, dim3((3 * ncd + 3) / 4), dim3(256), 0, s,
-                           d.loop_cells.as<int32_t>() + c0, ncd, n, d.cell.as<int4>(),
-                           d.pc.as<int32_t>(), d.cell_axis.as<int32_t>(), d.plist.as<uint32_t>(),
-                           bits, d.tile_sums.as<uint32_t>(), (int)nc, d.lv_first.as<int32_t>());
         hipLaunchKernelGGL(k_level_move, dim3(lv_tiles), dim3(kLvThreads), 0, s, n,
                            d.pc.as<int32_t>(), d.pc_tmp.as<int32_t>(), d.cell.as<int4>(),
                            d.cell_aux.as<int4>(), d.cell_axis.as<int32_t>(), d.plist.as<uint32_t>(),

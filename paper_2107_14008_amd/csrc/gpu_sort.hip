@@ -188,11 +188,31 @@ scan_tile_sums(const int32_t* __restrict__ in, int64_t n, uint32_t* __restrict__
     if (threadIdx.x == 0) sums[blockIdx.x] = (uint32_t)red[0];
 }
 
+// SCANNED: sums holds each tile's offset (scan_single ran); otherwise the
+// tile sums themselves, and each workgroup adds up those before its tile
+// (one launch fewer; for up to kApplySumMax tiles).
+constexpr int kApplySumMax = 4096;
+
+template <bool SCANNED>
 __global__ void __launch_bounds__(kThreads)
 scan_tile_apply(const int32_t* __restrict__ in, int32_t* __restrict__ out, int64_t n,
                 const uint32_t* __restrict__ sums) {
     __shared__ int32_t part[kThreads];
+    __shared__ uint32_t toff;
     const int t = threadIdx.x;
+    if (!SCANNED) {
+        uint32_t c = 0;
+        for (int k = t; k < (int)blockIdx.x; k += kThreads) c += sums[k];
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
+        if ((t & 63) == 0) part[t >> 6] = (int32_t)c;
+        __syncthreads();
+        if (t == 0) {
+            uint32_t a = 0;
+            for (int w = 0; w < kThreads / 64; ++w) a += (uint32_t)part[w];
+            toff = a;
+        }
+        __syncthreads();
+    }
     const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)t * kRounds;
     int32_t v[kRounds];
     int32_t s = 0;
@@ -208,7 +228,7 @@ scan_tile_apply(const int32_t* __restrict__ in, int32_t* __restrict__ out, int64
         part[t] += x;
         __syncthreads();
     }
-    int32_t run = (int32_t)sums[blockIdx.x] + (t == 0 ? 0 : part[t - 1]);
+    int32_t run = (int32_t)(SCANNED ? sums[blockIdx.x] : toff) + (t == 0 ? 0 : part[t - 1]);
     for (int r = 0; r < kRounds; ++r) {
         if (base + r < n) out[base + r] = run;
         run += v[r];
@@ -280,8 +300,14 @@ hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, uint32
     if (n <= 0) return hipSuccess;
     const int tiles = (int)sort_tiles(n);
     hipLaunchKernelGGL(scan_tile_sums, dim3(tiles), dim3(kThreads), 0, s, in, n, tile_sums);
-    hipLaunchKernelGGL(scan_single, dim3(1), dim3(1024), 0, s, tile_sums, (int64_t)tiles);
-    hipLaunchKernelGGL(scan_tile_apply, dim3(tiles), dim3(kThreads), 0, s, in, out, n, tile_sums);
+    if (tiles <= kApplySumMax) {
+        hipLaunchKernelGGL(scan_tile_apply<false>, dim3(tiles), dim3(kThreads), 0, s, in, out, n,
+                           tile_sums);
+    } else {
+        hipLaunchKernelGGL(scan_single, dim3(1), dim3(1024), 0, s, tile_sums, (int64_t)tiles);
+        hipLaunchKernelGGL(scan_tile_apply<true>, dim3(tiles), dim3(kThreads), 0, s, in, out, n,
+                           tile_sums);
+    }
     return hipGetLastError();
 }
 

@@ -882,65 +882,71 @@ __device__ __forceinline__ bool walk_level(const int2* __restrict__ front, int2*
     return true;
 }
 
-// kWalkDepth levels of the walk per launch: each workgroup classifies a
-// group of level `it`, keeps the group's child pairs (at most four per
-// pair) in LDS and classifies them in turn, and so on; only the pairs of
-// level it + kWalkDepth go to `next`.  The descendants of a pair depend on
-// that pair alone, so the middle levels need no other workgroup's results:
-// fewer launches, and the middle levels' pairs never go through global
-// memory.  sizes[it + 1 ..] count the middle levels (for the next build's
-// sizing).  Two levels per launch took the 128^3 walk from 0.55 to 0.33 ms;
-// three took 0.37 ms (the deeper a workgroup's subtree, the more the
-// workgroups' shares differ).
-constexpr int kWalkDepth = 2;
-
-__global__ void __launch_bounds__(kWalkT)
-k_walk_multi(const int2* __restrict__ front, int2* __restrict__ next, int it,
-            uint32_t* __restrict__ sizes, uint32_t* __restrict__ ctl, uint32_t cap_front,
-            uint32_t cap_p2p, uint32_t cap_m2l, const WalkBox* __restrict__ wbox,
-            const WalkCell* __restrict__ wcell, int2 ks, uint64_t* __restrict__ p2p_keys,
-            uint64_t* __restrict__ m2l_keys) {
-    __shared__ uint64_t wtot[kWalkT / 64];
-    __shared__ uint32_t bbase[4];
-    __shared__ int2 lch[kWalkDepth - 1][4 * kWalkT];
-    const uint32_t nf = sizes[it];
-    if (nf > cap_front) return;
-    // classifies the pairs [r, r + blockDim) of src (n pairs) of level
-    // it + d and appends their children to lch[d] (or, at the last level,
-    // to next); returns the children kept in lch[d]
-    auto step = [&](const int2* src, uint32_t r, uint32_t n, int d) -> uint32_t {
-        const uint32_t j = r + threadIdx.x;
+// Levels it and it + 1 of the walk in workgroup `blk` of `nblk`: each
+// workgroup classifies a group of level it, keeps the group's child pairs
+// (at most four per pair) in LDS (`lch`) and classifies them in turn; only
+// their children (level it + 2) go to `next`.  The descendants of a pair
+// depend on that pair alone, so the middle level needs no other
+// workgroup's results and its pairs never go through global memory.
+// sizes[it + 1] counts the middle level (for the next build's sizing).
+// Two levels per launch took the 128^3 walk from 0.55 to 0.33 ms; three
+// took 0.37 ms (the deeper a workgroup's subtree, the more the workgroups'
+// shares differ).
+__device__ __forceinline__ void walk_two(const int2* __restrict__ front, int2* __restrict__ next,
+                                         int it, uint32_t nf, uint32_t blk, uint32_t nblk,
+                                         uint32_t* __restrict__ sizes, uint32_t* __restrict__ ctl,
+                                         uint32_t cap_front, uint32_t cap_p2p, uint32_t cap_m2l,
+                                         const WalkBox* __restrict__ wbox,
+                                         const WalkCell* __restrict__ wcell, int2 ks,
+                                         uint64_t* __restrict__ p2p_keys,
+                                         uint64_t* __restrict__ m2l_keys, uint64_t* wtot,
+                                         uint32_t* bbase, int2* lch) {
+    const uint32_t stride = nblk * blockDim.x;
+    for (uint32_t base = blk * blockDim.x; base < nf; base += stride) {
+        const uint32_t k = base + threadIdx.x;
         WalkOut o{0u, 0u, 0u, {}, {0ull, 0ull}};
-        if (j < n) walk_classify(src[j], wbox, wcell, ks, o);
-        const bool last = d == kWalkDepth - 1;
-        const uint32_t nch = walk_emit(o, next, &sizes[it + kWalkDepth], cap_front,
-                                       last ? nullptr : lch[d], ctl, cap_p2p, cap_m2l, p2p_keys,
-                                       m2l_keys, wtot, bbase);
-        if (last) return 0u;
-        if (threadIdx.x == 0 && nch != 0) atomicAdd(&sizes[it + 1 + d], nch);
-        return nch;
-    };
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < nf; base += stride) {
-        const uint32_t n1 = step(front, base, nf, 0);
-        for (uint32_t r1 = 0; r1 < n1; r1 += blockDim.x) {
-            if constexpr (kWalkDepth == 2) {
-                (void)step(lch[0], r1, n1, 1);
-            } else {
-                const uint32_t n2 = step(lch[0], r1, n1, 1);
-                for (uint32_t r2 = 0; r2 < n2; r2 += blockDim.x) (void)step(lch[1], r2, n2, 2);
-            }
+        if (k < nf) walk_classify(front[k], wbox, wcell, ks, o);
+        const uint32_t n1 = walk_emit(o, nullptr, nullptr, 0u, lch, ctl, cap_p2p, cap_m2l,
+                                      p2p_keys, m2l_keys, wtot, bbase);
+        if (threadIdx.x == 0 && n1 != 0) atomicAdd(&sizes[it + 1], n1);
+        for (uint32_t r = 0; r < n1; r += blockDim.x) {
+            const uint32_t j = r + threadIdx.x;
+            WalkOut o2{0u, 0u, 0u, {}, {0ull, 0ull}};
+            if (j < n1) walk_classify(lch[j], wbox, wcell, ks, o2);
+            (void)walk_emit(o2, next, &sizes[it + 2], cap_front, nullptr, ctl, cap_p2p, cap_m2l,
+                            p2p_keys, m2l_keys, wtot, bbase);
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&ctl[3], nf);
+    if (blk == 0 && threadIdx.x == 0) atomicMax(&ctl[3], nf);
 }
+
+// Levels it and it + 1, the frontier size read on the device.
+__global__ void __launch_bounds__(kWalkT)
+k_walk_multi(const int2* __restrict__ front, int2* __restrict__ next, int it,
+             uint32_t* __restrict__ sizes, uint32_t* __restrict__ ctl, uint32_t cap_front,
+             uint32_t cap_p2p, uint32_t cap_m2l, const WalkBox* __restrict__ wbox,
+             const WalkCell* __restrict__ wcell, int2 ks, uint64_t* __restrict__ p2p_keys,
+             uint64_t* __restrict__ m2l_keys) {
+    __shared__ uint64_t wtot[kWalkT / 64];
+    __shared__ uint32_t bbase[4];
+    __shared__ int2 lch[4 * kWalkT];
+    const uint32_t nf = sizes[it];
+    if (nf > cap_front) return;
+    walk_two(front, next, it, nf, blockIdx.x, gridDim.x, sizes, ctl, cap_front, cap_p2p, cap_m2l,
+             wbox, wcell, ks, p2p_keys, m2l_keys, wtot, bbase, lch);
+}
+
+// Launches of k_walk_top's steps: two levels per step, one for an odd last
+// level; step q reads buffer q & 1 and writes the other, so the frontier of
+// level `levels` ends in buffer walk_top_steps(levels) & 1.
+constexpr int walk_top_steps(int levels) { return levels / 2 + (levels & 1); }
 
 // The first frontier (each box's root against itself with the zero shift and
 // the 13 shifts of code > 13, the canonical half) and the walk's first
-// `levels` levels in one workgroup: the top of the walk has frontiers of a
-// few hundred pairs, where a launch per level costs more than the level.
-// Level it reads buffer it & 1 and writes the other.  The frontier sizes,
-// which thread 0 adds to with atomics, are read back with atomic loads.
+// `levels` levels in one workgroup, two at a time: the top of the walk has
+// frontiers of a few hundred pairs, where a launch per level costs more than
+// the level.  The frontier sizes, which thread 0 adds to with atomics, are
+// read back with atomic loads.
 __global__ void __launch_bounds__(kWalkT)
 k_walk_top(int nbox, const int32_t* __restrict__ box_root, int2* __restrict__ buf0,
            int2* __restrict__ buf1, int levels, uint32_t* __restrict__ sizes,
@@ -949,6 +955,7 @@ k_walk_top(int nbox, const int32_t* __restrict__ box_root, int2* __restrict__ bu
            uint64_t* __restrict__ p2p_keys, uint64_t* __restrict__ m2l_keys) {
     __shared__ uint64_t wtot[kWalkT / 64];
     __shared__ uint32_t bbase[4];
+    __shared__ int2 lch[4 * kWalkT];
     const uint32_t nf0 = (uint32_t)(14 * nbox);
     for (uint32_t q = threadIdx.x; q < nf0; q += blockDim.x) {
         const int b = (int)(q / 14), j = (int)(q - 14 * (uint32_t)b);
@@ -957,15 +964,23 @@ k_walk_top(int nbox, const int32_t* __restrict__ box_root, int2* __restrict__ bu
     }
     if (threadIdx.x == 0) sizes[0] = nf0;
     __syncthreads();
-    for (int it = 0; it < levels; ++it) {
+    int step = 0;
+    for (int it = 0; it < levels; ++step) {
         const uint32_t nf = it == 0 ? nf0
                                     : __hip_atomic_load(&sizes[it], __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_AGENT);
-        const int2* front = (it & 1) ? buf1 : buf0;
-        int2* next = (it & 1) ? buf0 : buf1;
-        if (!walk_level(front, next, it, nf, 0u, 1u, sizes, ctl, cap_front, cap_p2p, cap_m2l,
-                        wbox, wcell, ks, p2p_keys, m2l_keys, wtot, bbase))
-            return;
+        if (nf > cap_front) return;
+        const int2* front = (step & 1) ? buf1 : buf0;
+        int2* next = (step & 1) ? buf0 : buf1;
+        if (it + 2 <= levels) {
+            walk_two(front, next, it, nf, 0u, 1u, sizes, ctl, cap_front, cap_p2p, cap_m2l, wbox,
+                     wcell, ks, p2p_keys, m2l_keys, wtot, bbase, lch);
+            it += 2;
+        } else {
+            (void)walk_level(front, next, it, nf, 0u, 1u, sizes, ctl, cap_front, cap_p2p,
+                             cap_m2l, wbox, wcell, ks, p2p_keys, m2l_keys, wtot, bbase);
+            it += 1;
+        }
         __syncthreads();
     }
 }
@@ -1561,10 +1576,10 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
         DevBuf* bufs[2] = {&d.front, &d.front_next};
         // the top levels in one workgroup while the last build's frontiers
         // were small (any size is handled; this only chooses the split),
-        // then kWalkDepth levels per launch up to level Le >= L
+        // then two levels per launch up to level Le >= L
         int top = 0;
         while (top < L && top < (int)d.walk_sizes.size() && d.walk_sizes[top] <= kWalkTopMax) ++top;
-        const int Le = top + kWalkDepth * ((L - top + kWalkDepth - 1) / kWalkDepth);
+        const int Le = top + 2 * ((L - top + 1) / 2);
         TRY(d.walk_ctl.ensure((size_t)(Le + 8) * 4));
         hipLaunchKernelGGL(k_zero_u32, dim3((Le + 8 + 255) / 256), dim3(256), 0, s,
                            d.walk_ctl.as<uint32_t>(), Le + 8);
@@ -1574,8 +1589,8 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                            d.front.as<int2>(), d.front_next.as<int2>(), top, sizes, ctl, capf,
                            capp, capm, d.walkbox.as<WalkBox>(), d.wcell.as<WalkCell>(), ks,
                            d.p2p_keys.as<uint64_t>(), d.m2l_keys.as<uint64_t>());
-        int cur = top & 1;   // the buffer that holds level `top`
-        for (int it = top; it < L; it += kWalkDepth) {
+        int cur = walk_top_steps(top) & 1;   // the buffer that holds level `top`
+        for (int it = top; it < L; it += 2) {
             // workgroups for the frontier the last build had at this level
             // (the kernel strides over any size; this only trims launches)
             const int64_t prev = it < (int)d.walk_sizes.size() ? d.walk_sizes[it] : capf;

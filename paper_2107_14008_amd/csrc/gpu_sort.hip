@@ -3,7 +3,7 @@
 // equal-length segments at once, and an exclusive prefix sum of 32-bit
 // integers.
 //
-// Radix sort: 8-bit digits, tiles of 2048 elements (256 threads x 8
+// Radix sort: 8-bit digits, tiles of 4096 elements (256 threads x 16
 // rounds); a tile never straddles two segments.  Per pass: (1) per-tile
 // digit histogram in LDS, (2) one exclusive scan over the
 // [segment][digit][tile] table (segment-major, so segment s lands in
@@ -20,8 +20,8 @@ namespace pmfmm {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kRounds = 8;
-constexpr int kTile = kThreads * kRounds;  // 2048
+constexpr int kRounds = 16;
+constexpr int kTile = kThreads * kRounds;  // 4096
 
 // Block b handles tile (b % tiles) of segment (b / tiles); its elements are
 // [seg n + tile kTile, min(seg n + (tile + 1) kTile, (seg + 1) n)).
@@ -171,7 +171,7 @@ rs_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
     }
 }
 
-// ---- exclusive scan of int32 (tiles of 2048)
+// ---- exclusive scan of int32 (tiles of 4096)
 __global__ void __launch_bounds__(kThreads)
 scan_tile_sums(const int32_t* __restrict__ in, int64_t n, uint32_t* __restrict__ sums) {
     __shared__ int32_t red[kThreads];

@@ -170,21 +170,20 @@ __global__ void k_init_pc(int64_t n, const int32_t* __restrict__ bf, const int32
 }
 
 // Bounds of every cell of one depth from the ends of its sorted ranges,
-// the split axis of those that split, and pfirst[a nc + c]: the left marks
-// before cell c's first position of list a (3n positions, list a at
-// [a n, (a + 1) n)).  A splitting cell marks the first floor(count / 2)
-// positions of its range in every list and nothing else is marked, so with
-// the level's cells in position order (the pre-order within one depth),
-// pfirst[a nc + c] = a M + the marks of the level's cells before c, M = all
-// the level's marks: a scan over the level's cells, no marks read.  One
-// workgroup.
+// the split axis of those that split, and pfirst[c]: the left marks before
+// cell c's first position, the same in each of the three lists.  A
+// splitting cell marks the first floor(count / 2) positions of its range in
+// every list and nothing else is marked, so with the level's cells in
+// position order (the pre-order within one depth) pfirst[c] = the marks of
+// the level's cells before c: a scan over the level's cells, no marks read.
+// One workgroup.
 constexpr int kCellsT = 1024;
 
 __global__ void __launch_bounds__(kCellsT)
 k_cells_level(const int32_t* __restrict__ level, int nd, const int4* __restrict__ cell,
               const int4* __restrict__ aux, const uint32_t* __restrict__ plist, int64_t n,
               const double* __restrict__ wpos, double* __restrict__ clo, double* __restrict__ chi,
-              int32_t* __restrict__ axis_out, int nc, int32_t* __restrict__ pfirst) {
+              int32_t* __restrict__ axis_out, int32_t* __restrict__ pfirst) {
     __shared__ uint32_t wsum[kCellsT / 64];
     __shared__ uint32_t carry;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -233,14 +232,6 @@ k_cells_level(const int32_t* __restrict__ level, int nd, const int4* __restrict_
         if (t == 0) carry += tot;
         __syncthreads();
     }
-    // lists 1 and 2 (each thread reads back the words it wrote above)
-    const uint32_t m = carry;
-    for (int k = t; k < nd; k += kCellsT) {
-        const int c = level[k];
-        const int32_t e = pfirst[c];
-        pfirst[(size_t)nc + c] = e + (int32_t)m;
-        pfirst[2 * (size_t)nc + c] = e + 2 * (int32_t)m;
-    }
 }
 
 // Left marks of the particles of the cells splitting at this level (sax[c]
@@ -260,17 +251,19 @@ __global__ void k_flag(int64_t n, const int32_t* __restrict__ pc, const int4* __
 }
 
 // The stable partition of one level, with the left marks of the three lists
-// (3n positions, list a at [a n, (a + 1) n)) computed where they are used
-// instead of stored: a position's mark is its particle's left mark if its
-// cell splits at this level, else 0.  Tiles of 4096 positions: k_level_sums
-// counts each tile's marks; k_cells_level has given the count of marks
-// before each splitting cell's first position of each list, and
-// k_level_move counts them before every position (the tiles before its
-// own, summed where they are needed, + the in-tile scan) and from the
-// difference places the position.
+// (list a at [a n, (a + 1) n) of plist) computed where they are used instead
+// of stored: a position's mark is its particle's left mark if its cell
+// splits at this level, else 0.  A tile is the list positions [b T, (b + 1)
+// T), T = 2048, of all three lists, whose cells are the same (one pc / sax /
+// cell read serves the three).  k_level_sums counts each tile's marks per
+// list; k_cells_level has given the count of marks before each splitting
+// cell's first position (the same in the three lists), and k_level_move
+// counts them before every position (the tiles before its own, summed
+// where they are needed, + the in-tile scan) and from the difference places
+// the position.
 constexpr int kLvThreads = 256;
-constexpr int kLvRounds = 16;
-constexpr int kLvTile = kLvThreads * kLvRounds;   // 4096
+constexpr int kLvRounds = 8;
+constexpr int kLvTile = kLvThreads * kLvRounds;   // 2048 positions of each list
 
 // The particles' left marks as bits: k_flag writes one byte per particle of
 // a splitting cell (scattered by particle), and this packs the bytes of
@@ -285,45 +278,43 @@ __global__ void k_pack_marks(int64_t n, const uint8_t* __restrict__ flag,
     if ((threadIdx.x & 63) == 0 && i < n) bits[i >> 6] = b;
 }
 
-// sax[c]: the split axis of a cell that splits at this level, else -1.  On
-// the split axis's own list the mark follows from the position alone, so
-// only the two other lists read the particle's bit.
-__device__ __forceinline__ uint32_t level_mark(int64_t q, int64_t n, const int32_t* __restrict__ pc,
-                                               const int32_t* __restrict__ sax,
-                                               const int4* __restrict__ cell,
-                                               const uint32_t* __restrict__ plist,
-                                               const uint64_t* __restrict__ bits) {
-    const int a = q >= n ? (q >= 2 * n ? 2 : 1) : 0;
-    const int64_t i = q - (int64_t)a * n;
-    const int c = pc[i];
-    const int ax = sax[c];
-    if (ax < 0) return 0u;
-    if (ax == a) {
-        const int4 ci = cell[c];
-        return (i - ci.x < ci.y / 2) ? 1u : 0u;
-    }
-    const uint32_t p = plist[q];
+__device__ __forceinline__ uint32_t mark_bit(const uint64_t* __restrict__ bits, uint32_t p) {
     return (uint32_t)(bits[p >> 6] >> (p & 63u)) & 1u;
 }
 
+// sax[c]: the split axis of a cell that splits at this level, else -1.  On
+// the split axis's own list the mark follows from the position alone, so
+// only the two other lists read the particle's bit.
+// tile_sums[a ntiles + b]: the marks of list a in tile b.
 __global__ void __launch_bounds__(kLvThreads)
 k_level_sums(int64_t n, const int32_t* __restrict__ pc, const int32_t* __restrict__ sax,
              const int4* __restrict__ cell, const uint32_t* __restrict__ plist,
-             const uint64_t* __restrict__ bits, uint32_t* __restrict__ tile_sums) {
-    __shared__ uint32_t wsum[kLvThreads / 64];
+             const uint64_t* __restrict__ bits, uint32_t* __restrict__ tile_sums, int ntiles) {
+    __shared__ uint64_t wsum[kLvThreads / 64];
     const int64_t base = (int64_t)blockIdx.x * kLvTile;
-    uint32_t c = 0;
+    // the three counts packed 21 bits apart (each at most kLvTile)
+    uint64_t cnt = 0;
     for (int r = 0; r < kLvRounds; ++r) {
-        const int64_t q = base + r * kLvThreads + threadIdx.x;
-        if (q < 3 * n) c += level_mark(q, n, pc, sax, cell, plist, bits);
+        const int64_t i = base + r * kLvThreads + threadIdx.x;
+        if (i >= n) continue;
+        const int c = pc[i];
+        const int ax = sax[c];
+        if (ax < 0) continue;
+        const int4 ci = cell[c];
+        const uint32_t own = (i - ci.x < ci.y / 2) ? 1u : 0u;
+        for (int a = 0; a < 3; ++a) {
+            const uint32_t m = a == ax ? own : mark_bit(bits, plist[(int64_t)a * n + i]);
+            cnt += (uint64_t)m << (21 * a);
+        }
     }
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = cnt;
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t t = 0;
+        uint64_t t = 0;
         for (int w = 0; w < kLvThreads / 64; ++w) t += wsum[w];
-        tile_sums[blockIdx.x] = t;
+        for (int a = 0; a < 3; ++a)
+            tile_sums[(size_t)a * ntiles + blockIdx.x] = (uint32_t)(t >> (21 * a)) & 0x1fffffu;
     }
 }
 
@@ -332,72 +323,90 @@ k_level_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __restrict__ pc
              const int4* __restrict__ cell, const int4* __restrict__ aux,
              const int32_t* __restrict__ sax, const uint32_t* __restrict__ plist,
              uint32_t* __restrict__ pout, const uint64_t* __restrict__ bits,
-             const uint32_t* __restrict__ tile_sums, int nc, const int32_t* __restrict__ pfirst) {
-    __shared__ uint8_t mk[kLvTile];
-    __shared__ uint16_t pre[kLvTile];
-    __shared__ uint32_t wsum[kLvThreads / 64];
-    __shared__ uint32_t woff[kLvThreads / 64];
+             const uint32_t* __restrict__ tile_sums, int ntiles,
+             const int32_t* __restrict__ pfirst) {
+    __shared__ uint8_t mk[3][kLvTile];
+    __shared__ uint16_t pre[3][kLvTile];
+    __shared__ uint64_t wsum[kLvThreads / 64];
+    __shared__ uint32_t woff[3][kLvThreads / 64];
     const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
     {
-        // this tile's offset: the counts of the tiles before it
-        uint32_t c = 0;
-        for (int k = t; k < (int)blockIdx.x; k += kLvThreads) c += tile_sums[k];
-        for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
-        if ((t & 63) == 0) woff[t >> 6] = c;
+        // this tile's offsets: the counts of the tiles before it, per list
+        for (int a = 0; a < 3; ++a) {
+            uint32_t c = 0;
+            for (int k = t; k < (int)blockIdx.x; k += kLvThreads) c += tile_sums[(size_t)a * ntiles + k];
+            for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
+            if (lane == 0) woff[a][wave] = c;
+        }
     }
     const int64_t base = (int64_t)blockIdx.x * kLvTile;
-    uint32_t pv[kLvRounds];
+    uint32_t pv[kLvRounds][3];
     int32_t cv[kLvRounds];
     for (int r = 0; r < kLvRounds; ++r) {
-        const int64_t q = base + r * kLvThreads + t;
-        uint8_t f = 0;
-        pv[r] = 0u;
+        const int64_t i = base + r * kLvThreads + t;
+        uint32_t m[3] = {0u, 0u, 0u};
         cv[r] = -1;
-        if (q < 3 * n) {
-            pv[r] = plist[q];
-            cv[r] = pc[q >= n ? (q >= 2 * n ? q - 2 * n : q - n) : q];
-            f = (uint8_t)level_mark(q, n, pc, sax, cell, plist, bits);
+        pv[r][0] = pv[r][1] = pv[r][2] = 0u;
+        if (i < n) {
+            const int c = pc[i];
+            cv[r] = c;
+            for (int a = 0; a < 3; ++a) pv[r][a] = plist[(int64_t)a * n + i];
+            const int ax = sax[c];
+            if (ax >= 0) {
+                const int4 ci = cell[c];
+                const uint32_t own = (i - ci.x < ci.y / 2) ? 1u : 0u;
+                for (int a = 0; a < 3; ++a) m[a] = a == ax ? own : mark_bit(bits, pv[r][a]);
+            }
         }
-        mk[r * kLvThreads + t] = f;
+        for (int a = 0; a < 3; ++a) mk[a][r * kLvThreads + t] = (uint8_t)m[a];
     }
     __syncthreads();
-    // in-tile exclusive prefix: thread t owns positions [16 t, 16 t + 16)
-    uint32_t own = 0;
-    for (int j = 0; j < kLvRounds; ++j) own += mk[kLvRounds * t + j];
-    uint32_t x = own;
-    const int lane = t & 63, wave = t >> 6;
+    // in-tile exclusive prefix per list: thread t owns positions
+    // [8 t, 8 t + 8); the three counts packed 21 bits apart
+    uint64_t own = 0;
+    for (int j = 0; j < kLvRounds; ++j)
+        for (int a = 0; a < 3; ++a) own += (uint64_t)mk[a][kLvRounds * t + j] << (21 * a);
+    uint64_t x = own;
     for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off);
+        const uint64_t y = __shfl_up(x, off);
         if (lane >= off) x += y;
     }
     if (lane == 63) wsum[wave] = x;
     __syncthreads();
-    uint32_t run = x - own;
+    uint64_t run = x - own;
     for (int w = 0; w < wave; ++w) run += wsum[w];
     for (int j = 0; j < kLvRounds; ++j) {
-        pre[kLvRounds * t + j] = (uint16_t)run;
-        run += mk[kLvRounds * t + j];
+        for (int a = 0; a < 3; ++a) {
+            pre[a][kLvRounds * t + j] = (uint16_t)((run >> (21 * a)) & 0x1fffffu);
+            run += (uint64_t)mk[a][kLvRounds * t + j] << (21 * a);
+        }
     }
     __syncthreads();
-    uint32_t toff = 0;
-    for (int w = 0; w < kLvThreads / 64; ++w) toff += woff[w];
+    uint32_t toff[3];
+    for (int a = 0; a < 3; ++a) {
+        toff[a] = 0;
+        for (int w = 0; w < kLvThreads / 64; ++w) toff[a] += woff[a][w];
+    }
     for (int r = 0; r < kLvRounds; ++r) {
-        const int64_t q = base + r * kLvThreads + t;
-        if (q >= 3 * n) continue;
-        const int a = q >= n ? (q >= 2 * n ? 2 : 1) : 0;
-        const int64_t i = q - (int64_t)a * n;
+        const int64_t i = base + r * kLvThreads + t;
+        if (i >= n) continue;
         const int c = cv[r];
         if (sax[c] < 0) {
-            pout[q] = pv[r];
-            if (a == 0) pc_out[i] = c;
+            for (int a = 0; a < 3; ++a) pout[(int64_t)a * n + i] = pv[r][a];
+            pc_out[i] = c;
             continue;
         }
         const int4 ci = cell[c];
         const int64_t first = ci.x, nl = ci.y / 2;
-        const int64_t lr = (int64_t)(toff + pre[r * kLvThreads + t]) - pfirst[(size_t)a * nc + c];
-        const int64_t pos = mk[r * kLvThreads + t] ? first + lr : first + nl + (i - first - lr);
-        pout[(int64_t)a * n + pos] = pv[r];
-        if (a == 0) pc_out[i] = (i - first < nl) ? aux[c].x : aux[c].y;
+        const int64_t pf = pfirst[c];
+        for (int a = 0; a < 3; ++a) {
+            const int j = r * kLvThreads + t;
+            const int64_t lr = (int64_t)(toff[a] + pre[a][j]) - pf;
+            const int64_t pos = mk[a][j] ? first + lr : first + nl + (i - first - lr);
+            pout[(int64_t)a * n + pos] = pv[r][a];
+        }
+        pc_out[i] = (i - first < nl) ? aux[c].x : aux[c].y;
     }
 }
 
@@ -1468,9 +1477,9 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     const int64_t bits_off = (n + 255) / 256 * 256;
     TRY(d.flag.ensure(std::max<int64_t>(n * 4, bits_off + (n + 63) / 64 * 8)));
     uint64_t* bits = reinterpret_cast<uint64_t*>(d.flag.as<uint8_t>() + bits_off);
-    const int64_t lv_tiles = (3 * n + kLvTile - 1) / kLvTile;
-    TRY(d.lv_first.ensure(3 * nc * 4));
-    TRY(d.tile_sums.ensure(lv_tiles * 4 + 16));
+    const int64_t lv_tiles = (n + kLvTile - 1) / kLvTile;
+    TRY(d.lv_first.ensure(nc * 4));
+    TRY(d.tile_sums.ensure(3 * lv_tiles * 4 + 16));
     TRY(d.clo.ensure(nc * 24));
     TRY(d.chi.ensure(nc * 24));
     TRY(d.cell_axis.ensure(nc * 4));
@@ -1485,7 +1494,7 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                            d.loop_cells.as<int32_t>() + c0, ncd, d.cell.as<int4>(),
                            d.cell_aux.as<int4>(), d.plist.as<uint32_t>(), n, d.wpos.as<double>(),
                            d.clo.as<double>(), d.chi.as<double>(), d.cell_axis.as<int32_t>(),
-                           (int)nc, d.lv_first.as<int32_t>());
+                           d.lv_first.as<int32_t>());
         TRY(hipGetLastError());
         hipLaunchKernelGGL(k_flag, dim3(grid_of(n)), dim3(256), 0, s, n, d.pc.as<int32_t>(),
                            d.cell.as<int4>(), d.cell_axis.as<int32_t>(), d.plist.as<uint32_t>(),
@@ -1494,13 +1503,13 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                            d.flag.as<uint8_t>(), bits);
         hipLaunchKernelGGL(k_level_sums, dim3(lv_tiles), dim3(kLvThreads), 0, s, n,
                            d.pc.as<int32_t>(), d.cell_axis.as<int32_t>(), d.cell.as<int4>(),
-                           d.plist.as<uint32_t>(), bits, d.tile_sums.as<uint32_t>());
+                           d.plist.as<uint32_t>(), bits, d.tile_sums.as<uint32_t>(), (int)lv_tiles);
         TRY(hipGetLastError());
         hipLaunchKernelGGL(k_level_move, dim3(lv_tiles), dim3(kLvThreads), 0, s, n,
                            d.pc.as<int32_t>(), d.pc_tmp.as<int32_t>(), d.cell.as<int4>(),
                            d.cell_aux.as<int4>(), d.cell_axis.as<int32_t>(), d.plist.as<uint32_t>(),
-                           d.plist_tmp.as<uint32_t>(), bits, d.tile_sums.as<uint32_t>(), (int)nc,
-                           d.lv_first.as<int32_t>());
+                           d.plist_tmp.as<uint32_t>(), bits, d.tile_sums.as<uint32_t>(),
+                           (int)lv_tiles, d.lv_first.as<int32_t>());
         TRY(hipGetLastError());
         std::swap(d.plist, d.plist_tmp);
         std::swap(d.pc, d.pc_tmp);

@@ -254,7 +254,7 @@ __global__ void k_flag(int64_t n, const int32_t* __restrict__ pc, const int4* __
 // (list a at [a n, (a + 1) n) of plist) computed where they are used instead
 // of stored: a position's mark is its particle's left mark if its cell
 // splits at this level, else 0.  A tile is the list positions [b T, (b + 1)
-// T), T = 2048, of all three lists, whose cells are the same (one pc / sax /
+// T), T = 1024, of all three lists, whose cells are the same (one pc / sax /
 // cell read serves the three).  k_level_sums counts each tile's marks per
 // list; k_cells_level has given the count of marks before each splitting
 // cell's first position (the same in the three lists), and k_level_move
@@ -262,8 +262,8 @@ __global__ void k_flag(int64_t n, const int32_t* __restrict__ pc, const int4* __
 // where they are needed, + the in-tile scan) and from the difference places
 // the position.
 constexpr int kLvThreads = 256;
-constexpr int kLvRounds = 8;
-constexpr int kLvTile = kLvThreads * kLvRounds;   // 2048 positions of each list
+constexpr int kLvRounds = 4;
+constexpr int kLvTile = kLvThreads * kLvRounds;   // 1024 positions of each list
 
 // The particles' left marks as bits: k_flag writes one byte per particle of
 // a splitting cell (scattered by particle), and this packs the bytes of
@@ -318,20 +318,27 @@ k_level_sums(int64_t n, const int32_t* __restrict__ pc, const int32_t* __restric
     }
 }
 
+// SCANNED: `offs` holds the exclusive scan of tile_sums over all 3 ntiles
+// entries, so the tiles before tile b of list a hold offs[a ntiles + b] -
+// offs[a ntiles] marks; otherwise each workgroup adds up tile_sums itself
+// (no scan launch; quadratic in the tiles, so for up to kLvSumMax of them).
+constexpr int kLvSumMax = 2048;
+
+template <bool SCANNED>
 __global__ void __launch_bounds__(kLvThreads)
 k_level_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __restrict__ pc_out,
              const int4* __restrict__ cell, const int4* __restrict__ aux,
              const int32_t* __restrict__ sax, const uint32_t* __restrict__ plist,
              uint32_t* __restrict__ pout, const uint64_t* __restrict__ bits,
-             const uint32_t* __restrict__ tile_sums, int ntiles,
-             const int32_t* __restrict__ pfirst) {
+             const uint32_t* __restrict__ tile_sums, const uint32_t* __restrict__ offs,
+             int ntiles, const int32_t* __restrict__ pfirst) {
     __shared__ uint8_t mk[3][kLvTile];
     __shared__ uint16_t pre[3][kLvTile];
     __shared__ uint64_t wsum[kLvThreads / 64];
     __shared__ uint32_t woff[3][kLvThreads / 64];
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
-    {
+    if (!SCANNED) {
         // this tile's offsets: the counts of the tiles before it, per list
         for (int a = 0; a < 3; ++a) {
             uint32_t c = 0;
@@ -363,7 +370,7 @@ k_level_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __restrict__ pc
     }
     __syncthreads();
     // in-tile exclusive prefix per list: thread t owns positions
-    // [8 t, 8 t + 8); the three counts packed 21 bits apart
+    // [kLvRounds t, kLvRounds (t + 1)); the three counts packed 21 bits apart
     uint64_t own = 0;
     for (int j = 0; j < kLvRounds; ++j)
         for (int a = 0; a < 3; ++a) own += (uint64_t)mk[a][kLvRounds * t + j] << (21 * a);
@@ -386,7 +393,11 @@ k_level_move(int64_t n, const int32_t* __restrict__ pc, int32_t* __restrict__ pc
     uint32_t toff[3];
     for (int a = 0; a < 3; ++a) {
         toff[a] = 0;
-        for (int w = 0; w < kLvThreads / 64; ++w) toff[a] += woff[a][w];
+        if (SCANNED) {
+            toff[a] = offs[(size_t)a * ntiles + blockIdx.x] - offs[(size_t)a * ntiles];
+        } else {
+            for (int w = 0; w < kLvThreads / 64; ++w) toff[a] += woff[a][w];
+        }
     }
     for (int r = 0; r < kLvRounds; ++r) {
         const int64_t i = base + r * kLvThreads + t;
@@ -1479,7 +1490,8 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
     uint64_t* bits = reinterpret_cast<uint64_t*>(d.flag.as<uint8_t>() + bits_off);
     const int64_t lv_tiles = (n + kLvTile - 1) / kLvTile;
     TRY(d.lv_first.ensure(nc * 4));
-    TRY(d.tile_sums.ensure(3 * lv_tiles * 4 + 16));
+    // per-list tile sums, their scan (large n) and the scan's scratch
+    TRY(d.tile_sums.ensure((6 * lv_tiles + sort_tiles(3 * lv_tiles)) * 4 + 16));
     TRY(d.clo.ensure(nc * 24));
     TRY(d.chi.ensure(nc * 24));
     TRY(d.cell_axis.ensure(nc * 4));
@@ -1505,11 +1517,24 @@ std::string gpu_build_plan(DevPlan& d, const Plan& topo, const double* pos, cons
                            d.pc.as<int32_t>(), d.cell_axis.as<int32_t>(), d.cell.as<int4>(),
                            d.plist.as<uint32_t>(), bits, d.tile_sums.as<uint32_t>(), (int)lv_tiles);
         TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_level_move, dim3(lv_tiles), dim3(kLvThreads), 0, s, n,
-                           d.pc.as<int32_t>(), d.pc_tmp.as<int32_t>(), d.cell.as<int4>(),
-                           d.cell_aux.as<int4>(), d.cell_axis.as<int32_t>(), d.plist.as<uint32_t>(),
-                           d.plist_tmp.as<uint32_t>(), bits, d.tile_sums.as<uint32_t>(),
-                           (int)lv_tiles, d.lv_first.as<int32_t>());
+        if (lv_tiles <= kLvSumMax) {
+            hipLaunchKernelGGL(k_level_move<false>, dim3(lv_tiles), dim3(kLvThreads), 0, s, n,
+                               d.pc.as<int32_t>(), d.pc_tmp.as<int32_t>(), d.cell.as<int4>(),
+                               d.cell_aux.as<int4>(), d.cell_axis.as<int32_t>(),
+                               d.plist.as<uint32_t>(), d.plist_tmp.as<uint32_t>(), bits,
+                               d.tile_sums.as<uint32_t>(), nullptr, (int)lv_tiles,
+                               d.lv_first.as<int32_t>());
+        } else {
+            uint32_t* offs = d.tile_sums.as<uint32_t>() + 3 * lv_tiles;
+            TRY(exclusive_scan_i32(d.tile_sums.as<int32_t>(), reinterpret_cast<int32_t*>(offs),
+                                   3 * lv_tiles, offs + 3 * lv_tiles, s));
+            hipLaunchKernelGGL(k_level_move<true>, dim3(lv_tiles), dim3(kLvThreads), 0, s, n,
+                               d.pc.as<int32_t>(), d.pc_tmp.as<int32_t>(), d.cell.as<int4>(),
+                               d.cell_aux.as<int4>(), d.cell_axis.as<int32_t>(),
+                               d.plist.as<uint32_t>(), d.plist_tmp.as<uint32_t>(), bits,
+                               d.tile_sums.as<uint32_t>(), offs, (int)lv_tiles,
+                               d.lv_first.as<int32_t>());
+        }
         TRY(hipGetLastError());
         std::swap(d.plist, d.plist_tmp);
         std::swap(d.pc, d.pc_tmp);

@@ -4,7 +4,8 @@
 // integers.
 //
 // Radix sort: 8-bit digits, tiles of 4096 elements (256 threads x 16
-// rounds); a tile never straddles two segments.  Per pass: (1) per-tile
+// rounds; 1024 for segments under kSmallSortN elements, whose few tiles
+// would otherwise leave most CUs idle); a tile never straddles two segments.  Per pass: (1) per-tile
 // digit histogram in LDS, (2) one exclusive scan over the
 // [segment][digit][tile] table (segment-major, so segment s lands in
 // [s n, (s + 1) n)), (3) scatter: inside a tile the 256 elements of a round
@@ -22,32 +23,42 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kRounds = 16;
 constexpr int kTile = kThreads * kRounds;  // 4096
+constexpr int kRoundsSmall = 4;
+constexpr int64_t kSmallSortN = int64_t(1) << 20;
+
+int radix_rounds(int64_t n) { return n < kSmallSortN ? kRoundsSmall : kRounds; }
+
+int64_t radix_tiles(int64_t n) {
+    const int64_t t = (int64_t)kThreads * radix_rounds(n);
+    return (n + t - 1) / t;
+}
 
 // Block b handles tile (b % tiles) of segment (b / tiles); its elements are
-// [seg n + tile kTile, min(seg n + (tile + 1) kTile, (seg + 1) n)).
+// [seg n + tile T, min(seg n + (tile + 1) T, (seg + 1) n)), T = 256 R.
 struct TileRange {
     int64_t begin, end;
     size_t col;   // (seg * 256) * tiles + tile: add digit * tiles
 };
 
+template <int R>
 __device__ __forceinline__ TileRange tile_range(int64_t n, int tiles) {
     const int seg = blockIdx.x / tiles, tile = blockIdx.x - seg * tiles;
     TileRange t;
-    t.begin = (int64_t)seg * n + (int64_t)tile * kTile;
-    t.end = min((int64_t)seg * n + n, t.begin + kTile);
+    t.begin = (int64_t)seg * n + (int64_t)tile * (kThreads * R);
+    t.end = min((int64_t)seg * n + n, t.begin + kThreads * R);
     t.col = (size_t)seg * 256 * tiles + tile;
     return t;
 }
 
-template <class K>
+template <class K, int R>
 __global__ void __launch_bounds__(kThreads)
 rs_hist(const K* __restrict__ keys, int64_t n, int shift, uint32_t* __restrict__ hist,
         int tiles) {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
-    const TileRange tr = tile_range(n, tiles);
-    for (int r = 0; r < kRounds; ++r) {
+    const TileRange tr = tile_range<R>(n, tiles);
+    for (int r = 0; r < R; ++r) {
         const int64_t i = tr.begin + r * kThreads + threadIdx.x;
         if (i < tr.end) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
     }
@@ -84,20 +95,20 @@ __global__ void __launch_bounds__(1024) scan_single(uint32_t* __restrict__ a, in
 // the tile's elements of that digit), then written out position by
 // position: consecutive positions of one digit go to consecutive addresses,
 // so the global writes come in runs instead of one element per line.
-template <class K, bool VALS>
+template <class K, bool VALS, int R>
 __global__ void __launch_bounds__(kThreads)
 rs_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
            K* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n, int shift,
            const uint32_t* __restrict__ hist, const uint32_t* __restrict__ offs, int tiles) {
-    __shared__ K ks[kTile];
-    __shared__ uint32_t vs[VALS ? kTile : 1];
+    __shared__ K ks[kThreads * R];
+    __shared__ uint32_t vs[VALS ? kThreads * R : 1];
     __shared__ uint32_t start[256];     // digit start inside the tile
     __shared__ uint32_t goff[256];      // digit start in the output
     __shared__ uint32_t run[256];       // elements of each digit placed so far
     __shared__ uint32_t wc[kThreads / 64][256];
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
-    const TileRange tr = tile_range(n, tiles);
+    const TileRange tr = tile_range<R>(n, tiles);
     // exclusive scan of the tile's digit counts (one wave scans 4 per lane)
     {
         const uint32_t c = hist[tr.col + (size_t)t * tiles];
@@ -126,7 +137,7 @@ rs_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
     }
     __syncthreads();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int r = 0; r < kRounds; ++r) {
+    for (int r = 0; r < R; ++r) {
         const int64_t i = tr.begin + r * kThreads + t;
         const bool valid = i < tr.end;
         K key = 0;
@@ -243,17 +254,15 @@ hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, uint32
 int64_t sort_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
 
 int64_t sort_hist_words(int64_t n, int nseg) {
-    const int64_t m = (int64_t)nseg * 256 * sort_tiles(n);
+    const int64_t m = (int64_t)nseg * 256 * radix_tiles(n);
     return 2 * m + sort_tiles(m) + 16;
 }
 
-template <class K>
-hipError_t radix_sort(K* keys, uint32_t* vals, K* tmp_keys, uint32_t* tmp_vals, uint32_t* hist,
-                      int64_t n, int bit_begin, int bit_end, hipStream_t s, bool* result_in_tmp,
-                      int nseg) {
-    *result_in_tmp = false;
-    if (n <= 1 || nseg < 1) return hipSuccess;
-    const int tiles = (int)sort_tiles(n);
+template <class K, int R>
+hipError_t radix_sort_r(K* keys, uint32_t* vals, K* tmp_keys, uint32_t* tmp_vals, uint32_t* hist,
+                        int64_t n, int bit_begin, int bit_end, hipStream_t s, bool* result_in_tmp,
+                        int nseg) {
+    const int tiles = (int)radix_tiles(n);
     const int blocks = nseg * tiles;
     K* ka = keys;
     K* kb = tmp_keys;
@@ -264,21 +273,35 @@ hipError_t radix_sort(K* keys, uint32_t* vals, K* tmp_keys, uint32_t* tmp_vals, 
     uint32_t* offs = hist + m;
     uint32_t* scan_scratch = hist + 2 * m;
     for (int shift = bit_begin; shift < bit_end; shift += 8) {
-        hipLaunchKernelGGL(rs_hist<K>, dim3(blocks), dim3(kThreads), 0, s, ka, n, shift, hist, tiles);
+        hipLaunchKernelGGL((rs_hist<K, R>), dim3(blocks), dim3(kThreads), 0, s, ka, n, shift, hist,
+                           tiles);
         const hipError_t e = exclusive_scan_i32(reinterpret_cast<const int32_t*>(hist),
                                                 reinterpret_cast<int32_t*>(offs), m, scan_scratch, s);
         if (e != hipSuccess) return e;
         if (vals)
-            hipLaunchKernelGGL((rs_scatter<K, true>), dim3(blocks), dim3(kThreads), 0, s, ka, va, kb,
-                               vb, n, shift, hist, offs, tiles);
+            hipLaunchKernelGGL((rs_scatter<K, true, R>), dim3(blocks), dim3(kThreads), 0, s, ka, va,
+                               kb, vb, n, shift, hist, offs, tiles);
         else
-            hipLaunchKernelGGL((rs_scatter<K, false>), dim3(blocks), dim3(kThreads), 0, s, ka, va, kb,
-                               vb, n, shift, hist, offs, tiles);
+            hipLaunchKernelGGL((rs_scatter<K, false, R>), dim3(blocks), dim3(kThreads), 0, s, ka, va,
+                               kb, vb, n, shift, hist, offs, tiles);
         std::swap(ka, kb);
         std::swap(va, vb);
         *result_in_tmp = !*result_in_tmp;
     }
     return hipGetLastError();
+}
+
+template <class K>
+hipError_t radix_sort(K* keys, uint32_t* vals, K* tmp_keys, uint32_t* tmp_vals, uint32_t* hist,
+                      int64_t n, int bit_begin, int bit_end, hipStream_t s, bool* result_in_tmp,
+                      int nseg) {
+    *result_in_tmp = false;
+    if (n <= 1 || nseg < 1) return hipSuccess;
+    if (radix_rounds(n) == kRoundsSmall)
+        return radix_sort_r<K, kRoundsSmall>(keys, vals, tmp_keys, tmp_vals, hist, n, bit_begin,
+                                             bit_end, s, result_in_tmp, nseg);
+    return radix_sort_r<K, kRounds>(keys, vals, tmp_keys, tmp_vals, hist, n, bit_begin, bit_end, s,
+                                    result_in_tmp, nseg);
 }
 
 hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals,

@@ -1172,8 +1172,17 @@ __global__ void k_items(int nl, const int32_t* __restrict__ row, const int32_t* 
             for (int k = lane; k < parts; k += 64) {
                 const int t = r0 + k * base + min(k, extra);
                 const int sz = base + (k < extra ? 1 : 0);
+                // the tasks' source counts, eight loads in flight at a time
                 unsigned long long c = 0;
-                for (int q = t; q < t + sz; ++q) c += (unsigned long long)leaf[js[q] >> 5].y;
+                int q = t;
+                for (; q + 8 <= t + sz; q += 8) {
+                    int jv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) jv[u] = js[q + u] >> 5;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) c += (unsigned long long)leaf[jv[u]].y;
+                }
+                for (; q < t + sz; ++q) c += (unsigned long long)leaf[js[q] >> 5].y;
                 c *= (unsigned long long)ni;
                 total += c;
                 const int s = slot0[i] + k;

@@ -98,24 +98,27 @@ def test_ties_duplicates_and_unwrapped():
     assert_same(L, tree, lists)
 
 
-# Coordinates closer together than the 32-bit sort key resolves (2^-32 of the
-# box), in scrambled caller order: a run of up to 64 equal keys is put in
+# Coordinates closer together than the sort key resolves (2^-24 of the box
+# here), in scrambled caller order: a run of up to 64 equal keys is put in
 # coordinate order in place; a longer one out of order makes the build sort
-# by the full 64-bit keys.
-@pytest.mark.parametrize("group", [5, 64, 65, 300])
-def test_coordinates_below_sort_key_resolution(group):
-    rng = np.random.default_rng(100 + group)
+# by the full 64-bit keys.  With `ties`, the coordinates of a run come in
+# equal pairs, which keep caller order.
+@pytest.mark.parametrize("group,ties", [(4, False), (4, True), (5, False), (5, True), (8, False),
+                                        (64, False), (64, True), (65, False), (300, False)])
+def test_coordinates_below_sort_key_resolution(group, ties):
+    rng = np.random.default_rng(100 + group + 1000 * ties)
     parts = [rng.uniform(0, 20.0, (3000, 3))]
     for axis in range(3):
         for _ in range(4):
             x0 = rng.uniform(1.0, 19.0)
             close = rng.uniform(0, 20.0, (group, 3))
-            close[:, axis] = x0 + np.arange(group) * 1e-12
+            step = np.arange(group) // 2 if ties else np.arange(group)
+            close[:, axis] = x0 + step * 1e-12
             parts.append(close)
     pos = np.concatenate(parts)
     pos = pos[rng.permutation(len(pos))]
     m = rng.uniform(0.5, 1.0, len(pos))
-    print(f"case: gpu plan sub-key-resolution runs of {group}", flush=True)
+    print(f"case: gpu plan sub-key-resolution runs of {group} (ties {ties})", flush=True)
     L, _ = gpu_lists(pos, m, 20.0, 0.6, 2.7, 16, 3, 0.4)
     tree, lists = oracle_lists(pos, 20.0, 2.7, 16, 3, 0.4)
     assert_same(L, tree, lists)

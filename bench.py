@@ -381,6 +381,9 @@ def secondary(args):
                  "fp32_r2_64": dict(precision=B.PMFMM_FP32, trunc=B.TRUNC_R2,
                                     table_size=64, table_level=2)}
         order, theta = args.order, args.theta
+    if args.headline_only:
+        # the float32 r^2 form alone (profiling runs)
+        forms = {"fp32_r2_64": forms["fp32_r2_64"]}
     n = len(w.mass)
     res = {}
     base = idx = ref = None
@@ -439,7 +442,8 @@ def main():
                     help="degree of the headline float32 table's segments")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
-                    help="time the headline float32 form only (profiling)")
+                    help="time the float32 r^2 form only (profiling; also "
+                         "for --config clustered_16m and uniform_32k)")
     ap.add_argument("--forms", default="",
                     help="comma-separated subset of the forms to time "
                          "(fp32, fp32_paper_table, fp64, fp64_table, fp64_r2)")
